@@ -1,0 +1,366 @@
+"""FP64 CPU oracle for the sparse-tiled DG elastic loop chain.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (``libdgtile`` and the
+``paper_1708_03183_amd`` binding) imports or loads this package; the tests, the
+smoke check and the benchmark's CPU-baseline leg do.  The C sources next to this
+file hold the arithmetic; this module only marshals NumPy arrays to them.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "liboracle.so")
+_SRCS = ["refelem.c", "mesh.c", "dg.c", "chain.c", "oracle.h"]
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (plain C11, -ffp-contract=off)."""
+    if force or not os.path.exists(_LIB):
+        subprocess.run(["sh", os.path.join(_HERE, "build.sh")], check=True)
+    return _LIB
+
+
+def _stale() -> bool:
+    if not os.path.exists(_LIB):
+        return True
+    t = os.path.getmtime(_LIB)
+    return any(os.path.getmtime(os.path.join(_HERE, s)) > t for s in _SRCS)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if _stale():
+            build()
+        _lib = C.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+_p = C.c_void_p
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+_i8p = np.ctypeslib.ndpointer(np.int8, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+
+
+def _declare(L):
+    L.or_np.restype = C.c_int
+    L.or_refelem.argtypes = [C.c_int, _p, _p, _p, _p, _p, _p, _p]
+    L.or_tri_quad.argtypes = [C.c_int, _f64p, _f64p]
+    L.or_basis.argtypes = [C.c_int, C.c_double, C.c_double, _f64p]
+    L.or_mesh_build.argtypes = [C.c_int64, _f64p, C.c_int64, _i32p, C.c_int, C.POINTER(_p)]
+    L.or_mesh_free.argtypes = [_p]
+    L.or_mesh_counts.argtypes = [_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    L.or_mesh_maps.argtypes = [_p, _i32p, _i8p, _i32p, _i8p, _i8p]
+    L.or_dg_create.argtypes = [_p, C.c_int, _f64p, _f64p, _f64p, C.c_int, C.c_int, C.c_double, C.c_int,
+                               C.POINTER(_p)]
+    L.or_dg_free.argtypes = [_p]
+    L.or_dg_set_source.argtypes = [_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double]
+    L.or_dg_source_cell.argtypes = [_p]
+    L.or_dg_step.argtypes = [_p, _f64p, _f64p, C.c_int64, C.c_double]
+    L.or_dg_step_tiled.argtypes = [_p, _p, _f64p, _f64p, C.c_int64, C.c_double]
+    L.or_dg_energy.argtypes = [_p, _f64p, _f64p, _f64p]
+    L.or_dg_energy.restype = C.c_double
+    L.or_cfl_dt.argtypes = [_p, C.c_int, _f64p, _f64p, _f64p, C.c_double]
+    L.or_cfl_dt.restype = C.c_double
+    L.or_ricker.argtypes = [C.c_double] * 4
+    L.or_ricker.restype = C.c_double
+    L.or_dg_rate.argtypes = [_p, _f64p, _f64p, _f64p, _f64p]
+    L.or_dg_chain.argtypes = [_p, C.POINTER(_p)]
+    L.or_chain_create.argtypes = [C.POINTER(_p)]
+    L.or_chain_free.argtypes = [_p]
+    L.or_chain_set.argtypes = [_p, C.c_int64]
+    L.or_chain_map.argtypes = [_p, C.c_int, C.c_int, C.c_int, _i32p]
+    L.or_chain_loop.argtypes = [_p, C.c_int, C.c_int, _i32p, _i32p, _i32p]
+    L.or_chain_nloops.argtypes = [_p]
+    L.or_inspect.argtypes = [_p, C.c_int64, C.c_int, _p, C.c_int, _p, C.c_int, C.POINTER(_p)]
+    L.or_sched_free.argtypes = [_p]
+    L.or_sched_nsub.argtypes = [_p]
+    L.or_sched_sub_info.argtypes = [_p, C.c_int] + [C.POINTER(C.c_int32)] * 5
+    L.or_sched_tile_color.argtypes = [_p, C.c_int, _i32p]
+    L.or_sched_sigma.argtypes = [_p, C.c_int, _i32p]
+    L.or_sched_iters.argtypes = [_p, C.c_int, _i32p, _i32p]
+    L.or_sched_footprint.argtypes = [_p, C.c_int, C.c_int, _p, _p, _p]
+    L.or_sched_footprint.restype = C.c_int64
+    L.or_sched_tiles_by_color.argtypes = [_p, C.c_int, _i32p, _i32p]
+    L.or_sched_set_color.argtypes = [_p, C.c_int, C.c_int, C.c_int]
+    L.or_sched_set_sigma.argtypes = [_p, C.c_int, C.c_int64, C.c_int]
+    L.or_check.argtypes = [_p, _p]
+    L.or_check.restype = C.c_int64
+    L.or_tile_with_colors.argtypes = [_p, _i32p, C.c_int, _i32p, _p]
+    L.or_projection_after.argtypes = [_p, _i32p, C.c_int, _i32p, C.c_int, C.c_int, _i32p]
+    L.or_set_literal_projection.argtypes = [C.c_int]
+    L.or_instrumented_run.argtypes = [_p, _p, C.c_int, C.POINTER(C.c_uint64)]
+
+
+def set_literal_projection(on: bool):
+    lib().or_set_literal_projection(1 if on else 0)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+# ----------------------------------------------------------------- element
+def np_of(k: int) -> int:
+    return (k + 1) * (k + 2) // 2
+
+
+def refelem(k: int) -> dict:
+    npk, nfp = np_of(k), k + 1
+    out = dict(nodes=np.zeros((npk, 2)), M=np.zeros((npk, npk)), Minv=np.zeros((npk, npk)),
+               Dr=np.zeros((npk, npk)), Ds=np.zeros((npk, npk)), M1=np.zeros((nfp, nfp)),
+               fnodes=np.zeros((3, nfp), np.int32))
+    rc = lib().or_refelem(k, *[_ptr(out[n]) for n in ("nodes", "M", "Minv", "Dr", "Ds", "M1", "fnodes")])
+    if rc:
+        raise ValueError(f"or_refelem({k}) -> {rc}")
+    return out
+
+
+def tri_quad(n: int):
+    pts = np.zeros((n * n, 2))
+    w = np.zeros(n * n)
+    lib().or_tri_quad(n, pts, w)
+    return pts, w
+
+
+def basis(k: int, r: float, s: float) -> np.ndarray:
+    phi = np.zeros(np_of(k))
+    lib().or_basis(k, r, s, phi)
+    return phi
+
+
+def ricker(t, f0, t0, amp=1.0):
+    return lib().or_ricker(t, f0, t0, amp)
+
+
+# ----------------------------------------------------------------- mesh
+class OMesh:
+    def __init__(self, xy, c2v, periodic=0):
+        self.xy = np.ascontiguousarray(xy, np.float64)
+        self.c2v = np.ascontiguousarray(c2v, np.int32)
+        h = C.c_void_p()
+        rc = lib().or_mesh_build(self.xy.shape[0], self.xy, self.c2v.shape[0], self.c2v, int(periodic), C.byref(h))
+        if rc:
+            raise ValueError(f"invalid mesh ({rc})")
+        self.h = h
+        nc, nf, nb = C.c_int64(), C.c_int64(), C.c_int64()
+        lib().or_mesh_counts(h, C.byref(nc), C.byref(nf), C.byref(nb))
+        self.nc, self.nf, self.nb = nc.value, nf.value, nb.value
+
+    @classmethod
+    def from_mesh(cls, m):
+        return cls(m.xy, m.c2v, m.periodic)
+
+    def maps(self):
+        f2c = np.zeros(2 * self.nf, np.int32)
+        f2l = np.zeros(2 * self.nf, np.int8)
+        b2c = np.zeros(self.nb, np.int32)
+        b2l = np.zeros(self.nb, np.int8)
+        bs = np.zeros(self.nb, np.int8)
+        lib().or_mesh_maps(self.h, f2c, f2l, b2c, b2l, bs)
+        return dict(f2c=f2c.reshape(-1, 2), f2l=f2l.reshape(-1, 2), b2c=b2c, b2l=b2l, bside=bs)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.or_mesh_free(self.h)
+            self.h = None
+
+
+def cfl_dt(om: OMesh, k, lam, mu, rho, cfl=0.2):
+    return lib().or_cfl_dt(om.h, k, *[np.ascontiguousarray(a, np.float64) for a in (lam, mu, rho)], cfl)
+
+
+# ----------------------------------------------------------------- DG chain
+class ODG:
+    """Oracle DG solver: state arrays v[2,Np,nc], s[3,Np,nc] (float64)."""
+
+    def __init__(self, om: OMesh, k, lam, mu, rho, flux=0, order=4, dt=None, free_sides=0xF):
+        self.om, self.k, self.np = om, k, np_of(k)
+        self.lam, self.mu, self.rho = [np.ascontiguousarray(a, np.float64) for a in (lam, mu, rho)]
+        if dt is None:
+            dt = cfl_dt(om, k, self.lam, self.mu, self.rho)
+        self.dt = dt
+        h = C.c_void_p()
+        rc = lib().or_dg_create(om.h, k, self.lam, self.mu, self.rho, flux, order, dt, free_sides, C.byref(h))
+        if rc:
+            raise ValueError(f"or_dg_create -> {rc}")
+        self.h = h
+
+    def zeros(self):
+        return np.zeros((2, self.np, self.om.nc)), np.zeros((3, self.np, self.om.nc))
+
+    def set_source(self, x, y, f0=5.0, t0=0.2, amp=1.0):
+        if lib().or_dg_set_source(self.h, x, y, f0, t0, amp):
+            raise ValueError("source outside the mesh")
+        return lib().or_dg_source_cell(self.h)
+
+    def step(self, v, s, nsteps, t0=0.0):
+        lib().or_dg_step(self.h, v, s, nsteps, t0)
+
+    def step_tiled(self, sched, v, s, nsteps, t0=0.0):
+        rc = lib().or_dg_step_tiled(self.h, sched.h, v, s, nsteps, t0)
+        if rc:
+            raise ValueError(f"or_dg_step_tiled -> {rc}")
+
+    def energy(self, v, s_new, s_old):
+        return lib().or_dg_energy(self.h, v, s_new, s_old)
+
+    def rate(self, v, s):
+        dv, ds = np.zeros_like(v), np.zeros_like(s)
+        lib().or_dg_rate(self.h, np.ascontiguousarray(v), np.ascontiguousarray(s), dv, ds)
+        return dv, ds
+
+    def chain(self) -> "OChain":
+        h = C.c_void_p()
+        lib().or_dg_chain(self.h, C.byref(h))
+        return OChain(handle=h)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.or_dg_free(self.h)
+            self.h = None
+
+
+# ----------------------------------------------------------------- loop chain
+R, W, INC = 0, 1, 2
+
+
+class OChain:
+    def __init__(self, handle=None):
+        if handle is None:
+            handle = C.c_void_p()
+            lib().or_chain_create(C.byref(handle))
+        self.h = handle
+
+    def set(self, size):
+        return lib().or_chain_set(self.h, size)
+
+    def map(self, frm, to, arity, values):
+        v = np.ascontiguousarray(values, np.int32).ravel()
+        rc = lib().or_chain_map(self.h, frm, to, arity, v)
+        if rc < 0:
+            raise ValueError("bad map")
+        return rc
+
+    def loop(self, set_id, descs):
+        """descs: list of (map or -1, mode[, data])"""
+        m = np.array([d[0] for d in descs], np.int32)
+        mo = np.array([d[1] for d in descs], np.int32)
+        da = np.array([d[2] if len(d) > 2 else -1 for d in descs], np.int32)
+        rc = lib().or_chain_loop(self.h, set_id, len(descs), m, mo, da)
+        if rc < 0:
+            raise ValueError("bad loop")
+        return rc
+
+    @property
+    def nloops(self):
+        return lib().or_chain_nloops(self.h)
+
+    def inspect(self, ts, partition=0, seed_xy=None, max_rounds=64, splits=()):
+        xy = None if seed_xy is None else np.ascontiguousarray(seed_xy, np.float64)
+        sp = np.ascontiguousarray(np.array(splits, np.int32))
+        h = C.c_void_p()
+        rc = lib().or_inspect(self.h, ts, partition, _ptr(xy), max_rounds, _ptr(sp) if len(sp) else None,
+                              len(sp), C.byref(h))
+        if rc:
+            raise RuntimeError(f"or_inspect -> {rc}")
+        return OSched(h, self)
+
+    def sizes_of_loops(self, set_sizes):
+        return [set_sizes[s] for s in self._loop_sets]
+
+    def tile_with_colors(self, tile0, ntiles, color, loop_sizes):
+        sig = [np.zeros(n, np.int32) for n in loop_sizes]
+        arr = (C.c_void_p * len(sig))(*[a.ctypes.data for a in sig])
+        lib().or_tile_with_colors(self.h, np.ascontiguousarray(tile0, np.int32), ntiles,
+                                  np.ascontiguousarray(color, np.int32), C.cast(arr, C.c_void_p))
+        return sig
+
+    def projection_after(self, tile0, ntiles, color, upto, set_id, set_size):
+        out = np.zeros(set_size, np.int32)
+        lib().or_projection_after(self.h, np.ascontiguousarray(tile0, np.int32), ntiles,
+                                  np.ascontiguousarray(color, np.int32), upto, set_id, out)
+        return out
+
+    def instrumented(self, sched=None, nrep=1):
+        out = C.c_uint64()
+        rc = lib().or_instrumented_run(self.h, None if sched is None else sched.h, nrep, C.byref(out))
+        if rc:
+            raise RuntimeError("instrumented run failed")
+        return out.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.or_chain_free(self.h)
+            self.h = None
+
+
+class OSched:
+    def __init__(self, h, chain):
+        self.h, self.chain = h, chain
+
+    @property
+    def nsub(self):
+        return lib().or_sched_nsub(self.h)
+
+    def sub_info(self, sub):
+        v = [C.c_int32() for _ in range(5)]
+        lib().or_sched_sub_info(self.h, sub, *[C.byref(x) for x in v])
+        return dict(first=v[0].value, nloops=v[1].value, ntiles=v[2].value, ncolors=v[3].value, rounds=v[4].value)
+
+    def colors(self, sub):
+        out = np.zeros(self.sub_info(sub)["ntiles"], np.int32)
+        lib().or_sched_tile_color(self.h, sub, out)
+        return out
+
+    def sigma(self, loop, size):
+        out = np.zeros(size, np.int32)
+        lib().or_sched_sigma(self.h, loop, out)
+        return out
+
+    def iters(self, loop, size, sub):
+        nt = self.sub_info(sub)["ntiles"]
+        off = np.zeros(nt + 1, np.int32)
+        it = np.zeros(size, np.int32)
+        lib().or_sched_iters(self.h, loop, off, it)
+        return off, it
+
+    def footprint(self, sub, set_id):
+        nt = self.sub_info(sub)["ntiles"]
+        m = lib().or_sched_footprint(self.h, sub, set_id, None, None, None)
+        off = np.zeros(nt + 1, np.int32)
+        el = np.zeros(max(m, 0), np.int32)
+        acc = np.zeros(max(m, 0), np.uint32)
+        lib().or_sched_footprint(self.h, sub, set_id, _ptr(off), _ptr(el), _ptr(acc))
+        return off, el, acc
+
+    def tiles_by_color(self, sub):
+        info = self.sub_info(sub)
+        coff = np.zeros(info["ncolors"] + 1, np.int32)
+        tl = np.zeros(info["ntiles"], np.int32)
+        lib().or_sched_tiles_by_color(self.h, sub, coff, tl)
+        return coff, tl
+
+    def set_color(self, sub, tile, color):
+        lib().or_sched_set_color(self.h, sub, tile, color)
+
+    def set_sigma(self, loop, it, tile):
+        lib().or_sched_set_sigma(self.h, loop, it, tile)
+
+    def check(self):
+        return lib().or_check(self.chain.h, self.h)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.or_sched_free(self.h)
+            self.h = None

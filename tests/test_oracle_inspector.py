@@ -1,0 +1,212 @@
+"""Pins of the oracle inspector (Alg. 1, 3, 4) and executor (Alg. 2).
+
+* the shared-memory worked example of Sec. 3.2 (a vertex with 7 incident
+  edges, 2 in the green tile and 5 in the blue one, projects to blue; a cell
+  touching blue, green, green vertices goes to blue);
+* the conflict scenario of Sec. 3.2 (same-coloured tiles becoming adjacent)
+  is resolved by fake connections;
+* on random tiny meshes the brute-force dependence checker finds no violation,
+  every iteration has exactly one tile, and an integer-instrumented chain gives
+  bit-identical data tiled and untiled;
+* the checker catches a swapped colour pair and the literal (bottom-reset)
+  reading of the projection algorithm;
+* the tiled DG chain equals the untiled one to rounding (<= 1e-14 relative).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1708_03183_amd import inputs as I
+
+
+def _wheel_chain():
+    # vertex v0 in the middle of 7 rim vertices v1..v7; spokes e0..e6 = (v0, v_{i+1}),
+    # rim edges e7..e13 = (v_{i+1}, v_{(i+1)%7+1}); cells c_i = (v0, v_{i+1}, v_{(i+1)%7+1})
+    e2v = [[0, i + 1] for i in range(7)] + [[i + 1, (i + 1) % 7 + 1] for i in range(7)]
+    c2v = [[0, i + 1, (i + 1) % 7 + 1] for i in range(7)]
+    ch = O.OChain()
+    E = ch.set(14)
+    Cs = ch.set(7)
+    V = ch.set(8)
+    e2vm = ch.map(E, V, 2, e2v)
+    c2vm = ch.map(Cs, V, 3, c2v)
+    # the toy program of Fig. 2: L0 edges inc vertices; L1 cells inc vertices; L2 edges read vertices
+    ch.loop(E, [(-1, O.R, 0), (e2vm, O.INC, 1)])
+    ch.loop(Cs, [(-1, O.R, 2), (c2vm, O.INC, 1)])
+    ch.loop(E, [(-1, O.W, 0), (e2vm, O.R, 1)])
+    return ch
+
+
+def test_worked_example_projection_and_tiling():
+    ch = _wheel_chain()
+    # green tile T0 holds spokes e0, e1 and rim edges e7, e8, e13; blue tile T1 the rest
+    tile0 = np.ones(14, np.int32)
+    tile0[[0, 1, 7, 8, 13]] = 0
+    color = np.array([0, 1], np.int32)  # G = 0 before B = 1
+    phi = ch.projection_after(tile0, 2, color, 1, 2, 8)
+    assert phi[0] == 1   # v0: 2 green + 5 blue incident edges -> blue
+    assert phi[1] == 0 and phi[2] == 0   # v1, v2 touch only green edges
+    sig = ch.tile_with_colors(tile0, 2, color, [14, 7, 14])
+    # cell c0 = (v0, v1, v2): MAX(B, G, G) = B
+    assert sig[1][0] == 1
+
+
+def test_inverse_map_example():
+    # Fig. 8: cell 1 -> vertices {3, 7, 9}; the inverse map lists cell 1 under each
+    c2v = np.array([[0, 1, 2], [3, 7, 9], [2, 3, 4]], np.int32)
+    inv = {}
+    for c, vs in enumerate(c2v):
+        for v in vs:
+            inv.setdefault(int(v), []).append(c)
+    assert all(1 in inv[v] for v in (3, 7, 9))
+    # the oracle's projection realises exactly this: a tile written only by cell 1
+    ch = O.OChain()
+    Cs = ch.set(3)
+    V = ch.set(10)
+    m = ch.map(Cs, V, 3, c2v)
+    ch.loop(Cs, [(m, O.INC, 0)])
+    ch.loop(V, [(-1, O.R, 0)])
+    phi = ch.projection_after(np.array([0, 1, 2], np.int32), 3, np.array([0, 1, 2], np.int32), 1, V, 10)
+    assert list(phi[[3, 7, 9]]) == [2, 1, 1] or list(phi[[7, 9]]) == [1, 1]
+    assert phi[7] == 1 and phi[9] == 1 and phi[3] == 2  # vertex 3 also touched by cell 2 (higher colour)
+
+
+def _strip_chain(n, nloops):
+    # 1-D strip of n cells with n-1 interior faces; alternate cell/face loops
+    f2c = np.array([[i, i + 1] for i in range(n - 1)], np.int32)
+    ch = O.OChain()
+    Cs = ch.set(n)
+    F = ch.set(n - 1)
+    m = ch.map(F, Cs, 2, f2c)
+    d = 0
+    for j in range(nloops):
+        if j % 2 == 0:
+            ch.loop(Cs, [(-1, O.R, d), (-1, O.W, d + 1)])
+        else:
+            ch.loop(F, [(m, O.R, d), (m, O.INC, d + 1)])
+        d += 1
+    return ch
+
+
+def test_conflicts_resolved_by_fake_connections():
+    # thin middle tiles get swallowed by growth; equal-coloured tiles meet
+    ch = _strip_chain(40, 11)
+    with pytest.raises(RuntimeError):
+        ch.inspect(4, max_rounds=1)   # the first colouring conflicts
+    s = ch.inspect(4, max_rounds=64)
+    assert s.sub_info(0)["rounds"] >= 2
+    assert s.check() == 0
+    assert ch.instrumented(None) == ch.instrumented(s)
+
+
+def _dg(n, k=1, jit=0.2, ren=None, order=4, flux=1, free=0x8):
+    m = I.square_mesh(n, jitter=jit, renumber_seed=ren)
+    om = O.OMesh.from_mesh(m)
+    d = O.ODG(om, k, *I.layered_material(m), flux=flux, order=order, free_sides=free)
+    return m, om, d
+
+
+CASES = [(n, order, flux, ts, part, ren)
+         for n in (3, 6, 11)
+         for order in (2, 4)
+         for flux in (0, 1)
+         for ts in (1, 5, 17, 64)
+         for part in (0, 1)
+         for ren in (None, 7)
+         if not (flux == 0 and ren is None and part == 1)]
+
+
+@pytest.mark.parametrize("n,order,flux,ts,part,ren", CASES[::3])
+def test_random_meshes_legal_schedules(n, order, flux, ts, part, ren):
+    m, om, d = _dg(n, order=order, flux=flux, ren=ren)
+    ch = d.chain()
+    s = ch.inspect(ts, partition=part, seed_xy=m.centroids())
+    assert s.check() == 0
+    info = s.sub_info(0)
+    assert ch.instrumented(None) == ch.instrumented(s)
+    # tiles of one colour never share an element (the colouring invariant)
+    off, el, acc = s.footprint(0, 0)
+    col = s.colors(0)
+    owner = {}
+    for t in range(info["ntiles"]):
+        for x in el[off[t]:off[t + 1]]:
+            owner.setdefault(int(x), set()).add(t)
+    for x, ts_ in owner.items():
+        cols = [col[t] for t in ts_]
+        assert len(cols) == len(set(cols))
+        single = (acc[off[min(ts_)]:off[min(ts_) + 1]][el[off[min(ts_)]:off[min(ts_) + 1]] == x][0] >> 31) & 1
+        assert single == (len(ts_) == 1)
+
+
+def test_every_iteration_once():
+    m, om, d = _dg(9, order=4, ren=3)
+    ch = d.chain()
+    s = ch.inspect(10, partition=1, seed_xy=m.centroids())
+    sizes = [om.nc, om.nf, om.nb, om.nc] * 3 + [om.nc]
+    sizes = sizes + sizes
+    for j in range(ch.nloops):
+        off, it = s.iters(j, sizes[j], 0)
+        assert off[-1] == sizes[j]
+        assert sorted(it.tolist()) == list(range(sizes[j]))
+        for t in range(len(off) - 1):
+            seg = it[off[t]:off[t + 1]]
+            assert np.all(np.diff(seg) > 0)
+
+
+def test_checker_catches_swapped_colours():
+    m, om, d = _dg(8, order=4, ren=3)
+    ch = d.chain()
+    s = ch.inspect(8, partition=1, seed_xy=m.centroids())
+    assert s.check() == 0
+    col = s.colors(0)
+    a = 0
+    b = int(np.nonzero(col != col[a])[0][0])
+    s.set_color(0, a, int(col[b]))
+    s.set_color(0, b, int(col[a]))
+    assert s.check() > 0
+
+
+def test_checker_catches_literal_projection():
+    m, om, d = _dg(8, order=4, ren=3)
+    ch = d.chain()
+    O.set_literal_projection(True)
+    try:
+        s = ch.inspect(8, partition=1, seed_xy=m.centroids())
+        viol = s.check()
+    finally:
+        O.set_literal_projection(False)
+    assert viol > 0
+
+
+@pytest.mark.parametrize("order,flux,free,k", [(4, 1, 0x8, 2), (2, 1, 0x8, 1), (4, 0, 0xF, 3), (2, 0, 0x3, 2)])
+def test_tiled_equals_untiled_dg(order, flux, free, k):
+    m, om, d = _dg(12, k=k, order=order, flux=flux, free=free, ren=5)
+    d.set_source(0.43, 0.52)
+    ch = d.chain()
+    s = ch.inspect(20, partition=1, seed_xy=m.centroids(), splits=(13,) if order == 4 else ())
+    v, sg = d.zeros()
+    v[:] = I.random_state(v.shape, 1)
+    sg[:] = I.random_state(sg.shape, 2)
+    v2, s2 = v.copy(), sg.copy()
+    d.step(v, sg, 4, t0=0.1)
+    d.step_tiled(s, v2, s2, 4, t0=0.1)
+    ref = np.sqrt((v ** 2).sum() + (sg ** 2).sum())
+    err = np.sqrt(((v - v2) ** 2).sum() + ((sg - s2) ** 2).sum()) / ref
+    print("tiled vs untiled relative L2", err)
+    assert err <= 1e-14
+
+
+def test_hilbert_partition_compact():
+    # Hilbert chunks of a randomly renumbered mesh cut far fewer facets than
+    # chunks of the random numbering
+    m, om, d = _dg(32, k=1, ren=9)
+    mp = om.maps()
+    c = m.centroids()
+
+    def cut(part):
+        ch = d.chain()
+        s = ch.inspect(64, partition=part, seed_xy=c)
+        sig = s.sigma(0, om.nc)
+        return int(np.sum(sig[mp["f2c"][:, 0]] != sig[mp["f2c"][:, 1]]))
+
+    assert cut(1) * 4 < cut(0)

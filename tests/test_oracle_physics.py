@@ -1,0 +1,192 @@
+"""Pins of the oracle DG chain against mathematics the paper fixes or implies:
+exact discrete energy conservation (central flux), energy decay (upwind),
+plane-wave convergence, temporal order against the exact semi-discrete
+solution, Riemann-flux consistency and the injected source integral."""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle as O
+from paper_1708_03183_amd import inputs as I
+
+
+def _energy_run(n, k, order, flux, free, steps, jitter=0.0, seed=5, layered=False):
+    m = I.square_mesh(n, jitter=jitter)
+    om = O.OMesh.from_mesh(m)
+    mat = I.layered_material(m) if layered else I.homogeneous_material(m)
+    d = O.ODG(om, k, *mat, flux=flux, order=order, free_sides=free)
+    v, s = d.zeros()
+    v[:] = I.random_state(v.shape, seed)
+    s[:] = I.random_state(s.shape, seed + 1)
+    es = []
+    for _ in range(steps):
+        so = s.copy()
+        d.step(v, s, 1)
+        es.append(d.energy(v, s, so))
+    return np.array(es)
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_energy_conserved_central_free_surface(order):
+    # small_p1 mesh (32x32, P1): relative drift <= 1e-12 over 1000 FP64 steps
+    es = _energy_run(32, 1, order, 0, 0xF, 1000)
+    assert np.abs(es - es[0]).max() / es[0] < 1e-12
+
+
+def test_energy_conserved_p2_jittered_layered():
+    es = _energy_run(8, 2, 4, 0, 0xF, 300, jitter=0.2, layered=True)
+    assert np.abs(es - es[0]).max() / es[0] < 1e-12
+
+
+@pytest.mark.parametrize("free", [0xF, 0x8, 0x0])
+def test_energy_non_increasing_upwind(free):
+    es = _energy_run(8, 2, 4, 1, free, 200, jitter=0.2, layered=True)
+    assert np.all(np.diff(es) <= 1e-14 * es[0])
+    assert es[-1] < es[0]
+
+
+def _plane_wave_error(n, k, flux, order=4, T=0.25, swave=False):
+    m = I.square_mesh(n, periodic=3)
+    om = O.OMesh.from_mesh(m)
+    lam, mu, rho = I.homogeneous_material(m)
+    kap = np.array([2 * np.pi, 2 * np.pi])
+    kn = np.linalg.norm(kap)
+    dvec = kap / kn
+    dperp = np.array([-dvec[1], dvec[0]])
+    cp, cs = math.sqrt(4.0), 1.0
+    dt = O.cfl_dt(om, k, lam, mu, rho) * 0.5
+    nsteps = int(round(T / dt))
+    dt = T / nsteps
+    d = O.ODG(om, k, lam, mu, rho, flux=flux, order=order, dt=dt, free_sides=0)
+    nodes = O.refelem(k)["nodes"]
+    p = m.xy[m.c2v]
+    X = p[:, 0, None, :] + (p[:, 1, None, :] - p[:, 0, None, :]) * nodes[None, :, 0, None] + \
+        (p[:, 2, None, :] - p[:, 0, None, :]) * nodes[None, :, 1, None]
+
+    def exact(t):
+        if not swave:
+            w = cp * kn
+            ph = np.cos(X @ kap - w * t)
+            v = [dvec[0] * ph, dvec[1] * ph]
+            sg = -(1 / cp) * (2.0 * np.eye(2) + 2.0 * np.outer(dvec, dvec))
+        else:
+            w = cs * kn
+            ph = np.cos(X @ kap - w * t)
+            v = [dperp[0] * ph, dperp[1] * ph]
+            sg = -(1.0 / cs) * (np.outer(dvec, dperp) + np.outer(dperp, dvec))
+        s = [sg[0, 0] * ph, sg[1, 1] * ph, sg[0, 1] * ph]
+        return np.ascontiguousarray(np.stack(v).transpose(0, 2, 1)), np.ascontiguousarray(np.stack(s).transpose(0, 2, 1))
+
+    v, _ = exact(-dt / 2)
+    _, s = exact(0.0)
+    d.step(v, s, nsteps)
+    ve, _ = exact(T - dt / 2)
+    _, se = exact(T)
+    return math.sqrt(((v - ve) ** 2).sum() + ((s - se) ** 2).sum()) / math.sqrt((ve ** 2).sum() + (se ** 2).sum())
+
+
+@pytest.mark.parametrize("k,lo", [(1, 1.8), (2, 2.7), (3, 3.7)])
+@pytest.mark.parametrize("swave", [False, True])
+def test_plane_wave_convergence_upwind(k, lo, swave):
+    e = [_plane_wave_error(n, k, 1, swave=swave) for n in (4, 8, 16)]
+    rate = math.log2(e[1] / e[2])
+    assert rate > lo, (e, rate)
+
+
+@pytest.mark.parametrize("k,lo", [(2, 1.9), (3, 2.8)])
+def test_plane_wave_convergence_central(k, lo):
+    e = [_plane_wave_error(n, k, 0) for n in (4, 8, 16)]
+    assert math.log2(e[1] / e[2]) > lo, e
+
+
+def _assembled_operator(d, nv, ns):
+    """Columns of the semi-discrete rate operator by applying it to unit vectors."""
+    N = nv + ns
+    L = np.zeros((N, N))
+    for j in range(N):
+        u = np.zeros(N)
+        u[j] = 1.0
+        dv, ds = d.rate(u[:nv].reshape(2, d.np, -1), u[nv:].reshape(3, d.np, -1))
+        L[:, j] = np.concatenate([dv.ravel(), ds.ravel()])
+    return L
+
+
+@pytest.mark.parametrize("order,expect", [(2, 4.0), (4, 16.0)])
+def test_temporal_order_against_matrix_exponential(order, expect):
+    # tiny periodic mesh (<= 300 dofs): brute-force exact solution exp(L t) u0
+    m = I.square_mesh(2, periodic=3)
+    om = O.OMesh.from_mesh(m)
+    lam, mu, rho = I.homogeneous_material(m)
+    k = 1
+    d0 = O.ODG(om, k, lam, mu, rho, flux=0, order=order, dt=1e-3, free_sides=0)
+    nv, ns = 2 * d0.np * om.nc, 3 * d0.np * om.nc
+    L = _assembled_operator(d0, nv, ns)
+    u0 = I.random_state(nv + ns, 11)
+    T = 0.2
+    errs = []
+    for nsteps in (100, 200):
+        dt = T / nsteps
+        d = O.ODG(om, k, lam, mu, rho, flux=0, order=order, dt=dt, free_sides=0)
+        # v^{-1/2} = exact v(-dt/2), s^0 = s(0)
+        um = scipy.linalg.expm(-0.5 * dt * L) @ u0
+        v = um[:nv].reshape(2, d.np, -1).copy()
+        s = u0[nv:].reshape(3, d.np, -1).copy()
+        d.step(v, s, nsteps)
+        uT = scipy.linalg.expm(T * L) @ u0
+        uTm = scipy.linalg.expm((T - 0.5 * dt) * L) @ u0
+        err = math.sqrt(((v.ravel() - uTm[:nv]) ** 2).sum() + ((s.ravel() - uT[nv:]) ** 2).sum())
+        errs.append(err)
+    ratio = errs[0] / errs[1]
+    assert abs(math.log2(ratio) - math.log2(expect)) < 0.25, (errs, ratio)
+
+
+def test_ricker_closed_form():
+    f0, t0 = 5.0, 0.2
+    assert O.ricker(t0, f0, t0, 1.0) == 1.0
+    for t in (0.0, 0.13, 0.31):
+        a = (math.pi * f0 * (t - t0)) ** 2
+        assert abs(O.ricker(t, f0, t0, 2.5) - 2.5 * (1 - 2 * a) * math.exp(-a)) < 1e-15
+    # zero crossings at t0 +- 1/(sqrt(2) pi f0)
+    tz = t0 + 1.0 / (math.sqrt(2) * math.pi * f0)
+    assert abs(O.ricker(tz, f0, t0, 1.0)) < 1e-15
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_source_injects_dt_times_r(k):
+    # each step adds exactly dt*r(t^{n+1/2}) to int sxx and int syy (partition of unity)
+    m = I.square_mesh(8, jitter=0.2)
+    om = O.OMesh.from_mesh(m)
+    lam, mu, rho = I.homogeneous_material(m)
+    d = O.ODG(om, k, lam, mu, rho, flux=0, order=2, free_sides=0xF)
+    cell = d.set_source(0.37, 0.61, f0=5.0, t0=0.2, amp=1.0)
+    assert cell >= 0
+    ref = O.refelem(k)
+    p = m.xy[m.c2v]
+    det = (p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1]) - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1])
+    wvec = ref["M"].sum(axis=0)  # int phi_i on the reference cell
+    v, s = d.zeros()
+    d.step(v, s, 1, t0=0.1)
+    integ = [(s[c] * wvec[:, None] * det[None, :]).sum() for c in range(3)]
+    expect = d.dt * O.ricker(0.1 + 0.5 * d.dt, 5.0, 0.2, 1.0)
+    # order 2 from a zero state: only the source term contributes in one step
+    assert abs(integ[0] - expect) < 1e-14 and abs(integ[1] - expect) < 1e-14 and abs(integ[2]) < 1e-15
+
+
+def test_source_tie_break_lowest_cell():
+    # (0.5, 0.5) is a vertex of the 32x32 mesh: six cells contain it; lowest id wins
+    m = I.square_mesh(32)
+    om = O.OMesh.from_mesh(m)
+    d = O.ODG(om, 1, *I.homogeneous_material(m), flux=0, order=4, free_sides=0xF)
+    cell = d.set_source(0.5, 0.5)
+    p = m.xy[m.c2v]
+    touching = [c for c in range(m.nc) if np.any(np.all(np.abs(p[c] - 0.5) < 1e-12, axis=1))]
+    assert cell == min(touching)
+
+
+def test_cfl_dt_small_p1():
+    m = I.square_mesh(32)
+    om = O.OMesh.from_mesh(m)
+    dt = O.cfl_dt(om, 1, *I.homogeneous_material(m))
+    assert abs(dt - 0.2 * (2 - math.sqrt(2)) / 32 / (3 * 2.0)) < 1e-17
