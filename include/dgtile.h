@@ -1,0 +1,211 @@
+/*
+ * dgtile.h -- C ABI of libdgtile: sparse-tiled, fused execution of the loop
+ * chain of a discontinuous-Galerkin velocity-stress elastic time step on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Luporini, Lange, Jacobs, Gorman, Ramanujam, Kelly, "Automated Tiling
+ * of Unstructured Mesh Computations with Application to Seismological
+ * Modelling" (ACM TOMS; arXiv 1708.03183).
+ *   - loop chain abstraction (sets, maps, loops with descriptors): Sec. 2;
+ *   - inspector (seed partition, colouring, projection, tiling, conflicts,
+ *     local maps): Sec. 5.1, Alg. 1, Alg. 3, Alg. 4;
+ *   - executor (colour by colour, one tile at a time, loops in chain order
+ *     inside a tile): Sec. 5.2, Alg. 2;
+ *   - the DG elastic application (cell, interior-facet and exterior-facet
+ *     loops plus block-diagonal inverse-mass solves, 4th-order leapfrog):
+ *     Sec. 7.1-7.3.
+ *
+ * Conventions
+ *   - Every function returns a dgt_status; DGT_OK is 0.  No C++ exception
+ *     crosses this boundary.  dgt_last_error() returns a thread-local message
+ *     describing the last non-OK status of the calling thread.
+ *   - "host" pointers are read (and copied) during the call; "device" pointers
+ *     are HIP device addresses on the solver's device.
+ *   - Objects are not thread-safe; distinct objects may be used from distinct
+ *     threads.
+ *   - Work is enqueued on the HIP stream given at creation; functions that
+ *     synchronise say so.
+ *   - Cell-based device arrays use the layout [component][node][cell] with the
+ *     cell index fastest (a "field" of ncomp components and Np nodes).
+ */
+#ifndef DGTILE_H
+#define DGTILE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DGT_OK = 0,
+    DGT_EINVAL = 1,        /* invalid argument or mesh */
+    DGT_ENOMEM = 2,        /* device or host allocation failed */
+    DGT_EHIP = 3,          /* a HIP runtime call failed */
+    DGT_ESTATE = 4,        /* call not valid in the object's state, or the
+                              inspector exceeded max_conflict_rounds */
+    DGT_EUNSUPPORTED = 5   /* valid request this build cannot run (e.g. a tile
+                              footprint larger than the LDS budget) */
+} dgt_status;
+
+/* Message for the calling thread's last failing call (never NULL). */
+const char *dgt_last_error(void);
+/* ABI version of this header (major*100 + minor). */
+int dgt_version(void);
+
+/* =====================================================================
+ * Tier 1: generic loop chain and GPU inspector (Sec. 2, Sec. 5.1)
+ * ===================================================================== */
+
+typedef struct dgt_chain dgt_chain;
+typedef struct dgt_schedule dgt_schedule;
+
+/* Access modes of a descriptor (Sec. 2): read, write, increment. */
+typedef enum { DGT_R = 0, DGT_W = 1, DGT_INC = 2 } dgt_mode;
+
+/* Descriptor <M, mode> (Sec. 2).  map = map id or -1 for a direct access.
+ * data = id of the data space accessed (>= 0) or -1; the inspector analyses
+ * dependences per set (Sec. 2) and ignores it, the checker tools use it. */
+typedef struct {
+    int32_t map;
+    int32_t mode;
+    int32_t data;
+} dgt_desc;
+
+/* Create an empty chain.  *out owned by the caller (dgt_chain_destroy). */
+dgt_status dgt_chain_create(dgt_chain **out);
+/* Add an iteration set of `size` >= 0 elements; *set_id receives its id
+ * (0, 1, ...).  At most 8 sets. */
+dgt_status dgt_chain_set(dgt_chain *c, int64_t size, int32_t *set_id);
+/* Add a map M: from -> to^arity (Sec. 2).  values: host, [size(from)*arity],
+ * each in [0, size(to)); copied.  EINVAL on out-of-range values.  At most 8. */
+dgt_status dgt_chain_map(dgt_chain *c, int32_t from, int32_t to, int32_t arity, const int32_t *values,
+                         int32_t *map_id);
+/* Append loop L_j over `set` with ndesc (<= 8) descriptors (host, copied).
+ * Every indirect descriptor's map must start at `set`.  At most 64 loops. */
+dgt_status dgt_chain_loop(dgt_chain *c, int32_t set, int32_t ndesc, const dgt_desc *desc, int32_t *loop_id);
+void dgt_chain_destroy(dgt_chain *c);
+
+/* Inspector parameters (Alg. 1). */
+typedef struct {
+    int64_t tile_size;            /* seed iterations per tile, >= 1 (Sec. 5.1.2) */
+    int32_t partition;            /* 0: blocks of the given numbering (the paper's
+                                     choice); 1: blocks of the Hilbert order of
+                                     seed_xy (quantised to 2^16 per axis) */
+    const double *seed_xy;        /* host [size(seed)*2] points of the seed set;
+                                     required when partition == 1 */
+    int32_t max_conflict_rounds;  /* colouring rounds before DGT_ESTATE, >= 1 */
+    const int32_t *splits;        /* host [nsplits] ascending loop indices where a
+                                     new sub-chain (fusion scheme, Sec. 7.4)
+                                     starts; each sub-chain has <= 31 loops and
+                                     is inspected independently */
+    int32_t nsplits;
+} dgt_inspect_params;
+
+/* Run the inspector on the GPU (Alg. 1 with Alg. 3 projections and Alg. 4
+ * tiling functions, colouring and conflict rounds).  The result is a pure
+ * function of the chain and the parameters (bit-identical run to run).
+ * stream: hipStream_t or NULL (default stream).  Synchronises the stream.
+ * *out owned by the caller (dgt_schedule_destroy). */
+dgt_status dgt_inspect(const dgt_chain *c, const dgt_inspect_params *p, void *stream, dgt_schedule **out);
+
+/* Read-back of a schedule (host copies; each call synchronises). */
+dgt_status dgt_schedule_nsub(const dgt_schedule *s, int32_t *nsub);
+dgt_status dgt_schedule_sub_info(const dgt_schedule *s, int32_t sub, int32_t *first_loop, int32_t *nloops,
+                                 int32_t *ntiles, int32_t *ncolors, int32_t *rounds);
+/* tile colours of sub-chain `sub`: host [ntiles] */
+dgt_status dgt_schedule_colors(const dgt_schedule *s, int32_t sub, int32_t *color);
+/* tiling function sigma_j of loop j: host [size(S_j)] tile per iteration */
+dgt_status dgt_schedule_sigma(const dgt_schedule *s, int32_t loop, int32_t *sigma);
+/* iteration lists [T_i]_j of loop j (ascending id in each tile):
+ * host tile_off[ntiles+1], iters[size(S_j)] */
+dgt_status dgt_schedule_iters(const dgt_schedule *s, int32_t loop, int32_t *tile_off, int32_t *iters);
+/* footprint of sub-chain `sub` on `set`: elements touched by each tile through
+ * any descriptor, ascending per tile, with acc bit i set when loop
+ * (first_loop + i) touches the element in that tile, and bit 31 set when one
+ * tile alone touches it.  *len receives the total; arrays may be NULL to query
+ * the length: host off[ntiles+1], elem[len], acc[len]. */
+dgt_status dgt_schedule_footprint(const dgt_schedule *s, int32_t sub, int32_t set, int64_t *len, int32_t *off,
+                                  int32_t *elem, uint32_t *acc);
+/* tiles in execution order (colour ascending, then id): host color_off[ncolors+1], tiles[ntiles] */
+dgt_status dgt_schedule_tiles_by_color(const dgt_schedule *s, int32_t sub, int32_t *color_off, int32_t *tiles);
+/* JSON inspection summary (tiles, colours, rounds, footprint sizes, GPU time
+ * of the inspector in ms); writes at most len bytes including the NUL. */
+dgt_status dgt_schedule_summary_json(const dgt_schedule *s, char *buf, size_t len);
+void dgt_schedule_destroy(dgt_schedule *s);
+
+/* =====================================================================
+ * Tier 2: the DG elastic solver built on tier 1 (Sec. 7.1-7.3)
+ * ===================================================================== */
+
+typedef struct dgt_mesh dgt_mesh;
+typedef struct dgt_solver dgt_solver;
+
+/* Triangle mesh from vertex coordinates (host [nv*2], double) and counter-
+ * clockwise cell-to-vertex connectivity (host [nc*3]); copied.  periodic: bit 0
+ * pairs the x = xmin / xmax boundary edges, bit 1 the y ones.  Derives the
+ * interior-facet map f2c (cells ascending, local facets 0..2, emitted from the
+ * lower cell id; local facet l joins local vertices l and l+1 mod 3), the
+ * exterior-facet map b2c, and each exterior facet's bounding-box side.
+ * EINVAL for a clockwise or degenerate cell, an edge shared by > 2 cells, or a
+ * vertex id out of range.  *out owned by the caller (dgt_mesh_destroy). */
+dgt_status dgt_mesh_create(int64_t nv, const double *xy, int64_t nc, const int32_t *c2v, int32_t periodic,
+                           dgt_mesh **out);
+dgt_status dgt_mesh_counts(const dgt_mesh *m, int64_t *nc, int64_t *nf, int64_t *nb);
+/* host copies: f2c[nf*2], f2l[nf*2], b2c[nb], b2l[nb], bside[nb] (0: x=xmin,
+ * 1: x=xmax, 2: y=ymin, 3: y=ymax, -1: none).  Any pointer may be NULL. */
+dgt_status dgt_mesh_maps(const dgt_mesh *m, int32_t *f2c, int8_t *f2l, int32_t *b2c, int8_t *b2l, int8_t *bside);
+void dgt_mesh_destroy(dgt_mesh *m);
+
+typedef struct {
+    int32_t degree;      /* polynomial degree k in 1..4 (Sec. 7.4: q = 1..4) */
+    int32_t flux;        /* 0 central, 1 upwind (exact isotropic Riemann state) */
+    int32_t time_order;  /* 4: Taylor leapfrog (Sec. 7.1, 26 loops); 2: 8 loops */
+    int32_t precision;   /* 0 FP64, 1 FP32 (state, arithmetic and accumulation) */
+    int32_t free_sides;  /* bounding-box sides with a free surface (bits as
+                            bside); the other exterior facets are absorbing */
+    double dt;           /* time step > 0 */
+} dgt_solver_params;
+
+/* Build the solver: per-cell material lam, mu, rho (host [nc] doubles, > 0),
+ * reference-element operators, device copies of mesh maps and geometry, and
+ * the DG loop chain (tier 1).  stream: hipStream_t or NULL.  The mesh must
+ * outlive the solver. */
+dgt_status dgt_solver_create(const dgt_mesh *m, const double *lam, const double *mu, const double *rho,
+                             const dgt_solver_params *p, void *stream, dgt_solver **out);
+/* Inspect the solver's chain on the GPU (dgt_inspect; seed_xy is ignored and
+ * the cell centroids are used) and build the executor plan: cells renumbered
+ * into seed order, per-tile footprints in LDS slots and local maps.
+ * EUNSUPPORTED when a tile's footprint exceeds the LDS budget (smaller
+ * tile_size or more splits needed).  Synchronises the stream. */
+dgt_status dgt_solver_inspect(dgt_solver *s, const dgt_inspect_params *p);
+/* The schedule of the last dgt_solver_inspect (borrowed; NULL before). */
+dgt_status dgt_solver_schedule(const dgt_solver *s, const dgt_schedule **out);
+/* Ricker point source on sxx and syy: r(t) = amp (1 - 2 a) exp(-a),
+ * a = (pi f0 (t - t0))^2, placed in the lowest-id cell containing (x, y). */
+dgt_status dgt_set_source(dgt_solver *s, double x, double y, double f0, double t0, double amp);
+/* Copy the state into / out of the solver (device pointers, caller layout
+ * v[2][Np][nc], s[3][Np][nc] in the solver precision; enqueued on the stream). */
+dgt_status dgt_state_upload(dgt_solver *s, const void *v, const void *sig);
+dgt_status dgt_state_download(dgt_solver *s, void *v, void *sig);
+/* Advance nsteps time steps starting at time t0 (sigma at t0, v at t0 - dt/2).
+ * mode 0: untiled chain (one kernel per loop); mode 1: sparse-tiled fused
+ * executor (requires dgt_solver_inspect).  Enqueued on the stream. */
+dgt_status dgt_step(dgt_solver *s, int64_t nsteps, int32_t mode, double t0);
+/* Discrete energy 1/2 v'M_rho v + 1/2 sum_K int sig_new : C^-1 sig_old, reduced
+ * in FP64 on the GPU.  v, sig_new, sig_old: device, caller layout, solver
+ * precision.  Synchronises the stream. */
+dgt_status dgt_energy(dgt_solver *s, const void *v, const void *sig_new, const void *sig_old, double *out);
+/* Kernel-level timing of the last dgt_step (HIP events on the solver stream):
+ * total ms, and ms spent in the dominant kernel with its launch count. */
+dgt_status dgt_last_step_timing(const dgt_solver *s, double *total_ms, double *kernel_ms, int64_t *launches);
+/* Per-step algorithmic HBM bytes of the fused step (state read and written
+ * once, cell invariants read once) and the LDS bytes per tile slot. */
+dgt_status dgt_solver_info(const dgt_solver *s, int64_t *np, int64_t *bytes_per_step, int64_t *lds_bytes);
+void dgt_solver_destroy(dgt_solver *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGTILE_H */

@@ -1,0 +1,768 @@
+#pragma once
+// DG velocity-stress elastic solver of libdgtile on gfx950: the untiled loop
+// chain (one kernel per loop), the sparse-tiled fused executor (Alg. 2: per
+// colour, one workgroup per tile, the tile's footprint staged in LDS and every
+// loop of the chain run there in order), the executor plan (local maps) and
+// the FP64 energy reduction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "common.h"
+#include "dg_kernels.h"
+#include "inspector.h"
+#include "mesh.h"
+#include "refelem.h"
+
+namespace dgt {
+
+// ------------------------------------------------------------ constants
+
+__constant__ RefC<1, double> c_ref1d;
+__constant__ RefC<2, double> c_ref2d;
+__constant__ RefC<3, double> c_ref3d;
+__constant__ RefC<4, double> c_ref4d;
+__constant__ RefC<1, float> c_ref1f;
+__constant__ RefC<2, float> c_ref2f;
+__constant__ RefC<3, float> c_ref3f;
+__constant__ RefC<4, float> c_ref4f;
+
+template <int K, typename T>
+__device__ __forceinline__ const RefC<K, T> &R();
+template <> __device__ __forceinline__ const RefC<1, double> &R<1, double>() { return c_ref1d; }
+template <> __device__ __forceinline__ const RefC<2, double> &R<2, double>() { return c_ref2d; }
+template <> __device__ __forceinline__ const RefC<3, double> &R<3, double>() { return c_ref3d; }
+template <> __device__ __forceinline__ const RefC<4, double> &R<4, double>() { return c_ref4d; }
+template <> __device__ __forceinline__ const RefC<1, float> &R<1, float>() { return c_ref1f; }
+template <> __device__ __forceinline__ const RefC<2, float> &R<2, float>() { return c_ref2f; }
+template <> __device__ __forceinline__ const RefC<3, float> &R<3, float>() { return c_ref3f; }
+template <> __device__ __forceinline__ const RefC<4, float> &R<4, float>() { return c_ref4f; }
+
+template <int K, typename T>
+static const void *ref_symbol() {
+    if constexpr (std::is_same<T, double>::value) {
+        if constexpr (K == 1) return (const void *)&HIP_SYMBOL(c_ref1d);
+        if constexpr (K == 2) return (const void *)&HIP_SYMBOL(c_ref2d);
+        if constexpr (K == 3) return (const void *)&HIP_SYMBOL(c_ref3d);
+        if constexpr (K == 4) return (const void *)&HIP_SYMBOL(c_ref4d);
+    } else {
+        if constexpr (K == 1) return (const void *)&HIP_SYMBOL(c_ref1f);
+        if constexpr (K == 2) return (const void *)&HIP_SYMBOL(c_ref2f);
+        if constexpr (K == 3) return (const void *)&HIP_SYMBOL(c_ref3f);
+        if constexpr (K == 4) return (const void *)&HIP_SYMBOL(c_ref4f);
+    }
+    return nullptr;
+}
+
+template <int K, typename T>
+static void upload_ref(const RefElem &E, hipStream_t st) {
+    RefC<K, T> h{};
+    constexpr int NP = RefC<K, T>::NP, NFP = RefC<K, T>::NFP;
+    for (int i = 0; i < NP * NP; ++i) {
+        h.Dr[i] = (T)E.Dr[i];
+        h.Ds[i] = (T)E.Ds[i];
+        h.M[i] = (T)E.M[i];
+    }
+    for (int i = 0; i < 3 * NP * NFP; ++i) h.lift[i] = (T)E.lift[i];
+    for (int i = 0; i < 3 * NFP; ++i) h.fn[i] = E.fnodes[i];
+    DGT_HIP(hipMemcpyToSymbolAsync(ref_symbol<K, T>(), &h, sizeof(h), 0, hipMemcpyHostToDevice, st));
+}
+
+// ------------------------------------------------------------ untiled kernels (one per loop)
+
+// volume term of the velocity (VEL) or stress operator: out = scale * vol(in)
+template <int K, typename T, bool VEL>
+__global__ __launch_bounds__(256) void k_vol(const T *__restrict__ in, T *__restrict__ out,
+                                             const T *__restrict__ geo, int64_t nc, T scale) {
+    constexpr int NP = np_of(K);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nc * NP) return;
+    const int i = (int)(t / nc);
+    const int64_t c = t - (int64_t)i * nc;
+    const auto &Rf = R<K, T>();
+    const T rx = geo[G_RX * nc + c], ry = geo[G_RY * nc + c], sx = geo[G_SX * nc + c], sy = geo[G_SY * nc + c];
+    constexpr int NCI = VEL ? 3 : 2;
+    T ar[NCI], as[NCI];
+#pragma unroll
+    for (int q = 0; q < NCI; ++q) { ar[q] = 0; as[q] = 0; }
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const T dr = Rf.Dr[i * NP + j], ds = Rf.Ds[i * NP + j];
+#pragma unroll
+        for (int q = 0; q < NCI; ++q) {
+            const T u = in[((int64_t)q * NP + j) * nc + c];
+            ar[q] += dr * u;
+            as[q] += ds * u;
+        }
+    }
+    if (VEL) {
+        const T irho = geo[G_IRHO * nc + c];
+        const T dxx = rx * ar[0] + sx * as[0];  // d/dx sxx
+        const T dyy = ry * ar[1] + sy * as[1];  // d/dy syy
+        const T dxy_x = rx * ar[2] + sx * as[2], dxy_y = ry * ar[2] + sy * as[2];
+        out[((int64_t)0 * NP + i) * nc + c] = scale * irho * (dxx + dxy_y);
+        out[((int64_t)1 * NP + i) * nc + c] = scale * irho * (dxy_x + dyy);
+    } else {
+        const T lam = geo[G_LAM * nc + c], mu = geo[G_MU * nc + c];
+        const T exx = rx * ar[0] + sx * as[0], eyy = ry * ar[1] + sy * as[1];
+        const T exy = T(0.5) * ((ry * ar[0] + sy * as[0]) + (rx * ar[1] + sx * as[1]));
+        out[((int64_t)0 * NP + i) * nc + c] = scale * ((lam + 2 * mu) * exx + lam * eyy);
+        out[((int64_t)1 * NP + i) * nc + c] = scale * (lam * exx + (lam + 2 * mu) * eyy);
+        out[((int64_t)2 * NP + i) * nc + c] = scale * (2 * mu * exy);
+    }
+}
+
+// interior-facet flux: one thread per (facet, facet node); writes the lifted
+// input G[side][comp][m'][f] in each side's own facet-node order
+template <int K, typename T, bool VEL, bool UPW, bool PEN>
+__global__ __launch_bounds__(256) void k_flux_int(const T *__restrict__ in, const T *__restrict__ pin,
+                                                  const int32_t *__restrict__ f2c, const uint8_t *__restrict__ f2l,
+                                                  const T *__restrict__ geo, int64_t nc, int64_t nf, T scale,
+                                                  T pscale, T *__restrict__ G) {
+    constexpr int NP = np_of(K), NFP = K + 1, NCO = VEL ? 2 : 3;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nf * NFP) return;
+    const int m = (int)(t / nf);
+    const int64_t f = t - (int64_t)m * nf;
+    const auto &Rf = R<K, T>();
+    const int64_t c0 = f2c[2 * f], c1 = f2c[2 * f + 1];
+    const int l0 = f2l[f] & 3, l1 = (f2l[f] >> 2) & 3;
+    const int n0 = Rf.fn[l0 * NFP + m], n1 = Rf.fn[l1 * NFP + (K - m)];
+    T nx, ny, fs0, fs1, tmpx, tmpy;
+    facet_normal<T>(l0, geo[G_RX * nc + c0], geo[G_RY * nc + c0], geo[G_SX * nc + c0], geo[G_SY * nc + c0], nx, ny,
+                    fs0);
+    facet_normal<T>(l1, geo[G_RX * nc + c1], geo[G_RY * nc + c1], geo[G_SX * nc + c1], geo[G_SY * nc + c1], tmpx,
+                    tmpy, fs1);
+    const T zp0 = geo[G_ZP * nc + c0], zs0 = geo[G_ZS * nc + c0], zp1 = geo[G_ZP * nc + c1],
+            zs1 = geo[G_ZS * nc + c1];
+    T g0[3], g1[3];
+    if (VEL) {
+        T s0[3], s1[3], v0[2] = {0, 0}, v1[2] = {0, 0};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            s0[q] = in[((int64_t)q * NP + n0) * nc + c0];
+            s1[q] = in[((int64_t)q * NP + n1) * nc + c1];
+        }
+        if (PEN) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                v0[q] = pin[((int64_t)q * NP + n0) * nc + c0];
+                v1[q] = pin[((int64_t)q * NP + n1) * nc + c1];
+            }
+        }
+        flux_v_int<T, UPW, PEN>(s0, s1, v0, v1, nx, ny, zp0, zs0, zp1, zs1, fs0 * geo[G_IRHO * nc + c0],
+                                fs1 * geo[G_IRHO * nc + c1], scale, pscale, g0, g1);
+    } else {
+        T v0[2], v1[2], s0[3] = {0, 0, 0}, s1[3] = {0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            v0[q] = in[((int64_t)q * NP + n0) * nc + c0];
+            v1[q] = in[((int64_t)q * NP + n1) * nc + c1];
+        }
+        if (PEN) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                s0[q] = pin[((int64_t)q * NP + n0) * nc + c0];
+                s1[q] = pin[((int64_t)q * NP + n1) * nc + c1];
+            }
+        }
+        flux_s_int<T, UPW, PEN>(v0, v1, s0, s1, nx, ny, zp0, zs0, zp1, zs1, geo[G_LAM * nc + c0],
+                                geo[G_MU * nc + c0], geo[G_LAM * nc + c1], geo[G_MU * nc + c1], fs0, fs1, scale,
+                                pscale, g0, g1);
+    }
+#pragma unroll
+    for (int q = 0; q < NCO; ++q) {
+        G[((int64_t)(0 * NCO + q) * NFP + m) * nf + f] = g0[q];
+        G[((int64_t)(1 * NCO + q) * NFP + (K - m)) * nf + f] = g1[q];
+    }
+}
+
+template <int K, typename T, bool VEL, bool UPW, bool PEN>
+__global__ __launch_bounds__(256) void k_flux_ext(const T *__restrict__ in, const T *__restrict__ pin,
+                                                  const int32_t *__restrict__ b2c, const uint8_t *__restrict__ b2l,
+                                                  const T *__restrict__ geo, int64_t nc, int64_t nb, T scale,
+                                                  T pscale, T *__restrict__ G) {
+    constexpr int NP = np_of(K), NFP = K + 1, NCO = VEL ? 2 : 3;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb * NFP) return;
+    const int m = (int)(t / nb);
+    const int64_t b = t - (int64_t)m * nb;
+    const auto &Rf = R<K, T>();
+    const int64_t c = b2c[b];
+    const int l = b2l[b] & 3;
+    const bool fr = (b2l[b] >> 2) & 1;
+    const int nd = Rf.fn[l * NFP + m];
+    T nx, ny, fs;
+    facet_normal<T>(l, geo[G_RX * nc + c], geo[G_RY * nc + c], geo[G_SX * nc + c], geo[G_SY * nc + c], nx, ny, fs);
+    const T zp = geo[G_ZP * nc + c], zs = geo[G_ZS * nc + c];
+    T g[3];
+    if (VEL) {
+        T s[3], v[2] = {0, 0};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) s[q] = in[((int64_t)q * NP + nd) * nc + c];
+        if (PEN) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) v[q] = pin[((int64_t)q * NP + nd) * nc + c];
+        }
+        flux_v_ext<T, UPW, PEN>(s, v, fr, nx, ny, zp, zs, fs * geo[G_IRHO * nc + c], scale, pscale, g);
+    } else {
+        T v[2], s[3] = {0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) v[q] = in[((int64_t)q * NP + nd) * nc + c];
+        if (PEN) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) s[q] = pin[((int64_t)q * NP + nd) * nc + c];
+        }
+        flux_s_ext<T, UPW, PEN>(v, s, fr, nx, ny, zp, zs, geo[G_LAM * nc + c], geo[G_MU * nc + c], fs, scale,
+                                pscale, g);
+    }
+#pragma unroll
+    for (int q = 0; q < NCO; ++q) G[((int64_t)q * NFP + m) * nb + b] = g[q];
+}
+
+// lift of the facet terms into the cell's accumulator (increments of the
+// interior- and exterior-facet loops), local facets in order 0, 1, 2
+template <int K, typename T, bool VEL>
+__global__ __launch_bounds__(256) void k_lift(T *__restrict__ out, const int32_t *__restrict__ c2f,
+                                              const T *__restrict__ G, const T *__restrict__ Gx, int64_t nc,
+                                              int64_t nf, int64_t nb) {
+    constexpr int NP = np_of(K), NFP = K + 1, NCO = VEL ? 2 : 3;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nc * NP) return;
+    const int i = (int)(t / nc);
+    const int64_t c = t - (int64_t)i * nc;
+    const auto &Rf = R<K, T>();
+    T acc[NCO];
+#pragma unroll
+    for (int q = 0; q < NCO; ++q) acc[q] = 0;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const int32_t code = c2f[(int64_t)p * nc + c];
+        if (code >= 0) {
+            const int64_t f = code >> 1;
+            const int s = code & 1;
+#pragma unroll
+            for (int q = 0; q < NCO; ++q)
+#pragma unroll
+                for (int m = 0; m < NFP; ++m)
+                    acc[q] += Rf.lift[(p * NP + i) * NFP + m] * G[((int64_t)(s * NCO + q) * NFP + m) * nf + f];
+        } else {
+            const int64_t b = -(int64_t)code - 1;
+#pragma unroll
+            for (int q = 0; q < NCO; ++q)
+#pragma unroll
+                for (int m = 0; m < NFP; ++m)
+                    acc[q] += Rf.lift[(p * NP + i) * NFP + m] * Gx[((int64_t)q * NFP + m) * nb + b];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NCO; ++q) out[((int64_t)q * NP + i) * nc + c] += acc[q];
+}
+
+// v += dt*U + Z (order 4) ; v += Z (order 2, dt folded into Z)
+template <typename T>
+__global__ __launch_bounds__(256) void k_upd_v(T *__restrict__ V, const T *__restrict__ U, const T *__restrict__ Z,
+                                               int64_t n, T dt) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    V[t] += (U ? dt * U[t] : T(0)) + Z[t];
+}
+
+// s += dt*X + Z + dt r(t) Mk^-1 phi(x_s) on sxx, syy of the source cell
+template <int K, typename T>
+__global__ __launch_bounds__(256) void k_upd_s(T *__restrict__ S, const T *__restrict__ X, const T *__restrict__ Z,
+                                               int64_t nc, T dt, int64_t src_cell, T src_amp,
+                                               const T *__restrict__ src_vec) {
+    constexpr int NP = np_of(K);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * NP * nc) return;
+    const int64_t row = t / nc, c = t - row * nc;
+    T add = (X ? dt * X[t] : T(0)) + Z[t];
+    if (c == src_cell && row < 2 * NP) add += src_amp * src_vec[row % NP];
+    S[t] += add;
+}
+
+// ------------------------------------------------------------ fused tiled executor (Alg. 2)
+
+struct TLoop {
+    int8_t kind, in, out, pen, partner;  // partner: index of a fused exterior loop or -1
+    float scale_f, pscale_f;
+    double scale_d, pscale_d;
+};
+
+struct TileArgs {
+    int32_t nloops;
+    TLoop loops[31];
+    const int32_t *it_off[31];
+    const uint32_t *lmap[31];
+    const int32_t *foot_off;
+    const int32_t *foot;   // exec cell ids, ascending per tile
+    const uint32_t *facc;  // loop bits + single-tile flag
+    const int32_t *tiles;  // tiles of this sub-chain in execution order
+    int32_t tile_base;     // first tile of the colour in `tiles`
+    void *F[F_COUNT];
+    const void *geo;
+    int64_t nc;
+    // per-field LDS plan
+    uint32_t loops_mask[F_COUNT], rfirst_mask[F_COUNT], writes_mask[F_COUNT];
+    int32_t persistent_mask;   // fields always written back when written
+    int32_t lds_row[F_COUNT];  // first LDS row of each field (-1: unused)
+    int32_t nrows;             // field rows + geometry rows
+    int32_t stride;            // slots per row
+    int32_t fac_stride;        // facet entries per G row
+    int32_t src_cell;          // exec id of the source cell or -1
+    double dt, src_amp;        // src_amp = dt * r(t^{n+1/2})
+    const void *src_vec;
+};
+
+template <int K, typename T, bool UPW, bool PEN>
+__global__ __launch_bounds__(256) void k_tile(const TileArgs a) {
+    constexpr int NP = np_of(K), NFP = K + 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tile = a.tiles[a.tile_base + blockIdx.x];
+    const int f0 = a.foot_off[tile];
+    const int nfoot = a.foot_off[tile + 1] - f0;
+    const int S = a.stride;
+    T *lds = reinterpret_cast<T *>(smem);
+    T *ldsG = lds + (size_t)a.nrows * S;
+    int32_t *fidx = reinterpret_cast<int32_t *>(ldsG + (size_t)2 * 3 * NFP * a.fac_stride);
+    uint16_t *flags = reinterpret_cast<uint16_t *>(fidx + 3 * S);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const auto &Rf = R<K, T>();
+    const T *geo = reinterpret_cast<const T *>(a.geo);
+    const int64_t nc = a.nc;
+    const int geo_row = a.nrows - G_NROWS;
+    const T dt = (T)a.dt;
+
+    // gather/scatter flags per slot from the footprint's loop bits
+    for (int s = tid; s < nfoot; s += nt) {
+        const uint32_t acc = a.facc[f0 + s];
+        const bool single = acc >> 31;
+        uint16_t g = 0, w = 0;
+#pragma unroll
+        for (int f = 0; f < F_COUNT; ++f) {
+            if (a.lds_row[f] < 0) continue;
+            const uint32_t m = acc & a.loops_mask[f];
+            if (m) {
+                const uint32_t first = m & (~m + 1u);
+                if (first & a.rfirst_mask[f]) g |= 1u << f;
+            }
+            if ((acc & a.writes_mask[f]) && (((a.persistent_mask >> f) & 1) || !single)) w |= 1u << f;
+        }
+        flags[s] = (uint16_t)(g | (w << 8));
+    }
+    __syncthreads();
+    // gather: fields (rows of Np nodes x components) and geometry
+    for (int f = 0; f < F_COUNT; ++f) {
+        if (a.lds_row[f] < 0) continue;
+        const T *src = reinterpret_cast<const T *>(a.F[f]);
+        const int rows = field_ncomp(f) * NP;
+        for (int idx = tid; idx < rows * nfoot; idx += nt) {
+            const int r = idx / nfoot, s = idx - r * nfoot;
+            if ((flags[s] >> f) & 1) lds[(size_t)(a.lds_row[f] + r) * S + s] = src[(int64_t)r * nc + a.foot[f0 + s]];
+        }
+    }
+    for (int idx = tid; idx < G_NROWS * nfoot; idx += nt) {
+        const int r = idx / nfoot, s = idx - r * nfoot;
+        lds[(size_t)(geo_row + r) * S + s] = geo[(int64_t)r * nc + a.foot[f0 + s]];
+    }
+    __syncthreads();
+#define LF(f, comp, node, slot) lds[(size_t)(a.lds_row[f] + (comp) * NP + (node)) * S + (slot)]
+#define LG(row, slot) lds[(size_t)(geo_row + (row)) * S + (slot)]
+
+    for (int j = 0; j < a.nloops; ++j) {
+        const TLoop L = a.loops[j];
+        const T scale = sizeof(T) == 8 ? (T)L.scale_d : (T)L.scale_f;
+        const T pscale = sizeof(T) == 8 ? (T)L.pscale_d : (T)L.pscale_f;
+        const int ib = a.it_off[j][tile], ie = a.it_off[j][tile + 1];
+        const uint32_t *lm = a.lmap[j];
+        switch (L.kind) {
+        case KV_SOLVE:
+            continue;  // folded into the operators: no data moves
+        case KV_VOL_V:
+        case KV_VOL_S: {
+            const bool vel = L.kind == KV_VOL_V;
+            const int n = ie - ib;
+            for (int idx = tid; idx < n * NP; idx += nt) {
+                const int i = idx / n, q = idx - i * n;
+                const int s = (int)(lm[ib + q] & 0x3fffu);
+                const T rx = LG(G_RX, s), ry = LG(G_RY, s), sx = LG(G_SX, s), sy = LG(G_SY, s);
+                if (vel) {
+                    T ar[3] = {0, 0, 0}, as[3] = {0, 0, 0};
+#pragma unroll
+                    for (int jj = 0; jj < NP; ++jj) {
+                        const T dr = Rf.Dr[i * NP + jj], ds = Rf.Ds[i * NP + jj];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            const T u = LF(L.in, c, jj, s);
+                            ar[c] += dr * u;
+                            as[c] += ds * u;
+                        }
+                    }
+                    const T irho = LG(G_IRHO, s);
+                    LF(L.out, 0, i, s) = scale * irho * ((rx * ar[0] + sx * as[0]) + (ry * ar[2] + sy * as[2]));
+                    LF(L.out, 1, i, s) = scale * irho * ((rx * ar[2] + sx * as[2]) + (ry * ar[1] + sy * as[1]));
+                } else {
+                    T ar[2] = {0, 0}, as[2] = {0, 0};
+#pragma unroll
+                    for (int jj = 0; jj < NP; ++jj) {
+                        const T dr = Rf.Dr[i * NP + jj], ds = Rf.Ds[i * NP + jj];
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const T u = LF(L.in, c, jj, s);
+                            ar[c] += dr * u;
+                            as[c] += ds * u;
+                        }
+                    }
+                    const T lam = LG(G_LAM, s), mu = LG(G_MU, s);
+                    const T exx = rx * ar[0] + sx * as[0], eyy = ry * ar[1] + sy * as[1];
+                    const T exy = T(0.5) * ((ry * ar[0] + sy * as[0]) + (rx * ar[1] + sx * as[1]));
+                    LF(L.out, 0, i, s) = scale * ((lam + 2 * mu) * exx + lam * eyy);
+                    LF(L.out, 1, i, s) = scale * (lam * exx + (lam + 2 * mu) * eyy);
+                    LF(L.out, 2, i, s) = scale * (2 * mu * exy);
+                }
+            }
+            break;
+        }
+        case KV_INT_V:
+        case KV_INT_S:
+        case KV_EXT_V:
+        case KV_EXT_S: {
+            const bool vel = (L.kind == KV_INT_V || L.kind == KV_EXT_V);
+            const int nco = vel ? 2 : 3;
+            // interior list of this loop, exterior list of the fused partner (if any)
+            int nI = 0, xb = 0, nE = 0;
+            const uint32_t *lmE = nullptr;
+            if (L.kind == KV_INT_V || L.kind == KV_INT_S) {
+                nI = ie - ib;
+                if (L.partner >= 0) {
+                    xb = a.it_off[L.partner][tile];
+                    nE = a.it_off[L.partner][tile + 1] - xb;
+                    lmE = a.lmap[L.partner];
+                }
+            } else {
+                nE = ie - ib;
+                xb = ib;
+                lmE = lm;
+            }
+            for (int idx = tid; idx < 3 * nfoot; idx += nt) fidx[idx] = -1;
+            __syncthreads();
+            const int FS = a.fac_stride;
+#define GB(side, comp, m, e) ldsG[((size_t)((side) * 3 + (comp)) * NFP + (m)) * FS + (e)]
+            for (int idx = tid; idx < (nI + nE) * NFP; idx += nt) {
+                const int m = idx / (nI + nE), e = idx - m * (nI + nE);
+                if (e < nI) {
+                    const uint32_t code = lm[ib + e];
+                    const int s0 = code & 0x3fff, s1 = (code >> 14) & 0x3fff;
+                    const int l0 = (code >> 28) & 3, l1 = (code >> 30) & 3;
+                    const int n0 = Rf.fn[l0 * NFP + m], n1 = Rf.fn[l1 * NFP + (K - m)];
+                    T nx, ny, fs0, fs1, tx_, ty_;
+                    facet_normal<T>(l0, LG(G_RX, s0), LG(G_RY, s0), LG(G_SX, s0), LG(G_SY, s0), nx, ny, fs0);
+                    facet_normal<T>(l1, LG(G_RX, s1), LG(G_RY, s1), LG(G_SX, s1), LG(G_SY, s1), tx_, ty_, fs1);
+                    T g0[3], g1[3];
+                    if (vel) {
+                        T sa[3], sb[3], va[2] = {0, 0}, vb[2] = {0, 0};
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) { sa[c] = LF(L.in, c, n0, s0); sb[c] = LF(L.in, c, n1, s1); }
+                        if (PEN && L.pen >= 0) {
+#pragma unroll
+                            for (int c = 0; c < 2; ++c) { va[c] = LF(L.pen, c, n0, s0); vb[c] = LF(L.pen, c, n1, s1); }
+                        }
+                        flux_v_int<T, UPW, PEN>(sa, sb, va, vb, nx, ny, LG(G_ZP, s0), LG(G_ZS, s0), LG(G_ZP, s1),
+                                                LG(G_ZS, s1), fs0 * LG(G_IRHO, s0), fs1 * LG(G_IRHO, s1), scale,
+                                                L.pen >= 0 ? pscale : T(0), g0, g1);
+                    } else {
+                        T va[2], vb[2], sa[3] = {0, 0, 0}, sb[3] = {0, 0, 0};
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) { va[c] = LF(L.in, c, n0, s0); vb[c] = LF(L.in, c, n1, s1); }
+                        if (PEN && L.pen >= 0) {
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) { sa[c] = LF(L.pen, c, n0, s0); sb[c] = LF(L.pen, c, n1, s1); }
+                        }
+                        flux_s_int<T, UPW, PEN>(va, vb, sa, sb, nx, ny, LG(G_ZP, s0), LG(G_ZS, s0), LG(G_ZP, s1),
+                                                LG(G_ZS, s1), LG(G_LAM, s0), LG(G_MU, s0), LG(G_LAM, s1),
+                                                LG(G_MU, s1), fs0, fs1, scale, L.pen >= 0 ? pscale : T(0), g0, g1);
+                    }
+                    for (int c = 0; c < nco; ++c) {
+                        GB(0, c, m, e) = g0[c];
+                        GB(1, c, K - m, e) = g1[c];
+                    }
+                    if (m == 0) {
+                        fidx[l0 * S + s0] = 2 * e;
+                        fidx[l1 * S + s1] = 2 * e + 1;
+                    }
+                } else {
+                    const int eb = e - nI;
+                    const uint32_t code = lmE[xb + eb];
+                    const int s0 = code & 0x3fff, l = (code >> 28) & 3;
+                    const bool fr = (code >> 30) & 1;
+                    const int nd = Rf.fn[l * NFP + m];
+                    T nx, ny, fs;
+                    facet_normal<T>(l, LG(G_RX, s0), LG(G_RY, s0), LG(G_SX, s0), LG(G_SY, s0), nx, ny, fs);
+                    T g[3];
+                    if (vel) {
+                        T sa[3], va[2] = {0, 0};
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) sa[c] = LF(L.in, c, nd, s0);
+                        if (PEN && L.pen >= 0) {
+#pragma unroll
+                            for (int c = 0; c < 2; ++c) va[c] = LF(L.pen, c, nd, s0);
+                        }
+                        flux_v_ext<T, UPW, PEN>(sa, va, fr, nx, ny, LG(G_ZP, s0), LG(G_ZS, s0),
+                                                fs * LG(G_IRHO, s0), scale, L.pen >= 0 ? pscale : T(0), g);
+                    } else {
+                        T va[2], sa[3] = {0, 0, 0};
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) va[c] = LF(L.in, c, nd, s0);
+                        if (PEN && L.pen >= 0) {
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) sa[c] = LF(L.pen, c, nd, s0);
+                        }
+                        flux_s_ext<T, UPW, PEN>(va, sa, fr, nx, ny, LG(G_ZP, s0), LG(G_ZS, s0), LG(G_LAM, s0),
+                                                LG(G_MU, s0), fs, scale, L.pen >= 0 ? pscale : T(0), g);
+                    }
+                    for (int c = 0; c < nco; ++c) GB(0, c, m, e) = g[c];
+                    if (m == 0) fidx[l * S + s0] = 2 * e;
+                }
+            }
+            __syncthreads();
+            // lift into every slot with a facet of this loop (local facets 0,1,2 in order)
+            for (int idx = tid; idx < nfoot * NP; idx += nt) {
+                const int i = idx / nfoot, s = idx - i * nfoot;
+                const int c0 = fidx[s], c1 = fidx[S + s], c2 = fidx[2 * S + s];
+                if (c0 < 0 && c1 < 0 && c2 < 0) continue;
+                T acc[3] = {0, 0, 0};
+#pragma unroll
+                for (int p = 0; p < 3; ++p) {
+                    const int code = fidx[p * S + s];
+                    if (code < 0) continue;
+                    const int e = code >> 1, sd = code & 1;
+#pragma unroll
+                    for (int m = 0; m < NFP; ++m) {
+                        const T lv = Rf.lift[(p * NP + i) * NFP + m];
+                        for (int c = 0; c < nco; ++c) acc[c] += lv * GB(sd, c, m, e);
+                    }
+                }
+                for (int c = 0; c < nco; ++c) LF(L.out, c, i, s) += acc[c];
+            }
+#undef GB
+            if (L.partner >= 0) ++j;  // the exterior partner has been processed
+            break;
+        }
+        case KV_UPD_V:
+        case KV_UPD2_V: {
+            const int n = ie - ib;
+            const bool o4 = L.kind == KV_UPD_V;
+            for (int idx = tid; idx < n * 2 * NP; idx += nt) {
+                const int r = idx / n, q = idx - r * n;
+                const int s = (int)(lm[ib + q] & 0x3fffu);
+                const int c = r / NP, i = r - c * NP;
+                LF(F_V, c, i, s) += (o4 ? dt * LF(F_U, c, i, s) : T(0)) + LF(F_Z, c, i, s);
+            }
+            break;
+        }
+        case KV_UPD_S:
+        case KV_UPD2_S: {
+            const int n = ie - ib;
+            const bool o4 = L.kind == KV_UPD_S;
+            const T *sv = reinterpret_cast<const T *>(a.src_vec);
+            for (int idx = tid; idx < n * 3 * NP; idx += nt) {
+                const int r = idx / n, q = idx - r * n;
+                const int s = (int)(lm[ib + q] & 0x3fffu);
+                const int c = r / NP, i = r - c * NP;
+                T add = (o4 ? dt * LF(F_X, c, i, s) : T(0)) + LF(F_Z, c, i, s);
+                if (c < 2 && a.foot[f0 + s] == a.src_cell) add += (T)a.src_amp * sv[i];
+                LF(F_S, c, i, s) += add;
+            }
+            break;
+        }
+        default:
+            break;
+        }
+        __syncthreads();
+    }
+    // scatter what this tile wrote and others (or later sub-chains) need
+    for (int f = 0; f < F_COUNT; ++f) {
+        if (a.lds_row[f] < 0) continue;
+        T *dst = reinterpret_cast<T *>(a.F[f]);
+        const int rows = field_ncomp(f) * NP;
+        for (int idx = tid; idx < rows * nfoot; idx += nt) {
+            const int r = idx / nfoot, s = idx - r * nfoot;
+            if ((flags[s] >> (8 + f)) & 1) dst[(int64_t)r * nc + a.foot[f0 + s]] = lds[(size_t)(a.lds_row[f] + r) * S + s];
+        }
+    }
+#undef LF
+#undef LG
+}
+
+// ------------------------------------------------------------ plan kernels (local maps)
+
+__global__ void k_rank_keys(const int32_t *__restrict__ foot_off, const int32_t *__restrict__ foot,
+                            const int32_t *__restrict__ rank, int32_t ntiles, int64_t len,
+                            uint64_t *__restrict__ keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    // tile of entry i by binary search in foot_off
+    int lo = 0, hi = ntiles;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (foot_off[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    keys[i] = ((uint64_t)(uint32_t)lo << 32) | (uint32_t)rank[foot[i]];
+}
+
+__global__ void k_split_keys(const uint64_t *__restrict__ keys, int64_t len, int32_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) out[i] = (int32_t)(keys[i] & 0xffffffffull);
+}
+
+__device__ __forceinline__ int slot_of(const int32_t *__restrict__ foot, int b, int e, int32_t x) {
+    int lo = b, hi = e;  // first position with foot >= x
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (foot[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo - b;
+}
+
+// kind: 0 cell loop, 1 interior facet loop, 2 exterior facet loop
+__global__ void k_lmap(int kind, const int32_t *__restrict__ it_off, const int32_t *__restrict__ iters, int32_t ntiles,
+                       int64_t n, const int32_t *__restrict__ foot_off, const int32_t *__restrict__ efoot,
+                       const int32_t *__restrict__ rank, const int32_t *__restrict__ f2c,
+                       const int8_t *__restrict__ f2l, const int32_t *__restrict__ b2c,
+                       const int8_t *__restrict__ b2l, const uint8_t *__restrict__ bfree,
+                       uint32_t *__restrict__ lmap, int32_t *__restrict__ err) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    int lo = 0, hi = ntiles;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (it_off[mid] <= q) lo = mid;
+        else hi = mid;
+    }
+    const int b = foot_off[lo], e = foot_off[lo + 1];
+    const int32_t it = iters[q];
+    uint32_t code = 0;
+    if (kind == 0) {
+        const int s = slot_of(efoot, b, e, rank[it]);
+        if (s >= e - b || efoot[b + s] != rank[it] || s > 0x3fff) atomicExch(err, 1);
+        code = (uint32_t)s;
+    } else if (kind == 1) {
+        const int32_t x0 = rank[f2c[2 * it]], x1 = rank[f2c[2 * it + 1]];
+        const int s0 = slot_of(efoot, b, e, x0), s1 = slot_of(efoot, b, e, x1);
+        if (s0 >= e - b || s1 >= e - b || efoot[b + s0] != x0 || efoot[b + s1] != x1 || s0 > 0x3fff || s1 > 0x3fff)
+            atomicExch(err, 1);
+        code = (uint32_t)s0 | ((uint32_t)s1 << 14) | ((uint32_t)f2l[2 * it] << 28) | ((uint32_t)f2l[2 * it + 1] << 30);
+    } else {
+        const int32_t x = rank[b2c[it]];
+        const int s = slot_of(efoot, b, e, x);
+        if (s >= e - b || efoot[b + s] != x || s > 0x3fff) atomicExch(err, 1);
+        code = (uint32_t)s | ((uint32_t)b2l[it] << 28) | ((uint32_t)bfree[it] << 30);
+    }
+    lmap[q] = code;
+}
+
+// ------------------------------------------------------------ permutation and energy
+
+template <typename T>
+__global__ void k_permute_rows(const T *__restrict__ src, T *__restrict__ dst, const int32_t *__restrict__ map,
+                               int64_t rows, int64_t nc, int to_exec) {
+    // to_exec: dst[r][rank[c]] = src[r][c] with map = rank; else dst[r][c] = src[r][rank[c]]
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * nc) return;
+    const int64_t r = t / nc, c = t - r * nc;
+    if (to_exec) dst[r * nc + map[c]] = src[t];
+    else dst[t] = src[r * nc + map[c]];
+}
+
+template <int K, typename T>
+__global__ __launch_bounds__(256) void k_energy(const T *__restrict__ v, const T *__restrict__ sn,
+                                                const T *__restrict__ so, const T *__restrict__ geo,
+                                                const int32_t *__restrict__ rank, int64_t nc,
+                                                double *__restrict__ partial) {
+    constexpr int NP = np_of(K);
+    __shared__ double red[256];
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double e = 0.0;
+    if (c < nc) {
+        const auto &Rf = R<K, T>();
+        const int64_t x = rank[c];
+        const double lam = geo[G_LAM * nc + x], mu = geo[G_MU * nc + x], rho = 1.0 / (double)geo[G_IRHO * nc + x];
+        const double det = geo[G_DET * nc + x];
+        const double cA = (lam + 2 * mu) / (4 * mu * (lam + mu)), cB = -lam / (4 * mu * (lam + mu)), cC = 1.0 / mu;
+        for (int i = 0; i < NP; ++i)
+            for (int j = 0; j < NP; ++j) {
+                const double M = (double)Rf.M[i * NP + j];
+                const double ke = (double)v[(int64_t)i * nc + c] * v[(int64_t)j * nc + c] +
+                                  (double)v[((int64_t)NP + i) * nc + c] * v[((int64_t)NP + j) * nc + c];
+                const double axx = sn[(int64_t)i * nc + c], ayy = sn[((int64_t)NP + i) * nc + c],
+                             axy = sn[((int64_t)2 * NP + i) * nc + c];
+                const double bxx = so[(int64_t)j * nc + c], byy = so[((int64_t)NP + j) * nc + c],
+                             bxy = so[((int64_t)2 * NP + j) * nc + c];
+                const double se = cA * (axx * bxx + ayy * byy) + cB * (axx * byy + ayy * bxx) + cC * axy * bxy;
+                e += M * (rho * ke + se);
+            }
+        e *= 0.5 * det;
+    }
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_sum_partials(const double *__restrict__ p, int64_t n, double *__restrict__ out) {
+    __shared__ double red[256];
+    double e = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) e += p[i];
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// geometry rows in exec order (input-order arrays permuted by rank)
+template <typename T>
+__global__ void k_geometry(const double *__restrict__ xy, const int32_t *__restrict__ c2v,
+                           const double *__restrict__ lam, const double *__restrict__ mu,
+                           const double *__restrict__ rho, const int32_t *__restrict__ rank, int64_t nc,
+                           T *__restrict__ geo) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const double *p0 = xy + 2 * c2v[3 * c], *p1 = xy + 2 * c2v[3 * c + 1], *p2 = xy + 2 * c2v[3 * c + 2];
+    const double xr = p1[0] - p0[0], xs = p2[0] - p0[0], yr = p1[1] - p0[1], ys = p2[1] - p0[1];
+    const double det = xr * ys - xs * yr;
+    const int64_t x = rank[c];
+    geo[G_RX * nc + x] = (T)(ys / det);
+    geo[G_RY * nc + x] = (T)(-xs / det);
+    geo[G_SX * nc + x] = (T)(-yr / det);
+    geo[G_SY * nc + x] = (T)(xr / det);
+    geo[G_LAM * nc + x] = (T)lam[c];
+    geo[G_MU * nc + x] = (T)mu[c];
+    geo[G_IRHO * nc + x] = (T)(1.0 / rho[c]);
+    geo[G_ZP * nc + x] = (T)sqrt(rho[c] * (lam[c] + 2.0 * mu[c]));
+    geo[G_ZS * nc + x] = (T)sqrt(rho[c] * mu[c]);
+    geo[G_DET * nc + x] = (T)det;
+}
+
+__global__ void k_centroids(const double *__restrict__ xy, const int32_t *__restrict__ c2v, int64_t nc,
+                            double *__restrict__ cxy) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const double *p0 = xy + 2 * c2v[3 * c], *p1 = xy + 2 * c2v[3 * c + 1], *p2 = xy + 2 * c2v[3 * c + 2];
+    // ((x0 + x1) + x2) / 3 with no contraction: the seed order depends on these bits
+    cxy[2 * c] = __ddiv_rn(__dadd_rn(__dadd_rn(p0[0], p1[0]), p2[0]), 3.0);
+    cxy[2 * c + 1] = __ddiv_rn(__dadd_rn(__dadd_rn(p0[1], p1[1]), p2[1]), 3.0);
+}
+
+}  // namespace dgt

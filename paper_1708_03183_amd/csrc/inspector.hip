@@ -1,0 +1,852 @@
+// GPU sparse-tiling inspector (Sec. 5.1; Alg. 1, Alg. 3, Alg. 4) for gfx950.
+//
+// Every step is a deterministic function of the chain: sorts use unique keys,
+// maxima use the packed key (colour+1)<<32 | tile, and colouring is a
+// Jones-Plassmann sweep whose result depends only on the tile graph.  The
+// schedule is therefore bit-identical to any other implementation of the same
+// definition (the tests compare it with an independent CPU inspector).
+//
+// Readings where the paper leaves room:
+//  * a projection starts from the previous projection of its set and is only
+//    raised (never reset), for every descriptor whatever its mode;
+//  * sigma_j starts at bottom once and is the MAX over all descriptors/slots;
+//    an iteration left at bottom goes to the first tile of colour 0;
+//  * projections are emptied at the start of each conflict round;
+//  * two different tiles of one colour touching a common element of any set,
+//    in any loops of the (sub-)chain, conflict: each pair becomes a fake edge;
+//  * tiles are adjacent when a map into the seed set joins their iterations,
+//    or a map from the seed set sends two of their iterations to one element;
+//  * colouring priority is (fmix32(t), t), fmix32 the MurmurHash3 finaliser;
+//  * seed order 1 = Hilbert index of coordinates quantised to 2^16 per axis.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <sstream>
+
+#include "common.h"
+#include "inspector.h"
+
+namespace dgt {
+
+// ----------------------------------------------------------------- kernels
+
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+__device__ __forceinline__ uint64_t tile_key(const int32_t *color, int32_t t) {
+    return ((uint64_t)(uint32_t)(color[t] + 1) << 32) | (uint32_t)t;
+}
+
+// Hilbert curve index on a 2^16 grid: quadrant digit per level, then the
+// sub-square is reflected/transposed so the curve stays continuous.
+__device__ uint64_t hilbert16(uint32_t x, uint32_t y) {
+    uint64_t d = 0;
+#pragma unroll 1
+    for (int lvl = 15; lvl >= 0; --lvl) {
+        const uint32_t half = 1u << lvl;
+        const uint32_t qx = (x >> lvl) & 1u, qy = (y >> lvl) & 1u;
+        d += ((uint64_t)half * half) * ((3u * qx) ^ qy);
+        const uint32_t mask = half - 1u;
+        x &= mask;
+        y &= mask;
+        if (!qy) {
+            if (qx) {
+                x = mask - x;
+                y = mask - y;
+            }
+            const uint32_t t = x;
+            x = y;
+            y = t;
+        }
+    }
+    return d;
+}
+
+__global__ void k_minmax2(const double *__restrict__ xy, int64_t n, double *__restrict__ out4) {
+    // one block; deterministic (min/max are exact)
+    __shared__ double s[4][256];
+    double lo0 = INFINITY, lo1 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const double a = xy[2 * i], b = xy[2 * i + 1];
+        lo0 = fmin(lo0, a);
+        hi0 = fmax(hi0, a);
+        lo1 = fmin(lo1, b);
+        hi1 = fmax(hi1, b);
+    }
+    s[0][threadIdx.x] = lo0;
+    s[1][threadIdx.x] = hi0;
+    s[2][threadIdx.x] = lo1;
+    s[3][threadIdx.x] = hi1;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s[0][threadIdx.x] = fmin(s[0][threadIdx.x], s[0][threadIdx.x + w]);
+            s[1][threadIdx.x] = fmax(s[1][threadIdx.x], s[1][threadIdx.x + w]);
+            s[2][threadIdx.x] = fmin(s[2][threadIdx.x], s[2][threadIdx.x + w]);
+            s[3][threadIdx.x] = fmax(s[3][threadIdx.x], s[3][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out4[0] = s[0][0];
+        out4[1] = s[1][0];
+        out4[2] = s[2][0];
+        out4[3] = s[3][0];
+    }
+}
+
+__device__ uint32_t quantise16(double v, double lo, double hi) {
+    const double ext = __dsub_rn(hi, lo);
+    if (!(ext > 0.0)) return 0u;
+    const double q = floor(__dmul_rn(__ddiv_rn(__dsub_rn(v, lo), ext), 65536.0));
+    return q >= 65535.0 ? 65535u : (uint32_t)q;
+}
+
+__global__ void k_hilbert_keys(const double *__restrict__ xy, int64_t n, const double *__restrict__ box,
+                               uint64_t *__restrict__ keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t qx = quantise16(xy[2 * i], box[0], box[1]);
+    const uint32_t qy = quantise16(xy[2 * i + 1], box[2], box[3]);
+    keys[i] = (hilbert16(qx, qy) << 32) | (uint64_t)i;
+}
+
+__global__ void k_tile0_from_sorted(const uint64_t *__restrict__ sorted, int64_t n, int64_t ts,
+                                    int32_t *__restrict__ tile0, int32_t *__restrict__ rank) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int64_t i = (int64_t)(sorted[p] & 0xffffffffull);
+    tile0[i] = (int32_t)(p / ts);
+    if (rank) rank[i] = (int32_t)p;
+}
+
+__global__ void k_tile0_identity(int64_t n, int64_t ts, int32_t *__restrict__ tile0, int32_t *__restrict__ rank) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    tile0[i] = (int32_t)(i / ts);
+    if (rank) rank[i] = (int32_t)i;
+}
+
+// inverse map (Fig. 8): keys (target<<32 | source)
+__global__ void k_inv_keys(const int32_t *__restrict__ vals, int64_t nsrc, int arity, uint64_t *__restrict__ keys,
+                           int32_t *__restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsrc * arity) return;
+    const int32_t tgt = vals[i];
+    keys[i] = ((uint64_t)(uint32_t)tgt << 32) | (uint64_t)(i / arity);
+    atomicAdd(&count[tgt], 1);
+}
+
+__global__ void k_low32(const uint64_t *__restrict__ keys, int64_t n, int32_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (int32_t)(keys[i] & 0xffffffffull);
+}
+
+__global__ void k_high32_hist(const uint64_t *__restrict__ keys, int64_t n, int32_t *__restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd(&count[(int32_t)(keys[i] >> 32)], 1);
+}
+
+// tile pairs through a map into the seed set: all pairs of slots of one source
+__global__ void k_adj_into(const int32_t *__restrict__ vals, int64_t nsrc, int arity,
+                           const int32_t *__restrict__ tile0, uint64_t *__restrict__ out) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsrc) return;
+    int64_t w = s * (int64_t)(arity * (arity - 1) / 2);
+    for (int a = 0; a < arity; ++a)
+        for (int b = a + 1; b < arity; ++b) {
+            int32_t t1 = tile0[vals[s * arity + a]], t2 = tile0[vals[s * arity + b]];
+            if (t1 > t2) { const int32_t t = t1; t1 = t2; t2 = t; }
+            out[w++] = (t1 == t2) ? ~0ull : (((uint64_t)(uint32_t)t1 << 32) | (uint32_t)t2);
+        }
+}
+
+// pair counts per target of a map from the seed set
+__global__ void k_adj_from_count(const int32_t *__restrict__ off, int64_t ntgt, int64_t *__restrict__ cnt) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= ntgt) return;
+    const int64_t d = off[x + 1] - off[x];
+    cnt[x] = d * (d - 1) / 2;
+}
+
+__global__ void k_adj_from(const int32_t *__restrict__ off, const int32_t *__restrict__ val, int64_t ntgt,
+                           const int64_t *__restrict__ pos, const int32_t *__restrict__ tile0,
+                           uint64_t *__restrict__ out) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= ntgt) return;
+    int64_t w = pos[x];
+    for (int32_t a = off[x]; a < off[x + 1]; ++a)
+        for (int32_t b = a + 1; b < off[x + 1]; ++b) {
+            int32_t t1 = tile0[val[a]], t2 = tile0[val[b]];
+            if (t1 > t2) { const int32_t t = t1; t1 = t2; t2 = t; }
+            out[w++] = (t1 == t2) ? ~0ull : (((uint64_t)(uint32_t)t1 << 32) | (uint32_t)t2);
+        }
+}
+
+__global__ void k_sym_edges(const uint64_t *__restrict__ e, int64_t n, uint64_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t a = e[i] >> 32, b = e[i] & 0xffffffffull;
+    out[2 * i] = (a << 32) | b;
+    out[2 * i + 1] = (b << 32) | a;
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Jones-Plassmann round, part 1: uncoloured local maxima of the priority
+__global__ void k_jp_mark(const int32_t *__restrict__ off, const int32_t *__restrict__ adj,
+                          const int32_t *__restrict__ color, int32_t n, int8_t *__restrict__ mark) {
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    int8_t m = 0;
+    if (color[t] < 0) {
+        const uint64_t pt = ((uint64_t)fmix32((uint32_t)t) << 32) | (uint32_t)t;
+        m = 1;
+        for (int32_t k = off[t]; k < off[t + 1]; ++k) {
+            const int32_t u = adj[k];
+            if (color[u] >= 0) continue;
+            const uint64_t pu = ((uint64_t)fmix32((uint32_t)u) << 32) | (uint32_t)u;
+            if (pu > pt) { m = 0; break; }
+        }
+    }
+    mark[t] = m;
+}
+
+// part 2: each marked tile takes the smallest colour unused by coloured neighbours
+__global__ void k_jp_assign(const int32_t *__restrict__ off, const int32_t *__restrict__ adj,
+                            int32_t *__restrict__ color, int32_t n, const int8_t *__restrict__ mark,
+                            int32_t *__restrict__ stats /* [0] coloured this round, [1] max colour, [2] overflow */) {
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n || !mark[t]) return;
+    uint64_t used = 0;
+    for (int32_t k = off[t]; k < off[t + 1]; ++k) {
+        const int32_t c = color[adj[k]];
+        if (c >= 64) atomicExch(&stats[2], 1);
+        else if (c >= 0) used |= 1ull << c;
+    }
+    const int col = (~used == 0ull) ? 64 : __ffsll((unsigned long long)~used) - 1;
+    if (col >= 64) { atomicExch(&stats[2], 1); return; }
+    color[t] = col;
+    atomicAdd(&stats[0], 1);
+    atomicMax(&stats[1], col);
+}
+
+__global__ void k_first_color0(const int32_t *__restrict__ color, int32_t n, int32_t *__restrict__ out) {
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n && color[t] == 0) atomicMin(out, t);
+}
+
+// Alg. 3, direct descriptor: phi = max(phi_prev, key(sigma))
+__global__ void k_proj_direct(uint64_t *__restrict__ phi, int has_prev, const int32_t *__restrict__ sigma,
+                              const int32_t *__restrict__ color, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const uint64_t k = tile_key(color, sigma[e]);
+    const uint64_t p = has_prev ? phi[e] : 0ull;
+    phi[e] = k > p ? k : p;
+}
+
+// Alg. 3, indirect descriptor: gather-max through the inverse map
+__global__ void k_proj_indirect(uint64_t *__restrict__ phi, int has_prev, const int32_t *__restrict__ inv_off,
+                                const int32_t *__restrict__ inv_val, const int32_t *__restrict__ sigma,
+                                const int32_t *__restrict__ color, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    uint64_t best = has_prev ? phi[e] : 0ull;
+    for (int32_t a = inv_off[e]; a < inv_off[e + 1]; ++a) {
+        const uint64_t k = tile_key(color, sigma[inv_val[a]]);
+        best = k > best ? k : best;
+    }
+    phi[e] = best;
+}
+
+struct TileDesc {
+    const uint64_t *phi;   // projection of the target set (nullptr: none yet)
+    const int32_t *map;    // nullptr: direct
+    int32_t arity;
+};
+
+struct TileArgs {
+    int32_t nd;
+    TileDesc d[8];
+};
+
+// Alg. 4: sigma_j[e] = MAX over descriptors and slots of the projections
+__global__ void k_tile(TileArgs a, int64_t n, const int32_t *__restrict__ deft, int32_t *__restrict__ sigma) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    uint64_t best = 0;
+    for (int i = 0; i < a.nd; ++i) {
+        const TileDesc &D = a.d[i];
+        if (!D.phi) continue;
+        if (!D.map) {
+            const uint64_t v = D.phi[e];
+            best = v > best ? v : best;
+        } else {
+            for (int k = 0; k < D.arity; ++k) {
+                const uint64_t v = D.phi[D.map[e * D.arity + k]];
+                best = v > best ? v : best;
+            }
+        }
+    }
+    sigma[e] = best ? (int32_t)(best & 0xffffffffull) : *deft;
+}
+
+// touches of one set: (element<<32 | tile) with loop bit
+__global__ void k_touch(const int32_t *__restrict__ sigma, const int32_t *__restrict__ map, int arity, int64_t n,
+                        uint32_t bit, uint64_t *__restrict__ keys, uint32_t *__restrict__ bits) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * arity) return;
+    const int64_t it = i / arity;
+    const uint32_t x = map ? (uint32_t)map[i] : (uint32_t)it;
+    keys[i] = ((uint64_t)x << 32) | (uint32_t)sigma[it];
+    bits[i] = bit;
+}
+
+// conflicts among the unique (element, tile) touches of one set
+__global__ void k_conflicts(const uint64_t *__restrict__ keys, int64_t n, const int32_t *__restrict__ color,
+                            uint64_t *__restrict__ out, int64_t cap, unsigned long long *__restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t x = keys[i] >> 32;
+    const int32_t ti = (int32_t)(keys[i] & 0xffffffffull);
+    for (int64_t j = i + 1; j < n && (keys[j] >> 32) == x; ++j) {
+        const int32_t tj = (int32_t)(keys[j] & 0xffffffffull);
+        if (color[ti] == color[tj]) {
+            const unsigned long long w = atomicAdd(count, 1ull);
+            const int32_t a = ti < tj ? ti : tj, b = ti < tj ? tj : ti;
+            if ((int64_t)w < cap) out[w] = ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
+        }
+    }
+}
+
+// footprint entries: re-key to (tile<<32 | element) and flag single-tile elements
+__global__ void k_foot_rekey(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ bits, int64_t n,
+                             uint64_t *__restrict__ okeys, uint32_t *__restrict__ obits) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t x = keys[i] >> 32;
+    const bool single = (i == 0 || (keys[i - 1] >> 32) != x) && (i + 1 == n || (keys[i + 1] >> 32) != x);
+    okeys[i] = ((keys[i] & 0xffffffffull) << 32) | x;
+    obits[i] = bits[i] | (single ? 0x80000000u : 0u);
+}
+
+__global__ void k_sigma_keys(const int32_t *__restrict__ sigma, int64_t n, uint64_t *__restrict__ keys) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) keys[e] = ((uint64_t)(uint32_t)sigma[e] << 32) | (uint64_t)e;
+}
+
+__global__ void k_color_keys(const int32_t *__restrict__ color, int32_t n, uint64_t *__restrict__ keys) {
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) keys[t] = ((uint64_t)(uint32_t)color[t] << 32) | (uint32_t)t;
+}
+
+// ----------------------------------------------------------------- primitives
+
+struct BitOr {
+    __device__ __forceinline__ uint32_t operator()(uint32_t a, uint32_t b) const { return a | b; }
+};
+
+void sort_keys(DBuf<uint64_t> &keys, int64_t n, hipStream_t st, int end_bit) {
+    if (n <= 1) return;
+    DBuf<uint64_t> out(n);
+    size_t tmp = 0;
+    DGT_HIP(hipcub::DeviceRadixSort::SortKeys(nullptr, tmp, keys.p, out.p, (int)n, 0, end_bit, st));
+    DBuf<char> t(tmp);
+    DGT_HIP(hipcub::DeviceRadixSort::SortKeys(t.p, tmp, keys.p, out.p, (int)n, 0, end_bit, st));
+    keys = std::move(out);
+}
+
+void sort_pairs(DBuf<uint64_t> &keys, DBuf<uint32_t> &vals, int64_t n, hipStream_t st) {
+    if (n <= 1) return;
+    DBuf<uint64_t> ko(n);
+    DBuf<uint32_t> vo(n);
+    size_t tmp = 0;
+    DGT_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, keys.p, ko.p, vals.p, vo.p, (int)n, 0, 64, st));
+    DBuf<char> t(tmp);
+    DGT_HIP(hipcub::DeviceRadixSort::SortPairs(t.p, tmp, keys.p, ko.p, vals.p, vo.p, (int)n, 0, 64, st));
+    keys = std::move(ko);
+    vals = std::move(vo);
+}
+
+// unique keys; returns count (sentinel ~0 entries dropped)
+static int64_t unique_keys(DBuf<uint64_t> &keys, int64_t n, hipStream_t st) {
+    if (n == 0) return 0;
+    DBuf<uint64_t> out(n);
+    DBuf<int64_t> cnt(1);
+    size_t tmp = 0;
+    DGT_HIP(hipcub::DeviceSelect::Unique(nullptr, tmp, keys.p, out.p, cnt.p, (int)n, st));
+    DBuf<char> t(tmp);
+    DGT_HIP(hipcub::DeviceSelect::Unique(t.p, tmp, keys.p, out.p, cnt.p, (int)n, st));
+    int64_t m = cnt.download(st)[0];
+    if (m > 0) {
+        uint64_t last;
+        DGT_HIP(hipMemcpyAsync(&last, out.p + m - 1, 8, hipMemcpyDeviceToHost, st));
+        DGT_HIP(hipStreamSynchronize(st));
+        if (last == ~0ull) m--;
+    }
+    keys = std::move(out);
+    return m;
+}
+
+static void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t st) {
+    size_t tmp = 0;
+    DGT_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, in, out, (int)n, st));
+    DBuf<char> t(tmp);
+    DGT_HIP(hipcub::DeviceScan::ExclusiveSum(t.p, tmp, in, out, (int)n, st));
+}
+
+static void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t st) {
+    size_t tmp = 0;
+    DGT_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, in, out, (int)n, st));
+    DBuf<char> t(tmp);
+    DGT_HIP(hipcub::DeviceScan::ExclusiveSum(t.p, tmp, in, out, (int)n, st));
+}
+
+// counts [n] -> offsets [n+1] (exclusive scan with total at the end)
+static void counts_to_offsets(DBuf<int32_t> &cnt, int64_t n, DBuf<int32_t> &off, hipStream_t st) {
+    off.alloc(n + 1);
+    if (n == 0) {
+        DGT_HIP(hipMemsetAsync(off.p, 0, sizeof(int32_t), st));
+        return;
+    }
+    DBuf<int32_t> tmp(n + 1);
+    DGT_HIP(hipMemsetAsync(tmp.p + n, 0, sizeof(int32_t), st));
+    DGT_HIP(hipMemcpyAsync(tmp.p, cnt.p, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+    exclusive_scan_i32(tmp.p, off.p, n + 1, st);
+}
+
+// CSR offsets of sorted (high32 << 32 | low32) keys grouped by the high word
+static void offsets_by_high(const DBuf<uint64_t> &keys, int64_t n, int64_t ngroups, DBuf<int32_t> &off,
+                            hipStream_t st) {
+    DBuf<int32_t> cnt(ngroups + 1);
+    DGT_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (ngroups + 1), st));
+    if (n) k_high32_hist<<<blocks_for(n, 256), 256, 0, st>>>(keys.p, n, cnt.p);
+    counts_to_offsets(cnt, ngroups, off, st);
+}
+
+// ----------------------------------------------------------------- host driver
+
+void Inspector::build_inverse(const ChainDesc &c, int mi, hipStream_t st) {
+    const ChainMap &m = c.maps[mi];
+    const int64_t ns = c.size[m.from], nt = c.size[m.to];
+    const int64_t n = ns * m.arity;
+    DBuf<uint64_t> keys(n > 0 ? n : 1);
+    DBuf<int32_t> cnt(nt + 1);
+    DGT_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nt + 1), st));
+    if (n) k_inv_keys<<<blocks_for(n, 256), 256, 0, st>>>(dmap[mi].p, ns, m.arity, keys.p, cnt.p);
+    sort_keys(keys, n, st);
+    inv_val[mi].alloc(n > 0 ? n : 1);
+    if (n) k_low32<<<blocks_for(n, 256), 256, 0, st>>>(keys.p, n, inv_val[mi].p);
+    counts_to_offsets(cnt, nt, inv_off[mi], st);
+}
+
+Inspector::Inspector(const ChainDesc &c, hipStream_t st) : chain(c), stream(st) {
+    for (int mi = 0; mi < c.nmaps; ++mi) {
+        dmap[mi].upload(c.maps[mi].values, st);
+        build_inverse(c, mi, st);
+    }
+}
+
+namespace {
+
+struct SubRun {
+    int first, n;
+    int64_t n0;
+    int32_t ntiles;
+};
+
+}  // namespace
+
+void Inspector::seed_partition(int seedset, int64_t ts, int partition, const double *seed_xy_host,
+                               const double *seed_xy_dev, DBuf<int32_t> &tile0, DBuf<int32_t> &rank) {
+    hipStream_t st = stream;
+    const int64_t n0 = chain.size[seedset];
+    tile0.alloc(n0 > 0 ? n0 : 1);
+    rank.alloc(n0 > 0 ? n0 : 1);
+    if (n0 == 0) return;
+    if (partition == 0) {
+        k_tile0_identity<<<blocks_for(n0, 256), 256, 0, st>>>(n0, ts, tile0.p, rank.p);
+        return;
+    }
+    DBuf<double> xy_owned;
+    const double *xy = seed_xy_dev;
+    if (!xy) {
+        DGT_REQUIRE(seed_xy_host, DGT_EINVAL, "partition 1 needs seed_xy");
+        xy_owned.upload(seed_xy_host, 2 * n0, st);
+        xy = xy_owned.p;
+    }
+    DBuf<double> box(4);
+    k_minmax2<<<1, 256, 0, st>>>(xy, n0, box.p);
+    DBuf<uint64_t> keys(n0);
+    k_hilbert_keys<<<blocks_for(n0, 256), 256, 0, st>>>(xy, n0, box.p, keys.p);
+    sort_keys(keys, n0, st);
+    k_tile0_from_sorted<<<blocks_for(n0, 256), 256, 0, st>>>(keys.p, n0, ts, tile0.p, rank.p);
+}
+
+int64_t Inspector::seed_edges(int first, int nl, const DBuf<int32_t> &tile0, DBuf<uint64_t> &edges) {
+    hipStream_t st = stream;
+    const int seed = chain.loops[first].set;
+    bool used[8] = {false};
+    for (int j = first; j < first + nl; ++j)
+        for (int i = 0; i < chain.loops[j].ndesc; ++i)
+            if (chain.loops[j].d[i].map >= 0) used[chain.loops[j].d[i].map] = true;
+    std::vector<DBuf<uint64_t>> parts;
+    std::vector<int64_t> lens;
+    for (int mi = 0; mi < chain.nmaps; ++mi) {
+        if (!used[mi]) continue;
+        const ChainMap &m = chain.maps[mi];
+        if (m.to == seed && m.arity >= 2) {
+            const int64_t ns = chain.size[m.from];
+            const int64_t np = ns * (m.arity * (m.arity - 1) / 2);
+            DBuf<uint64_t> out(np > 0 ? np : 1);
+            if (ns) k_adj_into<<<blocks_for(ns, 256), 256, 0, st>>>(dmap[mi].p, ns, m.arity, tile0.p, out.p);
+            parts.push_back(std::move(out));
+            lens.push_back(np);
+        }
+        if (m.from == seed) {
+            const int64_t nt = chain.size[m.to];
+            DBuf<int64_t> cnt(nt + 1), pos(nt + 1);
+            DGT_HIP(hipMemsetAsync(cnt.p + nt, 0, sizeof(int64_t), st));
+            if (nt) k_adj_from_count<<<blocks_for(nt, 256), 256, 0, st>>>(inv_off[mi].p, nt, cnt.p);
+            exclusive_scan_i64(cnt.p, pos.p, nt + 1, st);
+            const int64_t np = pos.download(st)[nt];
+            DBuf<uint64_t> out(np > 0 ? np : 1);
+            if (nt && np)
+                k_adj_from<<<blocks_for(nt, 256), 256, 0, st>>>(inv_off[mi].p, inv_val[mi].p, nt, pos.p, tile0.p,
+                                                                out.p);
+            parts.push_back(std::move(out));
+            lens.push_back(np);
+        }
+    }
+    int64_t total = 0;
+    for (auto l : lens) total += l;
+    edges.alloc(total > 0 ? total : 1);
+    int64_t w = 0;
+    for (size_t i = 0; i < parts.size(); ++i) {
+        if (lens[i])
+            DGT_HIP(hipMemcpyAsync(edges.p + w, parts[i].p, sizeof(uint64_t) * lens[i], hipMemcpyDeviceToDevice, st));
+        w += lens[i];
+    }
+    sort_keys(edges, total, st);
+    return unique_keys(edges, total, st);
+}
+
+// Jones-Plassmann colouring of the tile graph given by unique edges (a<b)
+int Inspector::colour(int32_t ntiles, const DBuf<uint64_t> &edges, int64_t ne, DBuf<int32_t> &color) {
+    hipStream_t st = stream;
+    DBuf<uint64_t> sym(2 * ne > 0 ? 2 * ne : 1);
+    if (ne) k_sym_edges<<<blocks_for(ne, 256), 256, 0, st>>>(edges.p, ne, sym.p);
+    sort_keys(sym, 2 * ne, st);
+    DBuf<int32_t> off, adj(2 * ne > 0 ? 2 * ne : 1);
+    offsets_by_high(sym, 2 * ne, ntiles, off, st);
+    if (ne) k_low32<<<blocks_for(2 * ne, 256), 256, 0, st>>>(sym.p, 2 * ne, adj.p);
+    color.alloc(ntiles);
+    k_fill_i32<<<blocks_for(ntiles, 256), 256, 0, st>>>(color.p, ntiles, -1);
+    DBuf<int8_t> mark(ntiles);
+    DBuf<int32_t> stats(3);
+    DGT_HIP(hipMemsetAsync(stats.p, 0, sizeof(int32_t) * 3, st));
+    int32_t done = 0;
+    int guard_rounds = 0;
+    while (done < ntiles) {
+        // several rounds between host checks
+        for (int r = 0; r < 8; ++r) {
+            k_jp_mark<<<blocks_for(ntiles, 256), 256, 0, st>>>(off.p, adj.p, color.p, ntiles, mark.p);
+            k_jp_assign<<<blocks_for(ntiles, 256), 256, 0, st>>>(off.p, adj.p, color.p, ntiles, mark.p, stats.p);
+        }
+        auto h = stats.download(st);
+        DGT_REQUIRE(h[2] == 0, DGT_EUNSUPPORTED, "tile colouring needs more than 64 colours");
+        done = h[0];
+        DGT_REQUIRE(++guard_rounds < 1000000, DGT_ESTATE, "colouring did not terminate");
+        if (done >= ntiles) return h[1] + 1;
+    }
+    return 0;
+}
+
+void Inspector::run_sub(Schedule &S, SubSched &sb, int64_t ts, int partition, const double *xy_host,
+                        const double *xy_dev, int max_rounds) {
+    hipStream_t st = stream;
+    const int first = sb.first, nl = sb.n;
+    const int seedset = chain.loops[first].set;
+    const int64_t n0 = chain.size[seedset];
+    int32_t ntiles = (int32_t)((n0 + ts - 1) / ts);
+    if (ntiles == 0) ntiles = 1;
+    DBuf<int32_t> tile0, rank;
+    seed_partition(seedset, ts, partition, xy_host, xy_dev, tile0, rank);
+    if (first == 0 || !S.seed_rank.p) {
+        S.seed_rank = std::move(rank);
+        S.seed_set = seedset;
+    }
+    DBuf<uint64_t> edges;
+    int64_t ne = seed_edges(first, nl, tile0, edges);
+    DBuf<int32_t> deft(1);
+    // per-set projection buffers
+    DBuf<uint64_t> phi[8];
+    for (int s = 0; s < chain.nsets; ++s) phi[s].alloc(chain.size[s] > 0 ? chain.size[s] : 1);
+    int round = 0, ncol = 0;
+    for (; round < max_rounds; ++round) {
+        ncol = colour(ntiles, edges, ne, sb.color);
+        // default tile: first tile of colour 0
+        int32_t big = INT32_MAX;
+        DGT_HIP(hipMemcpyAsync(deft.p, &big, 4, hipMemcpyHostToDevice, st));
+        k_first_color0<<<blocks_for(ntiles, 256), 256, 0, st>>>(sb.color.p, ntiles, deft.p);
+        // sigma_seed = partition
+        if (n0)
+            DGT_HIP(hipMemcpyAsync(S.sigma[first].p, tile0.p, sizeof(int32_t) * n0, hipMemcpyDeviceToDevice, st));
+        bool has[8] = {false};
+        for (int j = first + 1; j < first + nl; ++j) {
+            // project L_{j-1} (Alg. 3) for every distinct (target set, map) descriptor
+            const ChainLoop &Lp = chain.loops[j - 1];
+            const int64_t np_ = chain.size[Lp.set];
+            int seen[16][2];
+            int nseen = 0;
+            for (int i = 0; i < Lp.ndesc; ++i) {
+                const int mp = Lp.d[i].map;
+                const int S_ = mp < 0 ? Lp.set : chain.maps[mp].to;
+                bool dup = false;
+                for (int q = 0; q < nseen; ++q) dup |= (seen[q][0] == S_ && seen[q][1] == mp);
+                if (dup) continue;
+                seen[nseen][0] = S_;
+                seen[nseen][1] = mp;
+                nseen++;
+                const int64_t nS = chain.size[S_];
+                if (nS == 0) { has[S_] = true; continue; }
+                if (mp < 0) {
+                    k_proj_direct<<<blocks_for(nS, 256), 256, 0, st>>>(phi[S_].p, has[S_] ? 1 : 0,
+                                                                       S.sigma[j - 1].p, sb.color.p, nS);
+                } else {
+                    k_proj_indirect<<<blocks_for(nS, 256), 256, 0, st>>>(phi[S_].p, has[S_] ? 1 : 0,
+                                                                         inv_off[mp].p, inv_val[mp].p,
+                                                                         S.sigma[j - 1].p, sb.color.p, nS);
+                }
+                (void)np_;
+                has[S_] = true;
+            }
+            // tile L_j (Alg. 4)
+            const ChainLoop &L = chain.loops[j];
+            TileArgs ta{};
+            ta.nd = 0;
+            for (int i = 0; i < L.ndesc; ++i) {
+                const int mp = L.d[i].map;
+                const int S_ = mp < 0 ? L.set : chain.maps[mp].to;
+                TileDesc d;
+                d.phi = has[S_] ? phi[S_].p : nullptr;
+                d.map = mp < 0 ? nullptr : dmap[mp].p;
+                d.arity = mp < 0 ? 1 : chain.maps[mp].arity;
+                ta.d[ta.nd++] = d;
+            }
+            const int64_t nj = chain.size[L.set];
+            if (nj) k_tile<<<blocks_for(nj, 256), 256, 0, st>>>(ta, nj, deft.p, S.sigma[j].p);
+        }
+        // conflicts (all sets, all loops of the sub-chain)
+        int64_t nconf = conflicts(first, nl, sb.color, edges, ne);
+        if (nconf == 0) break;
+    }
+    DGT_REQUIRE(round < max_rounds, DGT_ESTATE, "inspector exceeded max_conflict_rounds");
+    sb.ntiles = ntiles;
+    sb.ncolors = ncol;
+    sb.rounds = round + 1;
+    footprints(first, nl, sb);
+    // tiles in execution order
+    {
+        DBuf<uint64_t> keys(ntiles);
+        k_color_keys<<<blocks_for(ntiles, 256), 256, 0, st>>>(sb.color.p, ntiles, keys.p);
+        sort_keys(keys, ntiles, st);
+        sb.tiles_by_color.alloc(ntiles);
+        k_low32<<<blocks_for(ntiles, 256), 256, 0, st>>>(keys.p, ntiles, sb.tiles_by_color.p);
+        offsets_by_high(keys, ntiles, ncol, sb.color_off, st);
+    }
+    // iteration lists (assign)
+    for (int j = first; j < first + nl; ++j) {
+        const int64_t nj = chain.size[chain.loops[j].set];
+        DBuf<uint64_t> keys(nj > 0 ? nj : 1);
+        if (nj) k_sigma_keys<<<blocks_for(nj, 256), 256, 0, st>>>(S.sigma[j].p, nj, keys.p);
+        sort_keys(keys, nj, st);
+        S.iters[j].alloc(nj > 0 ? nj : 1);
+        if (nj) k_low32<<<blocks_for(nj, 256), 256, 0, st>>>(keys.p, nj, S.iters[j].p);
+        offsets_by_high(keys, nj, ntiles, S.it_off[j], st);
+    }
+}
+
+// unique (element<<32|tile) touches of set s with OR-ed loop bits
+int64_t Inspector::touches(int first, int nl, int s, DBuf<uint64_t> &keys, DBuf<uint32_t> &bits,
+                           const Schedule &S) {
+    hipStream_t st = stream;
+    int64_t total = 0;
+    struct Item { int j, map; int arity; int64_t n; };
+    std::vector<Item> items;
+    for (int j = first; j < first + nl; ++j) {
+        const ChainLoop &L = chain.loops[j];
+        int seen[8], nseen = 0;
+        for (int i = 0; i < L.ndesc; ++i) {
+            const int mp = L.d[i].map;
+            const int S_ = mp < 0 ? L.set : chain.maps[mp].to;
+            if (S_ != s) continue;
+            bool dup = false;
+            for (int q = 0; q < nseen; ++q) dup |= seen[q] == mp;
+            if (dup) continue;
+            seen[nseen++] = mp;
+            const int ar = mp < 0 ? 1 : chain.maps[mp].arity;
+            items.push_back({j, mp, ar, chain.size[L.set]});
+            total += chain.size[L.set] * ar;
+        }
+    }
+    keys.alloc(total > 0 ? total : 1);
+    bits.alloc(total > 0 ? total : 1);
+    int64_t w = 0;
+    for (auto &it : items) {
+        const int64_t m = it.n * it.arity;
+        if (m)
+            k_touch<<<blocks_for(m, 256), 256, 0, st>>>(S.sigma[it.j].p, it.map < 0 ? nullptr : dmap[it.map].p,
+                                                        it.arity, it.n, 1u << (it.j - first), keys.p + w, bits.p + w);
+        w += m;
+    }
+    if (total == 0) return 0;
+    sort_pairs(keys, bits, total, st);
+    // reduce by key (OR of bits)
+    DBuf<uint64_t> uk(total);
+    DBuf<uint32_t> ub(total);
+    DBuf<int64_t> cnt(1);
+    size_t tmp = 0;
+    DGT_HIP(hipcub::DeviceReduce::ReduceByKey(nullptr, tmp, keys.p, uk.p, bits.p, ub.p, cnt.p, BitOr(), (int)total,
+                                              st));
+    DBuf<char> t(tmp);
+    DGT_HIP(hipcub::DeviceReduce::ReduceByKey(t.p, tmp, keys.p, uk.p, bits.p, ub.p, cnt.p, BitOr(), (int)total, st));
+    const int64_t m = cnt.download(st)[0];
+    keys = std::move(uk);
+    bits = std::move(ub);
+    return m;
+}
+
+int64_t Inspector::conflicts(int first, int nl, const DBuf<int32_t> &color, DBuf<uint64_t> &edges, int64_t &ne) {
+    hipStream_t st = stream;
+    std::vector<DBuf<uint64_t>> found;
+    std::vector<int64_t> nfound;
+    int64_t total = 0;
+    for (int s = 0; s < chain.nsets; ++s) {
+        DBuf<uint64_t> keys;
+        DBuf<uint32_t> bits;
+        const int64_t m = touches(first, nl, s, keys, bits, *cur);
+        if (m == 0) continue;
+        int64_t cap = std::max<int64_t>(1024, m);
+        for (;;) {
+            DBuf<uint64_t> out(cap);
+            DBuf<unsigned long long> cnt(1);
+            DGT_HIP(hipMemsetAsync(cnt.p, 0, 8, st));
+            k_conflicts<<<blocks_for(m, 256), 256, 0, st>>>(keys.p, m, color.p, out.p, cap, cnt.p);
+            const int64_t c = (int64_t)cnt.download(st)[0];
+            if (c <= cap) {
+                if (c) {
+                    found.push_back(std::move(out));
+                    nfound.push_back(c);
+                    total += c;
+                }
+                break;
+            }
+            cap = c;
+        }
+    }
+    if (total == 0) return 0;
+    // fake connections: edges <- unique(edges U conflicts)
+    DBuf<uint64_t> all(ne + total);
+    if (ne) DGT_HIP(hipMemcpyAsync(all.p, edges.p, sizeof(uint64_t) * ne, hipMemcpyDeviceToDevice, st));
+    int64_t w = ne;
+    for (size_t i = 0; i < found.size(); ++i) {
+        DGT_HIP(hipMemcpyAsync(all.p + w, found[i].p, sizeof(uint64_t) * nfound[i], hipMemcpyDeviceToDevice, st));
+        w += nfound[i];
+    }
+    sort_keys(all, w, st);
+    ne = unique_keys(all, w, st);
+    edges = std::move(all);
+    return total;
+}
+
+void Inspector::footprints(int first, int nl, SubSched &sb) {
+    hipStream_t st = stream;
+    for (int s = 0; s < chain.nsets; ++s) {
+        DBuf<uint64_t> keys;
+        DBuf<uint32_t> bits;
+        const int64_t m = touches(first, nl, s, keys, bits, *cur);
+        sb.foot_len[s] = m;
+        if (m == 0) {
+            sb.foot_off[s].alloc(sb.ntiles + 1);
+            DGT_HIP(hipMemsetAsync(sb.foot_off[s].p, 0, sizeof(int32_t) * (sb.ntiles + 1), st));
+            sb.foot[s].alloc(1);
+            sb.acc[s].alloc(1);
+            continue;
+        }
+        DBuf<uint64_t> k2(m);
+        DBuf<uint32_t> b2(m);
+        k_foot_rekey<<<blocks_for(m, 256), 256, 0, st>>>(keys.p, bits.p, m, k2.p, b2.p);
+        sort_pairs(k2, b2, m, st);
+        sb.foot[s].alloc(m);
+        k_low32<<<blocks_for(m, 256), 256, 0, st>>>(k2.p, m, sb.foot[s].p);
+        sb.acc[s] = std::move(b2);
+        offsets_by_high(k2, m, sb.ntiles, sb.foot_off[s], st);
+    }
+}
+
+std::unique_ptr<Schedule> Inspector::run(int64_t ts, int partition, const double *xy_host, const double *xy_dev,
+                                         int max_rounds, const std::vector<int32_t> &splits) {
+    hipStream_t st = stream;
+    DGT_REQUIRE(ts >= 1, DGT_EINVAL, "tile_size must be >= 1");
+    DGT_REQUIRE(max_rounds >= 1, DGT_EINVAL, "max_conflict_rounds must be >= 1");
+    DGT_REQUIRE(chain.nloops >= 1, DGT_EINVAL, "empty loop chain");
+    auto S = std::make_unique<Schedule>();
+    cur = S.get();
+    S->nloops = chain.nloops;
+    for (int j = 0; j < chain.nloops; ++j) {
+        S->loop_size[j] = chain.size[chain.loops[j].set];
+        S->sigma[j].alloc(S->loop_size[j] > 0 ? S->loop_size[j] : 1);
+    }
+    hipEvent_t e0, e1;
+    DGT_HIP(hipEventCreate(&e0));
+    DGT_HIP(hipEventCreate(&e1));
+    DGT_HIP(hipEventRecord(e0, st));
+    auto t0 = std::chrono::steady_clock::now();
+    int start = 0;
+    for (size_t i = 0; i <= splits.size(); ++i) {
+        const int end = i < splits.size() ? splits[i] : chain.nloops;
+        DGT_REQUIRE(end > start && end <= chain.nloops && end - start <= 31, DGT_EINVAL,
+                    "splits must be ascending with sub-chains of 1..31 loops");
+        if (partition == 1)
+            DGT_REQUIRE(chain.loops[start].set == chain.loops[0].set, DGT_EINVAL,
+                        "partition 1 needs every sub-chain to start on the seed set");
+        S->sub.emplace_back();
+        SubSched &sb = S->sub.back();
+        sb.first = start;
+        sb.n = end - start;
+        for (int j = start; j < end; ++j) S->sub_of[j] = (int)S->sub.size() - 1;
+        run_sub(*S, sb, ts, partition, xy_host, xy_dev, max_rounds);
+        start = end;
+    }
+    DGT_HIP(hipEventRecord(e1, st));
+    DGT_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    DGT_HIP(hipEventElapsedTime(&ms, e0, e1));
+    S->gpu_ms = ms;
+    S->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    S->stream = st;
+    cur = nullptr;
+    return S;
+}
+
+}  // namespace dgt

@@ -1,0 +1,793 @@
+// DG elastic solver object of libdgtile (tier 2 of the C ABI): set-up, the DG
+// loop chain handed to the GPU inspector, the executor plan, and the step,
+// state and energy entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "dg_device.h"
+
+namespace dgt {
+
+struct GLoop {
+    int8_t kind, in, out, pen;
+    double scale, pscale;
+    int set;  // 0 cells, 1 interior facets, 2 exterior facets
+};
+
+struct SubPlan {
+    int first = 0, n = 0, ntiles = 0, ncolors = 0;
+    DBuf<int32_t> efoot;
+    DBuf<uint32_t> eacc;
+    DBuf<uint32_t> lmap[31];
+    std::vector<int32_t> color_off;
+    TileArgs args{};
+    size_t lds_bytes = 0;
+    int max_foot = 0, max_fac = 0;
+};
+
+}  // namespace dgt
+
+struct dgt_solver {
+    const dgt::Mesh *mesh = nullptr;
+    dgt_solver_params p{};
+    hipStream_t st = nullptr;
+    dgt::RefElem E;
+    int K = 1, fp32 = 0, upw = 0, haspen = 0;
+    int64_t nc = 0, nf = 0, nb = 0;
+    size_t esz = 8;
+    // input-order mesh and material on the device
+    dgt::DBuf<double> xy, lam, mu, rho;
+    dgt::DBuf<int32_t> c2v, f2c, b2c;
+    dgt::DBuf<int8_t> f2l, b2l;
+    dgt::DBuf<uint8_t> bfree;
+    // exec order
+    std::vector<int32_t> rank_h;
+    dgt::DBuf<int32_t> rank;
+    dgt::DBuf<char> geo, fld[dgt::F_COUNT], G, Gx, tmp;
+    dgt::DBuf<int32_t> ef2c, eb2c, c2f;
+    dgt::DBuf<uint8_t> ef2l, eb2l;
+    bool state_valid = false;
+    // source
+    bool has_src = false;
+    int64_t src_in = -1, src_exec = -1;
+    double sf0 = 0, st0 = 0, samp = 0;
+    std::vector<double> src_vec_h;
+    dgt::DBuf<char> src_vec;
+    // chain, schedule, plan
+    std::vector<dgt::GLoop> loops;
+    dgt_chain chain;
+    dgt_schedule *sched = nullptr;
+    std::vector<dgt::SubPlan> plan;
+    // timing of the last step
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double last_ms = 0;
+    int64_t last_launches = 0;
+    ~dgt_solver() {
+        delete sched;
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+    }
+};
+
+namespace dgt {
+
+// ------------------------------------------------------------ dispatch helpers
+
+template <class F>
+static void dispatch(const dgt_solver *s, F &&f) {
+    switch (s->K * 2 + s->fp32) {
+    case 2: f.template operator()<1, double>(); break;
+    case 3: f.template operator()<1, float>(); break;
+    case 4: f.template operator()<2, double>(); break;
+    case 5: f.template operator()<2, float>(); break;
+    case 6: f.template operator()<3, double>(); break;
+    case 7: f.template operator()<3, float>(); break;
+    case 8: f.template operator()<4, double>(); break;
+    case 9: f.template operator()<4, float>(); break;
+    default: throw Error{DGT_EINVAL, "unsupported degree"};
+    }
+}
+
+static double ricker(double t, double f0, double t0, double amp) {
+    const double a = M_PI * M_PI * f0 * f0 * (t - t0) * (t - t0);
+    return amp * (1.0 - 2.0 * a) * std::exp(-a);
+}
+
+// ------------------------------------------------------------ chain of the DG step
+
+static void build_loops(dgt_solver *s) {
+    auto &L = s->loops;
+    L.clear();
+    const double dt = s->p.dt, c3 = dt * dt * dt / 24.0;
+    auto app = [&](bool vel, int in, int out, double sc, int pen, double ps) {
+        L.push_back({(int8_t)(vel ? KV_VOL_V : KV_VOL_S), (int8_t)in, (int8_t)out, -1, sc, 0.0, 0});
+        L.push_back({(int8_t)(vel ? KV_INT_V : KV_INT_S), (int8_t)in, (int8_t)out, (int8_t)pen, sc, ps, 1});
+        L.push_back({(int8_t)(vel ? KV_EXT_V : KV_EXT_S), (int8_t)in, (int8_t)out, (int8_t)pen, sc, ps, 2});
+    };
+    auto solve = [&](int f) { L.push_back({KV_SOLVE, (int8_t)f, (int8_t)f, -1, 0.0, 0.0, 0}); };
+    const int penv = s->haspen ? F_V : -1, pens = s->haspen ? F_S : -1;
+    if (s->p.time_order == 4) {
+        // velocity half step: U = A s; X = B U; Z = dt^3/24 A X + dt D_v v; v += dt U + Z
+        app(true, F_S, F_U, 1.0, -1, 0.0);
+        solve(F_U);
+        app(false, F_U, F_X, 1.0, -1, 0.0);
+        solve(F_X);
+        app(true, F_X, F_Z, c3, penv, dt);
+        solve(F_Z);
+        L.push_back({KV_UPD_V, -1, F_V, -1, dt, 0.0, 0});
+        // stress half step: X = B v; U = A X; Z = dt^3/24 B U + dt D_s s; s += dt X + Z + source
+        app(false, F_V, F_X, 1.0, -1, 0.0);
+        solve(F_X);
+        app(true, F_X, F_U, 1.0, -1, 0.0);
+        solve(F_U);
+        app(false, F_U, F_Z, c3, pens, dt);
+        solve(F_Z);
+        L.push_back({KV_UPD_S, -1, F_S, -1, dt, 0.0, 0});
+    } else {
+        app(true, F_S, F_Z, dt, penv, dt);
+        L.push_back({KV_UPD2_V, -1, F_V, -1, dt, 0.0, 0});
+        app(false, F_V, F_Z, dt, pens, dt);
+        L.push_back({KV_UPD2_S, -1, F_S, -1, dt, 0.0, 0});
+    }
+    // the loop chain seen by the inspector: sets C, F, B; maps f2c, b2c
+    dgt::ChainDesc &c = s->chain.c;
+    c = dgt::ChainDesc();
+    c.nsets = 3;
+    c.size[0] = s->nc;
+    c.size[1] = s->nf;
+    c.size[2] = s->nb;
+    c.nmaps = 2;
+    c.maps[0].from = 1;
+    c.maps[0].to = 0;
+    c.maps[0].arity = 2;
+    c.maps[0].values = s->mesh->f2c;
+    c.maps[1].from = 2;
+    c.maps[1].to = 0;
+    c.maps[1].arity = 1;
+    c.maps[1].values = s->mesh->b2c;
+    c.nloops = (int)L.size();
+    for (size_t j = 0; j < L.size(); ++j) {
+        ChainLoop &cl = c.loops[j];
+        const GLoop &g = L[j];
+        cl.set = g.set;
+        const int mp = g.set == 0 ? -1 : g.set - 1;
+        int nd = 0;
+        auto add = [&](int m, int mode, int data) { cl.d[nd++] = dgt_desc{m, mode, data}; };
+        switch (g.kind) {
+        case KV_VOL_V: case KV_VOL_S: case KV_SOLVE:
+            add(-1, DGT_R, g.in);
+            add(-1, DGT_W, g.out);
+            break;
+        case KV_INT_V: case KV_INT_S: case KV_EXT_V: case KV_EXT_S:
+            add(mp, DGT_R, g.in);
+            add(mp, DGT_INC, g.out);
+            if (g.pen >= 0) add(mp, DGT_R, g.pen);
+            break;
+        default: {  // updates
+            const bool vel = g.kind == KV_UPD_V || g.kind == KV_UPD2_V;
+            add(-1, DGT_R, F_Z);
+            if (g.kind == KV_UPD_V) add(-1, DGT_R, F_U);
+            if (g.kind == KV_UPD_S) add(-1, DGT_R, F_X);
+            add(-1, DGT_R, vel ? F_V : F_S);
+            add(-1, DGT_W, vel ? F_V : F_S);
+        }
+        }
+        cl.ndesc = nd;
+    }
+}
+
+// ------------------------------------------------------------ exec order
+
+static void to_caller(dgt_solver *s, void *v, void *sg) {
+    dispatch(s, [&]<int K, typename T>() {
+        constexpr int NP = np_of(K);
+        k_permute_rows<T><<<blocks_for(2 * NP * s->nc, 256), 256, 0, s->st>>>(
+            (const T *)s->fld[F_V].p, (T *)v, s->rank.p, 2 * NP, s->nc, 0);
+        k_permute_rows<T><<<blocks_for(3 * NP * s->nc, 256), 256, 0, s->st>>>(
+            (const T *)s->fld[F_S].p, (T *)sg, s->rank.p, 3 * NP, s->nc, 0);
+    });
+}
+
+static void from_caller(dgt_solver *s, const void *v, const void *sg) {
+    dispatch(s, [&]<int K, typename T>() {
+        constexpr int NP = np_of(K);
+        k_permute_rows<T><<<blocks_for(2 * NP * s->nc, 256), 256, 0, s->st>>>(
+            (const T *)v, (T *)s->fld[F_V].p, s->rank.p, 2 * NP, s->nc, 1);
+        k_permute_rows<T><<<blocks_for(3 * NP * s->nc, 256), 256, 0, s->st>>>(
+            (const T *)sg, (T *)s->fld[F_S].p, s->rank.p, 3 * NP, s->nc, 1);
+    });
+}
+
+static void set_source_exec(dgt_solver *s) {
+    if (!s->has_src) return;
+    s->src_exec = s->rank_h[s->src_in];
+}
+
+static void set_exec_order(dgt_solver *s, const std::vector<int32_t> &rank) {
+    hipStream_t st = s->st;
+    const int64_t nc = s->nc, nf = s->nf, nb = s->nb;
+    const int np = s->E.np;
+    // keep any state across the renumbering
+    DBuf<char> keep;
+    if (s->state_valid) {
+        keep.alloc(5 * np * nc * s->esz);
+        to_caller(s, keep.p, keep.p + 2 * np * nc * s->esz);
+    }
+    s->rank_h = rank;
+    s->rank.upload(rank, st);
+    dispatch(s, [&]<int K, typename T>() {
+        k_geometry<T><<<blocks_for(nc, 256), 256, 0, st>>>(s->xy.p, s->c2v.p, s->lam.p, s->mu.p, s->rho.p,
+                                                          s->rank.p, nc, (T *)s->geo.p);
+    });
+    // untiled maps in exec numbering; facets ordered by their lower exec cell
+    const auto &M = *s->mesh;
+    std::vector<int64_t> ford(nf);
+    std::iota(ford.begin(), ford.end(), 0);
+    std::vector<int32_t> fkey(nf);
+    for (int64_t f = 0; f < nf; ++f) fkey[f] = std::min(rank[M.f2c[2 * f]], rank[M.f2c[2 * f + 1]]);
+    std::stable_sort(ford.begin(), ford.end(), [&](int64_t a, int64_t b) { return fkey[a] < fkey[b]; });
+    std::vector<int32_t> ef2c(2 * std::max<int64_t>(nf, 1)), c2f(3 * std::max<int64_t>(nc, 1), INT32_MIN);
+    std::vector<uint8_t> ef2l(std::max<int64_t>(nf, 1));
+    for (int64_t e = 0; e < nf; ++e) {
+        const int64_t f = ford[e];
+        const int32_t x0 = rank[M.f2c[2 * f]], x1 = rank[M.f2c[2 * f + 1]];
+        ef2c[2 * e] = x0;
+        ef2c[2 * e + 1] = x1;
+        ef2l[e] = (uint8_t)(M.f2l[2 * f] | (M.f2l[2 * f + 1] << 2));
+        c2f[(int64_t)M.f2l[2 * f] * nc + x0] = (int32_t)(2 * e);
+        c2f[(int64_t)M.f2l[2 * f + 1] * nc + x1] = (int32_t)(2 * e + 1);
+    }
+    std::vector<int64_t> bord(nb);
+    std::iota(bord.begin(), bord.end(), 0);
+    std::stable_sort(bord.begin(), bord.end(), [&](int64_t a, int64_t b) { return rank[M.b2c[a]] < rank[M.b2c[b]]; });
+    std::vector<int32_t> eb2c(std::max<int64_t>(nb, 1));
+    std::vector<uint8_t> eb2l(std::max<int64_t>(nb, 1));
+    for (int64_t e = 0; e < nb; ++e) {
+        const int64_t b = bord[e];
+        const int32_t x = rank[M.b2c[b]];
+        const bool fr = M.bside[b] >= 0 && ((s->p.free_sides >> M.bside[b]) & 1);
+        eb2c[e] = x;
+        eb2l[e] = (uint8_t)(M.b2l[b] | (fr ? 4 : 0));
+        c2f[(int64_t)M.b2l[b] * nc + x] = (int32_t)(-(e + 1));
+    }
+    for (int64_t i = 0; i < 3 * nc; ++i)
+        DGT_REQUIRE(c2f[i] != INT32_MIN, DGT_EINVAL, "a cell facet is neither interior nor exterior");
+    s->ef2c.upload(ef2c, st);
+    s->ef2l.upload(ef2l, st);
+    s->eb2c.upload(eb2c, st);
+    s->eb2l.upload(eb2l, st);
+    s->c2f.upload(c2f, st);
+    DGT_HIP(hipStreamSynchronize(st));
+    set_source_exec(s);
+    if (s->state_valid) from_caller(s, keep.p, keep.p + 2 * np * nc * s->esz);
+    DGT_HIP(hipStreamSynchronize(st));
+}
+
+// ------------------------------------------------------------ executor plan (local maps, LDS plan)
+
+static void build_plan(dgt_solver *s) {
+    hipStream_t st = s->st;
+    const dgt::Schedule &S = *s->sched->s;
+    s->plan.clear();
+    s->plan.resize(S.sub.size());
+    int dev = 0;
+    DGT_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    DGT_HIP(hipGetDeviceProperties(&prop, dev));
+    const size_t budget = std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
+    const int np = s->E.np, nfp = s->E.nfp;
+    // fields touched by each sub-chain, for persistence across sub-chains
+    std::vector<int> used(S.sub.size(), 0);
+    auto fields_of = [&](const GLoop &g) {
+        int m = 0;
+        if (g.kind == KV_SOLVE) return 0;
+        if (g.in >= 0) m |= 1 << g.in;
+        if (g.out >= 0) m |= 1 << g.out;
+        if (g.pen >= 0) m |= 1 << g.pen;
+        if (g.kind == KV_UPD_V) m |= (1 << F_V) | (1 << F_U) | (1 << F_Z);
+        if (g.kind == KV_UPD2_V) m |= (1 << F_V) | (1 << F_Z);
+        if (g.kind == KV_UPD_S) m |= (1 << F_S) | (1 << F_X) | (1 << F_Z);
+        if (g.kind == KV_UPD2_S) m |= (1 << F_S) | (1 << F_Z);
+        return m;
+    };
+    for (size_t b = 0; b < S.sub.size(); ++b)
+        for (int j = S.sub[b].first; j < S.sub[b].first + S.sub[b].n; ++j) used[b] |= fields_of(s->loops[j]);
+    for (size_t b = 0; b < S.sub.size(); ++b) {
+        const SubSched &sb = S.sub[b];
+        SubPlan &P = s->plan[b];
+        P.first = sb.first;
+        P.n = sb.n;
+        P.ntiles = sb.ntiles;
+        P.ncolors = sb.ncolors;
+        P.color_off = sb.color_off.download(st, sb.ncolors + 1);
+        // footprints renumbered into exec order, sorted per tile
+        const int64_t len = sb.foot_len[0];
+        DGT_REQUIRE(len > 0 || s->nc == 0, DGT_ESTATE, "empty cell footprint");
+        {
+            DBuf<uint64_t> keys(std::max<int64_t>(len, 1));
+            DBuf<uint32_t> vals(std::max<int64_t>(len, 1));
+            if (len) {
+                k_rank_keys<<<blocks_for(len, 256), 256, 0, st>>>(sb.foot_off[0].p, sb.foot[0].p, s->rank.p,
+                                                                  sb.ntiles, len, keys.p);
+                DGT_HIP(hipMemcpyAsync(vals.p, sb.acc[0].p, sizeof(uint32_t) * len, hipMemcpyDeviceToDevice, st));
+                sort_pairs(keys, vals, len, st);
+            }
+            P.efoot.alloc(std::max<int64_t>(len, 1));
+            if (len) k_split_keys<<<blocks_for(len, 256), 256, 0, st>>>(keys.p, len, P.efoot.p);
+            P.eacc = std::move(vals);
+        }
+        auto foff = sb.foot_off[0].download(st, sb.ntiles + 1);
+        for (int t = 0; t < sb.ntiles; ++t) P.max_foot = std::max(P.max_foot, foff[t + 1] - foff[t]);
+        DGT_REQUIRE(P.max_foot <= 0x3fff, DGT_EUNSUPPORTED, "tile footprint exceeds 16383 cells");
+        // local maps per loop
+        DBuf<int32_t> err(1);
+        DGT_HIP(hipMemsetAsync(err.p, 0, 4, st));
+        for (int j = sb.first; j < sb.first + sb.n; ++j) {
+            const int64_t n = S.loop_size[j];
+            const int kind = s->loops[j].set;
+            auto &lm = P.lmap[j - sb.first];
+            lm.alloc(std::max<int64_t>(n, 1));
+            if (n)
+                k_lmap<<<blocks_for(n, 256), 256, 0, st>>>(kind, S.it_off[j].p, S.iters[j].p, sb.ntiles, n,
+                                                           sb.foot_off[0].p, P.efoot.p, s->rank.p, s->f2c.p,
+                                                           s->f2l.p, s->b2c.p, s->b2l.p, s->bfree.p, lm.p, err.p);
+        }
+        DGT_REQUIRE(err.download(st)[0] == 0, DGT_ESTATE, "local map construction failed");
+        // largest facet phase (interior + fused exterior iterations of one tile)
+        for (int j = sb.first; j < sb.first + sb.n; ++j) {
+            const GLoop &g = s->loops[j];
+            if (g.set == 0) continue;
+            auto o1 = S.it_off[j].download(st, sb.ntiles + 1);
+            std::vector<int32_t> o2;
+            const bool fuse = g.set == 1 && j + 1 < sb.first + sb.n && s->loops[j + 1].set == 2;
+            if (fuse) o2 = S.it_off[j + 1].download(st, sb.ntiles + 1);
+            for (int t = 0; t < sb.ntiles; ++t) {
+                int cnt = o1[t + 1] - o1[t];
+                if (fuse) cnt += o2[t + 1] - o2[t];
+                P.max_fac = std::max(P.max_fac, cnt);
+            }
+            if (fuse) ++j;
+        }
+        // per-field access table of this sub-chain
+        TileArgs &A = P.args;
+        std::memset(&A, 0, sizeof(A));
+        A.nloops = sb.n;
+        for (int f = 0; f < F_COUNT; ++f) A.lds_row[f] = -1;
+        int rows = 0;
+        for (int f = 0; f < F_COUNT; ++f)
+            if ((used[b] >> f) & 1) {
+                A.lds_row[f] = rows;
+                rows += field_ncomp(f) * np;
+            }
+        A.nrows = rows + G_NROWS;
+        int others = 0;
+        for (size_t b2 = 0; b2 < S.sub.size(); ++b2)
+            if (b2 != b) others |= used[b2];
+        A.persistent_mask = (1 << F_V) | (1 << F_S) | (others & used[b]);
+        for (int i = 0; i < sb.n; ++i) {
+            const GLoop &g = s->loops[sb.first + i];
+            TLoop &t = A.loops[i];
+            t.kind = g.kind;
+            t.in = g.in;
+            t.out = g.out;
+            t.pen = g.pen;
+            t.partner = -1;
+            if ((g.kind == KV_INT_V || g.kind == KV_INT_S) && i + 1 < sb.n) {
+                const GLoop &h = s->loops[sb.first + i + 1];
+                if (h.set == 2 && h.in == g.in && h.out == g.out && h.pen == g.pen) t.partner = (int8_t)(i + 1);
+            }
+            t.scale_d = g.scale;
+            t.pscale_d = g.pscale;
+            t.scale_f = (float)g.scale;
+            t.pscale_f = (float)g.pscale;
+            A.it_off[i] = S.it_off[sb.first + i].p;
+            A.lmap[i] = P.lmap[i].p;
+            const uint32_t bit = 1u << i;
+            auto acc = [&](int f, int mode) {  // mode 1 R, 2 W, 3 RW
+                if (f < 0) return;
+                A.loops_mask[f] |= bit;
+                if (mode & 1) A.rfirst_mask[f] |= bit;
+                if (mode & 2) A.writes_mask[f] |= bit;
+            };
+            switch (g.kind) {
+            case KV_VOL_V: case KV_VOL_S: acc(g.in, 1); acc(g.out, 2); break;
+            case KV_INT_V: case KV_INT_S: case KV_EXT_V: case KV_EXT_S: acc(g.in, 1); acc(g.out, 3); acc(g.pen, 1); break;
+            case KV_UPD_V: acc(F_V, 3); acc(F_U, 1); acc(F_Z, 1); break;
+            case KV_UPD2_V: acc(F_V, 3); acc(F_Z, 1); break;
+            case KV_UPD_S: acc(F_S, 3); acc(F_X, 1); acc(F_Z, 1); break;
+            case KV_UPD2_S: acc(F_S, 3); acc(F_Z, 1); break;
+            default: break;
+            }
+        }
+        A.foot_off = sb.foot_off[0].p;
+        A.foot = P.efoot.p;
+        A.facc = P.eacc.p;
+        A.tiles = sb.tiles_by_color.p;
+        for (int f = 0; f < F_COUNT; ++f) A.F[f] = s->fld[f].p;
+        A.geo = s->geo.p;
+        A.nc = s->nc;
+        A.stride = std::max(P.max_foot, 1);
+        A.fac_stride = std::max(P.max_fac, 1);
+        A.src_vec = s->src_vec.p;
+        P.lds_bytes = (size_t)A.nrows * A.stride * s->esz + (size_t)2 * 3 * nfp * A.fac_stride * s->esz +
+                      (size_t)3 * A.stride * 4 + (size_t)A.stride * 2 + 16;
+        DGT_REQUIRE(P.lds_bytes <= budget, DGT_EUNSUPPORTED,
+                    "tile footprint of " + std::to_string(P.max_foot) + " cells needs " +
+                        std::to_string(P.lds_bytes) + " B of LDS (budget " + std::to_string(budget) +
+                        "): use a smaller tile_size or split the chain");
+    }
+    DGT_HIP(hipStreamSynchronize(st));
+}
+
+// ------------------------------------------------------------ steps
+
+template <int K, typename T>
+static void apply_untiled(dgt_solver *s, bool vel, int in, int out, double scale, int pen, double pscale,
+                          int64_t &launches) {
+    hipStream_t st = s->st;
+    const int64_t nc = s->nc, nf = s->nf, nb = s->nb;
+    constexpr int NP = np_of(K), NFP = K + 1;
+    const T *fin = (const T *)s->fld[in].p;
+    T *fout = (T *)s->fld[out].p;
+    const T *fpen = pen >= 0 ? (const T *)s->fld[pen].p : nullptr;
+    const T *geo = (const T *)s->geo.p;
+    T *G = (T *)s->G.p, *Gx = (T *)s->Gx.p;
+    const T sc = (T)scale, ps = (T)pscale;
+    if (vel) k_vol<K, T, true><<<blocks_for(nc * NP, 256), 256, 0, st>>>(fin, fout, geo, nc, sc);
+    else k_vol<K, T, false><<<blocks_for(nc * NP, 256), 256, 0, st>>>(fin, fout, geo, nc, sc);
+    ++launches;
+    auto fi = [&]<bool VEL, bool UPW, bool PEN>() {
+        if (nf) {
+            k_flux_int<K, T, VEL, UPW, PEN><<<blocks_for(nf * NFP, 256), 256, 0, st>>>(
+                fin, fpen, s->ef2c.p, s->ef2l.p, geo, nc, nf, sc, ps, G);
+            ++launches;
+        }
+        if (nb) {
+            k_flux_ext<K, T, VEL, UPW, PEN><<<blocks_for(nb * NFP, 256), 256, 0, st>>>(
+                fin, fpen, s->eb2c.p, s->eb2l.p, geo, nc, nb, sc, ps, Gx);
+            ++launches;
+        }
+    };
+    const bool pn = fpen != nullptr;
+    if (vel) {
+        if (s->upw) { if (pn) fi.template operator()<true, true, true>(); else fi.template operator()<true, true, false>(); }
+        else { if (pn) fi.template operator()<true, false, true>(); else fi.template operator()<true, false, false>(); }
+        k_lift<K, T, true><<<blocks_for(nc * NP, 256), 256, 0, st>>>(fout, s->c2f.p, G, Gx, nc, nf, nb);
+    } else {
+        if (s->upw) { if (pn) fi.template operator()<false, true, true>(); else fi.template operator()<false, true, false>(); }
+        else { if (pn) fi.template operator()<false, false, true>(); else fi.template operator()<false, false, false>(); }
+        k_lift<K, T, false><<<blocks_for(nc * NP, 256), 256, 0, st>>>(fout, s->c2f.p, G, Gx, nc, nf, nb);
+    }
+    ++launches;
+}
+
+template <int K, typename T>
+static void step_untiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launches) {
+    hipStream_t st = s->st;
+    constexpr int NP = np_of(K);
+    const int64_t nc = s->nc;
+    const double dt = s->p.dt, c3 = dt * dt * dt / 24.0;
+    const int penv = s->haspen ? F_V : -1, pens = s->haspen ? F_S : -1;
+    T *V = (T *)s->fld[F_V].p, *Sg = (T *)s->fld[F_S].p, *U = (T *)s->fld[F_U].p, *X = (T *)s->fld[F_X].p,
+      *Z = (T *)s->fld[F_Z].p;
+    for (int64_t n = 0; n < nsteps; ++n) {
+        const double th = t0 + ((double)n + 0.5) * dt;
+        const double amp = s->has_src ? dt * ricker(th, s->sf0, s->st0, s->samp) : 0.0;
+        const int64_t src = s->has_src ? s->src_exec : -1;
+        if (s->p.time_order == 4) {
+            apply_untiled<K, T>(s, true, F_S, F_U, 1.0, -1, 0.0, launches);
+            apply_untiled<K, T>(s, false, F_U, F_X, 1.0, -1, 0.0, launches);
+            apply_untiled<K, T>(s, true, F_X, F_Z, c3, penv, dt, launches);
+            k_upd_v<T><<<blocks_for(2 * NP * nc, 256), 256, 0, st>>>(V, U, Z, 2 * NP * nc, (T)dt);
+            apply_untiled<K, T>(s, false, F_V, F_X, 1.0, -1, 0.0, launches);
+            apply_untiled<K, T>(s, true, F_X, F_U, 1.0, -1, 0.0, launches);
+            apply_untiled<K, T>(s, false, F_U, F_Z, c3, pens, dt, launches);
+            k_upd_s<K, T><<<blocks_for(3 * NP * nc, 256), 256, 0, st>>>(Sg, X, Z, nc, (T)dt, src, (T)amp,
+                                                                       (const T *)s->src_vec.p);
+        } else {
+            apply_untiled<K, T>(s, true, F_S, F_Z, dt, penv, dt, launches);
+            k_upd_v<T><<<blocks_for(2 * NP * nc, 256), 256, 0, st>>>(V, nullptr, Z, 2 * NP * nc, (T)dt);
+            apply_untiled<K, T>(s, false, F_V, F_Z, dt, pens, dt, launches);
+            k_upd_s<K, T><<<blocks_for(3 * NP * nc, 256), 256, 0, st>>>(Sg, nullptr, Z, nc, (T)dt, src, (T)amp,
+                                                                       (const T *)s->src_vec.p);
+        }
+        launches += 2;
+    }
+}
+
+template <int K, typename T>
+static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launches) {
+    hipStream_t st = s->st;
+    const double dt = s->p.dt;
+    for (auto &P : s->plan) {
+        auto kern = s->upw ? (s->haspen ? k_tile<K, T, true, true> : k_tile<K, T, true, false>)
+                           : (s->haspen ? k_tile<K, T, false, true> : k_tile<K, T, false, false>);
+        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
+    }
+    for (int64_t n = 0; n < nsteps; ++n) {
+        const double th = t0 + ((double)n + 0.5) * dt;
+        for (auto &P : s->plan) {
+            TileArgs A = P.args;
+            A.dt = dt;
+            A.src_cell = s->has_src ? (int32_t)s->src_exec : -1;
+            A.src_amp = s->has_src ? dt * ricker(th, s->sf0, s->st0, s->samp) : 0.0;
+            for (int c = 0; c < P.ncolors; ++c) {
+                const int nt = P.color_off[c + 1] - P.color_off[c];
+                if (nt == 0) continue;
+                A.tile_base = P.color_off[c];
+                if (s->upw) {
+                    if (s->haspen) k_tile<K, T, true, true><<<nt, 256, P.lds_bytes, st>>>(A);
+                    else k_tile<K, T, true, false><<<nt, 256, P.lds_bytes, st>>>(A);
+                } else {
+                    if (s->haspen) k_tile<K, T, false, true><<<nt, 256, P.lds_bytes, st>>>(A);
+                    else k_tile<K, T, false, false><<<nt, 256, P.lds_bytes, st>>>(A);
+                }
+                ++launches;
+            }
+        }
+    }
+}
+
+}  // namespace dgt
+
+using namespace dgt;
+
+extern "C" {
+
+dgt_status dgt_mesh_create(int64_t nv, const double *xy, int64_t nc, const int32_t *c2v, int32_t periodic,
+                           dgt_mesh **out) {
+    return guard([&] {
+        DGT_REQUIRE(out, DGT_EINVAL, "out is NULL");
+        *out = nullptr;
+        auto m = std::make_unique<dgt_mesh>();
+        m->m = build_mesh(nv, xy, nc, c2v, periodic);
+        *out = m.release();
+    });
+}
+
+dgt_status dgt_mesh_counts(const dgt_mesh *m, int64_t *nc, int64_t *nf, int64_t *nb) {
+    return guard([&] {
+        DGT_REQUIRE(m, DGT_EINVAL, "mesh is NULL");
+        if (nc) *nc = m->m.nc;
+        if (nf) *nf = m->m.nf;
+        if (nb) *nb = m->m.nb;
+    });
+}
+
+dgt_status dgt_mesh_maps(const dgt_mesh *m, int32_t *f2c, int8_t *f2l, int32_t *b2c, int8_t *b2l, int8_t *bside) {
+    return guard([&] {
+        DGT_REQUIRE(m, DGT_EINVAL, "mesh is NULL");
+        const Mesh &M = m->m;
+        if (f2c) std::copy(M.f2c.begin(), M.f2c.end(), f2c);
+        if (f2l) std::copy(M.f2l.begin(), M.f2l.end(), f2l);
+        if (b2c) std::copy(M.b2c.begin(), M.b2c.end(), b2c);
+        if (b2l) std::copy(M.b2l.begin(), M.b2l.end(), b2l);
+        if (bside) std::copy(M.bside.begin(), M.bside.end(), bside);
+    });
+}
+
+void dgt_mesh_destroy(dgt_mesh *m) { delete m; }
+
+dgt_status dgt_solver_create(const dgt_mesh *m, const double *lam, const double *mu, const double *rho,
+                             const dgt_solver_params *p, void *stream, dgt_solver **out) {
+    return guard([&] {
+        DGT_REQUIRE(m && p && out, DGT_EINVAL, "NULL argument");
+        *out = nullptr;
+        DGT_REQUIRE(p->degree >= 1 && p->degree <= 4, DGT_EINVAL, "degree must be 1..4");
+        DGT_REQUIRE(p->flux == 0 || p->flux == 1, DGT_EINVAL, "flux must be 0 or 1");
+        DGT_REQUIRE(p->time_order == 2 || p->time_order == 4, DGT_EINVAL, "time_order must be 2 or 4");
+        DGT_REQUIRE(p->precision == 0 || p->precision == 1, DGT_EINVAL, "precision must be 0 or 1");
+        DGT_REQUIRE(p->dt > 0 && std::isfinite(p->dt), DGT_EINVAL, "dt must be positive");
+        const Mesh &M = m->m;
+        DGT_REQUIRE(M.nc > 0, DGT_EINVAL, "empty mesh");
+        DGT_REQUIRE(lam && mu && rho, DGT_EINVAL, "material is NULL");
+        for (int64_t c = 0; c < M.nc; ++c)
+            DGT_REQUIRE(lam[c] > 0 && mu[c] > 0 && rho[c] > 0, DGT_EINVAL, "material must be positive");
+        auto s = std::make_unique<dgt_solver>();
+        s->mesh = &M;
+        s->p = *p;
+        s->st = (hipStream_t)stream;
+        s->K = p->degree;
+        s->fp32 = p->precision;
+        s->esz = p->precision ? 4 : 8;
+        s->upw = p->flux == 1;
+        s->nc = M.nc;
+        s->nf = M.nf;
+        s->nb = M.nb;
+        s->haspen = s->upw;
+        for (int64_t b = 0; b < M.nb; ++b)
+            if (!(M.bside[b] >= 0 && ((p->free_sides >> M.bside[b]) & 1))) s->haspen = 1;
+        s->E = make_refelem(p->degree);
+        hipStream_t st = s->st;
+        dispatch(s.get(), [&]<int K, typename T>() { upload_ref<K, T>(s->E, st); });
+        s->xy.upload(M.xy, st);
+        s->c2v.upload(M.c2v, st);
+        s->f2c.upload(M.f2c.empty() ? std::vector<int32_t>{0, 0} : M.f2c, st);
+        s->f2l.upload(M.f2l.empty() ? std::vector<int8_t>{0, 0} : M.f2l, st);
+        s->b2c.upload(M.b2c.empty() ? std::vector<int32_t>{0} : M.b2c, st);
+        s->b2l.upload(M.b2l.empty() ? std::vector<int8_t>{0} : M.b2l, st);
+        std::vector<uint8_t> bfree(std::max<int64_t>(M.nb, 1), 0);
+        for (int64_t b = 0; b < M.nb; ++b) bfree[b] = M.bside[b] >= 0 && ((p->free_sides >> M.bside[b]) & 1);
+        s->bfree.upload(bfree, st);
+        s->lam.upload(lam, M.nc, st);
+        s->mu.upload(mu, M.nc, st);
+        s->rho.upload(rho, M.nc, st);
+        const int np = s->E.np, nfp = s->E.nfp;
+        s->geo.alloc((size_t)(G_NROWS + 1) * M.nc * s->esz);
+        for (int f = 0; f < F_COUNT; ++f) {
+            s->fld[f].alloc((size_t)field_ncomp(f) * np * M.nc * s->esz);
+            DGT_HIP(hipMemsetAsync(s->fld[f].p, 0, s->fld[f].n, st));
+        }
+        s->G.alloc((size_t)2 * 3 * nfp * std::max<int64_t>(M.nf, 1) * s->esz);
+        s->Gx.alloc((size_t)3 * nfp * std::max<int64_t>(M.nb, 1) * s->esz);
+        s->src_vec.alloc((size_t)np * s->esz);
+        DGT_HIP(hipMemsetAsync(s->src_vec.p, 0, s->src_vec.n, st));
+        std::vector<int32_t> id(M.nc);
+        std::iota(id.begin(), id.end(), 0);
+        set_exec_order(s.get(), id);
+        build_loops(s.get());
+        DGT_HIP(hipEventCreate(&s->ev0));
+        DGT_HIP(hipEventCreate(&s->ev1));
+        *out = s.release();
+    });
+}
+
+dgt_status dgt_solver_inspect(dgt_solver *s, const dgt_inspect_params *p) {
+    return guard([&] {
+        DGT_REQUIRE(s && p, DGT_EINVAL, "NULL argument");
+        DGT_REQUIRE(p->partition == 0 || p->partition == 1, DGT_EINVAL, "partition must be 0 or 1");
+        DGT_REQUIRE(p->nsplits >= 0 && (p->nsplits == 0 || p->splits), DGT_EINVAL, "bad splits");
+        hipStream_t st = s->st;
+        delete s->sched;
+        s->sched = nullptr;
+        s->plan.clear();
+        DBuf<double> cxy(2 * s->nc);
+        k_centroids<<<blocks_for(s->nc, 256), 256, 0, st>>>(s->xy.p, s->c2v.p, s->nc, cxy.p);
+        auto sch = std::make_unique<dgt_schedule>();
+        sch->chain_copy = s->chain.c;
+        sch->chain = &sch->chain_copy;
+        Inspector insp(sch->chain_copy, st);
+        std::vector<int32_t> splits(p->splits, p->splits + p->nsplits);
+        sch->s = insp.run(p->tile_size, p->partition, nullptr, cxy.p, p->max_conflict_rounds, splits);
+        s->sched = sch.release();
+        // executor layout follows the seed order of the schedule
+        auto rank = s->sched->s->seed_rank.download(st, s->nc);
+        set_exec_order(s, rank);
+        build_plan(s);
+    });
+}
+
+dgt_status dgt_solver_schedule(const dgt_solver *s, const dgt_schedule **out) {
+    return guard([&] {
+        DGT_REQUIRE(s && out, DGT_EINVAL, "NULL argument");
+        *out = s->sched;
+    });
+}
+
+dgt_status dgt_set_source(dgt_solver *s, double x, double y, double f0, double t0, double amp) {
+    return guard([&] {
+        DGT_REQUIRE(s, DGT_EINVAL, "solver is NULL");
+        const Mesh &M = *s->mesh;
+        int64_t cell = -1;
+        double rs = 0, ss = 0;
+        for (int64_t c = 0; c < M.nc && cell < 0; ++c) {
+            const double *p0 = &M.xy[2 * M.c2v[3 * c]], *p1 = &M.xy[2 * M.c2v[3 * c + 1]],
+                         *p2 = &M.xy[2 * M.c2v[3 * c + 2]];
+            const double xr = p1[0] - p0[0], xs = p2[0] - p0[0], yr = p1[1] - p0[1], ys = p2[1] - p0[1];
+            const double det = xr * ys - xs * yr;
+            const double r = (ys * (x - p0[0]) - xs * (y - p0[1])) / det;
+            const double sv = (-yr * (x - p0[0]) + xr * (y - p0[1])) / det;
+            if (r >= -1e-12 && sv >= -1e-12 && 1.0 - r - sv >= -1e-12) {
+                cell = c;
+                rs = r;
+                ss = sv;
+            }
+        }
+        DGT_REQUIRE(cell >= 0, DGT_EINVAL, "source outside the mesh");
+        const int np = s->E.np;
+        std::vector<double> phi(np), sv(np);
+        s->E.phi(rs, ss, phi.data());
+        const double *p0 = &M.xy[2 * M.c2v[3 * cell]], *p1 = &M.xy[2 * M.c2v[3 * cell + 1]],
+                     *p2 = &M.xy[2 * M.c2v[3 * cell + 2]];
+        const double det = (p1[0] - p0[0]) * (p2[1] - p0[1]) - (p2[0] - p0[0]) * (p1[1] - p0[1]);
+        for (int i = 0; i < np; ++i) {
+            double a = 0;
+            for (int j = 0; j < np; ++j) a += s->E.Minv[i * np + j] * phi[j];
+            sv[i] = a / det;
+        }
+        s->src_vec_h = sv;
+        if (s->fp32) {
+            std::vector<float> f(sv.begin(), sv.end());
+            DGT_HIP(hipMemcpyAsync(s->src_vec.p, f.data(), 4 * np, hipMemcpyHostToDevice, s->st));
+        } else {
+            DGT_HIP(hipMemcpyAsync(s->src_vec.p, sv.data(), 8 * np, hipMemcpyHostToDevice, s->st));
+        }
+        DGT_HIP(hipStreamSynchronize(s->st));
+        s->has_src = true;
+        s->src_in = cell;
+        s->sf0 = f0;
+        s->st0 = t0;
+        s->samp = amp;
+        set_source_exec(s);
+    });
+}
+
+dgt_status dgt_state_upload(dgt_solver *s, const void *v, const void *sig) {
+    return guard([&] {
+        DGT_REQUIRE(s && v && sig, DGT_EINVAL, "NULL argument");
+        from_caller(s, v, sig);
+        s->state_valid = true;
+    });
+}
+
+dgt_status dgt_state_download(dgt_solver *s, void *v, void *sig) {
+    return guard([&] {
+        DGT_REQUIRE(s && v && sig, DGT_EINVAL, "NULL argument");
+        DGT_REQUIRE(s->state_valid, DGT_ESTATE, "no state uploaded");
+        to_caller(s, v, sig);
+    });
+}
+
+dgt_status dgt_step(dgt_solver *s, int64_t nsteps, int32_t mode, double t0) {
+    return guard([&] {
+        DGT_REQUIRE(s && nsteps >= 0, DGT_EINVAL, "bad arguments");
+        DGT_REQUIRE(s->state_valid, DGT_ESTATE, "state not uploaded");
+        DGT_REQUIRE(mode == 0 || mode == 1, DGT_EINVAL, "mode must be 0 or 1");
+        DGT_REQUIRE(mode == 0 || !s->plan.empty(), DGT_ESTATE, "tiled mode needs dgt_solver_inspect");
+        int64_t launches = 0;
+        DGT_HIP(hipEventRecord(s->ev0, s->st));
+        dispatch(s, [&]<int K, typename T>() {
+            if (mode == 0) step_untiled<K, T>(s, nsteps, t0, launches);
+            else step_tiled<K, T>(s, nsteps, t0, launches);
+        });
+        DGT_HIP(hipGetLastError());
+        DGT_HIP(hipEventRecord(s->ev1, s->st));
+        s->last_launches = launches;
+        s->last_ms = -1.0;
+    });
+}
+
+dgt_status dgt_last_step_timing(const dgt_solver *s, double *total_ms, double *kernel_ms, int64_t *launches) {
+    return guard([&] {
+        DGT_REQUIRE(s, DGT_EINVAL, "solver is NULL");
+        DGT_HIP(hipEventSynchronize(s->ev1));
+        float ms = 0;
+        DGT_HIP(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+        if (total_ms) *total_ms = ms;
+        if (kernel_ms) *kernel_ms = ms;
+        if (launches) *launches = s->last_launches;
+    });
+}
+
+dgt_status dgt_energy(dgt_solver *s, const void *v, const void *sig_new, const void *sig_old, double *out) {
+    return guard([&] {
+        DGT_REQUIRE(s && v && sig_new && sig_old && out, DGT_EINVAL, "NULL argument");
+        const int64_t nc = s->nc;
+        const int64_t nblk = (nc + 255) / 256;
+        DBuf<double> part(nblk), res(1);
+        dispatch(s, [&]<int K, typename T>() {
+            k_energy<K, T><<<nblk, 256, 0, s->st>>>((const T *)v, (const T *)sig_new, (const T *)sig_old,
+                                                  (const T *)s->geo.p, s->rank.p, nc, part.p);
+        });
+        k_sum_partials<<<1, 256, 0, s->st>>>(part.p, nblk, res.p);
+        *out = res.download(s->st)[0];
+    });
+}
+
+dgt_status dgt_solver_info(const dgt_solver *s, int64_t *np, int64_t *bytes_per_step, int64_t *lds_bytes) {
+    return guard([&] {
+        DGT_REQUIRE(s, DGT_EINVAL, "solver is NULL");
+        if (np) *np = s->E.np;
+        // state read and written once, per-cell invariants (9 geometry rows) read once
+        if (bytes_per_step) *bytes_per_step = (int64_t)(2 * 5 * s->E.np + G_NROWS) * (int64_t)s->esz * s->nc;
+        size_t mx = 0;
+        for (auto &P : s->plan) mx = std::max(mx, P.lds_bytes);
+        if (lds_bytes) *lds_bytes = (int64_t)mx;
+    });
+}
+
+void dgt_solver_destroy(dgt_solver *s) { delete s; }
+
+}  // extern "C"

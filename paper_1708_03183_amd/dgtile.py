@@ -1,0 +1,345 @@
+"""Python binding of libdgtile (ctypes; argument marshalling only).
+
+Every step of the hot path runs in the HIP kernels of ``libdgtile.so``.  PyTorch
+is used only for device memory (state tensors) and the current HIP stream.  The
+names mirror the C ABI in ``include/dgtile.h``.  Loading fails loudly when the
+library is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdgtile.so")
+
+DGT_OK, DGT_EINVAL, DGT_ENOMEM, DGT_EHIP, DGT_ESTATE, DGT_EUNSUPPORTED = range(6)
+R, W, INC = 0, 1, 2
+
+
+class DgtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libdgtile status {status}: {msg}")
+        self.status = status
+
+
+class _Desc(C.Structure):
+    _fields_ = [("map", C.c_int32), ("mode", C.c_int32), ("data", C.c_int32)]
+
+
+class _InspectParams(C.Structure):
+    _fields_ = [("tile_size", C.c_int64), ("partition", C.c_int32), ("seed_xy", C.c_void_p),
+                ("max_conflict_rounds", C.c_int32), ("splits", C.c_void_p), ("nsplits", C.c_int32)]
+
+
+class _SolverParams(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("flux", C.c_int32), ("time_order", C.c_int32),
+                ("precision", C.c_int32), ("free_sides", C.c_int32), ("dt", C.c_double)]
+
+
+_lib = None
+_p = C.c_void_p
+_i32 = C.POINTER(C.c_int32)
+_i64 = C.POINTER(C.c_int64)
+
+# symbol -> argtypes (every function returns dgt_status unless listed in _VOID)
+_SIGS = {
+    "dgt_chain_create": [C.POINTER(_p)],
+    "dgt_chain_set": [_p, C.c_int64, _i32],
+    "dgt_chain_map": [_p, C.c_int32, C.c_int32, C.c_int32, _p, _i32],
+    "dgt_chain_loop": [_p, C.c_int32, C.c_int32, C.POINTER(_Desc), _i32],
+    "dgt_chain_destroy": [_p],
+    "dgt_inspect": [_p, C.POINTER(_InspectParams), _p, C.POINTER(_p)],
+    "dgt_schedule_nsub": [_p, _i32],
+    "dgt_schedule_sub_info": [_p, C.c_int32, _i32, _i32, _i32, _i32, _i32],
+    "dgt_schedule_colors": [_p, C.c_int32, _p],
+    "dgt_schedule_sigma": [_p, C.c_int32, _p],
+    "dgt_schedule_iters": [_p, C.c_int32, _p, _p],
+    "dgt_schedule_footprint": [_p, C.c_int32, C.c_int32, _i64, _p, _p, _p],
+    "dgt_schedule_tiles_by_color": [_p, C.c_int32, _p, _p],
+    "dgt_schedule_summary_json": [_p, C.c_char_p, C.c_size_t],
+    "dgt_schedule_destroy": [_p],
+    "dgt_mesh_create": [C.c_int64, _p, C.c_int64, _p, C.c_int32, C.POINTER(_p)],
+    "dgt_mesh_counts": [_p, _i64, _i64, _i64],
+    "dgt_mesh_maps": [_p, _p, _p, _p, _p, _p],
+    "dgt_mesh_destroy": [_p],
+    "dgt_solver_create": [_p, _p, _p, _p, C.POINTER(_SolverParams), _p, C.POINTER(_p)],
+    "dgt_solver_inspect": [_p, C.POINTER(_InspectParams)],
+    "dgt_solver_schedule": [_p, C.POINTER(_p)],
+    "dgt_set_source": [_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double],
+    "dgt_state_upload": [_p, _p, _p],
+    "dgt_state_download": [_p, _p, _p],
+    "dgt_step": [_p, C.c_int64, C.c_int32, C.c_double],
+    "dgt_energy": [_p, _p, _p, _p, C.POINTER(C.c_double)],
+    "dgt_last_step_timing": [_p, C.POINTER(C.c_double), C.POINTER(C.c_double), _i64],
+    "dgt_solver_info": [_p, _i64, _i64, _i64],
+    "dgt_solver_destroy": [_p],
+    "dgt_last_error": [],
+    "dgt_version": [],
+}
+_VOID = {"dgt_chain_destroy", "dgt_schedule_destroy", "dgt_mesh_destroy", "dgt_solver_destroy"}
+
+
+def exported_symbols() -> list[str]:
+    return sorted(_SIGS)
+
+
+def lib():
+    """Load libdgtile.so (built by ``build()``); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1708_03183_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            if name in _VOID:
+                f.restype = None
+            elif name == "dgt_last_error":
+                f.restype = C.c_char_p
+            else:
+                f.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != DGT_OK:
+        raise DgtError(st, lib().dgt_last_error().decode())
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _inspect_params(tile_size, partition, seed_xy, max_rounds, splits):
+    sp = np.ascontiguousarray(np.array(list(splits), np.int32))
+    xy = None if seed_xy is None else np.ascontiguousarray(seed_xy, np.float64)
+    p = _InspectParams(int(tile_size), int(partition), _np_ptr(xy), int(max_rounds),
+                       _np_ptr(sp) if len(sp) else None, len(sp))
+    return p, (sp, xy)
+
+
+# --------------------------------------------------------------- tier 1
+class Chain:
+    """Generic loop chain (sets, maps, loops with descriptors)."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        _check(lib().dgt_chain_create(C.byref(h)))
+        self.h = h
+        self.sizes = []
+        self.loop_sets = []
+
+    def set(self, size: int) -> int:
+        out = C.c_int32()
+        _check(lib().dgt_chain_set(self.h, int(size), C.byref(out)))
+        self.sizes.append(int(size))
+        return out.value
+
+    def map(self, frm: int, to: int, arity: int, values) -> int:
+        v = np.ascontiguousarray(values, np.int32).ravel()
+        out = C.c_int32()
+        _check(lib().dgt_chain_map(self.h, frm, to, arity, _np_ptr(v), C.byref(out)))
+        return out.value
+
+    def loop(self, set_id: int, descs) -> int:
+        arr = (_Desc * max(len(descs), 1))(*[_Desc(d[0], d[1], d[2] if len(d) > 2 else -1) for d in descs])
+        out = C.c_int32()
+        _check(lib().dgt_chain_loop(self.h, set_id, len(descs), arr, C.byref(out)))
+        self.loop_sets.append(set_id)
+        return out.value
+
+    def inspect(self, tile_size, partition=0, seed_xy=None, max_rounds=64, splits=(), stream=None) -> "Schedule":
+        p, keep = _inspect_params(tile_size, partition, seed_xy, max_rounds, splits)
+        h = C.c_void_p()
+        _check(lib().dgt_inspect(self.h, C.byref(p), _stream_handle(stream), C.byref(h)))
+        return Schedule(h, owner=True, loop_sizes=[self.sizes[s] for s in self.loop_sets])
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.dgt_chain_destroy(self.h)
+            self.h = None
+
+
+class Schedule:
+    """Read-back view of an inspector schedule (host copies)."""
+
+    def __init__(self, h, owner: bool, loop_sizes):
+        self.h, self.owner, self.loop_sizes = h, owner, loop_sizes
+
+    @property
+    def nsub(self) -> int:
+        n = C.c_int32()
+        _check(lib().dgt_schedule_nsub(self.h, C.byref(n)))
+        return n.value
+
+    def sub_info(self, sub: int) -> dict:
+        v = [C.c_int32() for _ in range(5)]
+        _check(lib().dgt_schedule_sub_info(self.h, sub, *[C.byref(x) for x in v]))
+        return dict(first=v[0].value, nloops=v[1].value, ntiles=v[2].value, ncolors=v[3].value, rounds=v[4].value)
+
+    def colors(self, sub: int) -> np.ndarray:
+        out = np.zeros(self.sub_info(sub)["ntiles"], np.int32)
+        _check(lib().dgt_schedule_colors(self.h, sub, _np_ptr(out)))
+        return out
+
+    def sigma(self, loop: int) -> np.ndarray:
+        out = np.zeros(self.loop_sizes[loop], np.int32)
+        _check(lib().dgt_schedule_sigma(self.h, loop, _np_ptr(out)))
+        return out
+
+    def iters(self, loop: int, sub: int):
+        off = np.zeros(self.sub_info(sub)["ntiles"] + 1, np.int32)
+        it = np.zeros(self.loop_sizes[loop], np.int32)
+        _check(lib().dgt_schedule_iters(self.h, loop, _np_ptr(off), _np_ptr(it)))
+        return off, it
+
+    def footprint(self, sub: int, set_id: int):
+        n = C.c_int64()
+        _check(lib().dgt_schedule_footprint(self.h, sub, set_id, C.byref(n), None, None, None))
+        off = np.zeros(self.sub_info(sub)["ntiles"] + 1, np.int32)
+        el = np.zeros(n.value, np.int32)
+        acc = np.zeros(n.value, np.uint32)
+        _check(lib().dgt_schedule_footprint(self.h, sub, set_id, C.byref(n), _np_ptr(off), _np_ptr(el), _np_ptr(acc)))
+        return off, el, acc
+
+    def tiles_by_color(self, sub: int):
+        info = self.sub_info(sub)
+        coff = np.zeros(info["ncolors"] + 1, np.int32)
+        tl = np.zeros(info["ntiles"], np.int32)
+        _check(lib().dgt_schedule_tiles_by_color(self.h, sub, _np_ptr(coff), _np_ptr(tl)))
+        return coff, tl
+
+    def summary(self) -> str:
+        buf = C.create_string_buffer(1 << 16)
+        _check(lib().dgt_schedule_summary_json(self.h, buf, len(buf)))
+        return buf.value.decode()
+
+    def __del__(self):
+        if getattr(self, "owner", False) and getattr(self, "h", None) and _lib is not None:
+            _lib.dgt_schedule_destroy(self.h)
+            self.h = None
+
+
+# --------------------------------------------------------------- tier 2
+class Mesh:
+    def __init__(self, xy, c2v, periodic: int = 0):
+        self.xy = np.ascontiguousarray(xy, np.float64)
+        self.c2v = np.ascontiguousarray(c2v, np.int32)
+        h = C.c_void_p()
+        _check(lib().dgt_mesh_create(self.xy.shape[0], _np_ptr(self.xy), self.c2v.shape[0], _np_ptr(self.c2v),
+                                     int(periodic), C.byref(h)))
+        self.h = h
+        nc, nf, nb = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().dgt_mesh_counts(h, C.byref(nc), C.byref(nf), C.byref(nb)))
+        self.nc, self.nf, self.nb = nc.value, nf.value, nb.value
+
+    @classmethod
+    def from_mesh(cls, m):
+        return cls(m.xy, m.c2v, m.periodic)
+
+    def maps(self) -> dict:
+        f2c = np.zeros(2 * self.nf, np.int32)
+        f2l = np.zeros(2 * self.nf, np.int8)
+        b2c = np.zeros(self.nb, np.int32)
+        b2l = np.zeros(self.nb, np.int8)
+        bs = np.zeros(self.nb, np.int8)
+        _check(lib().dgt_mesh_maps(self.h, *[_np_ptr(a) for a in (f2c, f2l, b2c, b2l, bs)]))
+        return dict(f2c=f2c.reshape(-1, 2), f2l=f2l.reshape(-1, 2), b2c=b2c, b2l=b2l, bside=bs)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.dgt_mesh_destroy(self.h)
+            self.h = None
+
+
+class Solver:
+    """DG velocity-stress solver; state tensors v[2,Np,nc], s[3,Np,nc] on the GPU."""
+
+    def __init__(self, mesh: Mesh, lam, mu, rho, degree=2, flux=1, time_order=4, precision=0,
+                 free_sides=0xF, dt=None, stream=None):
+        if dt is None:
+            raise ValueError("dt is required")
+        self.mesh = mesh
+        self.degree, self.precision, self._time_order = degree, precision, time_order
+        self.np = (degree + 1) * (degree + 2) // 2
+        self._mat = [np.ascontiguousarray(a, np.float64) for a in (lam, mu, rho)]
+        prm = _SolverParams(degree, flux, time_order, precision, free_sides, float(dt))
+        self.dt = float(dt)
+        h = C.c_void_p()
+        _check(lib().dgt_solver_create(mesh.h, *[_np_ptr(a) for a in self._mat], C.byref(prm),
+                                       _stream_handle(stream), C.byref(h)))
+        self.h = h
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.float32 if self.precision == 1 else torch.float64
+
+    def zeros(self, device="cuda"):
+        import torch
+        return (torch.zeros((2, self.np, self.mesh.nc), dtype=self.dtype, device=device),
+                torch.zeros((3, self.np, self.mesh.nc), dtype=self.dtype, device=device))
+
+    def inspect(self, tile_size, partition=1, max_rounds=64, splits=()):
+        p, keep = _inspect_params(tile_size, partition, None, max_rounds, splits)
+        _check(lib().dgt_solver_inspect(self.h, C.byref(p)))
+
+    def schedule(self) -> Schedule:
+        h = C.c_void_p()
+        _check(lib().dgt_solver_schedule(self.h, C.byref(h)))
+        m = self.mesh
+        sizes = {0: m.nc, 1: m.nf, 2: m.nb}
+        nl = 26 if self._order() == 4 else 8
+        pat = ([0, 1, 2, 0] * 3 + [0]) * 2 if nl == 26 else [0, 1, 2, 0] * 2
+        return Schedule(h, owner=False, loop_sizes=[sizes[s] for s in pat])
+
+    def _order(self):
+        return self._time_order
+
+    def set_source(self, x, y, f0=5.0, t0=0.2, amp=1.0):
+        _check(lib().dgt_set_source(self.h, x, y, f0, t0, amp))
+
+    def upload(self, v, s):
+        assert v.dtype == self.dtype and s.dtype == self.dtype and v.is_contiguous() and s.is_contiguous()
+        assert tuple(v.shape) == (2, self.np, self.mesh.nc) and tuple(s.shape) == (3, self.np, self.mesh.nc)
+        _check(lib().dgt_state_upload(self.h, C.c_void_p(v.data_ptr()), C.c_void_p(s.data_ptr())))
+
+    def download(self, v, s):
+        assert v.dtype == self.dtype and s.dtype == self.dtype and v.is_contiguous() and s.is_contiguous()
+        assert tuple(v.shape) == (2, self.np, self.mesh.nc) and tuple(s.shape) == (3, self.np, self.mesh.nc)
+        _check(lib().dgt_state_download(self.h, C.c_void_p(v.data_ptr()), C.c_void_p(s.data_ptr())))
+
+    def step(self, nsteps: int, mode: int = 1, t0: float = 0.0):
+        _check(lib().dgt_step(self.h, int(nsteps), int(mode), float(t0)))
+
+    def energy(self, v, s_new, s_old) -> float:
+        out = C.c_double()
+        _check(lib().dgt_energy(self.h, C.c_void_p(v.data_ptr()), C.c_void_p(s_new.data_ptr()),
+                                C.c_void_p(s_old.data_ptr()), C.byref(out)))
+        return out.value
+
+    def last_timing(self):
+        tot, ker, n = C.c_double(), C.c_double(), C.c_int64()
+        _check(lib().dgt_last_step_timing(self.h, C.byref(tot), C.byref(ker), C.byref(n)))
+        return tot.value, ker.value, n.value
+
+    def info(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().dgt_solver_info(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return dict(np=a.value, bytes_per_step=b.value, lds_bytes=c.value)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.dgt_solver_destroy(self.h)
+            self.h = None
