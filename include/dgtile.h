@@ -176,9 +176,10 @@ dgt_status dgt_solver_create(const dgt_mesh *m, const double *lam, const double 
                              const dgt_solver_params *p, void *stream, dgt_solver **out);
 /* Inspect the solver's chain on the GPU (dgt_inspect; seed_xy is ignored and
  * the cell centroids are used) and build the executor plan: cells renumbered
- * into seed order, per-tile footprints in LDS slots and local maps.
- * EUNSUPPORTED when a tile's footprint exceeds the LDS budget (smaller
- * tile_size or more splits needed).  Synchronises the stream. */
+ * into seed order, per-tile footprints in LDS slots and local maps.  When a
+ * tile's footprint exceeds the LDS budget the schedule is still built and
+ * returned, and dgt_step in tiled mode then fails with DGT_EUNSUPPORTED
+ * (smaller tile_size or more splits needed).  Synchronises the stream. */
 dgt_status dgt_solver_inspect(dgt_solver *s, const dgt_inspect_params *p);
 /* The schedule of the last dgt_solver_inspect (borrowed; NULL before). */
 dgt_status dgt_solver_schedule(const dgt_solver *s, const dgt_schedule **out);

@@ -448,7 +448,10 @@ __global__ __launch_bounds__(256) void k_tile(const TileArgs a) {
                 xb = ib;
                 lmE = lm;
             }
-            for (int idx = tid; idx < 3 * nfoot; idx += nt) fidx[idx] = -1;
+            for (int idx = tid; idx < 3 * nfoot; idx += nt) {
+                const int p = idx / nfoot;
+                fidx[p * S + (idx - p * nfoot)] = -1;
+            }
             __syncthreads();
             const int FS = a.fac_stride;
 #define GB(side, comp, m, e) ldsG[((size_t)((side) * 3 + (comp)) * NFP + (m)) * FS + (e)]

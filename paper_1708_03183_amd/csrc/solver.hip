@@ -60,6 +60,8 @@ struct dgt_solver {
     dgt_chain chain;
     dgt_schedule *sched = nullptr;
     std::vector<dgt::SubPlan> plan;
+    dgt_status plan_status = DGT_ESTATE;  // why the tiled executor cannot run (DGT_OK when it can)
+    std::string plan_error = "tiled mode needs dgt_solver_inspect";
     // timing of the last step
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_ms = 0;
@@ -643,6 +645,8 @@ dgt_status dgt_solver_inspect(dgt_solver *s, const dgt_inspect_params *p) {
         delete s->sched;
         s->sched = nullptr;
         s->plan.clear();
+        s->plan_status = DGT_ESTATE;
+        s->plan_error = "tiled mode needs a successful dgt_solver_inspect";
         DBuf<double> cxy(2 * s->nc);
         k_centroids<<<blocks_for(s->nc, 256), 256, 0, st>>>(s->xy.p, s->c2v.p, s->nc, cxy.p);
         auto sch = std::make_unique<dgt_schedule>();
@@ -655,7 +659,17 @@ dgt_status dgt_solver_inspect(dgt_solver *s, const dgt_inspect_params *p) {
         // executor layout follows the seed order of the schedule
         auto rank = s->sched->s->seed_rank.download(st, s->nc);
         set_exec_order(s, rank);
-        build_plan(s);
+        // the schedule stays valid when its tiles do not fit the LDS budget;
+        // only the tiled executor is then unavailable
+        try {
+            build_plan(s);
+            s->plan_status = DGT_OK;
+        } catch (const Error &e) {
+            if (e.st != DGT_EUNSUPPORTED) throw;
+            s->plan.clear();
+            s->plan_status = e.st;
+            s->plan_error = e.msg;
+        }
     });
 }
 
@@ -735,7 +749,7 @@ dgt_status dgt_step(dgt_solver *s, int64_t nsteps, int32_t mode, double t0) {
         DGT_REQUIRE(s && nsteps >= 0, DGT_EINVAL, "bad arguments");
         DGT_REQUIRE(s->state_valid, DGT_ESTATE, "state not uploaded");
         DGT_REQUIRE(mode == 0 || mode == 1, DGT_EINVAL, "mode must be 0 or 1");
-        DGT_REQUIRE(mode == 0 || !s->plan.empty(), DGT_ESTATE, "tiled mode needs dgt_solver_inspect");
+        DGT_REQUIRE(mode == 0 || s->plan_status == DGT_OK, s->plan_status, s->plan_error);
         int64_t launches = 0;
         DGT_HIP(hipEventRecord(s->ev0, s->st));
         dispatch(s, [&]<int K, typename T>() {

