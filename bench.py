@@ -1,0 +1,213 @@
+"""Benchmark: DG dof-updates/s of the sparse-tiled fused time step vs the
+untiled chain on one MI355X.
+
+Workload (default): 512x512 jittered (0.2h) and randomly renumbered unit-square
+triangulation, 524288 cells, DG P2 velocity-stress elastic, three-layer
+material, upwind flux, free surface on top and absorbing elsewhere, Ricker
+source at (0.5, 0.5), 4th-order Taylor leapfrog (26 loops per step).
+
+Prints ONE JSON line (rank 0).  `value` is the tiled-fused rate in
+dof-updates/s (5 fields x Np nodes x cells per step, per second) with the state
+resident in HBM.  The untiled chain, the other precision, the inspector time,
+the measured error against the FP64 oracle / untiled run, the kernel roofline
+and the oracle timed on the host are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=512, help="squares per side")
+    ap.add_argument("--degree", type=int, default=2)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--tile-size", type=int, default=None)
+    ap.add_argument("--splits", type=str, default=None, help="comma-separated loop indices, or 'none'")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-untiled", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    return ap.parse_args()
+
+
+# tuned defaults per (degree, precision): seed tile size and fusion splits
+DEFAULTS = {
+    (1, "fp64"): (64, (4, 8, 13, 17, 21)),
+    (2, "fp64"): (32, (4, 8, 13, 17, 21)),
+    (2, "fp32"): (32, (4, 8, 13, 17, 21)),
+    (3, "fp32"): (64, (4, 8, 13, 17, 21)),
+    (4, "fp32"): (32, (4, 8, 13, 17, 21)),
+}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this build",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1708_03183_amd import dgtile as D
+    from paper_1708_03183_amd import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    prec = 1 if a.precision == "fp32" else 0
+    ts, splits = DEFAULTS.get((a.degree, a.precision), (64, (4, 8, 13, 17, 21)))
+    if a.tile_size:
+        ts = a.tile_size
+    if a.splits is not None:
+        splits = () if a.splits in ("", "none") else tuple(int(x) for x in a.splits.split(","))
+
+    t0 = time.time()
+    m = I.square_mesh(a.n, jitter=0.2, jitter_seed=1, renumber_seed=2)
+    lam, mu, rho = I.layered_material(m)
+    t_gen = time.time() - t0
+    k = a.degree
+    npk = (k + 1) * (k + 2) // 2
+    # CFL time step (C6 reading): 0.2 h_min / ((2k+1) c_p,max), h = 4|K|/perimeter
+    p = m.xy[m.c2v]
+    e = [np.hypot(*(p[:, (i + 1) % 3] - p[:, i]).T) for i in range(3)]
+    area = 0.5 * ((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1]) - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1]))
+    hmin = float(np.min(4.0 * area / (e[0] + e[1] + e[2])))
+    cmax = float(np.max(np.sqrt((lam + 2 * mu) / rho)))
+    dt = 0.2 * hmin / ((2 * k + 1) * cmax)
+
+    mesh = D.Mesh.from_mesh(m)
+    dofs = 5 * npk * mesh.nc
+    dtype = torch.float32 if prec else torch.float64
+
+    def make(pr):
+        s = D.Solver(mesh, lam, mu, rho, degree=k, flux=1, time_order=4, precision=pr, free_sides=0x8, dt=dt)
+        s.set_source(0.5, 0.5, 5.0, 0.2, 1.0)
+        return s
+
+    # ---- tiled fused executor
+    sol = make(prec)
+    torch.cuda.synchronize()
+    ti0 = time.time()
+    sol.inspect(ts, partition=1, splits=splits)
+    torch.cuda.synchronize()
+    t_insp_wall = time.time() - ti0
+    sched = json.loads(sol.schedule().summary())
+    info = sol.info()
+    v0, s0 = sol.zeros()
+
+    def run(solver, mode, steps, warm):
+        v, s = solver.zeros()
+        solver.upload(v, s)
+        if warm:
+            solver.step(warm, mode=mode, t0=0.0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        solver.step(steps, mode=mode, t0=warm * dt)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        tot_ms, ker_ms, launches = solver.last_timing()
+        solver.download(v, s)
+        torch.cuda.synchronize()
+        return wall, tot_ms, launches, v, s
+
+    wall_t, ev_t, launches_t, vt, st_ = run(sol, 1, a.steps, a.warmup)
+    rate_t = dofs * a.steps / wall_t
+    res = {}
+    if not a.no_untiled:
+        wall_u, ev_u, launches_u, vu, su = run(sol, 0, a.steps, a.warmup)
+        rate_u = dofs * a.steps / wall_u
+        num = torch.sqrt(((vt - vu) ** 2).sum() + ((st_ - su) ** 2).sum()).item()
+        den = torch.sqrt((vu ** 2).sum() + (su ** 2).sum()).item()
+        res["untiled"] = {"value": rate_u, "ms_per_step": 1e3 * wall_u / a.steps, "launches_per_step":
+                          launches_u / a.steps}
+        res["speedup_tiled_vs_untiled"] = rate_t / rate_u
+        res["err_tiled_vs_untiled_rel_l2"] = num / den if den > 0 else 0.0
+
+    # algorithmic bytes: state read+written once, 9 per-cell invariants read once
+    bytes_step = info["bytes_per_step"]
+    launches_per_step = launches_t / a.steps
+    bytes_launch = bytes_step / launches_per_step
+    avg_launch_s = (ev_t / 1e3) / launches_t
+    achieved = bytes_launch / avg_launch_s / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_tile", "bytes_per_launch": bytes_launch, "avg_launch_us": avg_launch_s * 1e6}
+
+    # ---- oracle on the host: a bounded sample of the same workload
+    cpu = None
+    err_oracle = None
+    if not a.no_cpu_baseline:
+        import oracle as O
+        om = O.OMesh.from_mesh(m)
+        od = O.ODG(om, k, lam, mu, rho, flux=1, order=4, dt=dt, free_sides=0x8)
+        od.set_source(0.5, 0.5, 5.0, 0.2, 1.0)
+        v, s = od.zeros()
+        # start from the GPU's state after the timed run (t = (warmup+steps) dt)
+        tstart = (a.warmup + a.steps) * dt
+        v[:] = vt.double().cpu().numpy()
+        s[:] = st_.double().cpu().numpy()
+        tc = time.perf_counter()
+        od.step(v, s, a.cpu_steps, t0=tstart)
+        tcpu = time.perf_counter() - tc
+        cpu = {"value": dofs * a.cpu_steps / tcpu, "unit": "dof-updates/s", "cores": 1, "kind": "oracle",
+               "sample": f"{a.cpu_steps} full steps of the same {mesh.nc}-cell mesh from the GPU's final state "
+                         f"({tcpu:.1f} s, FP64, single thread)"}
+        # GPU FP64 tiled from the same state, compared with the oracle
+        chk = make(0)
+        chk.inspect(ts, partition=1, splits=splits)
+        gv = torch.from_numpy(np.ascontiguousarray(vt.double().cpu().numpy())).cuda()
+        gs = torch.from_numpy(np.ascontiguousarray(st_.double().cpu().numpy())).cuda()
+        chk.upload(gv, gs)
+        chk.step(a.cpu_steps, mode=1, t0=tstart)
+        chk.download(gv, gs)
+        torch.cuda.synchronize()
+        num = math.sqrt(((gv.cpu().numpy() - v) ** 2).sum() + ((gs.cpu().numpy() - s) ** 2).sum())
+        den = math.sqrt((v ** 2).sum() + (s ** 2).sum())
+        err_oracle = num / den if den > 0 else 0.0
+
+    out = {
+        "metric": "DG dof-updates/s per step, tiled-fused vs untiled, 1 MI355X",
+        "value": rate_t,
+        "unit": "dof-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * wall_t / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"jitter{a.n}_p{k}: {a.n}x{a.n} jittered renumbered triangulation, "
+                               f"{mesh.nc} cells, DG P{k}, 3-layer, upwind, order-4 leapfrog",
+                   "cells": mesh.nc, "dofs_per_step": dofs, "tile_size": ts, "splits": list(splits),
+                   "partition": "hilbert"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "err_vs_fp64_oracle_rel_l2": err_oracle,
+        "inspector": {"gpu_ms": sched.get("inspector_gpu_ms"), "wall_s": t_insp_wall,
+                      "subchains": sched.get("subchains"), "lds_bytes": info["lds_bytes"]},
+        "launches_per_step": launches_per_step,
+        "mesh_gen_s": t_gen,
+    }
+    out.update(res)
+    if "untiled" in res:
+        gain = (res["untiled"]["ms_per_step"] - out["ms_per_step"]) / 1e3
+        out["inspector"]["steps_to_amortise"] = (t_insp_wall / gain) if gain > 0 else None
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
