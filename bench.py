@@ -45,11 +45,11 @@ def parse():
 
 # tuned defaults per (degree, precision): seed tile size and fusion splits
 DEFAULTS = {
-    (1, "fp64"): (64, (4, 8, 13, 17, 21)),
-    (2, "fp64"): (32, (4, 8, 13, 17, 21)),
-    (2, "fp32"): (32, (4, 8, 13, 17, 21)),
-    (3, "fp32"): (64, (4, 8, 13, 17, 21)),
-    (4, "fp32"): (32, (4, 8, 13, 17, 21)),
+    (1, "fp64"): (192, (4, 8, 13, 17, 21)),
+    (2, "fp64"): (192, (4, 8, 13, 17, 21)),
+    (2, "fp32"): (192, (4, 8, 13, 17, 21)),
+    (3, "fp32"): (128, (4, 8, 13, 17, 21)),
+    (4, "fp32"): (64, (4, 8, 13, 17, 21)),
 }
 
 

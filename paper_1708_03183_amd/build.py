@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdgtile.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["inspector.hip", "capi_chain.hip", "solver.hip", "refelem.cpp", "mesh.cpp"]
+SOURCES = ["inspector.hip", "capi_chain.hip", "solver.hip", "tile_k1.hip", "tile_k2.hip", "tile_k3.hip", "tile_k4.hip",
+           "refelem.cpp", "mesh.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++20", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

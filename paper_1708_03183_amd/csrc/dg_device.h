@@ -1,9 +1,8 @@
 #pragma once
 // DG velocity-stress elastic solver of libdgtile on gfx950: the untiled loop
-// chain (one kernel per loop), the sparse-tiled fused executor (Alg. 2: per
-// colour, one workgroup per tile, the tile's footprint staged in LDS and every
-// loop of the chain run there in order), the executor plan (local maps) and
-// the FP64 energy reduction.
+// chain (one kernel per loop), the executor plan (local maps), permutations
+// and the FP64 energy reduction.  The tiled executor's kernels are in
+// tile_kernel.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,61 +14,11 @@
 #include "dg_kernels.h"
 #include "inspector.h"
 #include "mesh.h"
+#include "refconst.h"
 #include "refelem.h"
+#include "tile_args.h"
 
 namespace dgt {
-
-// ------------------------------------------------------------ constants
-
-__constant__ RefC<1, double> c_ref1d;
-__constant__ RefC<2, double> c_ref2d;
-__constant__ RefC<3, double> c_ref3d;
-__constant__ RefC<4, double> c_ref4d;
-__constant__ RefC<1, float> c_ref1f;
-__constant__ RefC<2, float> c_ref2f;
-__constant__ RefC<3, float> c_ref3f;
-__constant__ RefC<4, float> c_ref4f;
-
-template <int K, typename T>
-__device__ __forceinline__ const RefC<K, T> &R();
-template <> __device__ __forceinline__ const RefC<1, double> &R<1, double>() { return c_ref1d; }
-template <> __device__ __forceinline__ const RefC<2, double> &R<2, double>() { return c_ref2d; }
-template <> __device__ __forceinline__ const RefC<3, double> &R<3, double>() { return c_ref3d; }
-template <> __device__ __forceinline__ const RefC<4, double> &R<4, double>() { return c_ref4d; }
-template <> __device__ __forceinline__ const RefC<1, float> &R<1, float>() { return c_ref1f; }
-template <> __device__ __forceinline__ const RefC<2, float> &R<2, float>() { return c_ref2f; }
-template <> __device__ __forceinline__ const RefC<3, float> &R<3, float>() { return c_ref3f; }
-template <> __device__ __forceinline__ const RefC<4, float> &R<4, float>() { return c_ref4f; }
-
-template <int K, typename T>
-static const void *ref_symbol() {
-    if constexpr (std::is_same<T, double>::value) {
-        if constexpr (K == 1) return (const void *)&HIP_SYMBOL(c_ref1d);
-        if constexpr (K == 2) return (const void *)&HIP_SYMBOL(c_ref2d);
-        if constexpr (K == 3) return (const void *)&HIP_SYMBOL(c_ref3d);
-        if constexpr (K == 4) return (const void *)&HIP_SYMBOL(c_ref4d);
-    } else {
-        if constexpr (K == 1) return (const void *)&HIP_SYMBOL(c_ref1f);
-        if constexpr (K == 2) return (const void *)&HIP_SYMBOL(c_ref2f);
-        if constexpr (K == 3) return (const void *)&HIP_SYMBOL(c_ref3f);
-        if constexpr (K == 4) return (const void *)&HIP_SYMBOL(c_ref4f);
-    }
-    return nullptr;
-}
-
-template <int K, typename T>
-static void upload_ref(const RefElem &E, hipStream_t st) {
-    RefC<K, T> h{};
-    constexpr int NP = RefC<K, T>::NP, NFP = RefC<K, T>::NFP;
-    for (int i = 0; i < NP * NP; ++i) {
-        h.Dr[i] = (T)E.Dr[i];
-        h.Ds[i] = (T)E.Ds[i];
-        h.M[i] = (T)E.M[i];
-    }
-    for (int i = 0; i < 3 * NP * NFP; ++i) h.lift[i] = (T)E.lift[i];
-    for (int i = 0; i < 3 * NFP; ++i) h.fn[i] = E.fnodes[i];
-    DGT_HIP(hipMemcpyToSymbolAsync(ref_symbol<K, T>(), &h, sizeof(h), 0, hipMemcpyHostToDevice, st));
-}
 
 // ------------------------------------------------------------ untiled kernels (one per loop)
 
@@ -80,8 +29,8 @@ __global__ __launch_bounds__(256) void k_vol(const T *__restrict__ in, T *__rest
     constexpr int NP = np_of(K);
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nc * NP) return;
-    const int i = (int)(t / nc);
-    const int64_t c = t - (int64_t)i * nc;
+    const int64_t c = t / NP;  // nodes of one cell are adjacent lanes: its inputs are read once
+    const int i = (int)(t - c * NP);
     const auto &Rf = R<K, T>();
     const T rx = geo[G_RX * nc + c], ry = geo[G_RY * nc + c], sx = geo[G_SX * nc + c], sy = geo[G_SY * nc + c];
     constexpr int NCI = VEL ? 3 : 2;
@@ -232,8 +181,8 @@ __global__ __launch_bounds__(256) void k_lift(T *__restrict__ out, const int32_t
     constexpr int NP = np_of(K), NFP = K + 1, NCO = VEL ? 2 : 3;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nc * NP) return;
-    const int i = (int)(t / nc);
-    const int64_t c = t - (int64_t)i * nc;
+    const int64_t c = t / NP;
+    const int i = (int)(t - c * NP);
     const auto &Rf = R<K, T>();
     T acc[NCO];
 #pragma unroll
@@ -283,322 +232,6 @@ __global__ __launch_bounds__(256) void k_upd_s(T *__restrict__ S, const T *__res
     T add = (X ? dt * X[t] : T(0)) + Z[t];
     if (c == src_cell && row < 2 * NP) add += src_amp * src_vec[row % NP];
     S[t] += add;
-}
-
-// ------------------------------------------------------------ fused tiled executor (Alg. 2)
-
-struct TLoop {
-    int8_t kind, in, out, pen, partner;  // partner: index of a fused exterior loop or -1
-    float scale_f, pscale_f;
-    double scale_d, pscale_d;
-};
-
-struct TileArgs {
-    int32_t nloops;
-    TLoop loops[31];
-    const int32_t *it_off[31];
-    const uint32_t *lmap[31];
-    const int32_t *foot_off;
-    const int32_t *foot;   // exec cell ids, ascending per tile
-    const uint32_t *facc;  // loop bits + single-tile flag
-    const int32_t *tiles;  // tiles of this sub-chain in execution order
-    int32_t tile_base;     // first tile of the colour in `tiles`
-    void *F[F_COUNT];
-    const void *geo;
-    int64_t nc;
-    // per-field LDS plan
-    uint32_t loops_mask[F_COUNT], rfirst_mask[F_COUNT], writes_mask[F_COUNT];
-    int32_t persistent_mask;   // fields always written back when written
-    int32_t lds_row[F_COUNT];  // first LDS row of each field (-1: unused)
-    int32_t nrows;             // field rows + geometry rows
-    int32_t stride;            // slots per row
-    int32_t fac_stride;        // facet entries per G row
-    int32_t src_cell;          // exec id of the source cell or -1
-    double dt, src_amp;        // src_amp = dt * r(t^{n+1/2})
-    const void *src_vec;
-};
-
-template <int K, typename T, bool UPW, bool PEN>
-__global__ __launch_bounds__(256) void k_tile(const TileArgs a) {
-    constexpr int NP = np_of(K), NFP = K + 1;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int tile = a.tiles[a.tile_base + blockIdx.x];
-    const int f0 = a.foot_off[tile];
-    const int nfoot = a.foot_off[tile + 1] - f0;
-    const int S = a.stride;
-    T *lds = reinterpret_cast<T *>(smem);
-    T *ldsG = lds + (size_t)a.nrows * S;
-    int32_t *fidx = reinterpret_cast<int32_t *>(ldsG + (size_t)2 * 3 * NFP * a.fac_stride);
-    uint16_t *flags = reinterpret_cast<uint16_t *>(fidx + 3 * S);
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const auto &Rf = R<K, T>();
-    const T *geo = reinterpret_cast<const T *>(a.geo);
-    const int64_t nc = a.nc;
-    const int geo_row = a.nrows - G_NROWS;
-    const T dt = (T)a.dt;
-
-    // gather/scatter flags per slot from the footprint's loop bits
-    for (int s = tid; s < nfoot; s += nt) {
-        const uint32_t acc = a.facc[f0 + s];
-        const bool single = acc >> 31;
-        uint16_t g = 0, w = 0;
-#pragma unroll
-        for (int f = 0; f < F_COUNT; ++f) {
-            if (a.lds_row[f] < 0) continue;
-            const uint32_t m = acc & a.loops_mask[f];
-            if (m) {
-                const uint32_t first = m & (~m + 1u);
-                if (first & a.rfirst_mask[f]) g |= 1u << f;
-            }
-            if ((acc & a.writes_mask[f]) && (((a.persistent_mask >> f) & 1) || !single)) w |= 1u << f;
-        }
-        flags[s] = (uint16_t)(g | (w << 8));
-    }
-    __syncthreads();
-    // gather: fields (rows of Np nodes x components) and geometry
-    for (int f = 0; f < F_COUNT; ++f) {
-        if (a.lds_row[f] < 0) continue;
-        const T *src = reinterpret_cast<const T *>(a.F[f]);
-        const int rows = field_ncomp(f) * NP;
-        for (int idx = tid; idx < rows * nfoot; idx += nt) {
-            const int r = idx / nfoot, s = idx - r * nfoot;
-            if ((flags[s] >> f) & 1) lds[(size_t)(a.lds_row[f] + r) * S + s] = src[(int64_t)r * nc + a.foot[f0 + s]];
-        }
-    }
-    for (int idx = tid; idx < G_NROWS * nfoot; idx += nt) {
-        const int r = idx / nfoot, s = idx - r * nfoot;
-        lds[(size_t)(geo_row + r) * S + s] = geo[(int64_t)r * nc + a.foot[f0 + s]];
-    }
-    __syncthreads();
-#define LF(f, comp, node, slot) lds[(size_t)(a.lds_row[f] + (comp) * NP + (node)) * S + (slot)]
-#define LG(row, slot) lds[(size_t)(geo_row + (row)) * S + (slot)]
-
-    for (int j = 0; j < a.nloops; ++j) {
-        const TLoop L = a.loops[j];
-        const T scale = sizeof(T) == 8 ? (T)L.scale_d : (T)L.scale_f;
-        const T pscale = sizeof(T) == 8 ? (T)L.pscale_d : (T)L.pscale_f;
-        const int ib = a.it_off[j][tile], ie = a.it_off[j][tile + 1];
-        const uint32_t *lm = a.lmap[j];
-        switch (L.kind) {
-        case KV_SOLVE:
-            continue;  // folded into the operators: no data moves
-        case KV_VOL_V:
-        case KV_VOL_S: {
-            const bool vel = L.kind == KV_VOL_V;
-            const int n = ie - ib;
-            for (int idx = tid; idx < n * NP; idx += nt) {
-                const int i = idx / n, q = idx - i * n;
-                const int s = (int)(lm[ib + q] & 0x3fffu);
-                const T rx = LG(G_RX, s), ry = LG(G_RY, s), sx = LG(G_SX, s), sy = LG(G_SY, s);
-                if (vel) {
-                    T ar[3] = {0, 0, 0}, as[3] = {0, 0, 0};
-#pragma unroll
-                    for (int jj = 0; jj < NP; ++jj) {
-                        const T dr = Rf.Dr[i * NP + jj], ds = Rf.Ds[i * NP + jj];
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            const T u = LF(L.in, c, jj, s);
-                            ar[c] += dr * u;
-                            as[c] += ds * u;
-                        }
-                    }
-                    const T irho = LG(G_IRHO, s);
-                    LF(L.out, 0, i, s) = scale * irho * ((rx * ar[0] + sx * as[0]) + (ry * ar[2] + sy * as[2]));
-                    LF(L.out, 1, i, s) = scale * irho * ((rx * ar[2] + sx * as[2]) + (ry * ar[1] + sy * as[1]));
-                } else {
-                    T ar[2] = {0, 0}, as[2] = {0, 0};
-#pragma unroll
-                    for (int jj = 0; jj < NP; ++jj) {
-                        const T dr = Rf.Dr[i * NP + jj], ds = Rf.Ds[i * NP + jj];
-#pragma unroll
-                        for (int c = 0; c < 2; ++c) {
-                            const T u = LF(L.in, c, jj, s);
-                            ar[c] += dr * u;
-                            as[c] += ds * u;
-                        }
-                    }
-                    const T lam = LG(G_LAM, s), mu = LG(G_MU, s);
-                    const T exx = rx * ar[0] + sx * as[0], eyy = ry * ar[1] + sy * as[1];
-                    const T exy = T(0.5) * ((ry * ar[0] + sy * as[0]) + (rx * ar[1] + sx * as[1]));
-                    LF(L.out, 0, i, s) = scale * ((lam + 2 * mu) * exx + lam * eyy);
-                    LF(L.out, 1, i, s) = scale * (lam * exx + (lam + 2 * mu) * eyy);
-                    LF(L.out, 2, i, s) = scale * (2 * mu * exy);
-                }
-            }
-            break;
-        }
-        case KV_INT_V:
-        case KV_INT_S:
-        case KV_EXT_V:
-        case KV_EXT_S: {
-            const bool vel = (L.kind == KV_INT_V || L.kind == KV_EXT_V);
-            const int nco = vel ? 2 : 3;
-            // interior list of this loop, exterior list of the fused partner (if any)
-            int nI = 0, xb = 0, nE = 0;
-            const uint32_t *lmE = nullptr;
-            if (L.kind == KV_INT_V || L.kind == KV_INT_S) {
-                nI = ie - ib;
-                if (L.partner >= 0) {
-                    xb = a.it_off[L.partner][tile];
-                    nE = a.it_off[L.partner][tile + 1] - xb;
-                    lmE = a.lmap[L.partner];
-                }
-            } else {
-                nE = ie - ib;
-                xb = ib;
-                lmE = lm;
-            }
-            for (int idx = tid; idx < 3 * nfoot; idx += nt) {
-                const int p = idx / nfoot;
-                fidx[p * S + (idx - p * nfoot)] = -1;
-            }
-            __syncthreads();
-            const int FS = a.fac_stride;
-#define GB(side, comp, m, e) ldsG[((size_t)((side) * 3 + (comp)) * NFP + (m)) * FS + (e)]
-            for (int idx = tid; idx < (nI + nE) * NFP; idx += nt) {
-                const int m = idx / (nI + nE), e = idx - m * (nI + nE);
-                if (e < nI) {
-                    const uint32_t code = lm[ib + e];
-                    const int s0 = code & 0x3fff, s1 = (code >> 14) & 0x3fff;
-                    const int l0 = (code >> 28) & 3, l1 = (code >> 30) & 3;
-                    const int n0 = Rf.fn[l0 * NFP + m], n1 = Rf.fn[l1 * NFP + (K - m)];
-                    T nx, ny, fs0, fs1, tx_, ty_;
-                    facet_normal<T>(l0, LG(G_RX, s0), LG(G_RY, s0), LG(G_SX, s0), LG(G_SY, s0), nx, ny, fs0);
-                    facet_normal<T>(l1, LG(G_RX, s1), LG(G_RY, s1), LG(G_SX, s1), LG(G_SY, s1), tx_, ty_, fs1);
-                    T g0[3], g1[3];
-                    if (vel) {
-                        T sa[3], sb[3], va[2] = {0, 0}, vb[2] = {0, 0};
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) { sa[c] = LF(L.in, c, n0, s0); sb[c] = LF(L.in, c, n1, s1); }
-                        if (PEN && L.pen >= 0) {
-#pragma unroll
-                            for (int c = 0; c < 2; ++c) { va[c] = LF(L.pen, c, n0, s0); vb[c] = LF(L.pen, c, n1, s1); }
-                        }
-                        flux_v_int<T, UPW, PEN>(sa, sb, va, vb, nx, ny, LG(G_ZP, s0), LG(G_ZS, s0), LG(G_ZP, s1),
-                                                LG(G_ZS, s1), fs0 * LG(G_IRHO, s0), fs1 * LG(G_IRHO, s1), scale,
-                                                L.pen >= 0 ? pscale : T(0), g0, g1);
-                    } else {
-                        T va[2], vb[2], sa[3] = {0, 0, 0}, sb[3] = {0, 0, 0};
-#pragma unroll
-                        for (int c = 0; c < 2; ++c) { va[c] = LF(L.in, c, n0, s0); vb[c] = LF(L.in, c, n1, s1); }
-                        if (PEN && L.pen >= 0) {
-#pragma unroll
-                            for (int c = 0; c < 3; ++c) { sa[c] = LF(L.pen, c, n0, s0); sb[c] = LF(L.pen, c, n1, s1); }
-                        }
-                        flux_s_int<T, UPW, PEN>(va, vb, sa, sb, nx, ny, LG(G_ZP, s0), LG(G_ZS, s0), LG(G_ZP, s1),
-                                                LG(G_ZS, s1), LG(G_LAM, s0), LG(G_MU, s0), LG(G_LAM, s1),
-                                                LG(G_MU, s1), fs0, fs1, scale, L.pen >= 0 ? pscale : T(0), g0, g1);
-                    }
-                    for (int c = 0; c < nco; ++c) {
-                        GB(0, c, m, e) = g0[c];
-                        GB(1, c, K - m, e) = g1[c];
-                    }
-                    if (m == 0) {
-                        fidx[l0 * S + s0] = 2 * e;
-                        fidx[l1 * S + s1] = 2 * e + 1;
-                    }
-                } else {
-                    const int eb = e - nI;
-                    const uint32_t code = lmE[xb + eb];
-                    const int s0 = code & 0x3fff, l = (code >> 28) & 3;
-                    const bool fr = (code >> 30) & 1;
-                    const int nd = Rf.fn[l * NFP + m];
-                    T nx, ny, fs;
-                    facet_normal<T>(l, LG(G_RX, s0), LG(G_RY, s0), LG(G_SX, s0), LG(G_SY, s0), nx, ny, fs);
-                    T g[3];
-                    if (vel) {
-                        T sa[3], va[2] = {0, 0};
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) sa[c] = LF(L.in, c, nd, s0);
-                        if (PEN && L.pen >= 0) {
-#pragma unroll
-                            for (int c = 0; c < 2; ++c) va[c] = LF(L.pen, c, nd, s0);
-                        }
-                        flux_v_ext<T, UPW, PEN>(sa, va, fr, nx, ny, LG(G_ZP, s0), LG(G_ZS, s0),
-                                                fs * LG(G_IRHO, s0), scale, L.pen >= 0 ? pscale : T(0), g);
-                    } else {
-                        T va[2], sa[3] = {0, 0, 0};
-#pragma unroll
-                        for (int c = 0; c < 2; ++c) va[c] = LF(L.in, c, nd, s0);
-                        if (PEN && L.pen >= 0) {
-#pragma unroll
-                            for (int c = 0; c < 3; ++c) sa[c] = LF(L.pen, c, nd, s0);
-                        }
-                        flux_s_ext<T, UPW, PEN>(va, sa, fr, nx, ny, LG(G_ZP, s0), LG(G_ZS, s0), LG(G_LAM, s0),
-                                                LG(G_MU, s0), fs, scale, L.pen >= 0 ? pscale : T(0), g);
-                    }
-                    for (int c = 0; c < nco; ++c) GB(0, c, m, e) = g[c];
-                    if (m == 0) fidx[l * S + s0] = 2 * e;
-                }
-            }
-            __syncthreads();
-            // lift into every slot with a facet of this loop (local facets 0,1,2 in order)
-            for (int idx = tid; idx < nfoot * NP; idx += nt) {
-                const int i = idx / nfoot, s = idx - i * nfoot;
-                const int c0 = fidx[s], c1 = fidx[S + s], c2 = fidx[2 * S + s];
-                if (c0 < 0 && c1 < 0 && c2 < 0) continue;
-                T acc[3] = {0, 0, 0};
-#pragma unroll
-                for (int p = 0; p < 3; ++p) {
-                    const int code = fidx[p * S + s];
-                    if (code < 0) continue;
-                    const int e = code >> 1, sd = code & 1;
-#pragma unroll
-                    for (int m = 0; m < NFP; ++m) {
-                        const T lv = Rf.lift[(p * NP + i) * NFP + m];
-                        for (int c = 0; c < nco; ++c) acc[c] += lv * GB(sd, c, m, e);
-                    }
-                }
-                for (int c = 0; c < nco; ++c) LF(L.out, c, i, s) += acc[c];
-            }
-#undef GB
-            if (L.partner >= 0) ++j;  // the exterior partner has been processed
-            break;
-        }
-        case KV_UPD_V:
-        case KV_UPD2_V: {
-            const int n = ie - ib;
-            const bool o4 = L.kind == KV_UPD_V;
-            for (int idx = tid; idx < n * 2 * NP; idx += nt) {
-                const int r = idx / n, q = idx - r * n;
-                const int s = (int)(lm[ib + q] & 0x3fffu);
-                const int c = r / NP, i = r - c * NP;
-                LF(F_V, c, i, s) += (o4 ? dt * LF(F_U, c, i, s) : T(0)) + LF(F_Z, c, i, s);
-            }
-            break;
-        }
-        case KV_UPD_S:
-        case KV_UPD2_S: {
-            const int n = ie - ib;
-            const bool o4 = L.kind == KV_UPD_S;
-            const T *sv = reinterpret_cast<const T *>(a.src_vec);
-            for (int idx = tid; idx < n * 3 * NP; idx += nt) {
-                const int r = idx / n, q = idx - r * n;
-                const int s = (int)(lm[ib + q] & 0x3fffu);
-                const int c = r / NP, i = r - c * NP;
-                T add = (o4 ? dt * LF(F_X, c, i, s) : T(0)) + LF(F_Z, c, i, s);
-                if (c < 2 && a.foot[f0 + s] == a.src_cell) add += (T)a.src_amp * sv[i];
-                LF(F_S, c, i, s) += add;
-            }
-            break;
-        }
-        default:
-            break;
-        }
-        __syncthreads();
-    }
-    // scatter what this tile wrote and others (or later sub-chains) need
-    for (int f = 0; f < F_COUNT; ++f) {
-        if (a.lds_row[f] < 0) continue;
-        T *dst = reinterpret_cast<T *>(a.F[f]);
-        const int rows = field_ncomp(f) * NP;
-        for (int idx = tid; idx < rows * nfoot; idx += nt) {
-            const int r = idx / nfoot, s = idx - r * nfoot;
-            if ((flags[s] >> (8 + f)) & 1) dst[(int64_t)r * nc + a.foot[f0 + s]] = lds[(size_t)(a.lds_row[f] + r) * S + s];
-        }
-    }
-#undef LF
-#undef LG
 }
 
 // ------------------------------------------------------------ plan kernels (local maps)

@@ -17,6 +17,12 @@ namespace dgt {
 
 constexpr int np_of(int k) { return (k + 1) * (k + 2) / 2; }
 
+// cell node of facet node t on local facet p (facet p joins local vertices p
+// and p+1, its nodes run from vertex p; cell nodes (i/K, j/K) ordered by j then i)
+__host__ __device__ constexpr int fnode(int K, int p, int t) {
+    return p == 0 ? t : (p == 1 ? t * (K + 1) - t * (t - 1) / 2 + (K - t) : (K - t) * (K + 1) - (K - t) * (K - t - 1) / 2);
+}
+
 template <int K, typename T>
 struct RefC {
     static constexpr int NP = np_of(K), NFP = K + 1;

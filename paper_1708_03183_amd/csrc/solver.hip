@@ -3,10 +3,12 @@
 // state and energy entry points.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
 #include "dg_device.h"
+#include "tile_exec.h"
 
 namespace dgt {
 
@@ -21,10 +23,15 @@ struct SubPlan {
     DBuf<int32_t> efoot;
     DBuf<uint32_t> eacc;
     DBuf<uint32_t> lmap[31];
+    DBuf<uint32_t> tnb;
+    DBuf<int32_t> tnb_off;
     std::vector<int32_t> color_off;
     TileArgs args{};
     size_t lds_bytes = 0;
-    int max_foot = 0, max_fac = 0;
+    int max_foot = 0;
+    int threads = 256;
+    TileKernel kind = TK_GENERIC;  // operator kernel for single-operator sub-chains
+    bool vel = false;  // workgroup size of the tile kernel
 };
 
 }  // namespace dgt
@@ -279,7 +286,7 @@ static void build_plan(dgt_solver *s) {
     hipDeviceProp_t prop;
     DGT_HIP(hipGetDeviceProperties(&prop, dev));
     const size_t budget = std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
-    const int np = s->E.np, nfp = s->E.nfp;
+    const int np = s->E.np;
     // fields touched by each sub-chain, for persistence across sub-chains
     std::vector<int> used(S.sub.size(), 0);
     auto fields_of = [&](const GLoop &g) {
@@ -323,12 +330,13 @@ static void build_plan(dgt_solver *s) {
         auto foff = sb.foot_off[0].download(st, sb.ntiles + 1);
         for (int t = 0; t < sb.ntiles; ++t) P.max_foot = std::max(P.max_foot, foff[t + 1] - foff[t]);
         DGT_REQUIRE(P.max_foot <= 0x3fff, DGT_EUNSUPPORTED, "tile footprint exceeds 16383 cells");
-        // local maps per loop
+        // local maps of the facet loops (cell loops take their iterations from the footprint's loop bits)
         DBuf<int32_t> err(1);
         DGT_HIP(hipMemsetAsync(err.p, 0, 4, st));
         for (int j = sb.first; j < sb.first + sb.n; ++j) {
             const int64_t n = S.loop_size[j];
             const int kind = s->loops[j].set;
+            if (kind == 0) continue;
             auto &lm = P.lmap[j - sb.first];
             lm.alloc(std::max<int64_t>(n, 1));
             if (n)
@@ -337,21 +345,6 @@ static void build_plan(dgt_solver *s) {
                                                            s->f2l.p, s->b2c.p, s->b2l.p, s->bfree.p, lm.p, err.p);
         }
         DGT_REQUIRE(err.download(st)[0] == 0, DGT_ESTATE, "local map construction failed");
-        // largest facet phase (interior + fused exterior iterations of one tile)
-        for (int j = sb.first; j < sb.first + sb.n; ++j) {
-            const GLoop &g = s->loops[j];
-            if (g.set == 0) continue;
-            auto o1 = S.it_off[j].download(st, sb.ntiles + 1);
-            std::vector<int32_t> o2;
-            const bool fuse = g.set == 1 && j + 1 < sb.first + sb.n && s->loops[j + 1].set == 2;
-            if (fuse) o2 = S.it_off[j + 1].download(st, sb.ntiles + 1);
-            for (int t = 0; t < sb.ntiles; ++t) {
-                int cnt = o1[t + 1] - o1[t];
-                if (fuse) cnt += o2[t + 1] - o2[t];
-                P.max_fac = std::max(P.max_fac, cnt);
-            }
-            if (fuse) ++j;
-        }
         // per-field access table of this sub-chain
         TileArgs &A = P.args;
         std::memset(&A, 0, sizeof(A));
@@ -363,11 +356,31 @@ static void build_plan(dgt_solver *s) {
                 A.lds_row[f] = rows;
                 rows += field_ncomp(f) * np;
             }
-        A.nrows = rows + G_NROWS;
-        int others = 0;
-        for (size_t b2 = 0; b2 < S.sub.size(); ++b2)
-            if (b2 != b) others |= used[b2];
-        A.persistent_mask = (1 << F_V) | (1 << F_S) | (others & used[b]);
+        A.nrow = rows + G_NROWS;
+        if (!(A.nrow & 1)) ++A.nrow;  // odd slot stride: consecutive slots fall in different LDS banks
+        // a field written here is kept (written back for every cell) unless the next sub-chain
+        // that uses it, cyclically over steps, starts by overwriting it in a volume loop
+        A.persistent_mask = (1 << F_V) | (1 << F_S);
+        for (int f = 0; f < F_COUNT; ++f) {
+            if (!((used[b] >> f) & 1)) continue;
+            bool live = true;
+            for (size_t d = 1; d <= S.sub.size(); ++d) {
+                const SubSched &nx = S.sub[(b + d) % S.sub.size()];
+                if (!((used[(b + d) % S.sub.size()] >> f) & 1)) continue;
+                for (int j = nx.first; j < nx.first + nx.n; ++j) {
+                    const int m = fields_of(s->loops[j]);
+                    if (!((m >> f) & 1)) continue;
+                    const GLoop &g = s->loops[j];
+                    live = !((g.kind == KV_VOL_V || g.kind == KV_VOL_S) && g.out == f);
+                    break;
+                }
+                break;
+            }
+            if (live) A.persistent_mask |= 1 << f;
+        }
+        // facet loops with their neighbour tables: an interior loop and the exterior loop that
+        // follows it with the same operands share one table and run in one pass
+        std::vector<std::vector<int>> groups;
         for (int i = 0; i < sb.n; ++i) {
             const GLoop &g = s->loops[sb.first + i];
             TLoop &t = A.loops[i];
@@ -376,16 +389,22 @@ static void build_plan(dgt_solver *s) {
             t.out = g.out;
             t.pen = g.pen;
             t.partner = -1;
-            if ((g.kind == KV_INT_V || g.kind == KV_INT_S) && i + 1 < sb.n) {
-                const GLoop &h = s->loops[sb.first + i + 1];
-                if (h.set == 2 && h.in == g.in && h.out == g.out && h.pen == g.pen) t.partner = (int8_t)(i + 1);
+            t.grp = -1;
+            if (g.set != 0 && !(i > 0 && A.loops[i - 1].partner == i)) {
+                t.grp = (int8_t)groups.size();
+                groups.push_back({i});
+                if ((g.kind == KV_INT_V || g.kind == KV_INT_S) && i + 1 < sb.n) {
+                    const GLoop &h = s->loops[sb.first + i + 1];
+                    if (h.set == 2 && h.in == g.in && h.out == g.out && h.pen == g.pen) {
+                        t.partner = (int8_t)(i + 1);
+                        groups.back().push_back(i + 1);
+                    }
+                }
             }
             t.scale_d = g.scale;
             t.pscale_d = g.pscale;
             t.scale_f = (float)g.scale;
             t.pscale_f = (float)g.pscale;
-            A.it_off[i] = S.it_off[sb.first + i].p;
-            A.lmap[i] = P.lmap[i].p;
             const uint32_t bit = 1u << i;
             auto acc = [&](int f, int mode) {  // mode 1 R, 2 W, 3 RW
                 if (f < 0) return;
@@ -403,6 +422,7 @@ static void build_plan(dgt_solver *s) {
             default: break;
             }
         }
+        A.nfl = (int32_t)groups.size();
         A.foot_off = sb.foot_off[0].p;
         A.foot = P.efoot.p;
         A.facc = P.eacc.p;
@@ -411,14 +431,100 @@ static void build_plan(dgt_solver *s) {
         A.geo = s->geo.p;
         A.nc = s->nc;
         A.stride = std::max(P.max_foot, 1);
-        A.fac_stride = std::max(P.max_fac, 1);
         A.src_vec = s->src_vec.p;
-        P.lds_bytes = (size_t)A.nrows * A.stride * s->esz + (size_t)2 * 3 * nfp * A.fac_stride * s->esz +
-                      (size_t)3 * A.stride * 4 + (size_t)A.stride * 2 + 16;
+        // neighbour tables: for each tile, facet group, local facet and footprint slot, the
+        // neighbour's slot and local facet (interior) or the boundary kind (exterior)
+        {
+            std::vector<std::vector<int32_t>> offs(sb.n);
+            std::vector<std::vector<uint32_t>> maps(sb.n);
+            for (auto &gr : groups)
+                for (int i : gr) {
+                    const int j = sb.first + i;
+                    offs[i] = S.it_off[j].download(st, sb.ntiles + 1);
+                    maps[i] = P.lmap[i].download(st, S.loop_size[j]);
+                }
+            std::vector<int32_t> toff(sb.ntiles + 1, 0);
+            for (int t = 0; t < sb.ntiles; ++t) {
+                const int64_t len = (int64_t)A.nfl * 3 * (foff[t + 1] - foff[t]);
+                DGT_REQUIRE(toff[t] + len < INT32_MAX, DGT_EUNSUPPORTED, "neighbour tables exceed 2^31 entries");
+                toff[t + 1] = (int32_t)(toff[t] + len);
+            }
+            std::vector<uint32_t> tab(std::max<int32_t>(toff[sb.ntiles], 1), 0u);
+            bool dup = false;
+            for (int t = 0; t < sb.ntiles; ++t) {
+                const int nfoot = foff[t + 1] - foff[t];
+                for (int gi = 0; gi < A.nfl; ++gi) {
+                    uint32_t *T3 = tab.data() + toff[t] + (size_t)gi * 3 * nfoot;
+                    auto put = [&](int l, int sl, uint32_t code) {
+                        uint32_t &e = T3[(size_t)l * nfoot + sl];
+                        dup |= (e != 0u);
+                        e = code;
+                    };
+                    for (int i : groups[gi]) {
+                        const bool interior = s->loops[sb.first + i].set == 1;
+                        for (int q = offs[i][t]; q < offs[i][t + 1]; ++q) {
+                            const uint32_t c = maps[i][q];
+                            if (interior) {
+                                const int s0 = c & 0x3fff, s1 = (c >> 14) & 0x3fff, l0 = (c >> 28) & 3, l1 = (c >> 30) & 3;
+                                put(l0, s0, NB_VALID | (uint32_t)s1 | ((uint32_t)l1 << 14));
+                                put(l1, s1, NB_VALID | (uint32_t)s0 | ((uint32_t)l0 << 14));
+                            } else {
+                                const int s0 = c & 0x3fff, l = (c >> 28) & 3;
+                                put(l, s0, NB_VALID | NB_BND | (((c >> 30) & 1) ? NB_FREE : 0u) | (uint32_t)s0);
+                            }
+                        }
+                    }
+                }
+            }
+            DGT_REQUIRE(!dup, DGT_ESTATE, "a cell facet appears twice in one facet loop of a tile");
+            P.tnb.upload(tab, st);
+            P.tnb_off.upload(toff, st);
+            A.tnb = P.tnb.p;
+            A.tnb_off = P.tnb_off.p;
+            for (int i = 0; i < sb.n; ++i) P.lmap[i].release();
+        }
+        P.lds_bytes = (size_t)A.nrow * A.stride * s->esz + (size_t)A.stride * (4 + 4 + 2) +
+                      (size_t)A.nfl * 3 * A.stride * 4 + 16;
+        // a sub-chain that is one operator application (volume, interior and exterior facets,
+        // optional solve) with an optional update of its output runs on the operator kernel
+        A.upd_loop = -1;
+        {
+            const GLoop *g = &s->loops[sb.first];
+            const bool vel = g[0].kind == KV_VOL_V;
+            bool op = sb.n >= 3 && sb.n <= 5 && (vel || g[0].kind == KV_VOL_S) &&
+                      g[1].kind == (vel ? KV_INT_V : KV_INT_S) && g[2].kind == (vel ? KV_EXT_V : KV_EXT_S) &&
+                      A.loops[1].partner == 2 && g[1].in == g[0].in && g[1].out == g[0].out && A.nfl == 1;
+            int j = 3;
+            if (op && j < sb.n && g[j].kind == KV_SOLVE && g[j].out == g[0].out) ++j;
+            if (op && j < sb.n) {
+                const int k = g[j].kind;
+                const bool ok = vel ? (k == KV_UPD_V || k == KV_UPD2_V) : (k == KV_UPD_S || k == KV_UPD2_S);
+                if (ok && g[0].out == F_Z) A.upd_loop = j++;
+            }
+            // (P4 FP64 keeps to 256 work items: a 512-item workgroup would spill registers)
+            op = op && j == sb.n && P.max_foot <= (s->K == 4 && s->esz == 8 ? TILE_NT[1] : TILE_NT[2]);
+            const char *env = std::getenv("DGT_TILE_OP");
+            if (env && std::atoi(env) == 0) op = false;
+            if (op) {
+                const int ni = vel ? 3 : 2, no = vel ? 2 : 3;
+                A.nrow = np * ni + (g[1].pen >= 0 ? np * no : 0) + 2;
+                if (!(A.nrow & 1)) ++A.nrow;
+                P.kind = TK_OP;
+                P.vel = vel;
+                P.lds_bytes = (size_t)A.nrow * A.stride * s->esz;
+            } else {
+                A.upd_loop = -1;
+            }
+        }
         DGT_REQUIRE(P.lds_bytes <= budget, DGT_EUNSUPPORTED,
                     "tile footprint of " + std::to_string(P.max_foot) + " cells needs " +
                         std::to_string(P.lds_bytes) + " B of LDS (budget " + std::to_string(budget) +
                         "): use a smaller tile_size or split the chain");
+        // one work item per footprint slot (and node group of the generic kernel)
+        const int ng = P.kind == TK_OP || s->K <= 2 ? 1 : (s->K == 3 ? 2 : 3);
+        const int items = A.stride * ng;
+        P.threads = items <= TILE_NT[0] ? TILE_NT[0] : (items <= TILE_NT[1] ? TILE_NT[1] : TILE_NT[2]);
+        if (const char *e = std::getenv("DGT_TILE_THREADS"); e && P.kind == TK_GENERIC) P.threads = std::atoi(e);
     }
     DGT_HIP(hipStreamSynchronize(st));
 }
@@ -503,11 +609,8 @@ template <int K, typename T>
 static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launches) {
     hipStream_t st = s->st;
     const double dt = s->p.dt;
-    for (auto &P : s->plan) {
-        auto kern = s->upw ? (s->haspen ? k_tile<K, T, true, true> : k_tile<K, T, true, false>)
-                           : (s->haspen ? k_tile<K, T, false, true> : k_tile<K, T, false, false>);
-        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes);
-    }
+    for (auto &P : s->plan)
+        tile_launch<K, T>(P.kind, P.threads, P.vel, s->upw, s->haspen, 0, P.lds_bytes, st, P.args, true);
     for (int64_t n = 0; n < nsteps; ++n) {
         const double th = t0 + ((double)n + 0.5) * dt;
         for (auto &P : s->plan) {
@@ -516,16 +619,10 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
             A.src_cell = s->has_src ? (int32_t)s->src_exec : -1;
             A.src_amp = s->has_src ? dt * ricker(th, s->sf0, s->st0, s->samp) : 0.0;
             for (int c = 0; c < P.ncolors; ++c) {
-                const int nt = P.color_off[c + 1] - P.color_off[c];
-                if (nt == 0) continue;
+                const int ntiles = P.color_off[c + 1] - P.color_off[c];
+                if (ntiles == 0) continue;
                 A.tile_base = P.color_off[c];
-                if (s->upw) {
-                    if (s->haspen) k_tile<K, T, true, true><<<nt, 256, P.lds_bytes, st>>>(A);
-                    else k_tile<K, T, true, false><<<nt, 256, P.lds_bytes, st>>>(A);
-                } else {
-                    if (s->haspen) k_tile<K, T, false, true><<<nt, 256, P.lds_bytes, st>>>(A);
-                    else k_tile<K, T, false, false><<<nt, 256, P.lds_bytes, st>>>(A);
-                }
+                tile_launch<K, T>(P.kind, P.threads, P.vel, s->upw, s->haspen, ntiles, P.lds_bytes, st, A, false);
                 ++launches;
             }
         }
@@ -603,7 +700,10 @@ dgt_status dgt_solver_create(const dgt_mesh *m, const double *lam, const double 
             if (!(M.bside[b] >= 0 && ((p->free_sides >> M.bside[b]) & 1))) s->haspen = 1;
         s->E = make_refelem(p->degree);
         hipStream_t st = s->st;
-        dispatch(s.get(), [&]<int K, typename T>() { upload_ref<K, T>(s->E, st); });
+        dispatch(s.get(), [&]<int K, typename T>() {
+            upload_ref<K, T>(s->E, st);
+            tile_upload_ref<K, T>(s->E, st);
+        });
         s->xy.upload(M.xy, st);
         s->c2v.upload(M.c2v, st);
         s->f2c.upload(M.f2c.empty() ? std::vector<int32_t>{0, 0} : M.f2c, st);

@@ -1,0 +1,45 @@
+#pragma once
+// Launch arguments of the tiled executor's kernels (host and device).
+#include <cstdint>
+
+#include "dg_kernels.h"
+
+namespace dgt {
+
+struct TLoop {
+    int8_t kind, in, out, pen;
+    int8_t partner;  // exterior loop fused into this interior loop, or -1
+    int8_t grp;      // neighbour table of a facet loop, or -1
+    float scale_f, pscale_f;
+    double scale_d, pscale_d;
+};
+
+// neighbour-table codes
+constexpr uint32_t NB_VALID = 1u << 31, NB_BND = 1u << 30, NB_FREE = 1u << 29;
+
+struct TileArgs {
+    int32_t nloops;
+    TLoop loops[31];
+    const int32_t *foot_off;  // [ntiles+1]
+    const int32_t *foot;      // exec cell ids, ascending per tile
+    const uint32_t *facc;     // loop bits + single-tile flag per footprint entry
+    const uint32_t *tnb;      // per tile: [nfl][3][nfoot] neighbour codes
+    const int32_t *tnb_off;   // [ntiles+1]
+    const int32_t *tiles;     // tiles of this sub-chain in execution order
+    int32_t tile_base;        // first tile of the colour in `tiles`
+    void *F[F_COUNT];
+    const void *geo;
+    int64_t nc;
+    uint32_t loops_mask[F_COUNT], rfirst_mask[F_COUNT], writes_mask[F_COUNT];
+    int32_t persistent_mask;   // fields always written back when written
+    int32_t lds_row[F_COUNT];  // offset of each field in a slot's LDS row (-1: unused)
+    int32_t nrow;              // LDS elements per slot (odd), geometry in the last G_NROWS
+    int32_t stride;            // slot capacity (largest footprint of the sub-chain)
+    int32_t nfl;               // facet loops with a neighbour table
+    int32_t upd_loop;          // single-operator sub-chains: loop index of the trailing update or -1
+    int32_t src_cell;          // exec id of the source cell or -1
+    double dt, src_amp;        // src_amp = dt * r(t^{n+1/2})
+    const void *src_vec;
+};
+
+}  // namespace dgt

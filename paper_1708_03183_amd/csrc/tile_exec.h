@@ -1,0 +1,29 @@
+#pragma once
+// Host entry points of the tiled executor's kernels, one translation unit per
+// polynomial degree (tile_k1.hip .. tile_k4.hip).
+#include <hip/hip_runtime.h>
+
+#include "refelem.h"
+#include "tile_args.h"
+
+namespace dgt {
+
+enum TileKernel { TK_GENERIC = 0, TK_OP = 1 };
+
+// Copies the reference element into the constant memory of the degree-K unit.
+template <int K, typename T>
+void tile_upload_ref(const RefElem &E, hipStream_t st);
+
+// Launches (attr = false) or prepares (attr = true: raises the dynamic LDS
+// limit) one colour of a sub-chain.  Generic kernel: any sub-chain, nt work
+// items per tile.  Operator kernel: one operator application (vel selects the
+// velocity operator) with an optional trailing update; needs nt >= the
+// largest footprint.
+template <int K, typename T>
+void tile_launch(TileKernel kind, int nt, bool vel, bool upw, bool pen, int grid, size_t lds, hipStream_t st,
+                 const TileArgs &A, bool attr);
+
+// workgroup sizes the tile kernels are built for
+constexpr int TILE_NT[3] = {128, 256, 512};
+
+}  // namespace dgt

@@ -186,6 +186,34 @@ def test_tiled_fp64_tile_sizes_and_splits(D, ts, part, splits):
     assert err <= 1e-12
 
 
+OP_CASES = [
+    # n, k, order, flux, free, ren, steps, ts, splits: one operator application per sub-chain,
+    # with the update fused into the operator before it (the operator kernel)
+    (12, 2, 4, 1, 0x8, 7, 10, 32, (4, 8, 13, 17, 21)),
+    (12, 2, 2, 1, 0x8, 7, 10, 32, (4,)),
+    (10, 1, 4, 0, 0xF, 3, 10, 64, (4, 8, 13, 17, 21)),
+    (10, 3, 4, 1, 0x8, 5, 20, 32, (4, 8, 13, 17, 21)),
+    (10, 4, 4, 1, 0x0, 5, 20, 16, (4, 8, 13, 17, 21)),
+    (9, 2, 2, 0, 0x3, 3, 10, 16, (4,)),
+    (14, 2, 4, 1, 0x8, 9, 6, 24, (4, 8, 12, 13, 17, 21, 25)),  # updates in sub-chains of their own
+]
+
+
+@pytest.mark.parametrize("n,k,order,flux,free,ren,steps,ts,splits", OP_CASES)
+def test_tiled_operator_kernel_fp64_matches_oracle(D, n, k, order, flux, free, ren, steps, ts, splits):
+    err = _run_pair(D, n, k, order, flux, free, ren, steps, mode=1, ts=ts, splits=splits)
+    print(f"operator-kernel tiled FP64 n={n} k={k} order={order} flux={flux} ts={ts} splits={splits}: "
+          f"rel L2 err {err:.3e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_tiled_operator_kernel_fp32_matches_oracle(D, k):
+    err = _run_pair(D, 10, k, 4, 1, 0x8, 4, 5, mode=1, ts=32, splits=(4, 8, 13, 17, 21), prec=1)
+    print(f"operator-kernel tiled FP32 k={k}: rel L2 err vs FP64 oracle {err:.3e}")
+    assert err <= 1e-5
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_fp32_matches_oracle(D, mode, k):
@@ -209,7 +237,7 @@ def test_energy_matches_oracle(D):
 
 def test_energy_conserved_on_gpu_tiled(D):
     m, om, od, gm, gd = _dg_pair(D, 16, 2, 4, 0, 0xF, 3)
-    gd.inspect(32, partition=1)
+    gd.inspect(32, partition=1, splits=(4, 8, 13, 17, 21))
     v, s = gd.zeros()
     v.copy_(torch.from_numpy(I.random_state(v.shape, 3)))
     s.copy_(torch.from_numpy(I.random_state(s.shape, 4)))
