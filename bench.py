@@ -4,13 +4,15 @@ untiled chain on one MI355X.
 Workload (default): 512x512 jittered (0.2h) and randomly renumbered unit-square
 triangulation, 524288 cells, DG P2 velocity-stress elastic, three-layer
 material, upwind flux, free surface on top and absorbing elsewhere, Ricker
-source at (0.5, 0.5), 4th-order Taylor leapfrog (26 loops per step).
+source at (0.5, 0.5), 4th-order Taylor leapfrog (26 loops per step), tiles
+grown from 128 seed cells in Hilbert order, the chain fused per half step.
 
-Prints ONE JSON line (rank 0).  `value` is the tiled-fused rate in
-dof-updates/s (5 fields x Np nodes x cells per step, per second) with the state
-resident in HBM.  The untiled chain, the other precision, the inspector time,
-the measured error against the FP64 oracle / untiled run, the kernel roofline
-and the oracle timed on the host are reported beside it.
+Prints ONE JSON line.  `value` is the tiled-fused rate in dof-updates/s (5
+fields x Np nodes x cells per step, per second) with the state resident in HBM.
+Reported beside it: the untiled chain on the same (Hilbert) cell order and on
+the mesh's own order, the inspector time and the steps that amortise it, the
+measured error against the FP64 oracle, the tile kernel's roofline from HIP
+events, and the oracle timed on the host.
 """
 from __future__ import annotations
 
@@ -40,17 +42,47 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-untiled", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain elementwise pass over 256 MiB (torch.neg: 256 MiB read, 256 MiB "
+                         "written) for scaling HBM byte counters")
     return ap.parse_args()
 
 
-# tuned defaults per (degree, precision): seed tile size and fusion splits
+# tuned defaults per (degree, precision): seed tile size and fusion splits (13 = half steps)
 DEFAULTS = {
-    (1, "fp64"): (192, (4, 8, 13, 17, 21)),
-    (2, "fp64"): (192, (4, 8, 13, 17, 21)),
-    (2, "fp32"): (192, (4, 8, 13, 17, 21)),
-    (3, "fp32"): (128, (4, 8, 13, 17, 21)),
-    (4, "fp32"): (64, (4, 8, 13, 17, 21)),
+    (1, "fp64"): (256, (13,)),
+    (2, "fp64"): (128, (13,)),
+    (2, "fp32"): (128, (13,)),
+    (3, "fp32"): (64, (13,)),
+    (4, "fp32"): (32, (13,)),
 }
+
+
+TILE_SOURCES = ("tile_chain.h", "dg_kernels.h", "tile_args.h")
+
+
+def measured_traffic(workload, dtype, ts, splits):
+    """HBM bytes per tile-kernel launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary of this configuration, scaled by the copy calibration; None
+    when there is none or when the kernel's sources changed since it was taken."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in TILE_SOURCES:
+        with open(os.path.join(ROOT, "paper_1708_03183_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    sha = h.hexdigest()[:16]
+    want = {"workload": workload, "dtype": dtype, "tile_size": str(ts), "splits": ",".join(map(str, splits)),
+            "src_sha": sha}
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        with open(path) as fh:
+            for line in fh:
+                if not line.startswith("traffic: "):
+                    continue
+                kv = dict(x.split("=", 1) for x in line.split()[1:])
+                if all(kv.get(key) == val for key, val in want.items()):
+                    return float(kv["bytes_per_launch"])
+    return None
 
 
 def main():
@@ -67,7 +99,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     prec = 1 if a.precision == "fp32" else 0
-    ts, splits = DEFAULTS.get((a.degree, a.precision), (64, (4, 8, 13, 17, 21)))
+    ts, splits = DEFAULTS.get((a.degree, a.precision), (64, (13,)))
     if a.tile_size:
         ts = a.tile_size
     if a.splits is not None:
@@ -79,7 +111,7 @@ def main():
     t_gen = time.time() - t0
     k = a.degree
     npk = (k + 1) * (k + 2) // 2
-    # CFL time step (C6 reading): 0.2 h_min / ((2k+1) c_p,max), h = 4|K|/perimeter
+    # CFL time step: 0.2 h_min / ((2k+1) c_p,max), h = 4|K| / perimeter
     p = m.xy[m.c2v]
     e = [np.hypot(*(p[:, (i + 1) % 3] - p[:, i]).T) for i in range(3)]
     area = 0.5 * ((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1]) - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1]))
@@ -89,12 +121,19 @@ def main():
 
     mesh = D.Mesh.from_mesh(m)
     dofs = 5 * npk * mesh.nc
-    dtype = torch.float32 if prec else torch.float64
 
     def make(pr):
         s = D.Solver(mesh, lam, mu, rho, degree=k, flux=1, time_order=4, precision=pr, free_sides=0x8, dt=dt)
         s.set_source(0.5, 0.5, 5.0, 0.2, 1.0)
         return s
+
+    if a.calibrate_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")  # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- tiled fused executor
     sol = make(prec)
@@ -105,7 +144,6 @@ def main():
     t_insp_wall = time.time() - ti0
     sched = json.loads(sol.schedule().summary())
     info = sol.info()
-    v0, s0 = sol.zeros()
 
     def run(solver, mode, steps, warm):
         v, s = solver.zeros()
@@ -120,30 +158,50 @@ def main():
         tot_ms, ker_ms, launches = solver.last_timing()
         solver.download(v, s)
         torch.cuda.synchronize()
-        return wall, tot_ms, launches, v, s
+        return wall, tot_ms, ker_ms, launches, v, s
 
-    wall_t, ev_t, launches_t, vt, st_ = run(sol, 1, a.steps, a.warmup)
+    wall_t, ev_t, _, launches_t, vt, st_ = run(sol, 1, a.steps, a.warmup)
     rate_t = dofs * a.steps / wall_t
+    # the same run again with an event pair around every tile-kernel launch
+    sol.profile(True)
+    psteps = min(a.steps, 200)
+    _, _, ker_p, launches_p, _, _ = run(sol, 1, psteps, a.warmup)
+    sol.profile(False)
+
     res = {}
     if not a.no_untiled:
-        wall_u, ev_u, launches_u, vu, su = run(sol, 0, a.steps, a.warmup)
+        wall_u, _, _, launches_u, vu, su = run(sol, 0, a.steps, a.warmup)
         rate_u = dofs * a.steps / wall_u
         num = torch.sqrt(((vt - vu) ** 2).sum() + ((st_ - su) ** 2).sum()).item()
         den = torch.sqrt((vu ** 2).sum() + (su ** 2).sum()).item()
-        res["untiled"] = {"value": rate_u, "ms_per_step": 1e3 * wall_u / a.steps, "launches_per_step":
-                          launches_u / a.steps}
+        res["untiled"] = {"value": rate_u, "ms_per_step": 1e3 * wall_u / a.steps,
+                          "launches_per_step": launches_u / a.steps, "cell_order": "hilbert (same as tiled)"}
         res["speedup_tiled_vs_untiled"] = rate_t / rate_u
         res["err_tiled_vs_untiled_rel_l2"] = num / den if den > 0 else 0.0
+        # the untiled chain on the mesh's own (randomly renumbered) cell order
+        raw = make(prec)
+        usteps = min(a.steps, 200)
+        wall_r, _, _, _, _, _ = run(raw, 0, usteps, a.warmup)
+        res["untiled_mesh_order"] = {"value": dofs * usteps / wall_r, "ms_per_step": 1e3 * wall_r / usteps,
+                                     "steps": usteps, "cell_order": "mesh numbering (random renumbering)"}
+        del raw
 
-    # algorithmic bytes: state read+written once, 9 per-cell invariants read once
+    # roofline of the tile kernel: algorithmic bytes (state read and written once, cell
+    # invariants read once per step) per launch over the launch's average duration.  The
+    # timed tiled region holds nothing but tile-kernel launches, back to back on the
+    # solver stream, so its HIP-event time over its launch count is that average (gaps
+    # included); the per-launch event pairs of the second run bound it from above.
     bytes_step = info["bytes_per_step"]
     launches_per_step = launches_t / a.steps
     bytes_launch = bytes_step / launches_per_step
     avg_launch_s = (ev_t / 1e3) / launches_t
     achieved = bytes_launch / avg_launch_s / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": "k_tile", "bytes_per_launch": bytes_launch, "avg_launch_us": avg_launch_s * 1e6}
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic(f"jitter{a.n}_p{k}", "f32" if prec else "f64", ts, splits),
+                "kernel": "k_tile_chain" if splits in ((13,), ()) else "k_tile_op",
+                "bytes_per_launch": bytes_launch, "avg_launch_us": avg_launch_s * 1e6,
+                "avg_launch_us_event_pairs": ker_p / launches_p * 1e3}
 
     # ---- oracle on the host: a bounded sample of the same workload
     cpu = None
@@ -199,7 +257,7 @@ def main():
         "err_vs_fp64_oracle_rel_l2": err_oracle,
         "inspector": {"gpu_ms": sched.get("inspector_gpu_ms"), "wall_s": t_insp_wall,
                       "subchains": sched.get("subchains"), "lds_bytes": info["lds_bytes"]},
-        "launches_per_step": launches_per_step,
+        "launches_per_step": launches_t / a.steps,
         "mesh_gen_s": t_gen,
     }
     out.update(res)

@@ -198,8 +198,16 @@ dgt_status dgt_step(dgt_solver *s, int64_t nsteps, int32_t mode, double t0);
  * in FP64 on the GPU.  v, sig_new, sig_old: device, caller layout, solver
  * precision.  Synchronises the stream. */
 dgt_status dgt_energy(dgt_solver *s, const void *v, const void *sig_new, const void *sig_old, double *out);
-/* Kernel-level timing of the last dgt_step (HIP events on the solver stream):
- * total ms, and ms spent in the dominant kernel with its launch count. */
+/* Per-launch timing switch (default off).  When on, the tiled executor of
+ * dgt_step records a HIP event pair on the solver stream around every tile
+ * kernel launch, so that dgt_last_step_timing reports the time spent inside
+ * tile kernels apart from launch gaps.  The events cost a little host time per
+ * launch: time throughput with it off.  on: 0 or 1, else DGT_EINVAL. */
+dgt_status dgt_solver_profile(dgt_solver *s, int32_t on);
+/* Timing of the last dgt_step (HIP events on the solver stream; synchronises
+ * with its end event): total_ms from the first to the last kernel of the call;
+ * kernel_ms the sum of the tile kernels' durations when per-launch timing was
+ * on for a tiled call, else equal to total_ms; launches: kernels launched. */
 dgt_status dgt_last_step_timing(const dgt_solver *s, double *total_ms, double *kernel_ms, int64_t *launches);
 /* Per-step algorithmic HBM bytes of the fused step (state read and written
  * once, cell invariants read once) and the LDS bytes per tile slot. */

@@ -8,6 +8,7 @@
 #include <numeric>
 
 #include "dg_device.h"
+#include "tile_chain.h"
 #include "tile_exec.h"
 
 namespace dgt {
@@ -31,7 +32,8 @@ struct SubPlan {
     int max_foot = 0;
     int threads = 256;
     TileKernel kind = TK_GENERIC;  // operator kernel for single-operator sub-chains
-    bool vel = false;  // workgroup size of the tile kernel
+    bool vel = false;
+    int o0 = 0, nops = 0;  // chain kernel: operators of the sub-chain  // workgroup size of the tile kernel
 };
 
 }  // namespace dgt
@@ -73,7 +75,21 @@ struct dgt_solver {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_ms = 0;
     int64_t last_launches = 0;
+    // per-launch timing of the tile kernels (event pairs of the last tiled call)
+    bool prof = false;
+    std::vector<hipEvent_t> pev;
+    size_t npev = 0;
+    void mark() {
+        if (!prof) return;
+        if (npev == pev.size()) {
+            hipEvent_t e;
+            DGT_HIP(hipEventCreate(&e));
+            pev.push_back(e);
+        }
+        DGT_HIP(hipEventRecord(pev[npev++], st));
+    }
     ~dgt_solver() {
+        for (auto e : pev) (void)hipEventDestroy(e);
         delete sched;
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
@@ -516,6 +532,55 @@ static void build_plan(dgt_solver *s) {
                 A.upd_loop = -1;
             }
         }
+        // a sub-chain of whole consecutive operator applications (each with its update, the
+        // last one's optional) runs on the chain kernel
+        if (P.kind == TK_GENERIC) {
+            const int order = s->p.time_order, nop = order == 4 ? 6 : 2;
+            int o = 0;
+            while (o < nop && op_first_loop(order, o) != sb.first) ++o;
+            const int first_op = o;
+            int j = sb.first;
+            const int end = sb.first + sb.n;
+            bool ok = o < nop;
+            while (ok && j < end && o < nop) {
+                const OpDesc D = op_desc(order, o);
+                const GLoop *g = &s->loops[j];
+                ok = j + 3 <= end && g[0].kind == (D.vel ? KV_VOL_V : KV_VOL_S) && g[0].in == D.in &&
+                     g[0].out == D.out && g[1].kind == (D.vel ? KV_INT_V : KV_INT_S) &&
+                     g[2].kind == (D.vel ? KV_EXT_V : KV_EXT_S) && A.loops[j - sb.first + 1].partner == j - sb.first + 2;
+                if (!ok) break;
+                j += 3;
+                if (order == 4) {
+                    ok = j < end && s->loops[j].kind == KV_SOLVE;
+                    ++j;
+                }
+                if (ok && D.upd && j < end) {
+                    const int k = s->loops[j].kind;
+                    ok = D.vel ? (k == KV_UPD_V || k == KV_UPD2_V) : (k == KV_UPD_S || k == KV_UPD2_S);
+                    ++j;
+                }
+                ++o;
+            }
+            const int nops = o - first_op;
+            bool known = false;
+            for (const auto &c : TILE_CHAINS) known |= c[0] == order && c[1] == first_op && c[2] == nops;
+            const int cap = s->K == 4 && s->esz == 8 ? TILE_NT[1] : TILE_NT[2];
+            const char *env = std::getenv("DGT_TILE_OP");
+            if (ok && j == end && known && A.nfl == nops && P.max_foot <= cap && !(env && std::atoi(env) == 0)) {
+                int w = 0;
+                for (int q = first_op; q < first_op + nops; ++q) {
+                    const OpDesc D = op_desc(order, q);
+                    const bool pn = D.pen >= 0 && s->loops[op_first_loop(order, q) + 1].pen >= 0;
+                    w = std::max(w, np * (D.vel ? 3 : 2) + (pn ? np * (D.vel ? 2 : 3) : 0));
+                }
+                A.nrow = 2 + w;
+                if (!(A.nrow & 1)) ++A.nrow;
+                P.kind = TK_CHAIN;
+                P.o0 = first_op;
+                P.nops = nops;
+                P.lds_bytes = (size_t)A.nrow * A.stride * s->esz;
+            }
+        }
         DGT_REQUIRE(P.lds_bytes <= budget, DGT_EUNSUPPORTED,
                     "tile footprint of " + std::to_string(P.max_foot) + " cells needs " +
                         std::to_string(P.lds_bytes) + " B of LDS (budget " + std::to_string(budget) +
@@ -524,6 +589,7 @@ static void build_plan(dgt_solver *s) {
         const int ng = P.kind == TK_OP || s->K <= 2 ? 1 : (s->K == 3 ? 2 : 3);
         const int items = A.stride * ng;
         P.threads = items <= TILE_NT[0] ? TILE_NT[0] : (items <= TILE_NT[1] ? TILE_NT[1] : TILE_NT[2]);
+        if (P.kind == TK_CHAIN) P.threads = std::max(P.threads, TILE_NT[1]);
         if (const char *e = std::getenv("DGT_TILE_THREADS"); e && P.kind == TK_GENERIC) P.threads = std::atoi(e);
     }
     DGT_HIP(hipStreamSynchronize(st));
@@ -610,7 +676,8 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
     hipStream_t st = s->st;
     const double dt = s->p.dt;
     for (auto &P : s->plan)
-        tile_launch<K, T>(P.kind, P.threads, P.vel, s->upw, s->haspen, 0, P.lds_bytes, st, P.args, true);
+        tile_launch<K, T>(P.kind, P.threads, P.vel, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, 0, P.lds_bytes,
+                          st, P.args, true);
     for (int64_t n = 0; n < nsteps; ++n) {
         const double th = t0 + ((double)n + 0.5) * dt;
         for (auto &P : s->plan) {
@@ -622,7 +689,10 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
                 const int ntiles = P.color_off[c + 1] - P.color_off[c];
                 if (ntiles == 0) continue;
                 A.tile_base = P.color_off[c];
-                tile_launch<K, T>(P.kind, P.threads, P.vel, s->upw, s->haspen, ntiles, P.lds_bytes, st, A, false);
+                s->mark();
+                tile_launch<K, T>(P.kind, P.threads, P.vel, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, ntiles,
+                                  P.lds_bytes, st, A, false);
+                s->mark();
                 ++launches;
             }
         }
@@ -851,6 +921,7 @@ dgt_status dgt_step(dgt_solver *s, int64_t nsteps, int32_t mode, double t0) {
         DGT_REQUIRE(mode == 0 || mode == 1, DGT_EINVAL, "mode must be 0 or 1");
         DGT_REQUIRE(mode == 0 || s->plan_status == DGT_OK, s->plan_status, s->plan_error);
         int64_t launches = 0;
+        s->npev = 0;
         DGT_HIP(hipEventRecord(s->ev0, s->st));
         dispatch(s, [&]<int K, typename T>() {
             if (mode == 0) step_untiled<K, T>(s, nsteps, t0, launches);
@@ -863,6 +934,13 @@ dgt_status dgt_step(dgt_solver *s, int64_t nsteps, int32_t mode, double t0) {
     });
 }
 
+dgt_status dgt_solver_profile(dgt_solver *s, int32_t on) {
+    return guard([&] {
+        DGT_REQUIRE(s && (on == 0 || on == 1), DGT_EINVAL, "bad arguments");
+        s->prof = on == 1;
+    });
+}
+
 dgt_status dgt_last_step_timing(const dgt_solver *s, double *total_ms, double *kernel_ms, int64_t *launches) {
     return guard([&] {
         DGT_REQUIRE(s, DGT_EINVAL, "solver is NULL");
@@ -870,7 +948,16 @@ dgt_status dgt_last_step_timing(const dgt_solver *s, double *total_ms, double *k
         float ms = 0;
         DGT_HIP(hipEventElapsedTime(&ms, s->ev0, s->ev1));
         if (total_ms) *total_ms = ms;
-        if (kernel_ms) *kernel_ms = ms;
+        double kms = ms;
+        if (s->npev >= 2) {
+            kms = 0;
+            for (size_t i = 0; i + 1 < s->npev; i += 2) {
+                float d = 0;
+                DGT_HIP(hipEventElapsedTime(&d, s->pev[i], s->pev[i + 1]));
+                kms += d;
+            }
+        }
+        if (kernel_ms) *kernel_ms = kms;
         if (launches) *launches = s->last_launches;
     });
 }

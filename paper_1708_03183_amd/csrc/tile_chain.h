@@ -1,0 +1,272 @@
+#pragma once
+// Tile executor for sub-chains made of several consecutive operator
+// applications of the DG time step (half a step or a whole step of the
+// leapfrog scheme).  One thread per footprint cell holds every field of its
+// cell in registers; before each operator the cells publish the traces their
+// neighbours read (the operator's input and penalty fields) to LDS.  The
+// gather at the start and the write-back at the end follow the same rule as
+// the other tile kernels (first access reads, written and needed elsewhere),
+// so the result is that of the chain executed in order.
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "dg_kernels.h"
+#include "refconst.h"
+#include "tile_args.h"
+
+namespace dgt {
+
+// The operator applications of one time step, in chain order (the chain the
+// solver builds: Taylor order 4 has six, leapfrog order 2 has two).
+struct OpDesc {
+    bool vel;     // velocity operator (stress-like input), else stress operator
+    int in, out;  // fields
+    int pen;      // penalty field (used when the flux is upwind), or -1
+    int upd;      // update after the operator: 0 none, 1 fourth order, 2 second order
+    int part;     // field added with weight dt by the fourth-order update, or -1
+};
+
+__host__ __device__ constexpr OpDesc op_desc(int order, int o) {
+    if (order == 2)
+        return o == 0 ? OpDesc{true, F_S, F_Z, F_V, 2, -1} : OpDesc{false, F_V, F_Z, F_S, 2, -1};
+    switch (o) {
+    case 0: return OpDesc{true, F_S, F_U, -1, 0, -1};
+    case 1: return OpDesc{false, F_U, F_X, -1, 0, -1};
+    case 2: return OpDesc{true, F_X, F_Z, F_V, 1, F_U};
+    case 3: return OpDesc{false, F_V, F_X, -1, 0, -1};
+    case 4: return OpDesc{true, F_X, F_U, -1, 0, -1};
+    default: return OpDesc{false, F_U, F_Z, F_S, 1, F_X};
+    }
+}
+
+// index of operator o's volume loop in the chain (each operator: volume,
+// interior facets, exterior facets, then a solve at order 4; updates after
+// operators 2 and 5 at order 4, after both at order 2)
+__host__ __device__ constexpr int op_first_loop(int order, int o) {
+    return order == 2 ? 4 * o : 4 * o + (o >= 3 ? 1 : 0);
+}
+
+__host__ __device__ constexpr int op_upd_loop(int order, int o) { return op_first_loop(order, o) + (order == 2 ? 3 : 4); }
+
+template <int K, typename T>
+struct CellRegs {
+    static constexpr int NP = np_of(K);
+    T f[F_COUNT][3][NP];  // fields of the cell (velocity-like ones use two components)
+    T g[G_NROWS];
+};
+
+template <int K, typename T, bool UPW, int ORDER, int O0, int O>
+__device__ __forceinline__ void chain_op(CellRegs<K, T> &r, const TileArgs &a, T *__restrict__ lds, int NR, bool act,
+                                         int s, uint32_t acc, const uint32_t (&nb)[3], int64_t x) {
+    constexpr int NP = np_of(K), NFP = K + 1;
+    constexpr OpDesc D = op_desc(ORDER, O);
+    constexpr int NI = D.vel ? 3 : 2, NO = D.vel ? 2 : 3;
+    constexpr int j0 = op_first_loop(ORDER, O) - op_first_loop(ORDER, O0);
+    constexpr int ju = op_upd_loop(ORDER, O) - op_first_loop(ORDER, O0);
+    constexpr int PO = 2 + NP * NI;  // penalty traces in a row; impedances at 0 and 1
+    const auto &Rf = R<K, T>();
+    const bool pen = D.pen >= 0 && a.loops[j0 + 1].pen >= 0;
+    T(&vin)[3][NP] = r.f[D.in];
+    T(&o)[3][NP] = r.f[D.out];
+
+    if (O > O0) __syncthreads();  // the neighbours have read the previous operator's traces
+    if (act) {
+        T *row = lds + (size_t)s * NR;
+        if (O == O0) {
+            row[0] = r.g[G_ZP];
+            row[1] = r.g[G_ZS];
+        }
+#pragma unroll
+        for (int c = 0; c < NI; ++c)
+#pragma unroll
+            for (int i = 0; i < NP; ++i) row[2 + c * NP + i] = vin[c][i];
+        if (D.pen >= 0 && pen) {
+#pragma unroll
+            for (int c = 0; c < NO; ++c)
+#pragma unroll
+                for (int i = 0; i < NP; ++i) row[PO + c * NP + i] = r.f[D.pen < 0 ? 0 : D.pen][c][i];
+        }
+    }
+    __syncthreads();
+    if (!act) return;
+
+    const T rx = r.g[G_RX], ry = r.g[G_RY], sx = r.g[G_SX], sy = r.g[G_SY];
+    if ((acc >> j0) & 1u) {  // volume term
+        const T scale = sizeof(T) == 8 ? (T)a.loops[j0].scale_d : (T)a.loops[j0].scale_f;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            T ar[NI], as[NI];
+#pragma unroll
+            for (int c = 0; c < NI; ++c) ar[c] = as[c] = 0;
+#pragma unroll
+            for (int jj = 0; jj < NP; ++jj) {
+                const T dr = Rf.Dr[i * NP + jj], ds = Rf.Ds[i * NP + jj];
+#pragma unroll
+                for (int c = 0; c < NI; ++c) {
+                    ar[c] += dr * vin[c][jj];
+                    as[c] += ds * vin[c][jj];
+                }
+            }
+            if constexpr (D.vel) {
+                const T irho = r.g[G_IRHO];
+                o[0][i] = scale * irho * ((rx * ar[0] + sx * as[0]) + (ry * ar[2] + sy * as[2]));
+                o[1][i] = scale * irho * ((rx * ar[2] + sx * as[2]) + (ry * ar[1] + sy * as[1]));
+            } else {
+                const T lam = r.g[G_LAM], mu = r.g[G_MU];
+                const T exx = rx * ar[0] + sx * as[0], eyy = ry * ar[1] + sy * as[1];
+                const T exy = T(0.5) * ((ry * ar[0] + sy * as[0]) + (rx * ar[1] + sx * as[1]));
+                o[0][i] = scale * ((lam + 2 * mu) * exx + lam * eyy);
+                o[1][i] = scale * (lam * exx + (lam + 2 * mu) * eyy);
+                o[2][i] = scale * (2 * mu * exy);
+            }
+        }
+    }
+    if ((nb[0] | nb[1] | nb[2]) & NB_VALID) {  // this cell's side of the operator's facets in the tile
+        const T scale = sizeof(T) == 8 ? (T)a.loops[j0 + 1].scale_d : (T)a.loops[j0 + 1].scale_f;
+        const T psc = pen ? (sizeof(T) == 8 ? (T)a.loops[j0 + 1].pscale_d : (T)a.loops[j0 + 1].pscale_f) : T(0);
+        const T(&vp)[3][NP] = r.f[D.pen < 0 ? D.out : D.pen];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            const uint32_t code = nb[p];
+            if (!(code & NB_VALID)) continue;
+            T nx, ny, fs;
+            facet_normal<T>(p, rx, ry, sx, sy, nx, ny, fs);
+            const bool bnd = code & NB_BND;
+            const int l1 = (code >> 14) & 3;
+            const T *row1 = lds + (size_t)(code & 0x3fff) * NR;
+            const T zp1 = row1[0], zs1 = row1[1];
+            T gq[NFP][3];
+#pragma unroll
+            for (int m = 0; m < NFP; ++m) {
+                const int n0 = fnode(K, p, m);
+                const int n1 = l1 == 0 ? fnode(K, 0, K - m) : (l1 == 1 ? fnode(K, 1, K - m) : fnode(K, 2, K - m));
+                T a0[NI], p0[NO];
+#pragma unroll
+                for (int c = 0; c < NI; ++c) a0[c] = vin[c][n0];
+#pragma unroll
+                for (int c = 0; c < NO; ++c) p0[c] = pen ? vp[c][n0] : T(0);
+                gq[m][0] = gq[m][1] = gq[m][2] = 0;
+                if (bnd) {
+                    const bool fr = code & NB_FREE;
+                    if constexpr (D.vel)
+                        flux_v_ext<T, UPW, true>(a0, p0, fr, nx, ny, r.g[G_ZP], r.g[G_ZS], fs * r.g[G_IRHO], scale,
+                                                 psc, gq[m]);
+                    else
+                        flux_s_ext<T, UPW, true>(a0, p0, fr, nx, ny, r.g[G_ZP], r.g[G_ZS], r.g[G_LAM], r.g[G_MU], fs,
+                                                 scale, psc, gq[m]);
+                } else {
+                    T a1[NI], p1[NO], g1[3];
+#pragma unroll
+                    for (int c = 0; c < NI; ++c) a1[c] = row1[2 + c * NP + n1];
+#pragma unroll
+                    for (int c = 0; c < NO; ++c) p1[c] = pen ? row1[PO + c * NP + n1] : T(0);
+                    if constexpr (D.vel)
+                        flux_v_int<T, UPW, true>(a0, a1, p0, p1, nx, ny, r.g[G_ZP], r.g[G_ZS], zp1, zs1,
+                                                 fs * r.g[G_IRHO], T(0), scale, psc, gq[m], g1);
+                    else
+                        flux_s_int<T, UPW, true>(a0, a1, p0, p1, nx, ny, r.g[G_ZP], r.g[G_ZS], zp1, zs1, r.g[G_LAM],
+                                                 r.g[G_MU], T(0), T(0), fs, T(0), scale, psc, gq[m], g1);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NP; ++i)
+#pragma unroll
+                for (int m = 0; m < NFP; ++m) {
+                    const T lv = Rf.lift[(p * NP + i) * NFP + m];
+#pragma unroll
+                    for (int c = 0; c < NO; ++c) o[c][i] += lv * gq[m][c];
+                }
+        }
+    }
+    if constexpr (D.upd != 0) {  // the update consuming this operator's output
+        if (ju < a.nloops && ((acc >> ju) & 1u)) {
+            T(&q)[3][NP] = r.f[D.vel ? F_V : F_S];
+            const T dt = (T)a.dt;
+            const bool src = !D.vel && x == a.src_cell;
+            const T *sv = reinterpret_cast<const T *>(a.src_vec);
+#pragma unroll
+            for (int c = 0; c < NO; ++c)
+#pragma unroll
+                for (int i = 0; i < NP; ++i) {
+                    T add = o[c][i];
+                    if constexpr (D.upd == 1) add = dt * r.f[D.part < 0 ? 0 : D.part][c][i] + add;
+                    if (src && c < 2) add += (T)a.src_amp * sv[i];
+                    q[c][i] += add;
+                }
+        }
+    }
+}
+
+template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int NT>
+__global__ __launch_bounds__(NT) void k_tile_chain(const TileArgs a) {
+    constexpr int NP = np_of(K);
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *lds = reinterpret_cast<T *>(smem);
+    const int tile = a.tiles[a.tile_base + blockIdx.x];
+    const int f0 = a.foot_off[tile];
+    const int nfoot = a.foot_off[tile + 1] - f0;
+    const int s = threadIdx.x;
+    const bool act = s < nfoot;
+    const int64_t nc = a.nc;
+
+    CellRegs<K, T> r;
+    uint32_t acc = 0, nb[NOPS][3];
+    int64_t x = 0;
+    uint16_t fl = 0;
+#pragma unroll
+    for (int q = 0; q < NOPS; ++q) nb[q][0] = nb[q][1] = nb[q][2] = 0;
+#pragma unroll
+    for (int f = 0; f < F_COUNT; ++f)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int i = 0; i < NP; ++i) r.f[f][c][i] = 0;
+    if (act) {
+        acc = a.facc[f0 + s];
+        x = a.foot[f0 + s];
+        const bool single = acc >> 31;
+#pragma unroll
+        for (int f = 0; f < F_COUNT; ++f) {
+            const uint32_t m = acc & a.loops_mask[f];
+            if (m && ((m & (~m + 1u)) & a.rfirst_mask[f])) fl |= 1u << f;
+            if ((acc & a.writes_mask[f]) && (((a.persistent_mask >> f) & 1) || !single)) fl |= 1u << (8 + f);
+        }
+        const int b0 = a.tnb_off[tile];
+#pragma unroll
+        for (int q = 0; q < NOPS; ++q)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) nb[q][p] = a.tnb[b0 + (q * 3 + p) * nfoot + s];
+        const T *geo = reinterpret_cast<const T *>(a.geo);
+#pragma unroll
+        for (int q = 0; q < G_NROWS; ++q) r.g[q] = geo[(int64_t)q * nc + x];
+#pragma unroll
+        for (int f = 0; f < F_COUNT; ++f) {
+            if (!((fl >> f) & 1)) continue;
+            const T *F = reinterpret_cast<const T *>(a.F[f]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (c >= field_ncomp(f)) break;
+#pragma unroll
+                for (int i = 0; i < NP; ++i) r.f[f][c][i] = F[(int64_t)(c * NP + i) * nc + x];
+            }
+        }
+    }
+    [&]<int... Q>(std::integer_sequence<int, Q...>) {
+        (chain_op<K, T, UPW, ORDER, O0, O0 + Q>(r, a, lds, a.nrow, act, s, acc, nb[Q], x), ...);
+    }(std::make_integer_sequence<int, NOPS>{});
+    if (!act) return;
+#pragma unroll
+    for (int f = 0; f < F_COUNT; ++f) {
+        if (!((fl >> (8 + f)) & 1)) continue;
+        T *F = reinterpret_cast<T *>(a.F[f]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (c >= field_ncomp(f)) break;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) F[(int64_t)(c * NP + i) * nc + x] = r.f[f][c][i];
+        }
+    }
+}
+
+}  // namespace dgt

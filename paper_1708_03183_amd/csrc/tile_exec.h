@@ -8,7 +8,10 @@
 
 namespace dgt {
 
-enum TileKernel { TK_GENERIC = 0, TK_OP = 1 };
+enum TileKernel { TK_GENERIC = 0, TK_OP = 1, TK_CHAIN = 2 };
+
+// operator sequences the chain kernel is built for: (time order, first operator, operators)
+constexpr int TILE_CHAINS[4][3] = {{4, 0, 3}, {4, 3, 3}, {4, 0, 6}, {2, 0, 2}};
 
 // Copies the reference element into the constant memory of the degree-K unit.
 template <int K, typename T>
@@ -18,10 +21,11 @@ void tile_upload_ref(const RefElem &E, hipStream_t st);
 // limit) one colour of a sub-chain.  Generic kernel: any sub-chain, nt work
 // items per tile.  Operator kernel: one operator application (vel selects the
 // velocity operator) with an optional trailing update; needs nt >= the
-// largest footprint.
+// largest footprint.  Chain kernel: operators [o0, o0 + nops) of the order-`order`
+// step (one of TILE_CHAINS), nt >= the largest footprint.
 template <int K, typename T>
-void tile_launch(TileKernel kind, int nt, bool vel, bool upw, bool pen, int grid, size_t lds, hipStream_t st,
-                 const TileArgs &A, bool attr);
+void tile_launch(TileKernel kind, int nt, bool vel, bool upw, bool pen, int order, int o0, int nops, int grid,
+                 size_t lds, hipStream_t st, const TileArgs &A, bool attr);
 
 // workgroup sizes the tile kernels are built for
 constexpr int TILE_NT[3] = {128, 256, 512};

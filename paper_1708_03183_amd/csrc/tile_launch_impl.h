@@ -3,6 +3,7 @@
 // each tile_k*.hip unit).
 #include "common.h"
 #include "tile_exec.h"
+#include "tile_chain.h"
 #include "tile_kernel.h"
 
 namespace dgt {
@@ -14,6 +15,20 @@ static void tile_go(Kern kern, int nt, int grid, size_t lds, hipStream_t st, con
         return;
     }
     kern<<<grid, nt, lds, st>>>(A);
+}
+
+template <int K, typename T, int NT>
+static void tile_launch_chain(bool upw, int order, int o0, int nops, int grid, size_t lds, hipStream_t st,
+                              const TileArgs &A, bool attr) {
+    auto pick = [&]<int ORD, int O0, int N>() {
+        auto kern = upw ? k_tile_chain<K, T, true, ORD, O0, N, NT> : k_tile_chain<K, T, false, ORD, O0, N, NT>;
+        tile_go(kern, NT, grid, lds, st, A, attr);
+    };
+    if (order == 4 && o0 == 0 && nops == 3) pick.template operator()<4, 0, 3>();
+    else if (order == 4 && o0 == 3 && nops == 3) pick.template operator()<4, 3, 3>();
+    else if (order == 4 && o0 == 0 && nops == 6) pick.template operator()<4, 0, 6>();
+    else if (order == 2 && o0 == 0 && nops == 2) pick.template operator()<2, 0, 2>();
+    else DGT_REQUIRE(false, DGT_EINVAL, "no chain kernel for this operator sequence");
 }
 
 template <int K, typename T, int NT>
@@ -30,32 +45,31 @@ static void tile_launch_nt(TileKernel kind, bool vel, bool upw, bool pen, int gr
     }
 }
 
-template <>
-void tile_launch<DGT_TILE_K, double>(TileKernel kind, int nt, bool vel, bool upw, bool pen, int grid, size_t lds,
-                                     hipStream_t st, const TileArgs &A, bool attr);
-template <>
-void tile_launch<DGT_TILE_K, float>(TileKernel kind, int nt, bool vel, bool upw, bool pen, int grid, size_t lds,
-                                    hipStream_t st, const TileArgs &A, bool attr);
-
 template <int K, typename T>
-static void tile_launch_any(TileKernel kind, int nt, bool vel, bool upw, bool pen, int grid, size_t lds,
-                            hipStream_t st, const TileArgs &A, bool attr) {
+static void tile_launch_any(TileKernel kind, int nt, bool vel, bool upw, bool pen, int order, int o0, int nops,
+                            int grid, size_t lds, hipStream_t st, const TileArgs &A, bool attr) {
     DGT_REQUIRE(nt == 128 || nt == 256 || nt == 512, DGT_EINVAL, "tile workgroup size must be 128, 256 or 512");
+    if (kind == TK_CHAIN) {
+        DGT_REQUIRE(nt != 128, DGT_EINVAL, "the chain kernel runs with 256 or 512 work items");
+        if (nt == 512) tile_launch_chain<K, T, 512>(upw, order, o0, nops, grid, lds, st, A, attr);
+        else tile_launch_chain<K, T, 256>(upw, order, o0, nops, grid, lds, st, A, attr);
+        return;
+    }
     if (nt == 512) tile_launch_nt<K, T, 512>(kind, vel, upw, pen, grid, lds, st, A, attr);
     else if (nt == 256) tile_launch_nt<K, T, 256>(kind, vel, upw, pen, grid, lds, st, A, attr);
     else tile_launch_nt<K, T, 128>(kind, vel, upw, pen, grid, lds, st, A, attr);
 }
 
 template <>
-void tile_launch<DGT_TILE_K, double>(TileKernel kind, int nt, bool vel, bool upw, bool pen, int grid, size_t lds,
-                                     hipStream_t st, const TileArgs &A, bool attr) {
-    tile_launch_any<DGT_TILE_K, double>(kind, nt, vel, upw, pen, grid, lds, st, A, attr);
+void tile_launch<DGT_TILE_K, double>(TileKernel kind, int nt, bool vel, bool upw, bool pen, int order, int o0, int nops,
+                                     int grid, size_t lds, hipStream_t st, const TileArgs &A, bool attr) {
+    tile_launch_any<DGT_TILE_K, double>(kind, nt, vel, upw, pen, order, o0, nops, grid, lds, st, A, attr);
 }
 
 template <>
-void tile_launch<DGT_TILE_K, float>(TileKernel kind, int nt, bool vel, bool upw, bool pen, int grid, size_t lds,
-                                    hipStream_t st, const TileArgs &A, bool attr) {
-    tile_launch_any<DGT_TILE_K, float>(kind, nt, vel, upw, pen, grid, lds, st, A, attr);
+void tile_launch<DGT_TILE_K, float>(TileKernel kind, int nt, bool vel, bool upw, bool pen, int order, int o0, int nops,
+                                    int grid, size_t lds, hipStream_t st, const TileArgs &A, bool attr) {
+    tile_launch_any<DGT_TILE_K, float>(kind, nt, vel, upw, pen, order, o0, nops, grid, lds, st, A, attr);
 }
 
 template <>

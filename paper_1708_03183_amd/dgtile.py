@@ -74,6 +74,7 @@ _SIGS = {
     "dgt_step": [_p, C.c_int64, C.c_int32, C.c_double],
     "dgt_energy": [_p, _p, _p, _p, C.POINTER(C.c_double)],
     "dgt_last_step_timing": [_p, C.POINTER(C.c_double), C.POINTER(C.c_double), _i64],
+    "dgt_solver_profile": [_p, C.c_int32],
     "dgt_solver_info": [_p, _i64, _i64, _i64],
     "dgt_solver_destroy": [_p],
     "dgt_last_error": [],
@@ -328,6 +329,10 @@ class Solver:
         _check(lib().dgt_energy(self.h, C.c_void_p(v.data_ptr()), C.c_void_p(s_new.data_ptr()),
                                 C.c_void_p(s_old.data_ptr()), C.byref(out)))
         return out.value
+
+    def profile(self, on: bool):
+        """Per-launch event timing of the tile kernels on (off by default)."""
+        _check(lib().dgt_solver_profile(self.h, 1 if on else 0))
 
     def last_timing(self):
         tot, ker, n = C.c_double(), C.c_double(), C.c_int64()

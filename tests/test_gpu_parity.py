@@ -214,6 +214,39 @@ def test_tiled_operator_kernel_fp32_matches_oracle(D, k):
     assert err <= 1e-5
 
 
+CHAIN_CASES = [
+    # n, k, order, flux, free, ren, steps, ts, splits: whole-step and half-step sub-chains
+    (12, 2, 4, 1, 0x8, 7, 10, 24, ()),
+    (12, 2, 4, 0, 0xF, 7, 10, 24, (13,)),
+    (12, 2, 2, 1, 0x8, 7, 10, 24, ()),
+    (10, 1, 4, 1, 0x8, 3, 10, 32, ()),
+    (10, 3, 4, 1, 0x8, 5, 10, 12, (13,)),
+    (10, 4, 4, 1, 0x0, 5, 10, 6, (13,)),
+    (16, 2, 4, 1, 0x8, None, 8, 40, (13,)),  # structured mesh in input order
+]
+
+
+@pytest.mark.parametrize("kernel", ["generic", "specialised"])
+@pytest.mark.parametrize("n,k,order,flux,free,ren,steps,ts,splits", CHAIN_CASES)
+def test_tiled_chain_kernels_fp64_match_oracle(D, monkeypatch, kernel, n, k, order, flux, free, ren, steps, ts,
+                                               splits):
+    """The same schedule on the generic in-tile executor (every field in LDS)
+    and on the register-resident chain kernel."""
+    if kernel == "generic":
+        monkeypatch.setenv("DGT_TILE_OP", "0")
+    err = _run_pair(D, n, k, order, flux, free, ren, steps, mode=1, ts=ts, splits=splits)
+    print(f"{kernel} tiled FP64 n={n} k={k} order={order} flux={flux} ts={ts} splits={splits}: rel L2 err {err:.3e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("splits", [(), (13,)])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_tiled_chain_kernel_fp32_matches_oracle(D, k, splits):
+    err = _run_pair(D, 10, k, 4, 1, 0x8, 4, 5, mode=1, ts=8 if k == 4 else 16, splits=splits, prec=1)
+    print(f"chain-kernel tiled FP32 k={k} splits={splits}: rel L2 err vs FP64 oracle {err:.3e}")
+    assert err <= 1e-5
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_fp32_matches_oracle(D, mode, k):
