@@ -282,13 +282,13 @@ struct TileDesc {
     int32_t arity;
 };
 
-struct TileArgs {
+struct LoopTilingArgs {
     int32_t nd;
     TileDesc d[8];
 };
 
 // Alg. 4: sigma_j[e] = MAX over descriptors and slots of the projections
-__global__ void k_tile(TileArgs a, int64_t n, const int32_t *__restrict__ deft, int32_t *__restrict__ sigma) {
+__global__ void k_tile_loop(LoopTilingArgs a, int64_t n, const int32_t *__restrict__ deft, int32_t *__restrict__ sigma) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     uint64_t best = 0;
@@ -640,7 +640,7 @@ void Inspector::run_sub(Schedule &S, SubSched &sb, int64_t ts, int partition, co
             }
             // tile L_j (Alg. 4)
             const ChainLoop &L = chain.loops[j];
-            TileArgs ta{};
+            LoopTilingArgs ta{};
             ta.nd = 0;
             for (int i = 0; i < L.ndesc; ++i) {
                 const int mp = L.d[i].map;
@@ -652,7 +652,7 @@ void Inspector::run_sub(Schedule &S, SubSched &sb, int64_t ts, int partition, co
                 ta.d[ta.nd++] = d;
             }
             const int64_t nj = chain.size[L.set];
-            if (nj) k_tile<<<blocks_for(nj, 256), 256, 0, st>>>(ta, nj, deft.p, S.sigma[j].p);
+            if (nj) k_tile_loop<<<blocks_for(nj, 256), 256, 0, st>>>(ta, nj, deft.p, S.sigma[j].p);
         }
         // conflicts (all sets, all loops of the sub-chain)
         int64_t nconf = conflicts(first, nl, sb.color, edges, ne);

@@ -12,11 +12,16 @@
   reading of the projection algorithm;
 * the tiled DG chain equals the untiled one to rounding (<= 1e-14 relative).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
 import oracle as O
 from paper_1708_03183_amd import inputs as I
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "running_example_sec3.json")))
 
 
 def _wheel_chain():
@@ -38,27 +43,34 @@ def _wheel_chain():
 
 
 def test_worked_example_projection_and_tiling():
+    g = GOLDEN
+    order = g["colour_order"]
     ch = _wheel_chain()
     # green tile T0 holds spokes e0, e1 and rim edges e7, e8, e13; blue tile T1 the rest
     tile0 = np.ones(14, np.int32)
     tile0[[0, 1, 7, 8, 13]] = 0
-    color = np.array([0, 1], np.int32)  # G = 0 before B = 1
+    spokes = tile0[:7]
+    assert (len(spokes), int((spokes == 0).sum()), int((spokes == 1).sum())) == (
+        g["projection"]["incident_edges"], g["projection"]["green_edges"], g["projection"]["blue_edges"])
+    color = np.array([order["green"], order["blue"]], np.int32)  # tile 0 green, tile 1 blue
     phi = ch.projection_after(tile0, 2, color, 1, 2, 8)
-    assert phi[0] == 1   # v0: 2 green + 5 blue incident edges -> blue
+    assert phi[0] == 1 and color[phi[0]] == order[g["projection"]["phi_v0"]]
     assert phi[1] == 0 and phi[2] == 0   # v1, v2 touch only green edges
+    assert [int(color[phi[v]]) for v in (0, 1, 2)] == [order[c] for c in g["cell_tiling"]["vertex_projections"]]
     sig = ch.tile_with_colors(tile0, 2, color, [14, 7, 14])
     # cell c0 = (v0, v1, v2): MAX(B, G, G) = B
-    assert sig[1][0] == 1
+    assert sig[1][0] == g["cell_tiling"]["sigma"]
 
 
 def test_inverse_map_example():
     # Fig. 8: cell 1 -> vertices {3, 7, 9}; the inverse map lists cell 1 under each
-    c2v = np.array([[0, 1, 2], [3, 7, 9], [2, 3, 4]], np.int32)
+    ex = GOLDEN["inverse_map"]
+    c2v = np.array([[0, 1, 2], ex["vertices"], [2, 3, 4]], np.int32)
     inv = {}
     for c, vs in enumerate(c2v):
         for v in vs:
             inv.setdefault(int(v), []).append(c)
-    assert all(1 in inv[v] for v in (3, 7, 9))
+    assert all(ex["cell"] in inv[v] for v in ex["vertices"])
     # the oracle's projection realises exactly this: a tile written only by cell 1
     ch = O.OChain()
     Cs = ch.set(3)
@@ -67,7 +79,6 @@ def test_inverse_map_example():
     ch.loop(Cs, [(m, O.INC, 0)])
     ch.loop(V, [(-1, O.R, 0)])
     phi = ch.projection_after(np.array([0, 1, 2], np.int32), 3, np.array([0, 1, 2], np.int32), 1, V, 10)
-    assert list(phi[[3, 7, 9]]) == [2, 1, 1] or list(phi[[7, 9]]) == [1, 1]
     assert phi[7] == 1 and phi[9] == 1 and phi[3] == 2  # vertex 3 also touched by cell 2 (higher colour)
 
 
