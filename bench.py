@@ -5,7 +5,8 @@ Workload (default): 512x512 jittered (0.2h) and randomly renumbered unit-square
 triangulation, 524288 cells, DG P2 velocity-stress elastic, three-layer
 material, upwind flux, free surface on top and absorbing elsewhere, Ricker
 source at (0.5, 0.5), 4th-order Taylor leapfrog (26 loops per step), tiles
-grown from 128 seed cells in Hilbert order, the chain fused per half step.
+grown from 128 seed cells in Hilbert order, the chain fused per half step,
+tiles of a half step started by dependence counters in one launch.
 
 Prints ONE JSON line.  `value` is the tiled-fused rate in dof-updates/s (5
 fields x Np nodes x cells per step, per second) with the state resident in HBM.
@@ -39,6 +40,10 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--tile-size", type=int, default=None)
     ap.add_argument("--splits", type=str, default=None, help="comma-separated loop indices, or 'none'")
+    ap.add_argument("--colour-cap", type=int, default=0,
+                    help="tiles per colour class: -1 the GPU's resident tile workgroups, 0 uncapped")
+    ap.add_argument("--schedule", type=int, default=1,
+                    help="tiled executor: 0 one launch per colour, 1 dependence-driven (one launch per sub-chain)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-untiled", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
@@ -61,7 +66,7 @@ DEFAULTS = {
 TILE_SOURCES = ("tile_chain.h", "dg_kernels.h", "tile_args.h")
 
 
-def measured_traffic(workload, dtype, ts, splits):
+def measured_traffic(workload, dtype, ts, splits, schedule):
     """HBM bytes per tile-kernel launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary of this configuration, scaled by the copy calibration; None
     when there is none or when the kernel's sources changed since it was taken."""
@@ -73,7 +78,7 @@ def measured_traffic(workload, dtype, ts, splits):
             h.update(fh.read())
     sha = h.hexdigest()[:16]
     want = {"workload": workload, "dtype": dtype, "tile_size": str(ts), "splits": ",".join(map(str, splits)),
-            "src_sha": sha}
+            "schedule": str(schedule), "src_sha": sha}
     for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
         with open(path) as fh:
             for line in fh:
@@ -139,7 +144,8 @@ def main():
     sol = make(prec)
     torch.cuda.synchronize()
     ti0 = time.time()
-    sol.inspect(ts, partition=1, splits=splits)
+    sol.inspect(ts, partition=1, splits=splits, max_colour_tiles=a.colour_cap)
+    sol.set_schedule(a.schedule)
     torch.cuda.synchronize()
     t_insp_wall = time.time() - ti0
     sched = json.loads(sol.schedule().summary())
@@ -198,7 +204,7 @@ def main():
     achieved = bytes_launch / avg_launch_s / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic(f"jitter{a.n}_p{k}", "f32" if prec else "f64", ts, splits),
+                "traffic": measured_traffic(f"jitter{a.n}_p{k}", "f32" if prec else "f64", ts, splits, a.schedule),
                 "kernel": "k_tile_chain" if splits in ((13,), ()) else "k_tile_op",
                 "bytes_per_launch": bytes_launch, "avg_launch_us": avg_launch_s * 1e6,
                 "avg_launch_us_event_pairs": ker_p / launches_p * 1e3}
@@ -224,7 +230,8 @@ def main():
                          f"({tcpu:.1f} s, FP64, single thread)"}
         # GPU FP64 tiled from the same state, compared with the oracle
         chk = make(0)
-        chk.inspect(ts, partition=1, splits=splits)
+        chk.inspect(ts, partition=1, splits=splits, max_colour_tiles=a.colour_cap)
+        chk.set_schedule(a.schedule)
         gv = torch.from_numpy(np.ascontiguousarray(vt.double().cpu().numpy())).cuda()
         gs = torch.from_numpy(np.ascontiguousarray(st_.double().cpu().numpy())).cuda()
         chk.upload(gv, gs)
@@ -251,7 +258,8 @@ def main():
         "config": {"workload": f"jitter{a.n}_p{k}: {a.n}x{a.n} jittered renumbered triangulation, "
                                f"{mesh.nc} cells, DG P{k}, 3-layer, upwind, order-4 leapfrog",
                    "cells": mesh.nc, "dofs_per_step": dofs, "tile_size": ts, "splits": list(splits),
-                   "partition": "hilbert"},
+                   "partition": "hilbert", "colour_cap": a.colour_cap,
+                   "schedule": "dependence-driven" if a.schedule == 1 else "colour launches"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "err_vs_fp64_oracle_rel_l2": err_oracle,

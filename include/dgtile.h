@@ -101,6 +101,16 @@ typedef struct {
                                      starts; each sub-chain has <= 31 loops and
                                      is inspected independently */
     int32_t nsplits;
+    int32_t max_colour_tiles;     /* 0: colour classes as Jones-Plassmann leaves them;
+                                     > 0: after each colouring, a deterministic
+                                     greedy pass (tiles in ascending id) moves tiles
+                                     out of classes larger than this into the
+                                     smallest colour with room that no neighbour
+                                     has, or into a new colour, so that no colour
+                                     launch needs more than one round of resident
+                                     workgroups.  -1 (dgt_solver_inspect only): the
+                                     solver picks the number of tile workgroups the
+                                     GPU holds at once when a class exceeds it. */
 } dgt_inspect_params;
 
 /* Run the inspector on the GPU (Alg. 1 with Alg. 3 projections and Alg. 4
@@ -198,6 +208,16 @@ dgt_status dgt_step(dgt_solver *s, int64_t nsteps, int32_t mode, double t0);
  * in FP64 on the GPU.  v, sig_new, sig_old: device, caller layout, solver
  * precision.  Synchronises the stream. */
 dgt_status dgt_energy(dgt_solver *s, const void *v, const void *sig_new, const void *sig_old, double *out);
+/* Schedule of the tiled executor (default 0).  0: one kernel launch per colour
+ * of every sub-chain (Alg. 2's colour loop).  1: sub-chains that run on the
+ * chain kernel (whole operator applications) launch once; workgroups take tiles
+ * in colour order from a ticket counter and a tile starts when every tile of a
+ * lower colour whose footprint meets its own has finished (device-scope
+ * counters, release/acquire), so no colour waits for a whole earlier colour.
+ * Every wait is bounded: if one gives up, the next dgt_step or
+ * dgt_state_download returns DGT_ESTATE and the counters are reset.  In mode 1,
+ * dgt_step synchronises the stream on entry.  mode: 0 or 1, else DGT_EINVAL. */
+dgt_status dgt_solver_set_schedule(dgt_solver *s, int32_t mode);
 /* Per-launch timing switch (default off).  When on, the tiled executor of
  * dgt_step records a HIP event pair on the solver stream around every tile
  * kernel launch, so that dgt_last_step_timing reports the time spent inside

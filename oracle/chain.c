@@ -218,8 +218,35 @@ static void edges_add_sorted_unique(edges_t *E) {
     E->n = w;
 }
 
-/* Jones-Plassmann colouring (R5); returns ncolors or -1 */
-static int colour_tiles(int ntiles, const edges_t *E, int32_t *color) {
+/* Colour-class cap (R5b, used when cap > 0): one pass over the tiles in
+ * ascending id; a tile whose colour class holds more than cap tiles moves to the
+ * smallest colour that holds fewer than cap tiles and that no neighbour has, or
+ * to a new colour.  Afterwards every class holds at most cap tiles and the
+ * colouring is still proper.  Returns the new number of colours, or -1 past 64. */
+static int cap_colour_classes(int ntiles, const int32_t *deg, const int32_t *adj, int32_t *color, int ncol,
+                              int cap) {
+    int32_t size[64] = {0};
+    for (int t = 0; t < ntiles; t++) size[color[t]]++;
+    for (int t = 0; t < ntiles; t++) {
+        int c = color[t];
+        if (size[c] <= cap) continue;
+        uint64_t used = 0;
+        for (int32_t k = deg[t]; k < deg[t + 1]; k++) used |= 1ull << color[adj[k]];
+        int c2 = 0;
+        while (c2 < ncol && (c2 == c || size[c2] >= cap || ((used >> c2) & 1))) c2++;
+        if (c2 == ncol) {
+            if (ncol >= 64) return -1;
+            ncol++;
+        }
+        color[t] = c2;
+        size[c]--;
+        size[c2]++;
+    }
+    return ncol;
+}
+
+/* Jones-Plassmann colouring (R5), then the class cap (R5b); returns ncolors or -1 */
+static int colour_tiles(int ntiles, const edges_t *E, int32_t *color, int cap) {
     /* symmetric adjacency CSR */
     int32_t *deg = calloc(ntiles + 1, sizeof(int32_t));
     for (int64_t i = 0; i < E->n; i++) {
@@ -271,6 +298,7 @@ static int colour_tiles(int ntiles, const edges_t *E, int32_t *color) {
             remaining--;
         }
     }
+    if (cap > 0) ncol = cap_colour_classes(ntiles, deg, adj, color, ncol, cap);
     free(deg);
     free(adj);
     free(mark);
@@ -519,7 +547,8 @@ int or_projection_after(const or_chain *c, const int32_t *tile0, int ntiles, con
 }
 
 static int inspect_sub(const or_chain *c, or_sched *s, sub_t *sb, int64_t ts, int partition, const double *seed_xy,
-                       int max_rounds) {
+                       int max_rounds,
+                       int cap) {
     int first = sb->first, nl = sb->n;
     int seedset = c->loops[first].set;
     int64_t n0 = c->size[seedset];
@@ -535,7 +564,7 @@ static int inspect_sub(const or_chain *c, or_sched *s, sub_t *sb, int64_t ts, in
     int32_t *color = malloc(sizeof(int32_t) * ntiles);
     int round, ncol = 0;
     for (round = 0; round < max_rounds; round++) {
-        ncol = colour_tiles(ntiles, &adj, color);
+        ncol = colour_tiles(ntiles, &adj, color, cap);
         if (ncol < 0) { free(tile0); free(color); free(adj.e); return -3; }
         uint64_t *Phi[MAXSETS] = {0};
         memcpy(s->sigma[first], tile0, sizeof(int32_t) * n0);
@@ -594,9 +623,9 @@ static int inspect_sub(const or_chain *c, or_sched *s, sub_t *sb, int64_t ts, in
 }
 
 int or_inspect(const or_chain *c, int64_t ts, int partition, const double *seed_xy, int max_rounds,
-               const int32_t *splits, int nsplits, or_sched **out) {
+               int max_colour_tiles, const int32_t *splits, int nsplits, or_sched **out) {
     *out = NULL;
-    if (ts < 1 || c->nloops == 0 || max_rounds < 1) return -1;
+    if (ts < 1 || c->nloops == 0 || max_rounds < 1 || max_colour_tiles < 0) return -1;
     or_sched *s = calloc(1, sizeof(*s));
     s->nloops = c->nloops;
     for (int j = 0; j < c->nloops; j++) {
@@ -611,7 +640,7 @@ int or_inspect(const or_chain *c, int64_t ts, int partition, const double *seed_
         sb->first = start;
         sb->n = end - start;
         for (int j = start; j < end; j++) s->sub_of[j] = s->nsub - 1;
-        int rc = inspect_sub(c, s, sb, ts, partition, seed_xy, max_rounds);
+        int rc = inspect_sub(c, s, sb, ts, partition, seed_xy, max_rounds, max_colour_tiles);
         if (rc) { or_sched_free(s); return rc; }
         start = end;
     }

@@ -22,7 +22,7 @@ extern "C" {
 
 const char *dgt_last_error(void) { return g_last_error.c_str(); }
 
-int dgt_version(void) { return 100; }
+int dgt_version(void) { return 101; }
 
 dgt_status dgt_chain_create(dgt_chain **out) {
     return guard([&] {
@@ -96,7 +96,9 @@ dgt_status dgt_inspect(const dgt_chain *c, const dgt_inspect_params *p, void *st
         hipStream_t st = (hipStream_t)stream;
         Inspector insp(sch->chain_copy, st);
         std::vector<int32_t> splits(p->splits, p->splits + p->nsplits);
-        sch->s = insp.run(p->tile_size, p->partition, p->seed_xy, nullptr, p->max_conflict_rounds, splits);
+        DGT_REQUIRE(p->max_colour_tiles >= 0, DGT_EINVAL, "max_colour_tiles must be >= 0");
+        sch->s = insp.run(p->tile_size, p->partition, p->seed_xy, nullptr, p->max_conflict_rounds,
+                          p->max_colour_tiles, splits);
         *out = sch.release();
     });
 }

@@ -74,15 +74,18 @@ __device__ __forceinline__ void flux_v_int(const T *s0, const T *s1, const T *v0
         tsx = T(0.5) * (T0x + T1x);
         tsy = T(0.5) * (T0y + T1y);
     } else {
-        const T tn = (zp1 * (T0x * nx + T0y * ny) + zp0 * (T1x * nx + T1y * ny)) / (zp0 + zp1);
-        const T tt = (zs1 * (T0x * tx + T0y * ty) + zs0 * (T1x * tx + T1y * ty)) / (zs0 + zs1);
+        // reciprocals of the impedance sums: the same for every node of a facet, so
+        // they are computed once per facet where the nodes are unrolled
+        const T ip = T(1) / (zp0 + zp1), is = T(1) / (zs0 + zs1);
+        const T tn = (zp1 * (T0x * nx + T0y * ny) + zp0 * (T1x * nx + T1y * ny)) * ip;
+        const T tt = (zs1 * (T0x * tx + T0y * ty) + zs0 * (T1x * tx + T1y * ty)) * is;
         tsx = tn * nx + tt * tx;
         tsy = tn * ny + tt * ty;
     }
     T px = 0, py = 0;
     if (UPW && PEN) {
-        const T a = zp0 * zp1 / (zp0 + zp1) * ((v1[0] - v0[0]) * nx + (v1[1] - v0[1]) * ny);
-        const T b = zs0 * zs1 / (zs0 + zs1) * ((v1[0] - v0[0]) * tx + (v1[1] - v0[1]) * ty);
+        const T a = zp0 * zp1 * (T(1) / (zp0 + zp1)) * ((v1[0] - v0[0]) * nx + (v1[1] - v0[1]) * ny);
+        const T b = zs0 * zs1 * (T(1) / (zs0 + zs1)) * ((v1[0] - v0[0]) * tx + (v1[1] - v0[1]) * ty);
         px = a * nx + b * tx;
         py = a * ny + b * ty;
     }
@@ -113,8 +116,9 @@ __device__ __forceinline__ void flux_s_int(const T *v0, const T *v1, const T *s0
         vsx = T(0.5) * (v0[0] + v1[0]);
         vsy = T(0.5) * (v0[1] + v1[1]);
     } else {
-        const T vn = (zp0 * (v0[0] * nx + v0[1] * ny) + zp1 * (v1[0] * nx + v1[1] * ny)) / (zp0 + zp1);
-        const T vt = (zs0 * (v0[0] * tx + v0[1] * ty) + zs1 * (v1[0] * tx + v1[1] * ty)) / (zs0 + zs1);
+        const T ip = T(1) / (zp0 + zp1), is = T(1) / (zs0 + zs1);
+        const T vn = (zp0 * (v0[0] * nx + v0[1] * ny) + zp1 * (v1[0] * nx + v1[1] * ny)) * ip;
+        const T vt = (zs0 * (v0[0] * tx + v0[1] * ty) + zs1 * (v1[0] * tx + v1[1] * ty)) * is;
         vsx = vn * nx + vt * tx;
         vsy = vn * ny + vt * ty;
     }
@@ -122,8 +126,8 @@ __device__ __forceinline__ void flux_s_int(const T *v0, const T *v1, const T *s0
     if (UPW && PEN) {
         const T T0x = s0[0] * nx + s0[2] * ny, T0y = s0[2] * nx + s0[1] * ny;
         const T T1x = s1[0] * nx + s1[2] * ny, T1y = s1[2] * nx + s1[1] * ny;
-        const T a = ((T1x - T0x) * nx + (T1y - T0y) * ny) / (zp0 + zp1);
-        const T b = ((T1x - T0x) * tx + (T1y - T0y) * ty) / (zs0 + zs1);
+        const T a = ((T1x - T0x) * nx + (T1y - T0y) * ny) * (T(1) / (zp0 + zp1));
+        const T b = ((T1x - T0x) * tx + (T1y - T0y) * ty) * (T(1) / (zs0 + zs1));
         px = a * nx + b * tx;
         py = a * ny + b * ty;
     }
@@ -163,7 +167,7 @@ __device__ __forceinline__ void flux_s_ext(const T *v, const T *s, bool free_sur
     if (free_surf) {
         if (UPW && PEN) {
             const T Tx = s[0] * nx + s[2] * ny, Ty = s[2] * nx + s[1] * ny;
-            const T a = -(Tx * nx + Ty * ny) / zp, b = -(Tx * tx + Ty * ty) / zs;
+            const T a = -(Tx * nx + Ty * ny) * (T(1) / zp), b = -(Tx * tx + Ty * ty) * (T(1) / zs);
             ex = pscale * (a * nx + b * tx);
             ey = pscale * (a * ny + b * ty);
         }
@@ -172,7 +176,7 @@ __device__ __forceinline__ void flux_s_ext(const T *v, const T *s, bool free_sur
         ey = scale * T(-0.5) * v[1];
         if (PEN) {
             const T Tx = s[0] * nx + s[2] * ny, Ty = s[2] * nx + s[1] * ny;
-            const T a = T(-0.5) * (Tx * nx + Ty * ny) / zp, b = T(-0.5) * (Tx * tx + Ty * ty) / zs;
+            const T a = T(-0.5) * (Tx * nx + Ty * ny) * (T(1) / zp), b = T(-0.5) * (Tx * tx + Ty * ty) * (T(1) / zs);
             ex += pscale * (a * nx + b * tx);
             ey += pscale * (a * ny + b * ty);
         }

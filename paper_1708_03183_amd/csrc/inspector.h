@@ -59,7 +59,7 @@ class Inspector {
    public:
     Inspector(const ChainDesc &c, hipStream_t st);
     std::unique_ptr<Schedule> run(int64_t ts, int partition, const double *xy_host, const double *xy_dev,
-                                  int max_rounds, const std::vector<int32_t> &splits);
+                                  int max_rounds, int cap, const std::vector<int32_t> &splits);
     const ChainDesc &chain;
     hipStream_t stream;
     DBuf<int32_t> dmap[kMaxMaps], inv_off[kMaxMaps], inv_val[kMaxMaps];
@@ -70,9 +70,9 @@ class Inspector {
     void seed_partition(int seedset, int64_t ts, int partition, const double *xy_host, const double *xy_dev,
                         DBuf<int32_t> &tile0, DBuf<int32_t> &rank);
     int64_t seed_edges(int first, int nl, const DBuf<int32_t> &tile0, DBuf<uint64_t> &edges);
-    int colour(int32_t ntiles, const DBuf<uint64_t> &edges, int64_t ne, DBuf<int32_t> &color);
+    int colour(int32_t ntiles, const DBuf<uint64_t> &edges, int64_t ne, DBuf<int32_t> &color, int cap);
     void run_sub(Schedule &S, SubSched &sb, int64_t ts, int partition, const double *xy_host,
-                 const double *xy_dev, int max_rounds);
+                 const double *xy_dev, int max_rounds, int cap);
     int64_t touches(int first, int nl, int s, DBuf<uint64_t> &keys, DBuf<uint32_t> &bits, const Schedule &S);
     int64_t conflicts(int first, int nl, const DBuf<int32_t> &color, DBuf<uint64_t> &edges, int64_t &ne);
     void footprints(int first, int nl, SubSched &sb);

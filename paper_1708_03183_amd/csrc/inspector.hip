@@ -548,8 +548,37 @@ int64_t Inspector::seed_edges(int first, int nl, const DBuf<int32_t> &tile0, DBu
     return unique_keys(edges, total, st);
 }
 
-// Jones-Plassmann colouring of the tile graph given by unique edges (a<b)
-int Inspector::colour(int32_t ntiles, const DBuf<uint64_t> &edges, int64_t ne, DBuf<int32_t> &color) {
+// Colour-class cap: one pass over the tiles in ascending id; a tile whose class
+// holds more than cap tiles moves to the smallest colour holding fewer than cap
+// tiles that none of its neighbours has, or to a new colour.  Every class then
+// holds at most cap tiles and the colouring stays proper.  Sequential by nature
+// (each move depends on the previous ones), so it runs on the host between the
+// GPU colouring and the GPU tiling; returns the new number of colours.
+static int cap_colour_classes(int32_t ntiles, const std::vector<int32_t> &off, const std::vector<int32_t> &adj,
+                              std::vector<int32_t> &color, int ncol, int cap) {
+    std::vector<int32_t> size(64, 0);
+    for (int32_t t = 0; t < ntiles; ++t) size[color[t]]++;
+    for (int32_t t = 0; t < ntiles; ++t) {
+        const int c = color[t];
+        if (size[c] <= cap) continue;
+        uint64_t used = 0;
+        for (int32_t k = off[t]; k < off[t + 1]; ++k) used |= 1ull << color[adj[k]];
+        int c2 = 0;
+        while (c2 < ncol && (c2 == c || size[c2] >= cap || ((used >> c2) & 1))) ++c2;
+        if (c2 == ncol) {
+            DGT_REQUIRE(ncol < 64, DGT_EUNSUPPORTED, "the colour-class cap needs more than 64 colours");
+            ++ncol;
+        }
+        color[t] = c2;
+        size[c]--;
+        size[c2]++;
+    }
+    return ncol;
+}
+
+// Jones-Plassmann colouring of the tile graph given by unique edges (a<b),
+// then the colour-class cap when cap > 0
+int Inspector::colour(int32_t ntiles, const DBuf<uint64_t> &edges, int64_t ne, DBuf<int32_t> &color, int cap) {
     hipStream_t st = stream;
     DBuf<uint64_t> sym(2 * ne > 0 ? 2 * ne : 1);
     if (ne) k_sym_edges<<<blocks_for(ne, 256), 256, 0, st>>>(edges.p, ne, sym.p);
@@ -574,13 +603,23 @@ int Inspector::colour(int32_t ntiles, const DBuf<uint64_t> &edges, int64_t ne, D
         DGT_REQUIRE(h[2] == 0, DGT_EUNSUPPORTED, "tile colouring needs more than 64 colours");
         done = h[0];
         DGT_REQUIRE(++guard_rounds < 1000000, DGT_ESTATE, "colouring did not terminate");
-        if (done >= ntiles) return h[1] + 1;
+        if (done >= ntiles) {
+            int ncol = h[1] + 1;
+            if (cap > 0) {
+                auto hc = color.download(st, ntiles);
+                auto ho = off.download(st, ntiles + 1);
+                auto ha = adj.download(st, 2 * ne > 0 ? 2 * ne : 1);
+                ncol = cap_colour_classes(ntiles, ho, ha, hc, ncol, cap);
+                color.upload(hc, st);
+            }
+            return ncol;
+        }
     }
     return 0;
 }
 
 void Inspector::run_sub(Schedule &S, SubSched &sb, int64_t ts, int partition, const double *xy_host,
-                        const double *xy_dev, int max_rounds) {
+                        const double *xy_dev, int max_rounds, int cap) {
     hipStream_t st = stream;
     const int first = sb.first, nl = sb.n;
     const int seedset = chain.loops[first].set;
@@ -601,7 +640,7 @@ void Inspector::run_sub(Schedule &S, SubSched &sb, int64_t ts, int partition, co
     for (int s = 0; s < chain.nsets; ++s) phi[s].alloc(chain.size[s] > 0 ? chain.size[s] : 1);
     int round = 0, ncol = 0;
     for (; round < max_rounds; ++round) {
-        ncol = colour(ntiles, edges, ne, sb.color);
+        ncol = colour(ntiles, edges, ne, sb.color, cap);
         // default tile: first tile of colour 0
         int32_t big = INT32_MAX;
         DGT_HIP(hipMemcpyAsync(deft.p, &big, 4, hipMemcpyHostToDevice, st));
@@ -803,9 +842,10 @@ void Inspector::footprints(int first, int nl, SubSched &sb) {
 }
 
 std::unique_ptr<Schedule> Inspector::run(int64_t ts, int partition, const double *xy_host, const double *xy_dev,
-                                         int max_rounds, const std::vector<int32_t> &splits) {
+                                         int max_rounds, int cap, const std::vector<int32_t> &splits) {
     hipStream_t st = stream;
     DGT_REQUIRE(ts >= 1, DGT_EINVAL, "tile_size must be >= 1");
+    DGT_REQUIRE(cap >= 0, DGT_EINVAL, "max_colour_tiles must be >= 0");
     DGT_REQUIRE(max_rounds >= 1, DGT_EINVAL, "max_conflict_rounds must be >= 1");
     DGT_REQUIRE(chain.nloops >= 1, DGT_EINVAL, "empty loop chain");
     auto S = std::make_unique<Schedule>();
@@ -833,7 +873,7 @@ std::unique_ptr<Schedule> Inspector::run(int64_t ts, int partition, const double
         sb.first = start;
         sb.n = end - start;
         for (int j = start; j < end; ++j) S->sub_of[j] = (int)S->sub.size() - 1;
-        run_sub(*S, sb, ts, partition, xy_host, xy_dev, max_rounds);
+        run_sub(*S, sb, ts, partition, xy_host, xy_dev, max_rounds, cap);
         start = end;
     }
     DGT_HIP(hipEventRecord(e1, st));

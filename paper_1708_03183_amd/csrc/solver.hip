@@ -33,7 +33,13 @@ struct SubPlan {
     int threads = 256;
     TileKernel kind = TK_GENERIC;  // operator kernel for single-operator sub-chains
     bool vel = false;
-    int o0 = 0, nops = 0;  // chain kernel: operators of the sub-chain  // workgroup size of the tile kernel
+    int o0 = 0, nops = 0;  // chain kernel: operators of the sub-chain
+    // dependence-driven schedule (built on first use)
+    bool graph = false;
+    DBuf<int32_t> need, succ_off, succ, err;
+    DBuf<uint32_t> cnt, head;
+    uint32_t epoch = 0;
+    int slots = 0;  // workgroup size of the tile kernel
 };
 
 }  // namespace dgt
@@ -58,6 +64,7 @@ struct dgt_solver {
     dgt::DBuf<int32_t> ef2c, eb2c, c2f;
     dgt::DBuf<uint8_t> ef2l, eb2l;
     bool state_valid = false;
+    int sched_mode = 0;  // tiled executor: 0 one launch per colour, 1 dependence-driven
     // source
     bool has_src = false;
     int64_t src_in = -1, src_exec = -1;
@@ -301,7 +308,7 @@ static void build_plan(dgt_solver *s) {
     DGT_HIP(hipGetDevice(&dev));
     hipDeviceProp_t prop;
     DGT_HIP(hipGetDeviceProperties(&prop, dev));
-    const size_t budget = std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
+    const size_t budget = std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024) - 256;  // room for static LDS
     const int np = s->E.np;
     // fields touched by each sub-chain, for persistence across sub-chains
     std::vector<int> used(S.sub.size(), 0);
@@ -671,13 +678,83 @@ static void step_untiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &laun
     }
 }
 
+// Dependence graph of a sub-chain's tiles for the dependence-driven schedule: tile a
+// precedes tile b when their footprints share an element of any set and a has the
+// lower colour (tiles of one colour never share one).  Built on the host from the
+// schedule's footprints; counters start at zero.
+static void build_graph(dgt_solver *s, int b, SubPlan &P) {
+    hipStream_t st = s->st;
+    const dgt::Schedule &S = *s->sched->s;
+    const SubSched &sb = S.sub[b];
+    const auto col = sb.color.download(st, sb.ntiles);
+    std::vector<uint64_t> pairs, edges;
+    for (int set = 0; set < s->sched->chain->nsets; ++set) {
+        const int64_t m = sb.foot_len[set];
+        if (m <= 0) continue;
+        const auto off = sb.foot_off[set].download(st, sb.ntiles + 1);
+        const auto el = sb.foot[set].download(st, m);
+        pairs.assign(m, 0);
+        for (int t = 0; t < sb.ntiles; ++t)
+            for (int64_t q = off[t]; q < off[t + 1]; ++q) pairs[q] = ((uint64_t)(uint32_t)el[q] << 32) | (uint32_t)t;
+        std::sort(pairs.begin(), pairs.end());
+        for (size_t i = 0; i < pairs.size();) {
+            size_t j = i;
+            while (j < pairs.size() && (pairs[j] >> 32) == (pairs[i] >> 32)) ++j;
+            for (size_t u = i; u < j; ++u)
+                for (size_t v = u + 1; v < j; ++v) {
+                    uint32_t x = (uint32_t)pairs[u], y = (uint32_t)pairs[v];
+                    DGT_REQUIRE(col[x] != col[y], DGT_ESTATE, "two tiles of one colour share an element");
+                    if (col[x] > col[y]) std::swap(x, y);
+                    edges.push_back(((uint64_t)x << 32) | y);
+                }
+            i = j;
+        }
+    }
+    std::sort(edges.begin(), edges.end());
+    edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
+    std::vector<int32_t> need(sb.ntiles, 0), off(sb.ntiles + 1, 0), succ(std::max<size_t>(edges.size(), 1));
+    for (uint64_t e : edges) {
+        off[(e >> 32) + 1]++;
+        need[(uint32_t)e]++;
+    }
+    for (int t = 0; t < sb.ntiles; ++t) off[t + 1] += off[t];
+    for (size_t i = 0; i < edges.size(); ++i) succ[i] = (int32_t)(uint32_t)edges[i];  // edges sorted by source
+    P.need.upload(need, st);
+    P.succ_off.upload(off, st);
+    P.succ.upload(succ, st);
+    P.cnt.alloc(sb.ntiles);
+    P.head.alloc(1);
+    P.err.alloc(1);
+    DGT_HIP(hipMemsetAsync(P.cnt.p, 0, sizeof(uint32_t) * sb.ntiles, st));
+    DGT_HIP(hipMemsetAsync(P.head.p, 0, sizeof(uint32_t), st));
+    DGT_HIP(hipMemsetAsync(P.err.p, 0, sizeof(int32_t), st));
+    P.epoch = 0;
+    P.graph = true;
+}
+
+// Raises DGT_ESTATE (and resets the counters) when a dependence wait timed out.
+static void check_graphs(dgt_solver *s) {
+    bool bad = false;
+    for (auto &P : s->plan) {
+        if (!P.graph) continue;
+        if (P.err.download(s->st)[0] != 0) {
+            bad = true;
+            DGT_HIP(hipMemsetAsync(P.cnt.p, 0, sizeof(uint32_t) * P.ntiles, s->st));
+            DGT_HIP(hipMemsetAsync(P.head.p, 0, sizeof(uint32_t), s->st));
+            DGT_HIP(hipMemsetAsync(P.err.p, 0, sizeof(int32_t), s->st));
+            P.epoch = 0;
+        }
+    }
+    DGT_REQUIRE(!bad, DGT_ESTATE, "a dependence wait of the tiled executor timed out; its results are invalid");
+}
+
 template <int K, typename T>
 static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launches) {
     hipStream_t st = s->st;
     const double dt = s->p.dt;
     for (auto &P : s->plan)
         tile_launch<K, T>(P.kind, P.threads, P.vel, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, 0, P.lds_bytes,
-                          st, P.args, true);
+                          st, P.args, TA_ATTR);
     for (int64_t n = 0; n < nsteps; ++n) {
         const double th = t0 + ((double)n + 0.5) * dt;
         for (auto &P : s->plan) {
@@ -685,13 +762,33 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
             A.dt = dt;
             A.src_cell = s->has_src ? (int32_t)s->src_exec : -1;
             A.src_amp = s->has_src ? dt * ricker(th, s->sf0, s->st0, s->samp) : 0.0;
+            if (s->sched_mode == 1 && P.kind == TK_CHAIN) {  // one launch for all colours
+                A.persist = 1;
+                A.ntiles = P.ntiles;
+                A.tile_base = 0;
+                A.need = P.need.p;
+                A.succ_off = P.succ_off.p;
+                A.succ = P.succ.p;
+                A.cnt = P.cnt.p;
+                A.head = P.head.p;
+                A.err = P.err.p;
+                A.head_base = P.epoch * (uint32_t)(P.ntiles + P.slots);
+                A.epoch = ++P.epoch;
+                A.spin_limit = 1u << 20;
+                s->mark();
+                tile_launch<K, T>(P.kind, P.threads, P.vel, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, P.slots,
+                                  P.lds_bytes, st, A, TA_LAUNCH);
+                s->mark();
+                ++launches;
+                continue;
+            }
             for (int c = 0; c < P.ncolors; ++c) {
                 const int ntiles = P.color_off[c + 1] - P.color_off[c];
                 if (ntiles == 0) continue;
                 A.tile_base = P.color_off[c];
                 s->mark();
                 tile_launch<K, T>(P.kind, P.threads, P.vel, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, ntiles,
-                                  P.lds_bytes, st, A, false);
+                                  P.lds_bytes, st, A, TA_LAUNCH);
                 s->mark();
                 ++launches;
             }
@@ -806,39 +903,71 @@ dgt_status dgt_solver_create(const dgt_mesh *m, const double *lam, const double 
     });
 }
 
+// workgroups of a sub-chain's tile kernel that the whole GPU holds at once
+static int plan_slots(dgt_solver *s, const SubPlan &P) {
+    int occ = 0, dev = 0;
+    dispatch(s, [&]<int K, typename T>() {
+        tile_launch<K, T>(P.kind, P.threads, P.vel, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, 0, P.lds_bytes,
+                          s->st, P.args, TA_ATTR);
+        tile_launch<K, T>(P.kind, P.threads, P.vel, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, 0, P.lds_bytes,
+                          s->st, P.args, TA_OCCUPANCY, &occ);
+    });
+    DGT_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    DGT_HIP(hipGetDeviceProperties(&prop, dev));
+    return occ * prop.multiProcessorCount;
+}
+
+static void solver_inspect_once(dgt_solver *s, const dgt_inspect_params *p, int cap) {
+    hipStream_t st = s->st;
+    delete s->sched;
+    s->sched = nullptr;
+    s->plan.clear();
+    s->plan_status = DGT_ESTATE;
+    s->plan_error = "tiled mode needs a successful dgt_solver_inspect";
+    DBuf<double> cxy(2 * s->nc);
+    k_centroids<<<blocks_for(s->nc, 256), 256, 0, st>>>(s->xy.p, s->c2v.p, s->nc, cxy.p);
+    auto sch = std::make_unique<dgt_schedule>();
+    sch->chain_copy = s->chain.c;
+    sch->chain = &sch->chain_copy;
+    Inspector insp(sch->chain_copy, st);
+    std::vector<int32_t> splits(p->splits, p->splits + p->nsplits);
+    sch->s = insp.run(p->tile_size, p->partition, nullptr, cxy.p, p->max_conflict_rounds, cap, splits);
+    s->sched = sch.release();
+    // executor layout follows the seed order of the schedule
+    auto rank = s->sched->s->seed_rank.download(st, s->nc);
+    set_exec_order(s, rank);
+    // the schedule stays valid when its tiles do not fit the LDS budget;
+    // only the tiled executor is then unavailable
+    try {
+        build_plan(s);
+        s->plan_status = DGT_OK;
+    } catch (const Error &e) {
+        if (e.st != DGT_EUNSUPPORTED) throw;
+        s->plan.clear();
+        s->plan_status = e.st;
+        s->plan_error = e.msg;
+    }
+}
+
 dgt_status dgt_solver_inspect(dgt_solver *s, const dgt_inspect_params *p) {
     return guard([&] {
         DGT_REQUIRE(s && p, DGT_EINVAL, "NULL argument");
         DGT_REQUIRE(p->partition == 0 || p->partition == 1, DGT_EINVAL, "partition must be 0 or 1");
         DGT_REQUIRE(p->nsplits >= 0 && (p->nsplits == 0 || p->splits), DGT_EINVAL, "bad splits");
-        hipStream_t st = s->st;
-        delete s->sched;
-        s->sched = nullptr;
-        s->plan.clear();
-        s->plan_status = DGT_ESTATE;
-        s->plan_error = "tiled mode needs a successful dgt_solver_inspect";
-        DBuf<double> cxy(2 * s->nc);
-        k_centroids<<<blocks_for(s->nc, 256), 256, 0, st>>>(s->xy.p, s->c2v.p, s->nc, cxy.p);
-        auto sch = std::make_unique<dgt_schedule>();
-        sch->chain_copy = s->chain.c;
-        sch->chain = &sch->chain_copy;
-        Inspector insp(sch->chain_copy, st);
-        std::vector<int32_t> splits(p->splits, p->splits + p->nsplits);
-        sch->s = insp.run(p->tile_size, p->partition, nullptr, cxy.p, p->max_conflict_rounds, splits);
-        s->sched = sch.release();
-        // executor layout follows the seed order of the schedule
-        auto rank = s->sched->s->seed_rank.download(st, s->nc);
-        set_exec_order(s, rank);
-        // the schedule stays valid when its tiles do not fit the LDS budget;
-        // only the tiled executor is then unavailable
-        try {
-            build_plan(s);
-            s->plan_status = DGT_OK;
-        } catch (const Error &e) {
-            if (e.st != DGT_EUNSUPPORTED) throw;
-            s->plan.clear();
-            s->plan_status = e.st;
-            s->plan_error = e.msg;
+        DGT_REQUIRE(p->max_colour_tiles >= -1, DGT_EINVAL, "max_colour_tiles must be >= -1");
+        solver_inspect_once(s, p, p->max_colour_tiles > 0 ? p->max_colour_tiles : 0);
+        if (p->max_colour_tiles == -1 && s->plan_status == DGT_OK) {
+            // cap the colour classes at the number of tile workgroups resident at once when
+            // some class would need more than one round of them
+            int slots = INT32_MAX;
+            bool over = false;
+            for (const auto &P : s->plan) {
+                const int sl = plan_slots(s, P);
+                slots = std::min(slots, sl);
+                for (int c = 0; c < P.ncolors; ++c) over |= P.color_off[c + 1] - P.color_off[c] > sl;
+            }
+            if (over && slots > 0) solver_inspect_once(s, p, slots);
         }
     });
 }
@@ -910,6 +1039,7 @@ dgt_status dgt_state_download(dgt_solver *s, void *v, void *sig) {
     return guard([&] {
         DGT_REQUIRE(s && v && sig, DGT_EINVAL, "NULL argument");
         DGT_REQUIRE(s->state_valid, DGT_ESTATE, "no state uploaded");
+        check_graphs(s);
         to_caller(s, v, sig);
     });
 }
@@ -920,6 +1050,16 @@ dgt_status dgt_step(dgt_solver *s, int64_t nsteps, int32_t mode, double t0) {
         DGT_REQUIRE(s->state_valid, DGT_ESTATE, "state not uploaded");
         DGT_REQUIRE(mode == 0 || mode == 1, DGT_EINVAL, "mode must be 0 or 1");
         DGT_REQUIRE(mode == 0 || s->plan_status == DGT_OK, s->plan_status, s->plan_error);
+        if (mode == 1 && s->sched_mode == 1) {
+            check_graphs(s);  // synchronises: reports a wait that timed out earlier
+            for (size_t b = 0; b < s->plan.size(); ++b) {
+                SubPlan &P = s->plan[b];
+                if (P.kind != TK_CHAIN) continue;
+                if (!P.graph) build_graph(s, (int)b, P);
+                if (!P.slots) P.slots = plan_slots(s, P);
+                DGT_REQUIRE(P.slots > 0, DGT_EUNSUPPORTED, "the tile kernel does not fit on a compute unit");
+            }
+        }
         int64_t launches = 0;
         s->npev = 0;
         DGT_HIP(hipEventRecord(s->ev0, s->st));
@@ -931,6 +1071,13 @@ dgt_status dgt_step(dgt_solver *s, int64_t nsteps, int32_t mode, double t0) {
         DGT_HIP(hipEventRecord(s->ev1, s->st));
         s->last_launches = launches;
         s->last_ms = -1.0;
+    });
+}
+
+dgt_status dgt_solver_set_schedule(dgt_solver *s, int32_t mode) {
+    return guard([&] {
+        DGT_REQUIRE(s && (mode == 0 || mode == 1), DGT_EINVAL, "bad arguments");
+        s->sched_mode = mode;
     });
 }
 

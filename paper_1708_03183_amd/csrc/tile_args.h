@@ -40,6 +40,20 @@ struct TileArgs {
     int32_t src_cell;          // exec id of the source cell or -1
     double dt, src_amp;        // src_amp = dt * r(t^{n+1/2})
     const void *src_vec;
+    // dependence-driven schedule (chain kernel): one launch per sub-chain; workgroups take
+    // tiles in colour order from a ticket counter, and a tile starts once every
+    // lower-colour tile whose footprint meets its own has finished
+    int32_t persist;            // 0: one launch per colour (tiles[tile_base + blockIdx.x])
+    int32_t ntiles;             // tiles of the sub-chain
+    const int32_t *need;        // [ntiles] predecessors per tile
+    const int32_t *succ_off;    // [ntiles+1] successors (CSR)
+    const int32_t *succ;
+    uint32_t *cnt;              // [ntiles] finished predecessors, counted across launches
+    uint32_t *head;             // ticket counter, counted across launches
+    int32_t *err;               // set when a wait times out
+    uint32_t epoch;             // launches of this plan so far (this one included)
+    uint32_t head_base;         // tickets taken by earlier launches
+    uint32_t spin_limit;        // polls before a wait gives up
 };
 
 }  // namespace dgt

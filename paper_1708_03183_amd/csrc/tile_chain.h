@@ -49,6 +49,48 @@ __host__ __device__ constexpr int op_first_loop(int order, int o) {
 
 __host__ __device__ constexpr int op_upd_loop(int order, int o) { return op_first_loop(order, o) + (order == 2 ? 3 : 4); }
 
+// fields operator o touches, its update included (bit per field)
+__host__ __device__ constexpr uint32_t op_fields(int order, int o) {
+    const OpDesc D = op_desc(order, o);
+    uint32_t m = (1u << D.in) | (1u << D.out);
+    if (D.pen >= 0) m |= 1u << D.pen;
+    if (D.upd) m |= 1u << (D.vel ? F_V : F_S);
+    if (D.part >= 0) m |= 1u << D.part;
+    return m;
+}
+
+// fields operator o writes (its output, and the updated field)
+__host__ __device__ constexpr uint32_t op_writes(int order, int o) {
+    const OpDesc D = op_desc(order, o);
+    return (1u << D.out) | (D.upd ? 1u << (D.vel ? F_V : F_S) : 0u);
+}
+
+// first operator of [o0, o0 + n) touching field f, and the last one writing it (-1: none)
+__host__ __device__ constexpr int field_first_op(int order, int o0, int n, int f) {
+    for (int o = o0; o < o0 + n; ++o)
+        if ((op_fields(order, o) >> f) & 1u) return o;
+    return -1;
+}
+__host__ __device__ constexpr int field_last_write(int order, int o0, int n, int f) {
+    int last = -1;
+    for (int o = o0; o < o0 + n; ++o)
+        if ((op_writes(order, o) >> f) & 1u) last = o;
+    return last;
+}
+
+// Field accesses of the dependence-driven schedule are coherent at device scope
+// (they neither hit a stale line of another XCD's L2 nor stay dirty in one), so
+// no cache write-back or invalidation is needed between dependent tiles.
+template <typename T>
+__device__ __forceinline__ T load_field(const T *p, bool coherent) {
+    return coherent ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
+}
+template <typename T>
+__device__ __forceinline__ void store_field(T *p, T v, bool coherent) {
+    if (coherent) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+
 template <int K, typename T>
 struct CellRegs {
     static constexpr int NP = np_of(K);
@@ -56,9 +98,9 @@ struct CellRegs {
     T g[G_NROWS];
 };
 
-template <int K, typename T, bool UPW, int ORDER, int O0, int O>
+template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int O>
 __device__ __forceinline__ void chain_op(CellRegs<K, T> &r, const TileArgs &a, T *__restrict__ lds, int NR, bool act,
-                                         int s, uint32_t acc, const uint32_t (&nb)[3], int64_t x) {
+                                         int s, uint32_t acc, uint16_t fl, const uint32_t (&nb)[3], int64_t x) {
     constexpr int NP = np_of(K), NFP = K + 1;
     constexpr OpDesc D = op_desc(ORDER, O);
     constexpr int NI = D.vel ? 3 : 2, NO = D.vel ? 2 : 3;
@@ -70,6 +112,23 @@ __device__ __forceinline__ void chain_op(CellRegs<K, T> &r, const TileArgs &a, T
     T(&vin)[3][NP] = r.f[D.in];
     T(&o)[3][NP] = r.f[D.out];
 
+    // gather the fields whose first use in the sub-chain is this operator (those this
+    // cell reads before writing); their loads overlap the previous operator's barrier
+    if (act) {
+#pragma unroll
+        for (int f = 0; f < F_COUNT; ++f) {
+            if (field_first_op(ORDER, O0, NOPS, f) != O || !((fl >> f) & 1)) continue;
+            const T *F = reinterpret_cast<const T *>(a.F[f]);
+            const bool coh = a.persist;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (c >= field_ncomp(f)) break;
+#pragma unroll
+                for (int i = 0; i < NP; ++i)
+                    r.f[f][c][i] = load_field(F + (int64_t)(c * NP + i) * a.nc + x, coh);
+            }
+        }
+    }
     if (O > O0) __syncthreads();  // the neighbours have read the previous operator's traces
     if (act) {
         T *row = lds + (size_t)s * NR;
@@ -196,19 +255,27 @@ __device__ __forceinline__ void chain_op(CellRegs<K, T> &r, const TileArgs &a, T
                 }
         }
     }
+    // write back the fields this operator writes for the last time in the sub-chain
+#pragma unroll
+    for (int f = 0; f < F_COUNT; ++f) {
+        if (field_last_write(ORDER, O0, NOPS, f) != O || !((fl >> (8 + f)) & 1)) continue;
+        T *F = reinterpret_cast<T *>(a.F[f]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (c >= field_ncomp(f)) break;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) store_field(F + (int64_t)(c * NP + i) * a.nc + x, r.f[f][c][i], a.persist);
+        }
+    }
 }
 
-template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int NT>
-__global__ __launch_bounds__(NT) void k_tile_chain(const TileArgs a) {
+template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS>
+__device__ __forceinline__ void chain_tile(const TileArgs &a, T *__restrict__ lds, int tile) {
     constexpr int NP = np_of(K);
-    extern __shared__ __align__(16) unsigned char smem[];
-    T *lds = reinterpret_cast<T *>(smem);
-    const int tile = a.tiles[a.tile_base + blockIdx.x];
     const int f0 = a.foot_off[tile];
     const int nfoot = a.foot_off[tile + 1] - f0;
     const int s = threadIdx.x;
     const bool act = s < nfoot;
-    const int64_t nc = a.nc;
 
     CellRegs<K, T> r;
     uint32_t acc = 0, nb[NOPS][3];
@@ -239,33 +306,57 @@ __global__ __launch_bounds__(NT) void k_tile_chain(const TileArgs a) {
             for (int p = 0; p < 3; ++p) nb[q][p] = a.tnb[b0 + (q * 3 + p) * nfoot + s];
         const T *geo = reinterpret_cast<const T *>(a.geo);
 #pragma unroll
-        for (int q = 0; q < G_NROWS; ++q) r.g[q] = geo[(int64_t)q * nc + x];
-#pragma unroll
-        for (int f = 0; f < F_COUNT; ++f) {
-            if (!((fl >> f) & 1)) continue;
-            const T *F = reinterpret_cast<const T *>(a.F[f]);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                if (c >= field_ncomp(f)) break;
-#pragma unroll
-                for (int i = 0; i < NP; ++i) r.f[f][c][i] = F[(int64_t)(c * NP + i) * nc + x];
-            }
-        }
+        for (int q = 0; q < G_NROWS; ++q) r.g[q] = geo[(int64_t)q * a.nc + x];
     }
+    // fields are gathered at their first use and written back after their last write
     [&]<int... Q>(std::integer_sequence<int, Q...>) {
-        (chain_op<K, T, UPW, ORDER, O0, O0 + Q>(r, a, lds, a.nrow, act, s, acc, nb[Q], x), ...);
+        (chain_op<K, T, UPW, ORDER, O0, NOPS, O0 + Q>(r, a, lds, a.nrow, act, s, acc, fl, nb[Q], x), ...);
     }(std::make_integer_sequence<int, NOPS>{});
-    if (!act) return;
-#pragma unroll
-    for (int f = 0; f < F_COUNT; ++f) {
-        if (!((fl >> (8 + f)) & 1)) continue;
-        T *F = reinterpret_cast<T *>(a.F[f]);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            if (c >= field_ncomp(f)) break;
-#pragma unroll
-            for (int i = 0; i < NP; ++i) F[(int64_t)(c * NP + i) * nc + x] = r.f[f][c][i];
+}
+
+// Dependence-driven schedule, thread 0 of a workgroup: take the next ticket (tiles
+// in colour order) and wait until every predecessor of its tile has finished.
+// Predecessors have lower colours, hence lower tickets, so they were taken by
+// workgroups already running: the wait ends unless a counter is wrong, and the
+// poll limit ends it then too (the error flag tells the host).  -1: no tile left.
+__device__ __forceinline__ int next_tile(const TileArgs &a) {
+    const uint32_t ticket = atomicAdd(a.head, 1u) - a.head_base;
+    if (ticket >= (uint32_t)a.ntiles) return -1;
+    const int tile = a.tiles[ticket];
+    const uint32_t need = (uint32_t)a.need[tile], base = (a.epoch - 1u) * need;
+    uint32_t polls = 0;
+    while (__hip_atomic_load(a.cnt + tile, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - base < need) {
+        if (++polls > a.spin_limit) {
+            atomicExch(a.err, 1);
+            return -1;
         }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return tile;
+}
+
+template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int NT>
+__global__ __launch_bounds__(NT) void k_tile_chain(const TileArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_next;
+    T *lds = reinterpret_cast<T *>(smem);
+    if (!a.persist) {  // one launch per colour
+        chain_tile<K, T, UPW, ORDER, O0, NOPS>(a, lds, a.tiles[a.tile_base + blockIdx.x]);
+        return;
+    }
+    for (;;) {
+        if (threadIdx.x == 0) s_next = next_tile(a);
+        __syncthreads();
+        const int tile = s_next;
+        if (tile < 0) return;
+        chain_tile<K, T, UPW, ORDER, O0, NOPS>(a, lds, tile);
+        // every wave waits for its coherent field stores to complete, so once the barrier
+        // is passed the whole tile is visible at device scope and its successors may start
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int k = a.succ_off[tile]; k < a.succ_off[tile + 1]; ++k)
+                __hip_atomic_fetch_add(a.cnt + a.succ[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

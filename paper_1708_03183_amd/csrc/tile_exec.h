@@ -17,15 +17,18 @@ constexpr int TILE_CHAINS[4][3] = {{4, 0, 3}, {4, 3, 3}, {4, 0, 6}, {2, 0, 2}};
 template <int K, typename T>
 void tile_upload_ref(const RefElem &E, hipStream_t st);
 
-// Launches (attr = false) or prepares (attr = true: raises the dynamic LDS
-// limit) one colour of a sub-chain.  Generic kernel: any sub-chain, nt work
+enum TileAction { TA_LAUNCH = 0, TA_ATTR = 1, TA_OCCUPANCY = 2 };
+
+// Launches one colour of a sub-chain (TA_LAUNCH), raises the kernel's dynamic
+// LDS limit (TA_ATTR), or stores in *occ how many of its workgroups one CU holds
+// (TA_OCCUPANCY).  Generic kernel: any sub-chain, nt work
 // items per tile.  Operator kernel: one operator application (vel selects the
 // velocity operator) with an optional trailing update; needs nt >= the
 // largest footprint.  Chain kernel: operators [o0, o0 + nops) of the order-`order`
 // step (one of TILE_CHAINS), nt >= the largest footprint.
 template <int K, typename T>
 void tile_launch(TileKernel kind, int nt, bool vel, bool upw, bool pen, int order, int o0, int nops, int grid,
-                 size_t lds, hipStream_t st, const TileArgs &A, bool attr);
+                 size_t lds, hipStream_t st, const TileArgs &A, TileAction act, int *occ = nullptr);
 
 // workgroup sizes the tile kernels are built for
 constexpr int TILE_NT[3] = {128, 256, 512};

@@ -9,9 +9,14 @@
 namespace dgt {
 
 template <typename Kern>
-static void tile_go(Kern kern, int nt, int grid, size_t lds, hipStream_t st, const TileArgs &A, bool attr) {
-    if (attr) {
+static void tile_go(Kern kern, int nt, int grid, size_t lds, hipStream_t st, const TileArgs &A, TileAction act,
+                    int *occ) {
+    if (act == TA_ATTR) {
         DGT_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        return;
+    }
+    if (act == TA_OCCUPANCY) {
+        DGT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, kern, nt, lds));
         return;
     }
     kern<<<grid, nt, lds, st>>>(A);
@@ -19,10 +24,10 @@ static void tile_go(Kern kern, int nt, int grid, size_t lds, hipStream_t st, con
 
 template <int K, typename T, int NT>
 static void tile_launch_chain(bool upw, int order, int o0, int nops, int grid, size_t lds, hipStream_t st,
-                              const TileArgs &A, bool attr) {
+                              const TileArgs &A, TileAction act, int *occ) {
     auto pick = [&]<int ORD, int O0, int N>() {
         auto kern = upw ? k_tile_chain<K, T, true, ORD, O0, N, NT> : k_tile_chain<K, T, false, ORD, O0, N, NT>;
-        tile_go(kern, NT, grid, lds, st, A, attr);
+        tile_go(kern, NT, grid, lds, st, A, act, occ);
     };
     if (order == 4 && o0 == 0 && nops == 3) pick.template operator()<4, 0, 3>();
     else if (order == 4 && o0 == 3 && nops == 3) pick.template operator()<4, 3, 3>();
@@ -33,43 +38,43 @@ static void tile_launch_chain(bool upw, int order, int o0, int nops, int grid, s
 
 template <int K, typename T, int NT>
 static void tile_launch_nt(TileKernel kind, bool vel, bool upw, bool pen, int grid, size_t lds, hipStream_t st,
-                           const TileArgs &A, bool attr) {
+                           const TileArgs &A, TileAction act, int *occ) {
     if (kind == TK_OP) {
         auto kern = vel ? (upw ? k_tile_op<K, T, true, true, NT> : k_tile_op<K, T, true, false, NT>)
                         : (upw ? k_tile_op<K, T, false, true, NT> : k_tile_op<K, T, false, false, NT>);
-        tile_go(kern, NT, grid, lds, st, A, attr);
+        tile_go(kern, NT, grid, lds, st, A, act, occ);
     } else {
         auto kern = upw ? (pen ? k_tile<K, T, true, true, NT> : k_tile<K, T, true, false, NT>)
                         : (pen ? k_tile<K, T, false, true, NT> : k_tile<K, T, false, false, NT>);
-        tile_go(kern, NT, grid, lds, st, A, attr);
+        tile_go(kern, NT, grid, lds, st, A, act, occ);
     }
 }
 
 template <int K, typename T>
 static void tile_launch_any(TileKernel kind, int nt, bool vel, bool upw, bool pen, int order, int o0, int nops,
-                            int grid, size_t lds, hipStream_t st, const TileArgs &A, bool attr) {
+                            int grid, size_t lds, hipStream_t st, const TileArgs &A, TileAction act, int *occ) {
     DGT_REQUIRE(nt == 128 || nt == 256 || nt == 512, DGT_EINVAL, "tile workgroup size must be 128, 256 or 512");
     if (kind == TK_CHAIN) {
         DGT_REQUIRE(nt != 128, DGT_EINVAL, "the chain kernel runs with 256 or 512 work items");
-        if (nt == 512) tile_launch_chain<K, T, 512>(upw, order, o0, nops, grid, lds, st, A, attr);
-        else tile_launch_chain<K, T, 256>(upw, order, o0, nops, grid, lds, st, A, attr);
+        if (nt == 512) tile_launch_chain<K, T, 512>(upw, order, o0, nops, grid, lds, st, A, act, occ);
+        else tile_launch_chain<K, T, 256>(upw, order, o0, nops, grid, lds, st, A, act, occ);
         return;
     }
-    if (nt == 512) tile_launch_nt<K, T, 512>(kind, vel, upw, pen, grid, lds, st, A, attr);
-    else if (nt == 256) tile_launch_nt<K, T, 256>(kind, vel, upw, pen, grid, lds, st, A, attr);
-    else tile_launch_nt<K, T, 128>(kind, vel, upw, pen, grid, lds, st, A, attr);
+    if (nt == 512) tile_launch_nt<K, T, 512>(kind, vel, upw, pen, grid, lds, st, A, act, occ);
+    else if (nt == 256) tile_launch_nt<K, T, 256>(kind, vel, upw, pen, grid, lds, st, A, act, occ);
+    else tile_launch_nt<K, T, 128>(kind, vel, upw, pen, grid, lds, st, A, act, occ);
 }
 
 template <>
 void tile_launch<DGT_TILE_K, double>(TileKernel kind, int nt, bool vel, bool upw, bool pen, int order, int o0, int nops,
-                                     int grid, size_t lds, hipStream_t st, const TileArgs &A, bool attr) {
-    tile_launch_any<DGT_TILE_K, double>(kind, nt, vel, upw, pen, order, o0, nops, grid, lds, st, A, attr);
+                                     int grid, size_t lds, hipStream_t st, const TileArgs &A, TileAction act, int *occ) {
+    tile_launch_any<DGT_TILE_K, double>(kind, nt, vel, upw, pen, order, o0, nops, grid, lds, st, A, act, occ);
 }
 
 template <>
 void tile_launch<DGT_TILE_K, float>(TileKernel kind, int nt, bool vel, bool upw, bool pen, int order, int o0, int nops,
-                                    int grid, size_t lds, hipStream_t st, const TileArgs &A, bool attr) {
-    tile_launch_any<DGT_TILE_K, float>(kind, nt, vel, upw, pen, order, o0, nops, grid, lds, st, A, attr);
+                                    int grid, size_t lds, hipStream_t st, const TileArgs &A, TileAction act, int *occ) {
+    tile_launch_any<DGT_TILE_K, float>(kind, nt, vel, upw, pen, order, o0, nops, grid, lds, st, A, act, occ);
 }
 
 template <>

@@ -31,7 +31,8 @@ class _Desc(C.Structure):
 
 class _InspectParams(C.Structure):
     _fields_ = [("tile_size", C.c_int64), ("partition", C.c_int32), ("seed_xy", C.c_void_p),
-                ("max_conflict_rounds", C.c_int32), ("splits", C.c_void_p), ("nsplits", C.c_int32)]
+                ("max_conflict_rounds", C.c_int32), ("splits", C.c_void_p), ("nsplits", C.c_int32),
+                ("max_colour_tiles", C.c_int32)]
 
 
 class _SolverParams(C.Structure):
@@ -75,6 +76,7 @@ _SIGS = {
     "dgt_energy": [_p, _p, _p, _p, C.POINTER(C.c_double)],
     "dgt_last_step_timing": [_p, C.POINTER(C.c_double), C.POINTER(C.c_double), _i64],
     "dgt_solver_profile": [_p, C.c_int32],
+    "dgt_solver_set_schedule": [_p, C.c_int32],
     "dgt_solver_info": [_p, _i64, _i64, _i64],
     "dgt_solver_destroy": [_p],
     "dgt_last_error": [],
@@ -122,11 +124,11 @@ def _stream_handle(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
-def _inspect_params(tile_size, partition, seed_xy, max_rounds, splits):
+def _inspect_params(tile_size, partition, seed_xy, max_rounds, splits, max_colour_tiles=0):
     sp = np.ascontiguousarray(np.array(list(splits), np.int32))
     xy = None if seed_xy is None else np.ascontiguousarray(seed_xy, np.float64)
     p = _InspectParams(int(tile_size), int(partition), _np_ptr(xy), int(max_rounds),
-                       _np_ptr(sp) if len(sp) else None, len(sp))
+                       _np_ptr(sp) if len(sp) else None, len(sp), int(max_colour_tiles))
     return p, (sp, xy)
 
 
@@ -160,8 +162,9 @@ class Chain:
         self.loop_sets.append(set_id)
         return out.value
 
-    def inspect(self, tile_size, partition=0, seed_xy=None, max_rounds=64, splits=(), stream=None) -> "Schedule":
-        p, keep = _inspect_params(tile_size, partition, seed_xy, max_rounds, splits)
+    def inspect(self, tile_size, partition=0, seed_xy=None, max_rounds=64, splits=(), stream=None,
+                max_colour_tiles=0) -> "Schedule":
+        p, keep = _inspect_params(tile_size, partition, seed_xy, max_rounds, splits, max_colour_tiles)
         h = C.c_void_p()
         _check(lib().dgt_inspect(self.h, C.byref(p), _stream_handle(stream), C.byref(h)))
         return Schedule(h, owner=True, loop_sizes=[self.sizes[s] for s in self.loop_sets])
@@ -292,8 +295,9 @@ class Solver:
         return (torch.zeros((2, self.np, self.mesh.nc), dtype=self.dtype, device=device),
                 torch.zeros((3, self.np, self.mesh.nc), dtype=self.dtype, device=device))
 
-    def inspect(self, tile_size, partition=1, max_rounds=64, splits=()):
-        p, keep = _inspect_params(tile_size, partition, None, max_rounds, splits)
+    def inspect(self, tile_size, partition=1, max_rounds=64, splits=(), max_colour_tiles=0):
+        """max_colour_tiles: 0 none, > 0 cap per colour class, -1 the GPU's resident tile count."""
+        p, keep = _inspect_params(tile_size, partition, None, max_rounds, splits, max_colour_tiles)
         _check(lib().dgt_solver_inspect(self.h, C.byref(p)))
 
     def schedule(self) -> Schedule:
@@ -329,6 +333,10 @@ class Solver:
         _check(lib().dgt_energy(self.h, C.c_void_p(v.data_ptr()), C.c_void_p(s_new.data_ptr()),
                                 C.c_void_p(s_old.data_ptr()), C.byref(out)))
         return out.value
+
+    def set_schedule(self, mode: int):
+        """0: one launch per colour; 1: dependence-driven tiles, one launch per sub-chain."""
+        _check(lib().dgt_solver_set_schedule(self.h, int(mode)))
 
     def profile(self, on: bool):
         """Per-launch event timing of the tile kernels on (off by default)."""

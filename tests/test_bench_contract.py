@@ -18,4 +18,4 @@ def test_measured_traffic_lookup_requires_matching_sources():
     sys.path.insert(0, ROOT)
     import bench
     # a configuration with no committed counter summary has no traffic figure
-    assert bench.measured_traffic("jitter7_p9", "f64", 1, (13,)) is None
+    assert bench.measured_traffic("jitter7_p9", "f64", 1, (13,), 1) is None

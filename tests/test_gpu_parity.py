@@ -121,9 +121,33 @@ def test_dg_schedule_matches_oracle(D, n, k, order, flux, free, ts, part, splits
     assert os_.check() == 0
 
 
+CAP_CASES = [
+    # n, k, order, flux, free, ts, partition, splits, renumber, colour-class cap
+    (12, 2, 4, 1, 0x8, 10, 1, (13,), 7, 3),
+    (16, 1, 4, 0, 0xF, 16, 1, (), 3, 5),
+    (12, 2, 2, 1, 0x8, 8, 0, (), None, 2),
+    (20, 2, 4, 1, 0x8, 12, 1, (4, 8, 13, 17, 21), 5, 7),
+]
+
+
+@pytest.mark.parametrize("n,k,order,flux,free,ts,part,splits,ren,cap", CAP_CASES)
+def test_dg_schedule_with_colour_cap_matches_oracle(D, n, k, order, flux, free, ts, part, splits, ren, cap):
+    m, om, od, gm, gd = _dg_pair(D, n, k, order, flux, free, ren)
+    gd.inspect(ts, partition=part, splits=splits, max_colour_tiles=cap)
+    gs = gd.schedule()
+    os_ = od.chain().inspect(ts, partition=part, seed_xy=m.centroids(), splits=splits, max_colour_tiles=cap)
+    sizes = {0: om.nc, 1: om.nf, 2: om.nb}
+    pat = ([0, 1, 2, 0] * 3 + [0]) * 2 if order == 4 else [0, 1, 2, 0] * 2
+    _compare_schedules(gs, os_, [sizes[s] for s in pat], [om.nc, om.nf, om.nb], len(splits) + 1)
+    assert os_.check() == 0
+    for sub in range(gs.nsub):
+        assert np.diff(gs.tiles_by_color(sub)[0]).max() <= cap
+
+
 # ------------------------------------------------------------------ executors
 
-def _run_pair(D, n, k, order, flux, free, ren, steps, mode, ts=24, part=1, splits=(), prec=0, seed=1):
+def _run_pair(D, n, k, order, flux, free, ren, steps, mode, ts=24, part=1, splits=(), prec=0, seed=1, cap=0,
+              schedule=0):
     """Random nodal state for k <= 2; for k >= 3 the workload's own start (at
     rest, driven by the Ricker source), since a random nodal state is rough
     enough that rounding alone separates two FP64 evaluations of the P3/P4
@@ -140,7 +164,8 @@ def _run_pair(D, n, k, order, flux, free, ren, steps, mode, ts=24, part=1, split
     gs = torch.from_numpy(s).to(dtype).cuda().contiguous()
     od.step(v, s, steps, t0=0.1)
     if mode == 1:
-        gd.inspect(ts, partition=part, splits=splits)
+        gd.inspect(ts, partition=part, splits=splits, max_colour_tiles=cap)
+        gd.set_schedule(schedule)
     gd.upload(gv, gs)
     gd.step(steps, mode=mode, t0=0.1)
     gd.download(gv, gs)
@@ -239,6 +264,43 @@ def test_tiled_chain_kernels_fp64_match_oracle(D, monkeypatch, kernel, n, k, ord
     assert err <= 1e-12
 
 
+@pytest.mark.parametrize("n,k,order,flux,free,ren,steps,ts,splits", CHAIN_CASES)
+def test_dependence_driven_schedule_fp64_matches_oracle(D, n, k, order, flux, free, ren, steps, ts, splits):
+    """Schedule 1: one launch per sub-chain, tiles started by device-scope
+    dependence counters instead of colour launches."""
+    err = _run_pair(D, n, k, order, flux, free, ren, steps, mode=1, ts=ts, splits=splits, schedule=1)
+    print(f"dependence-driven tiled FP64 n={n} k={k} order={order} flux={flux} ts={ts} splits={splits}: "
+          f"rel L2 err {err:.3e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_dependence_driven_schedule_fp32_matches_oracle(D, k):
+    err = _run_pair(D, 10, k, 4, 1, 0x8, 4, 5, mode=1, ts=8 if k == 4 else 16, splits=(13,), prec=1, schedule=1)
+    print(f"dependence-driven tiled FP32 k={k}: rel L2 err vs FP64 oracle {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_dependence_driven_schedule_repeated_calls(D):
+    """Counters carry over between launches: many one-step calls equal one call."""
+    m, om, od, gm, gd = _dg_pair(D, 16, 2, 4, 1, 0x8, 5)
+    gd.inspect(12, partition=1, splits=(13,))
+    gd.set_schedule(1)
+    v, s = od.zeros()
+    v[:] = I.random_state(v.shape, 11)
+    s[:] = I.random_state(s.shape, 12)
+    gv = torch.from_numpy(v.copy()).cuda()
+    gs = torch.from_numpy(s.copy()).cuda()
+    gd.upload(gv, gs)
+    for i in range(7):
+        gd.step(1, mode=1, t0=0.1 + i * gd.dt)
+    gd.download(gv, gs)
+    od.step(v, s, 7, t0=0.1)
+    err = rel_l2([gv.cpu().numpy(), gs.cpu().numpy()], [v, s])
+    print(f"dependence-driven, 7 single-step calls: rel L2 err {err:.3e}")
+    assert err <= 1e-12
+
+
 @pytest.mark.parametrize("splits", [(), (13,)])
 @pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_tiled_chain_kernel_fp32_matches_oracle(D, k, splits):
@@ -253,6 +315,15 @@ def test_fp32_matches_oracle(D, mode, k):
     err = _run_pair(D, 10, k, 4, 1, 0x8, 4, 5, mode=mode, ts=16, prec=1)
     print(f"FP32 mode={mode} k={k}: rel L2 err vs FP64 oracle {err:.3e}")
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("cap,splits", [(3, (13,)), (5, (4, 8, 13, 17, 21)), (-1, (13,))])
+def test_tiled_with_colour_cap_matches_oracle(D, cap, splits):
+    """Capped colour classes (and the solver's automatic cap, -1) change the
+    schedule, not the result."""
+    err = _run_pair(D, 14, 2, 4, 1, 0x8, 9, 6, mode=1, ts=12, splits=splits, cap=cap)
+    print(f"tiled FP64 colour cap {cap} splits={splits}: rel L2 err {err:.3e}")
+    assert err <= 1e-12
 
 
 def test_energy_matches_oracle(D):

@@ -221,3 +221,36 @@ def test_hilbert_partition_compact():
         return int(np.sum(sig[mp["f2c"][:, 0]] != sig[mp["f2c"][:, 1]]))
 
     assert cut(1) * 4 < cut(0)
+
+
+@pytest.mark.parametrize("cap", [1, 2, 3, 5, 9])
+def test_colour_class_cap(cap):
+    """The colour-class cap keeps every class within the cap, the colouring proper
+    (the checker finds no violation) and the chain's result unchanged."""
+    m, om, d = _dg(11, ren=7)
+    base = d.chain().inspect(5, partition=1, seed_xy=m.centroids(), splits=(13,))
+    s = d.chain().inspect(5, partition=1, seed_xy=m.centroids(), splits=(13,), max_colour_tiles=cap)
+    assert s.check() == 0
+    for sub in range(s.nsub):
+        co, _ = s.tiles_by_color(sub)
+        sizes = np.diff(co)
+        assert sizes.max() <= cap and sizes.sum() == s.sub_info(sub)["ntiles"]
+    ch = d.chain()
+    assert ch.instrumented(None) == ch.instrumented(s)
+    # a cap at least as large as every class leaves the schedule as it was
+    big = max(int(np.diff(base.tiles_by_color(q)[0]).max()) for q in range(base.nsub))
+    same = d.chain().inspect(5, partition=1, seed_xy=m.centroids(), splits=(13,), max_colour_tiles=big)
+    for q in range(base.nsub):
+        assert np.array_equal(same.colors(q), base.colors(q))
+
+
+def test_colour_class_cap_greedy_order():
+    """On a strip of cells the tiles form a path; cap 1 forces one tile per colour
+    and the pass must still give neighbouring tiles different colours."""
+    ch = _strip_chain(40, 3)
+    s = ch.inspect(10, max_colour_tiles=1)
+    co, tl = s.tiles_by_color(0)
+    assert np.all(np.diff(co) <= 1)
+    col = s.colors(0)
+    assert all(col[t] != col[t + 1] for t in range(len(col) - 1))
+    assert s.check() == 0
