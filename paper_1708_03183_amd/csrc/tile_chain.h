@@ -194,38 +194,109 @@ __device__ __forceinline__ void chain_op(CellRegs<K, T> &r, const TileArgs &a, T
             const bool bnd = code & NB_BND;
             const int l1 = (code >> 14) & 3;
             const T *row1 = lds + (size_t)(code & 0x3fff) * NR;
-            const T zp1 = row1[0], zs1 = row1[1];
             T gq[NFP][3];
+            if (bnd) {
+                const bool fr = code & NB_FREE;
 #pragma unroll
-            for (int m = 0; m < NFP; ++m) {
-                const int n0 = fnode(K, p, m);
-                const int n1 = l1 == 0 ? fnode(K, 0, K - m) : (l1 == 1 ? fnode(K, 1, K - m) : fnode(K, 2, K - m));
-                T a0[NI], p0[NO];
+                for (int m = 0; m < NFP; ++m) {
+                    const int n0 = fnode(K, p, m);
+                    T a0[NI], p0[NO];
 #pragma unroll
-                for (int c = 0; c < NI; ++c) a0[c] = vin[c][n0];
+                    for (int c = 0; c < NI; ++c) a0[c] = vin[c][n0];
 #pragma unroll
-                for (int c = 0; c < NO; ++c) p0[c] = pen ? vp[c][n0] : T(0);
-                gq[m][0] = gq[m][1] = gq[m][2] = 0;
-                if (bnd) {
-                    const bool fr = code & NB_FREE;
+                    for (int c = 0; c < NO; ++c) p0[c] = pen ? vp[c][n0] : T(0);
+                    gq[m][0] = gq[m][1] = gq[m][2] = 0;
                     if constexpr (D.vel)
                         flux_v_ext<T, UPW, true>(a0, p0, fr, nx, ny, r.g[G_ZP], r.g[G_ZS], fs * r.g[G_IRHO], scale,
                                                  psc, gq[m]);
                     else
                         flux_s_ext<T, UPW, true>(a0, p0, fr, nx, ny, r.g[G_ZP], r.g[G_ZS], r.g[G_LAM], r.g[G_MU], fs,
                                                  scale, psc, gq[m]);
+                }
+            } else {
+                // This cell's side of the interior flux written through the jumps across
+                // the facet: with T = sigma n and t = (-ny, nx), the upwind traction state
+                // minus this side's traction is zp0/(zp0+zp1) [T.n] n + zs0/(zs0+zs1) [T.t] t,
+                // and the velocity state minus this side's velocity is zp1/(zp0+zp1) [v.n] n
+                // + zs1/(zs0+zs1) [v.t] t (the same flux as the facet loop's, one side of it);
+                // the central flux halves the jump.  Facet constants first, then per node.
+                const T zp0 = r.g[G_ZP], zs0 = r.g[G_ZS], zp1 = row1[0], zs1 = row1[1];
+                const T nn = nx * nx, mm = ny * ny, nm = nx * ny, nd = nn - mm;
+                const T ip = T(1) / (zp0 + zp1), is = T(1) / (zs0 + zs1);
+                T kn, kt, qn, qt, C1[3], C2[3];
+                if constexpr (D.vel) {
+                    const T w0 = fs * r.g[G_IRHO];
+                    kn = UPW ? w0 * scale * zp0 * ip : T(0.5) * w0 * scale;
+                    kt = UPW ? w0 * scale * zs0 * is : T(0);
+                    qn = w0 * psc * zp0 * zp1 * ip;
+                    qt = w0 * psc * zs0 * zs1 * is;
+                    (void)C1;
+                    (void)C2;
                 } else {
-                    T a1[NI], p1[NO], g1[3];
+                    const T lam = r.g[G_LAM], mu = r.g[G_MU];
+                    const T w = fs, l2m = w * (lam + 2 * mu), lw = w * lam, mw = w * mu;
+                    if (UPW) {
+                        kn = scale * zp1 * ip;
+                        kt = scale * zs1 * is;
+                        qn = psc * ip;
+                        qt = psc * is;
+                        C1[0] = l2m * nn + lw * mm;
+                        C1[1] = lw * nn + l2m * mm;
+                        C1[2] = 2 * mw * nm;
+                        C2[0] = -2 * mw * nm;
+                        C2[1] = 2 * mw * nm;
+                        C2[2] = mw * nd;
+                    } else {
+                        const T kc = T(0.5) * scale;
+                        kn = kt = qn = qt = T(0);
+                        C1[0] = kc * l2m * nx;  // out = C1 * dvx + C2 * dvy
+                        C2[0] = kc * lw * ny;
+                        C1[1] = kc * lw * nx;
+                        C2[1] = kc * l2m * ny;
+                        C1[2] = kc * mw * ny;
+                        C2[2] = kc * mw * nx;
+                    }
+                }
 #pragma unroll
-                    for (int c = 0; c < NI; ++c) a1[c] = row1[2 + c * NP + n1];
+                for (int m = 0; m < NFP; ++m) {
+                    const int n0 = fnode(K, p, m);
+                    const int n1 = l1 == 0 ? fnode(K, 0, K - m) : (l1 == 1 ? fnode(K, 1, K - m) : fnode(K, 2, K - m));
+                    T d[NI];  // jump of the operated field (neighbour minus this cell)
 #pragma unroll
-                    for (int c = 0; c < NO; ++c) p1[c] = pen ? row1[PO + c * NP + n1] : T(0);
-                    if constexpr (D.vel)
-                        flux_v_int<T, UPW, true>(a0, a1, p0, p1, nx, ny, r.g[G_ZP], r.g[G_ZS], zp1, zs1,
-                                                 fs * r.g[G_IRHO], T(0), scale, psc, gq[m], g1);
-                    else
-                        flux_s_int<T, UPW, true>(a0, a1, p0, p1, nx, ny, r.g[G_ZP], r.g[G_ZS], zp1, zs1, r.g[G_LAM],
-                                                 r.g[G_MU], T(0), T(0), fs, T(0), scale, psc, gq[m], g1);
+                    for (int c = 0; c < NI; ++c) d[c] = row1[2 + c * NP + n1] - vin[c][n0];
+                    if constexpr (D.vel) {
+                        if (UPW) {
+                            T An = kn * ((d[0] * nn + d[1] * mm) + d[2] * (2 * nm));
+                            T At = kt * (d[2] * nd + nm * (d[1] - d[0]));
+                            if constexpr (D.pen >= 0) {  // upwind flux: penalties are on whenever the operator has one
+                                const T ex = row1[PO + n1] - vp[0][n0], ey = row1[PO + NP + n1] - vp[1][n0];
+                                An += qn * (ex * nx + ey * ny);
+                                At += qt * (ey * nx - ex * ny);
+                            }
+                            gq[m][0] = An * nx - At * ny;
+                            gq[m][1] = An * ny + At * nx;
+                        } else {
+                            gq[m][0] = kn * (d[0] * nx + d[2] * ny);
+                            gq[m][1] = kn * (d[2] * nx + d[1] * ny);
+                        }
+                        gq[m][2] = 0;
+                    } else {
+                        if (UPW) {
+                            T En = kn * (d[0] * nx + d[1] * ny);
+                            T Et = kt * (d[1] * nx - d[0] * ny);
+                            if constexpr (D.pen >= 0) {
+                                const T sxx = row1[PO + n1] - vp[0][n0], syy = row1[PO + NP + n1] - vp[1][n0],
+                                        sxy = row1[PO + 2 * NP + n1] - vp[2][n0];
+                                En += qn * ((sxx * nn + syy * mm) + sxy * (2 * nm));
+                                Et += qt * (sxy * nd + nm * (syy - sxx));
+                            }
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) gq[m][c] = En * C1[c] + Et * C2[c];
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) gq[m][c] = C1[c] * d[0] + C2[c] * d[1];
+                        }
+                    }
                 }
             }
 #pragma unroll
