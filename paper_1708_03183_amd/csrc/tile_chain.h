@@ -96,6 +96,7 @@ struct CellRegs {
     static constexpr int NP = np_of(K);
     T f[F_COUNT][3][NP];  // fields of the cell (velocity-like ones use two components)
     T g[G_NROWS];
+    T nrm[3][3];  // per local facet: unit outward normal (x, y) and |facet| / |J|
 };
 
 template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int O>
@@ -189,8 +190,7 @@ __device__ __forceinline__ void chain_op(CellRegs<K, T> &r, const TileArgs &a, T
         for (int p = 0; p < 3; ++p) {
             const uint32_t code = nb[p];
             if (!(code & NB_VALID)) continue;
-            T nx, ny, fs;
-            facet_normal<T>(p, rx, ry, sx, sy, nx, ny, fs);
+            const T nx = r.nrm[p][0], ny = r.nrm[p][1], fs = r.nrm[p][2];
             const bool bnd = code & NB_BND;
             const int l1 = (code >> 14) & 3;
             const T *row1 = lds + (size_t)(code & 0x3fff) * NR;
@@ -378,6 +378,10 @@ __device__ __forceinline__ void chain_tile(const TileArgs &a, T *__restrict__ ld
         const T *geo = reinterpret_cast<const T *>(a.geo);
 #pragma unroll
         for (int q = 0; q < G_NROWS; ++q) r.g[q] = geo[(int64_t)q * a.nc + x];
+        // the facet normals serve every operator of the sub-chain
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+            facet_normal<T>(p, r.g[G_RX], r.g[G_RY], r.g[G_SX], r.g[G_SY], r.nrm[p][0], r.nrm[p][1], r.nrm[p][2]);
     }
     // fields are gathered at their first use and written back after their last write
     [&]<int... Q>(std::integer_sequence<int, Q...>) {
