@@ -168,6 +168,9 @@ def main():
 
     wall_t, ev_t, _, launches_t, vt, st_ = run(sol, 1, a.steps, a.warmup)
     rate_t = dofs * a.steps / wall_t
+    # five more timed repeats of a shorter window, for the spread
+    rsteps = min(a.steps, 200)
+    reps = sorted(1e3 * run(sol, 1, rsteps, a.warmup)[0] / rsteps for _ in range(5))
     # the same run again with an event pair around every tile-kernel launch
     sol.profile(True)
     psteps = min(a.steps, 200)
@@ -212,6 +215,7 @@ def main():
     # ---- oracle on the host: a bounded sample of the same workload
     cpu = None
     err_oracle = None
+    err_fp32 = None
     if not a.no_cpu_baseline:
         import oracle as O
         om = O.OMesh.from_mesh(m)
@@ -241,6 +245,15 @@ def main():
         num = math.sqrt(((gv.cpu().numpy() - v) ** 2).sum() + ((gs.cpu().numpy() - s) ** 2).sum())
         den = math.sqrt((v ** 2).sum() + (s ** 2).sum())
         err_oracle = num / den if den > 0 else 0.0
+        if prec:  # the FP32 path itself over the same window, against the FP64 oracle
+            fv = vt.clone()
+            fs_ = st_.clone()
+            sol.upload(fv, fs_)
+            sol.step(a.cpu_steps, mode=1, t0=tstart)
+            sol.download(fv, fs_)
+            torch.cuda.synchronize()
+            num = math.sqrt(((fv.double().cpu().numpy() - v) ** 2).sum() + ((fs_.double().cpu().numpy() - s) ** 2).sum())
+            err_fp32 = num / den if den > 0 else 0.0
 
     out = {
         "metric": "DG dof-updates/s per step, tiled-fused vs untiled, 1 MI355X",
@@ -263,6 +276,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "err_vs_fp64_oracle_rel_l2": err_oracle,
+        "err_fp32_run_vs_fp64_oracle_rel_l2": err_fp32,
+        "repeats_ms_per_step": {"steps": rsteps, "median": reps[2], "min": reps[0], "max": reps[-1]},
         "inspector": {"gpu_ms": sched.get("inspector_gpu_ms"), "wall_s": t_insp_wall,
                       "subchains": sched.get("subchains"), "lds_bytes": info["lds_bytes"]},
         "launches_per_step": launches_t / a.steps,

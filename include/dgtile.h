@@ -218,6 +218,11 @@ dgt_status dgt_energy(dgt_solver *s, const void *v, const void *sig_new, const v
  * dgt_state_download returns DGT_ESTATE and the counters are reset.  In mode 1,
  * dgt_step synchronises the stream on entry.  mode: 0 or 1, else DGT_EINVAL. */
 dgt_status dgt_solver_set_schedule(dgt_solver *s, int32_t mode);
+/* Polls of a dependence wait (schedule 1) before it gives up, 1..2^32-1; default
+ * 2^20 (about a second).  A tiny value makes waits time out on purpose, which
+ * exercises the error path (the kernels still exit normally).  DGT_EINVAL
+ * outside the range. */
+dgt_status dgt_solver_set_wait_limit(dgt_solver *s, int64_t polls);
 /* Per-launch timing switch (default off).  When on, the tiled executor of
  * dgt_step records a HIP event pair on the solver stream around every tile
  * kernel launch, so that dgt_last_step_timing reports the time spent inside

@@ -65,6 +65,7 @@ struct dgt_solver {
     dgt::DBuf<uint8_t> ef2l, eb2l;
     bool state_valid = false;
     int sched_mode = 0;  // tiled executor: 0 one launch per colour, 1 dependence-driven
+    uint32_t wait_limit = 1u << 20;  // polls before a dependence wait gives up
     // source
     bool has_src = false;
     int64_t src_in = -1, src_exec = -1;
@@ -774,7 +775,7 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
                 A.err = P.err.p;
                 A.head_base = P.epoch * (uint32_t)(P.ntiles + P.slots);
                 A.epoch = ++P.epoch;
-                A.spin_limit = 1u << 20;
+                A.spin_limit = s->wait_limit;
                 s->mark();
                 tile_launch<K, T>(P.kind, P.threads, P.vel, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, P.slots,
                                   P.lds_bytes, st, A, TA_LAUNCH);
@@ -1078,6 +1079,13 @@ dgt_status dgt_solver_set_schedule(dgt_solver *s, int32_t mode) {
     return guard([&] {
         DGT_REQUIRE(s && (mode == 0 || mode == 1), DGT_EINVAL, "bad arguments");
         s->sched_mode = mode;
+    });
+}
+
+dgt_status dgt_solver_set_wait_limit(dgt_solver *s, int64_t polls) {
+    return guard([&] {
+        DGT_REQUIRE(s && polls >= 1 && polls <= (int64_t)UINT32_MAX, DGT_EINVAL, "bad arguments");
+        s->wait_limit = (uint32_t)polls;
     });
 }
 

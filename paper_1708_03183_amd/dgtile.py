@@ -77,6 +77,7 @@ _SIGS = {
     "dgt_last_step_timing": [_p, C.POINTER(C.c_double), C.POINTER(C.c_double), _i64],
     "dgt_solver_profile": [_p, C.c_int32],
     "dgt_solver_set_schedule": [_p, C.c_int32],
+    "dgt_solver_set_wait_limit": [_p, C.c_int64],
     "dgt_solver_info": [_p, _i64, _i64, _i64],
     "dgt_solver_destroy": [_p],
     "dgt_last_error": [],
@@ -337,6 +338,10 @@ class Solver:
     def set_schedule(self, mode: int):
         """0: one launch per colour; 1: dependence-driven tiles, one launch per sub-chain."""
         _check(lib().dgt_solver_set_schedule(self.h, int(mode)))
+
+    def set_wait_limit(self, polls: int):
+        """Polls before a dependence wait of schedule 1 gives up (default 2**20)."""
+        _check(lib().dgt_solver_set_wait_limit(self.h, int(polls)))
 
     def profile(self, on: bool):
         """Per-launch event timing of the tile kernels on (off by default)."""

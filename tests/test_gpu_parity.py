@@ -301,6 +301,35 @@ def test_dependence_driven_schedule_repeated_calls(D):
     assert err <= 1e-12
 
 
+def test_dependence_wait_timeout_is_reported_and_recovered(D):
+    """A poll limit of 1 (set from the host) makes dependence waits give up: the
+    kernels exit, the error is reported, the counters are reset, and with the
+    default limit the next run is correct again."""
+    m, om, od, gm, gd = _dg_pair(D, 16, 2, 4, 1, 0x8, 5)
+    gd.inspect(8, partition=1, splits=(13,))
+    gd.set_schedule(1)
+    v, s = od.zeros()
+    v[:] = I.random_state(v.shape, 21)
+    s[:] = I.random_state(s.shape, 22)
+    gv = torch.from_numpy(v.copy()).cuda()
+    gs = torch.from_numpy(s.copy()).cuda()
+    gd.set_wait_limit(1)
+    gd.upload(gv, gs)
+    gd.step(3, mode=1)
+    with pytest.raises(D.DgtError):
+        gd.download(gv, gs)
+    gd.set_wait_limit(1 << 20)
+    gv.copy_(torch.from_numpy(v))
+    gs.copy_(torch.from_numpy(s))
+    gd.upload(gv, gs)
+    gd.step(3, mode=1, t0=0.0)
+    gd.download(gv, gs)
+    od.step(v, s, 3, t0=0.0)
+    err = rel_l2([gv.cpu().numpy(), gs.cpu().numpy()], [v, s])
+    print(f"after a forced timeout and reset: rel L2 err {err:.3e}")
+    assert err <= 1e-12
+
+
 @pytest.mark.parametrize("splits", [(), (13,)])
 @pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_tiled_chain_kernel_fp32_matches_oracle(D, k, splits):
