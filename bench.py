@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--splits", type=str, default=None, help="comma-separated loop indices, or 'none'")
     ap.add_argument("--colour-cap", type=int, default=0,
                     help="tiles per colour class: -1 the GPU's resident tile workgroups, 0 uncapped")
-    ap.add_argument("--schedule", type=int, default=1,
+    ap.add_argument("--schedule", type=int, default=None,
                     help="tiled executor: 0 one launch per colour, 1 dependence-driven (one launch per sub-chain)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-untiled", action="store_true")
@@ -53,13 +53,15 @@ def parse():
     return ap.parse_args()
 
 
-# tuned defaults per (degree, precision): seed tile size and fusion splits (13 = half steps)
+# tuned defaults per (degree, precision): seed tile size, fusion splits (13: half steps;
+# 4,8,13,17,21: one operator per sub-chain) and schedule (1: dependence-driven)
+OPS = (4, 8, 13, 17, 21)
 DEFAULTS = {
-    (1, "fp64"): (256, (13,)),
-    (2, "fp64"): (128, (13,)),
-    (2, "fp32"): (128, (13,)),
-    (3, "fp32"): (64, (13,)),
-    (4, "fp32"): (32, (13,)),
+    (1, "fp64"): (256, (13,), 1),
+    (2, "fp64"): (128, (13,), 1),
+    (2, "fp32"): (128, (13,), 1),
+    (3, "fp32"): (64, OPS, 0),
+    (4, "fp32"): (32, OPS, 0),
 }
 
 
@@ -104,7 +106,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     prec = 1 if a.precision == "fp32" else 0
-    ts, splits = DEFAULTS.get((a.degree, a.precision), (64, (13,)))
+    ts, splits, schedule = DEFAULTS.get((a.degree, a.precision), (64, OPS, 0))
+    if a.schedule is not None:
+        schedule = a.schedule
     if a.tile_size:
         ts = a.tile_size
     if a.splits is not None:
@@ -145,7 +149,7 @@ def main():
     torch.cuda.synchronize()
     ti0 = time.time()
     sol.inspect(ts, partition=1, splits=splits, max_colour_tiles=a.colour_cap)
-    sol.set_schedule(a.schedule)
+    sol.set_schedule(schedule)
     torch.cuda.synchronize()
     t_insp_wall = time.time() - ti0
     sched = json.loads(sol.schedule().summary())
@@ -207,8 +211,8 @@ def main():
     achieved = bytes_launch / avg_launch_s / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic(f"jitter{a.n}_p{k}", "f32" if prec else "f64", ts, splits, a.schedule),
-                "kernel": "k_tile_chain" if splits in ((13,), ()) else "k_tile_op",
+                "traffic": measured_traffic(f"jitter{a.n}_p{k}", "f32" if prec else "f64", ts, splits, schedule),
+                "kernel": "k_tile_chain",
                 "bytes_per_launch": bytes_launch, "avg_launch_us": avg_launch_s * 1e6,
                 "avg_launch_us_event_pairs": ker_p / launches_p * 1e3}
 
@@ -235,7 +239,7 @@ def main():
         # GPU FP64 tiled from the same state, compared with the oracle
         chk = make(0)
         chk.inspect(ts, partition=1, splits=splits, max_colour_tiles=a.colour_cap)
-        chk.set_schedule(a.schedule)
+        chk.set_schedule(schedule)
         gv = torch.from_numpy(np.ascontiguousarray(vt.double().cpu().numpy())).cuda()
         gs = torch.from_numpy(np.ascontiguousarray(st_.double().cpu().numpy())).cuda()
         chk.upload(gv, gs)
@@ -272,7 +276,7 @@ def main():
                                f"{mesh.nc} cells, DG P{k}, 3-layer, upwind, order-4 leapfrog",
                    "cells": mesh.nc, "dofs_per_step": dofs, "tile_size": ts, "splits": list(splits),
                    "partition": "hilbert", "colour_cap": a.colour_cap,
-                   "schedule": "dependence-driven" if a.schedule == 1 else "colour launches"},
+                   "schedule": "dependence-driven" if schedule == 1 else "colour launches"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "err_vs_fp64_oracle_rel_l2": err_oracle,

@@ -31,8 +31,7 @@ struct SubPlan {
     size_t lds_bytes = 0;
     int max_foot = 0;
     int threads = 256;
-    TileKernel kind = TK_GENERIC;  // operator kernel for single-operator sub-chains
-    bool vel = false;
+    TileKernel kind = TK_GENERIC;  // chain kernel for sub-chains of whole operator applications
     int o0 = 0, nops = 0;  // chain kernel: operators of the sub-chain
     // dependence-driven schedule (built on first use)
     bool graph = false;
@@ -509,40 +508,9 @@ static void build_plan(dgt_solver *s) {
         }
         P.lds_bytes = (size_t)A.nrow * A.stride * s->esz + (size_t)A.stride * (4 + 4 + 2) +
                       (size_t)A.nfl * 3 * A.stride * 4 + 16;
-        // a sub-chain that is one operator application (volume, interior and exterior facets,
-        // optional solve) with an optional update of its output runs on the operator kernel
-        A.upd_loop = -1;
-        {
-            const GLoop *g = &s->loops[sb.first];
-            const bool vel = g[0].kind == KV_VOL_V;
-            bool op = sb.n >= 3 && sb.n <= 5 && (vel || g[0].kind == KV_VOL_S) &&
-                      g[1].kind == (vel ? KV_INT_V : KV_INT_S) && g[2].kind == (vel ? KV_EXT_V : KV_EXT_S) &&
-                      A.loops[1].partner == 2 && g[1].in == g[0].in && g[1].out == g[0].out && A.nfl == 1;
-            int j = 3;
-            if (op && j < sb.n && g[j].kind == KV_SOLVE && g[j].out == g[0].out) ++j;
-            if (op && j < sb.n) {
-                const int k = g[j].kind;
-                const bool ok = vel ? (k == KV_UPD_V || k == KV_UPD2_V) : (k == KV_UPD_S || k == KV_UPD2_S);
-                if (ok && g[0].out == F_Z) A.upd_loop = j++;
-            }
-            // (P4 FP64 keeps to 256 work items: a 512-item workgroup would spill registers)
-            op = op && j == sb.n && P.max_foot <= (s->K == 4 && s->esz == 8 ? TILE_NT[1] : TILE_NT[2]);
-            const char *env = std::getenv("DGT_TILE_OP");
-            if (env && std::atoi(env) == 0) op = false;
-            if (op) {
-                const int ni = vel ? 3 : 2, no = vel ? 2 : 3;
-                A.nrow = np * ni + (g[1].pen >= 0 ? np * no : 0) + 2;
-                if (!(A.nrow & 1)) ++A.nrow;
-                P.kind = TK_OP;
-                P.vel = vel;
-                P.lds_bytes = (size_t)A.nrow * A.stride * s->esz;
-            } else {
-                A.upd_loop = -1;
-            }
-        }
         // a sub-chain of whole consecutive operator applications (each with its update, the
         // last one's optional) runs on the chain kernel
-        if (P.kind == TK_GENERIC) {
+        {
             const int order = s->p.time_order, nop = order == 4 ? 6 : 2;
             int o = 0;
             while (o < nop && op_first_loop(order, o) != sb.first) ++o;
@@ -572,6 +540,7 @@ static void build_plan(dgt_solver *s) {
             const int nops = o - first_op;
             bool known = false;
             for (const auto &c : TILE_CHAINS) known |= c[0] == order && c[1] == first_op && c[2] == nops;
+            known = known && chain_built(s->K, nops);
             const int cap = s->K == 4 && s->esz == 8 ? TILE_NT[1] : TILE_NT[2];
             const char *env = std::getenv("DGT_TILE_OP");
             if (ok && j == end && known && A.nfl == nops && P.max_foot <= cap && !(env && std::atoi(env) == 0)) {
@@ -594,10 +563,9 @@ static void build_plan(dgt_solver *s) {
                         std::to_string(P.lds_bytes) + " B of LDS (budget " + std::to_string(budget) +
                         "): use a smaller tile_size or split the chain");
         // one work item per footprint slot (and node group of the generic kernel)
-        const int ng = P.kind == TK_OP || s->K <= 2 ? 1 : (s->K == 3 ? 2 : 3);
+        const int ng = P.kind == TK_CHAIN || s->K <= 2 ? 1 : (s->K == 3 ? 2 : 3);
         const int items = A.stride * ng;
         P.threads = items <= TILE_NT[0] ? TILE_NT[0] : (items <= TILE_NT[1] ? TILE_NT[1] : TILE_NT[2]);
-        if (P.kind == TK_CHAIN) P.threads = std::max(P.threads, TILE_NT[1]);
         if (const char *e = std::getenv("DGT_TILE_THREADS"); e && P.kind == TK_GENERIC) P.threads = std::atoi(e);
     }
     DGT_HIP(hipStreamSynchronize(st));
@@ -754,7 +722,7 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
     hipStream_t st = s->st;
     const double dt = s->p.dt;
     for (auto &P : s->plan)
-        tile_launch<K, T>(P.kind, P.threads, P.vel, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, 0, P.lds_bytes,
+        tile_launch<K, T>(P.kind, P.threads, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, 0, P.lds_bytes,
                           st, P.args, TA_ATTR);
     for (int64_t n = 0; n < nsteps; ++n) {
         const double th = t0 + ((double)n + 0.5) * dt;
@@ -777,7 +745,7 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
                 A.epoch = ++P.epoch;
                 A.spin_limit = s->wait_limit;
                 s->mark();
-                tile_launch<K, T>(P.kind, P.threads, P.vel, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, P.slots,
+                tile_launch<K, T>(P.kind, P.threads, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, P.slots,
                                   P.lds_bytes, st, A, TA_LAUNCH);
                 s->mark();
                 ++launches;
@@ -788,7 +756,7 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
                 if (ntiles == 0) continue;
                 A.tile_base = P.color_off[c];
                 s->mark();
-                tile_launch<K, T>(P.kind, P.threads, P.vel, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, ntiles,
+                tile_launch<K, T>(P.kind, P.threads, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, ntiles,
                                   P.lds_bytes, st, A, TA_LAUNCH);
                 s->mark();
                 ++launches;
@@ -908,9 +876,9 @@ dgt_status dgt_solver_create(const dgt_mesh *m, const double *lam, const double 
 static int plan_slots(dgt_solver *s, const SubPlan &P) {
     int occ = 0, dev = 0;
     dispatch(s, [&]<int K, typename T>() {
-        tile_launch<K, T>(P.kind, P.threads, P.vel, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, 0, P.lds_bytes,
+        tile_launch<K, T>(P.kind, P.threads, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, 0, P.lds_bytes,
                           s->st, P.args, TA_ATTR);
-        tile_launch<K, T>(P.kind, P.threads, P.vel, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, 0, P.lds_bytes,
+        tile_launch<K, T>(P.kind, P.threads, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, 0, P.lds_bytes,
                           s->st, P.args, TA_OCCUPANCY, &occ);
     });
     DGT_HIP(hipGetDevice(&dev));

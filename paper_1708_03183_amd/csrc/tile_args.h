@@ -36,7 +36,6 @@ struct TileArgs {
     int32_t nrow;              // LDS elements per slot (odd), geometry in the last G_NROWS
     int32_t stride;            // slot capacity (largest footprint of the sub-chain)
     int32_t nfl;               // facet loops with a neighbour table
-    int32_t upd_loop;          // single-operator sub-chains: loop index of the trailing update or -1
     int32_t src_cell;          // exec id of the source cell or -1
     double dt, src_amp;        // src_amp = dt * r(t^{n+1/2})
     const void *src_vec;

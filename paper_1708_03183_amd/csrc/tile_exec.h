@@ -8,10 +8,15 @@
 
 namespace dgt {
 
-enum TileKernel { TK_GENERIC = 0, TK_OP = 1, TK_CHAIN = 2 };
+enum TileKernel { TK_GENERIC = 0, TK_CHAIN = 1 };
 
 // operator sequences the chain kernel is built for: (time order, first operator, operators)
-constexpr int TILE_CHAINS[4][3] = {{4, 0, 3}, {4, 3, 3}, {4, 0, 6}, {2, 0, 2}};
+constexpr int TILE_CHAINS[12][3] = {{4, 0, 3}, {4, 3, 3}, {4, 0, 6}, {2, 0, 2}, {4, 0, 1}, {4, 1, 1},
+                                    {4, 2, 1}, {4, 3, 1}, {4, 4, 1}, {4, 5, 1}, {2, 0, 1}, {2, 1, 1}};
+
+// Multi-operator chains hold every field of a cell in registers; from P3 on they
+// no longer fit (spills, one wave per SIMD), so only single operators are built.
+constexpr bool chain_built(int k, int nops) { return nops == 1 || k <= 2; }
 
 // Copies the reference element into the constant memory of the degree-K unit.
 template <int K, typename T>
@@ -27,7 +32,7 @@ enum TileAction { TA_LAUNCH = 0, TA_ATTR = 1, TA_OCCUPANCY = 2 };
 // largest footprint.  Chain kernel: operators [o0, o0 + nops) of the order-`order`
 // step (one of TILE_CHAINS), nt >= the largest footprint.
 template <int K, typename T>
-void tile_launch(TileKernel kind, int nt, bool vel, bool upw, bool pen, int order, int o0, int nops, int grid,
+void tile_launch(TileKernel kind, int nt, bool upw, bool pen, int order, int o0, int nops, int grid,
                  size_t lds, hipStream_t st, const TileArgs &A, TileAction act, int *occ = nullptr);
 
 // workgroup sizes the tile kernels are built for

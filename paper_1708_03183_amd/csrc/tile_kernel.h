@@ -312,213 +312,3 @@ __global__ __launch_bounds__(NT) void k_tile(const TileArgs a) {
 }
 
 }  // namespace dgt
-
-namespace dgt {
-
-// Tile executor for a sub-chain that is one operator application (volume,
-// interior facets, exterior facets, folded solve), optionally followed by the
-// update that consumes it.  One thread per footprint cell: the operator's
-// output and the cell's own operands stay in registers, and only the traces
-// the neighbours read (input, penalty field, impedances) go through LDS, so a
-// tile costs one barrier.  Same gather/scatter rule as k_tile.
-//   VEL: velocity operator (stress-like input, 2 output components), else the
-//        stress operator (velocity-like input, 3 output components)
-//   UPD: 0 none, 1 fourth-order update (adds dt * partner field), 2 second-order
-template <int K, typename T, bool VEL, bool UPW, int NT>
-__global__ __launch_bounds__(NT) void k_tile_op(const TileArgs a) {
-    constexpr int NP = np_of(K), NFP = K + 1;
-    constexpr int NI = VEL ? 3 : 2, NO = VEL ? 2 : 3;
-    extern __shared__ __align__(16) unsigned char smem[];
-    T *lds = reinterpret_cast<T *>(smem);
-    const int tile = a.tiles[a.tile_base + blockIdx.x];
-    const int f0 = a.foot_off[tile];
-    const int nfoot = a.foot_off[tile + 1] - f0;
-    const int s = threadIdx.x;
-    const int NR = a.nrow;
-    const bool pen = a.loops[1].pen >= 0;
-    const int uj = a.upd_loop;  // loop index of the update, or -1
-    const int upd = uj < 0 ? 0 : (a.loops[uj].kind == KV_UPD_V || a.loops[uj].kind == KV_UPD_S ? 1 : 2);
-    const int fin = a.loops[0].in, fout = a.loops[0].out, fpen = pen ? a.loops[1].pen : 0;
-    const int64_t nc = a.nc;
-    const auto &Rf = R<K, T>();
-    const bool act = s < nfoot;
-    const int PO = NP * NI;               // penalty trace offset in a row
-    const int ZO = PO + (pen ? NP * NO : 0);  // impedances
-
-    uint32_t acc = 0, nb[3] = {0, 0, 0};
-    int64_t x = 0;
-    uint16_t fl = 0;
-    T vin[NI][NP], vpen[NO][NP], g[G_NROWS];
-    if (act) {
-        acc = a.facc[f0 + s];
-        x = a.foot[f0 + s];
-        const bool single = acc >> 31;
-#pragma unroll
-        for (int f = 0; f < F_COUNT; ++f) {
-            const uint32_t m = acc & a.loops_mask[f];
-            if (m && ((m & (~m + 1u)) & a.rfirst_mask[f])) fl |= 1u << f;
-            if ((acc & a.writes_mask[f]) && (((a.persistent_mask >> f) & 1) || !single)) fl |= 1u << (8 + f);
-        }
-        const int b0 = a.tnb_off[tile];
-#pragma unroll
-        for (int p = 0; p < 3; ++p) nb[p] = a.tnb[b0 + p * nfoot + s];
-        const T *geo = reinterpret_cast<const T *>(a.geo);
-#pragma unroll
-        for (int r = 0; r < G_NROWS; ++r) g[r] = geo[(int64_t)r * nc + x];
-        const bool gin = (fl >> fin) & 1, gpen = pen && ((fl >> fpen) & 1);
-        const T *Fi = reinterpret_cast<const T *>(a.F[fin]);
-        const T *Fp = reinterpret_cast<const T *>(a.F[fpen]);
-#pragma unroll
-        for (int c = 0; c < NI; ++c)
-#pragma unroll
-            for (int i = 0; i < NP; ++i) vin[c][i] = gin ? Fi[(int64_t)(c * NP + i) * nc + x] : T(0);
-#pragma unroll
-        for (int c = 0; c < NO; ++c)
-#pragma unroll
-            for (int i = 0; i < NP; ++i) vpen[c][i] = gpen ? Fp[(int64_t)(c * NP + i) * nc + x] : T(0);
-        T *row = lds + (size_t)s * NR;
-#pragma unroll
-        for (int c = 0; c < NI; ++c)
-#pragma unroll
-            for (int i = 0; i < NP; ++i) row[c * NP + i] = vin[c][i];
-        if (pen) {
-#pragma unroll
-            for (int c = 0; c < NO; ++c)
-#pragma unroll
-                for (int i = 0; i < NP; ++i) row[PO + c * NP + i] = vpen[c][i];
-        }
-        row[ZO] = g[G_ZP];
-        row[ZO + 1] = g[G_ZS];
-    }
-    __syncthreads();
-    if (!act) return;
-
-    // volume term (loop 0) or the partial sum gathered from an earlier tile
-    T o[NO][NP];
-    const T rx = g[G_RX], ry = g[G_RY], sx = g[G_SX], sy = g[G_SY];
-    if (acc & 1u) {
-        const T scale = sizeof(T) == 8 ? (T)a.loops[0].scale_d : (T)a.loops[0].scale_f;
-#pragma unroll
-        for (int i = 0; i < NP; ++i) {
-            T ar[NI], as[NI];
-#pragma unroll
-            for (int c = 0; c < NI; ++c) ar[c] = as[c] = 0;
-#pragma unroll
-            for (int jj = 0; jj < NP; ++jj) {
-                const T dr = Rf.Dr[i * NP + jj], ds = Rf.Ds[i * NP + jj];
-#pragma unroll
-                for (int c = 0; c < NI; ++c) {
-                    ar[c] += dr * vin[c][jj];
-                    as[c] += ds * vin[c][jj];
-                }
-            }
-            if (VEL) {
-                const T irho = g[G_IRHO];
-                o[0][i] = scale * irho * ((rx * ar[0] + sx * as[0]) + (ry * ar[2] + sy * as[2]));
-                o[1][i] = scale * irho * ((rx * ar[2] + sx * as[2]) + (ry * ar[1] + sy * as[1]));
-            } else {
-                const T lam = g[G_LAM], mu = g[G_MU];
-                const T exx = rx * ar[0] + sx * as[0], eyy = ry * ar[1] + sy * as[1];
-                const T exy = T(0.5) * ((ry * ar[0] + sy * as[0]) + (rx * ar[1] + sx * as[1]));
-                o[0][i] = scale * ((lam + 2 * mu) * exx + lam * eyy);
-                o[1][i] = scale * (lam * exx + (lam + 2 * mu) * eyy);
-                o[NO - 1][i] = scale * (2 * mu * exy);
-            }
-        }
-    } else {
-        const bool gout = (fl >> fout) & 1;
-        const T *Fo = reinterpret_cast<const T *>(a.F[fout]);
-#pragma unroll
-        for (int c = 0; c < NO; ++c)
-#pragma unroll
-            for (int i = 0; i < NP; ++i) o[c][i] = gout ? Fo[(int64_t)(c * NP + i) * nc + x] : T(0);
-    }
-
-    // facet terms (loops 1 and 2): this cell's side of each facet in the tile
-    if ((nb[0] | nb[1] | nb[2]) & NB_VALID) {
-        const T scale = sizeof(T) == 8 ? (T)a.loops[1].scale_d : (T)a.loops[1].scale_f;
-        const T psc = pen ? (sizeof(T) == 8 ? (T)a.loops[1].pscale_d : (T)a.loops[1].pscale_f) : T(0);
-#pragma unroll
-        for (int p = 0; p < 3; ++p) {
-            const uint32_t code = nb[p];
-            if (!(code & NB_VALID)) continue;
-            T nx, ny, fs;
-            facet_normal<T>(p, rx, ry, sx, sy, nx, ny, fs);
-            const bool bnd = code & NB_BND;
-            const int l1 = (code >> 14) & 3;
-            const T *row1 = lds + (size_t)(code & 0x3fff) * NR;
-            const T zp1 = row1[ZO], zs1 = row1[ZO + 1];
-            T gq[NFP][3];
-#pragma unroll
-            for (int m = 0; m < NFP; ++m) {
-                const int n0 = fnode(K, p, m);
-                const int n1 = l1 == 0 ? fnode(K, 0, K - m) : (l1 == 1 ? fnode(K, 1, K - m) : fnode(K, 2, K - m));
-                T a0[NI], p0[NO];
-#pragma unroll
-                for (int c = 0; c < NI; ++c) a0[c] = vin[c][n0];
-#pragma unroll
-                for (int c = 0; c < NO; ++c) p0[c] = vpen[c][n0];
-                gq[m][0] = gq[m][1] = gq[m][2] = 0;
-                if (bnd) {
-                    const bool fr = code & NB_FREE;
-                    if (VEL) {
-                        if (pen) flux_v_ext<T, UPW, true>(a0, p0, fr, nx, ny, g[G_ZP], g[G_ZS], fs * g[G_IRHO], scale, psc, gq[m]);
-                        else flux_v_ext<T, UPW, false>(a0, p0, fr, nx, ny, g[G_ZP], g[G_ZS], fs * g[G_IRHO], scale, psc, gq[m]);
-                    } else {
-                        if (pen) flux_s_ext<T, UPW, true>(a0, p0, fr, nx, ny, g[G_ZP], g[G_ZS], g[G_LAM], g[G_MU], fs, scale, psc, gq[m]);
-                        else flux_s_ext<T, UPW, false>(a0, p0, fr, nx, ny, g[G_ZP], g[G_ZS], g[G_LAM], g[G_MU], fs, scale, psc, gq[m]);
-                    }
-                } else {
-                    T a1[NI], p1[NO], g1[3];
-#pragma unroll
-                    for (int c = 0; c < NI; ++c) a1[c] = row1[c * NP + n1];
-#pragma unroll
-                    for (int c = 0; c < NO; ++c) p1[c] = pen ? row1[PO + c * NP + n1] : T(0);
-                    if (VEL) {
-                        if (pen) flux_v_int<T, UPW, true>(a0, a1, p0, p1, nx, ny, g[G_ZP], g[G_ZS], zp1, zs1, fs * g[G_IRHO], T(0), scale, psc, gq[m], g1);
-                        else flux_v_int<T, UPW, false>(a0, a1, p0, p1, nx, ny, g[G_ZP], g[G_ZS], zp1, zs1, fs * g[G_IRHO], T(0), scale, psc, gq[m], g1);
-                    } else {
-                        if (pen) flux_s_int<T, UPW, true>(a0, a1, p0, p1, nx, ny, g[G_ZP], g[G_ZS], zp1, zs1, g[G_LAM], g[G_MU], T(0), T(0), fs, T(0), scale, psc, gq[m], g1);
-                        else flux_s_int<T, UPW, false>(a0, a1, p0, p1, nx, ny, g[G_ZP], g[G_ZS], zp1, zs1, g[G_LAM], g[G_MU], T(0), T(0), fs, T(0), scale, psc, gq[m], g1);
-                    }
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < NP; ++i)
-#pragma unroll
-                for (int m = 0; m < NFP; ++m) {
-                    const T lv = Rf.lift[(p * NP + i) * NFP + m];
-#pragma unroll
-                    for (int c = 0; c < NO; ++c) o[c][i] += lv * gq[m][c];
-                }
-        }
-    }
-
-    // the update that consumes the operator's output
-    if (upd && ((acc >> uj) & 1u)) {
-        const int fq = VEL ? F_V : F_S, fr = VEL ? F_U : F_X;
-        T *Q = reinterpret_cast<T *>(a.F[fq]);
-        const T *Pf = reinterpret_cast<const T *>(a.F[fr]);
-        const T dt = (T)a.dt;
-        const bool src = !VEL && x == a.src_cell;
-        const T *sv = reinterpret_cast<const T *>(a.src_vec);
-#pragma unroll
-        for (int c = 0; c < NO; ++c)
-#pragma unroll
-            for (int i = 0; i < NP; ++i) {
-                const int64_t gi = (int64_t)(c * NP + i) * nc + x;
-                T add = (upd == 1 ? dt * Pf[gi] : T(0)) + o[c][i];
-                if (src && c < 2) add += (T)a.src_amp * sv[i];
-                Q[gi] += add;
-            }
-    }
-    if ((fl >> (8 + fout)) & 1) {
-        T *Fo = reinterpret_cast<T *>(a.F[fout]);
-#pragma unroll
-        for (int c = 0; c < NO; ++c)
-#pragma unroll
-            for (int i = 0; i < NP; ++i) Fo[(int64_t)(c * NP + i) * nc + x] = o[c][i];
-    }
-}
-
-}  // namespace dgt

@@ -29,52 +29,57 @@ static void tile_launch_chain(bool upw, int order, int o0, int nops, int grid, s
         auto kern = upw ? k_tile_chain<K, T, true, ORD, O0, N, NT> : k_tile_chain<K, T, false, ORD, O0, N, NT>;
         tile_go(kern, NT, grid, lds, st, A, act, occ);
     };
-    if (order == 4 && o0 == 0 && nops == 3) pick.template operator()<4, 0, 3>();
-    else if (order == 4 && o0 == 3 && nops == 3) pick.template operator()<4, 3, 3>();
-    else if (order == 4 && o0 == 0 && nops == 6) pick.template operator()<4, 0, 6>();
-    else if (order == 2 && o0 == 0 && nops == 2) pick.template operator()<2, 0, 2>();
+    DGT_REQUIRE(chain_built(K, nops), DGT_EINVAL, "no chain kernel for this operator sequence at this degree");
+    if constexpr (chain_built(K, 3)) {
+        if (order == 4 && o0 == 0 && nops == 3) return pick.template operator()<4, 0, 3>();
+        if (order == 4 && o0 == 3 && nops == 3) return pick.template operator()<4, 3, 3>();
+        if (order == 4 && o0 == 0 && nops == 6) return pick.template operator()<4, 0, 6>();
+        if (order == 2 && o0 == 0 && nops == 2) return pick.template operator()<2, 0, 2>();
+    }
+    if (order == 4 && nops == 1 && o0 == 0) pick.template operator()<4, 0, 1>();
+    else if (order == 4 && nops == 1 && o0 == 1) pick.template operator()<4, 1, 1>();
+    else if (order == 4 && nops == 1 && o0 == 2) pick.template operator()<4, 2, 1>();
+    else if (order == 4 && nops == 1 && o0 == 3) pick.template operator()<4, 3, 1>();
+    else if (order == 4 && nops == 1 && o0 == 4) pick.template operator()<4, 4, 1>();
+    else if (order == 4 && nops == 1 && o0 == 5) pick.template operator()<4, 5, 1>();
+    else if (order == 2 && nops == 1 && o0 == 0) pick.template operator()<2, 0, 1>();
+    else if (order == 2 && nops == 1 && o0 == 1) pick.template operator()<2, 1, 1>();
     else DGT_REQUIRE(false, DGT_EINVAL, "no chain kernel for this operator sequence");
 }
 
 template <int K, typename T, int NT>
-static void tile_launch_nt(TileKernel kind, bool vel, bool upw, bool pen, int grid, size_t lds, hipStream_t st,
-                           const TileArgs &A, TileAction act, int *occ) {
-    if (kind == TK_OP) {
-        auto kern = vel ? (upw ? k_tile_op<K, T, true, true, NT> : k_tile_op<K, T, true, false, NT>)
-                        : (upw ? k_tile_op<K, T, false, true, NT> : k_tile_op<K, T, false, false, NT>);
-        tile_go(kern, NT, grid, lds, st, A, act, occ);
-    } else {
-        auto kern = upw ? (pen ? k_tile<K, T, true, true, NT> : k_tile<K, T, true, false, NT>)
-                        : (pen ? k_tile<K, T, false, true, NT> : k_tile<K, T, false, false, NT>);
-        tile_go(kern, NT, grid, lds, st, A, act, occ);
-    }
+static void tile_launch_nt(bool upw, bool pen, int grid, size_t lds, hipStream_t st, const TileArgs &A, TileAction act,
+                           int *occ) {
+    auto kern = upw ? (pen ? k_tile<K, T, true, true, NT> : k_tile<K, T, true, false, NT>)
+                    : (pen ? k_tile<K, T, false, true, NT> : k_tile<K, T, false, false, NT>);
+    tile_go(kern, NT, grid, lds, st, A, act, occ);
 }
 
 template <int K, typename T>
-static void tile_launch_any(TileKernel kind, int nt, bool vel, bool upw, bool pen, int order, int o0, int nops,
+static void tile_launch_any(TileKernel kind, int nt, bool upw, bool pen, int order, int o0, int nops,
                             int grid, size_t lds, hipStream_t st, const TileArgs &A, TileAction act, int *occ) {
     DGT_REQUIRE(nt == 128 || nt == 256 || nt == 512, DGT_EINVAL, "tile workgroup size must be 128, 256 or 512");
     if (kind == TK_CHAIN) {
-        DGT_REQUIRE(nt != 128, DGT_EINVAL, "the chain kernel runs with 256 or 512 work items");
         if (nt == 512) tile_launch_chain<K, T, 512>(upw, order, o0, nops, grid, lds, st, A, act, occ);
-        else tile_launch_chain<K, T, 256>(upw, order, o0, nops, grid, lds, st, A, act, occ);
+        else if (nt == 256) tile_launch_chain<K, T, 256>(upw, order, o0, nops, grid, lds, st, A, act, occ);
+        else tile_launch_chain<K, T, 128>(upw, order, o0, nops, grid, lds, st, A, act, occ);
         return;
     }
-    if (nt == 512) tile_launch_nt<K, T, 512>(kind, vel, upw, pen, grid, lds, st, A, act, occ);
-    else if (nt == 256) tile_launch_nt<K, T, 256>(kind, vel, upw, pen, grid, lds, st, A, act, occ);
-    else tile_launch_nt<K, T, 128>(kind, vel, upw, pen, grid, lds, st, A, act, occ);
+    if (nt == 512) tile_launch_nt<K, T, 512>(upw, pen, grid, lds, st, A, act, occ);
+    else if (nt == 256) tile_launch_nt<K, T, 256>(upw, pen, grid, lds, st, A, act, occ);
+    else tile_launch_nt<K, T, 128>(upw, pen, grid, lds, st, A, act, occ);
 }
 
 template <>
-void tile_launch<DGT_TILE_K, double>(TileKernel kind, int nt, bool vel, bool upw, bool pen, int order, int o0, int nops,
+void tile_launch<DGT_TILE_K, double>(TileKernel kind, int nt, bool upw, bool pen, int order, int o0, int nops,
                                      int grid, size_t lds, hipStream_t st, const TileArgs &A, TileAction act, int *occ) {
-    tile_launch_any<DGT_TILE_K, double>(kind, nt, vel, upw, pen, order, o0, nops, grid, lds, st, A, act, occ);
+    tile_launch_any<DGT_TILE_K, double>(kind, nt, upw, pen, order, o0, nops, grid, lds, st, A, act, occ);
 }
 
 template <>
-void tile_launch<DGT_TILE_K, float>(TileKernel kind, int nt, bool vel, bool upw, bool pen, int order, int o0, int nops,
+void tile_launch<DGT_TILE_K, float>(TileKernel kind, int nt, bool upw, bool pen, int order, int o0, int nops,
                                     int grid, size_t lds, hipStream_t st, const TileArgs &A, TileAction act, int *occ) {
-    tile_launch_any<DGT_TILE_K, float>(kind, nt, vel, upw, pen, order, o0, nops, grid, lds, st, A, act, occ);
+    tile_launch_any<DGT_TILE_K, float>(kind, nt, upw, pen, order, o0, nops, grid, lds, st, A, act, occ);
 }
 
 template <>

@@ -213,7 +213,7 @@ def test_tiled_fp64_tile_sizes_and_splits(D, ts, part, splits):
 
 OP_CASES = [
     # n, k, order, flux, free, ren, steps, ts, splits: one operator application per sub-chain,
-    # with the update fused into the operator before it (the operator kernel)
+    # with the update fused into the operator before it (chain kernel, one operator)
     (12, 2, 4, 1, 0x8, 7, 10, 32, (4, 8, 13, 17, 21)),
     (12, 2, 2, 1, 0x8, 7, 10, 32, (4,)),
     (10, 1, 4, 0, 0xF, 3, 10, 64, (4, 8, 13, 17, 21)),
