@@ -198,7 +198,8 @@ dgt_status dgt_schedule_summary_json(const dgt_schedule *s, char *buf, size_t le
             const SubSched &b = s->s->sub[i];
             if (i) o << ", ";
             o << "{\"first_loop\": " << b.first << ", \"nloops\": " << b.n << ", \"ntiles\": " << b.ntiles
-              << ", \"ncolors\": " << b.ncolors << ", \"rounds\": " << b.rounds << ", \"footprint\": [";
+              << ", \"ncolors\": " << b.ncolors << ", \"rounds\": " << b.rounds
+              << ", \"dependences\": " << b.dep_edges << ", \"footprint\": [";
             for (int st = 0; st < s->chain->nsets; ++st) o << (st ? ", " : "") << b.foot_len[st];
             o << "]}";
         }

@@ -36,6 +36,10 @@ struct SubSched {
     int64_t foot_len[kMaxSets] = {0};
     DBuf<int32_t> foot_off[kMaxSets], foot[kMaxSets];
     DBuf<uint32_t> acc[kMaxSets];
+    // dependence graph for the dependence-driven executor: edge a -> b when the
+    // footprints of tiles a and b share an element of any set and a has the lower colour
+    int64_t dep_edges = 0;
+    DBuf<int32_t> dep_need, dep_off, dep_succ;  // [ntiles], [ntiles+1], [dep_edges]
 };
 
 // Output of the inspector, resident in device memory.
@@ -66,6 +70,11 @@ class Inspector {
 
    private:
     Schedule *cur = nullptr;
+    // unique touches of each set from the last conflict pass (reused by footprints)
+    bool tk_valid = false;
+    int64_t tk_len[kMaxSets] = {0};
+    DBuf<uint64_t> tk_keys[kMaxSets];
+    DBuf<uint32_t> tk_bits[kMaxSets];
     void build_inverse(const ChainDesc &c, int mi, hipStream_t st);
     void seed_partition(int seedset, int64_t ts, int partition, const double *xy_host, const double *xy_dev,
                         DBuf<int32_t> &tile0, DBuf<int32_t> &rank);
@@ -76,6 +85,7 @@ class Inspector {
     int64_t touches(int first, int nl, int s, DBuf<uint64_t> &keys, DBuf<uint32_t> &bits, const Schedule &S);
     int64_t conflicts(int first, int nl, const DBuf<int32_t> &color, DBuf<uint64_t> &edges, int64_t &ne);
     void footprints(int first, int nl, SubSched &sb);
+    void dependences(SubSched &sb, const DBuf<uint64_t> *keys, const int64_t *len);
 };
 
 }  // namespace dgt

@@ -336,6 +336,38 @@ __global__ void k_conflicts(const uint64_t *__restrict__ keys, int64_t n, const 
     }
 }
 
+// dependence edges among the tiles that share one element: every pair of entries of
+// one group of the sorted unique (element<<32 | tile) touches; count pass, then emit
+// pass oriented from the lower colour to the higher (equal colours flag an error)
+__global__ void k_dep_count(const uint64_t *__restrict__ keys, int64_t n, int64_t *__restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t x = keys[i] >> 32;
+    int64_t c = 0;
+    for (int64_t j = i + 1; j < n && (keys[j] >> 32) == x; ++j) ++c;
+    cnt[i] = c;
+}
+
+__global__ void k_dep_emit(const uint64_t *__restrict__ keys, int64_t n, const int64_t *__restrict__ pos,
+                           const int32_t *__restrict__ color, uint64_t *__restrict__ out, int32_t *__restrict__ bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t x = keys[i] >> 32;
+    const uint32_t ti = (uint32_t)(keys[i] & 0xffffffffull);
+    int64_t w = pos[i];
+    for (int64_t j = i + 1; j < n && (keys[j] >> 32) == x; ++j) {
+        const uint32_t tj = (uint32_t)(keys[j] & 0xffffffffull);
+        if (color[ti] == color[tj]) *bad = 1;
+        const bool lo = color[ti] < color[tj];
+        out[w++] = ((uint64_t)(lo ? ti : tj) << 32) | (lo ? tj : ti);
+    }
+}
+
+__global__ void k_low32_hist(const uint64_t *__restrict__ keys, int64_t n, int32_t *__restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd(&count[(int32_t)(keys[i] & 0xffffffffull)], 1);
+}
+
 // footprint entries: re-key to (tile<<32 | element) and flag single-tile elements
 __global__ void k_foot_rekey(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ bits, int64_t n,
                              uint64_t *__restrict__ okeys, uint32_t *__restrict__ obits) {
@@ -778,10 +810,12 @@ int64_t Inspector::conflicts(int first, int nl, const DBuf<int32_t> &color, DBuf
     std::vector<DBuf<uint64_t>> found;
     std::vector<int64_t> nfound;
     int64_t total = 0;
+    tk_valid = false;
     for (int s = 0; s < chain.nsets; ++s) {
-        DBuf<uint64_t> keys;
-        DBuf<uint32_t> bits;
+        DBuf<uint64_t> &keys = tk_keys[s];
+        DBuf<uint32_t> &bits = tk_bits[s];
         const int64_t m = touches(first, nl, s, keys, bits, *cur);
+        tk_len[s] = m;
         if (m == 0) continue;
         int64_t cap = std::max<int64_t>(1024, m);
         for (;;) {
@@ -801,6 +835,7 @@ int64_t Inspector::conflicts(int first, int nl, const DBuf<int32_t> &color, DBuf
             cap = c;
         }
     }
+    tk_valid = true;
     if (total == 0) return 0;
     // fake connections: edges <- unique(edges U conflicts)
     DBuf<uint64_t> all(ne + total);
@@ -818,10 +853,15 @@ int64_t Inspector::conflicts(int first, int nl, const DBuf<int32_t> &color, DBuf
 
 void Inspector::footprints(int first, int nl, SubSched &sb) {
     hipStream_t st = stream;
+    // the last conflict pass found none, so its touches are those of the final tiling
+    if (!tk_valid)
+        for (int s = 0; s < chain.nsets; ++s) tk_len[s] = touches(first, nl, s, tk_keys[s], tk_bits[s], *cur);
+    tk_valid = false;
+    dependences(sb, tk_keys, tk_len);
     for (int s = 0; s < chain.nsets; ++s) {
-        DBuf<uint64_t> keys;
-        DBuf<uint32_t> bits;
-        const int64_t m = touches(first, nl, s, keys, bits, *cur);
+        DBuf<uint64_t> keys = std::move(tk_keys[s]);
+        DBuf<uint32_t> bits = std::move(tk_bits[s]);
+        const int64_t m = tk_len[s];
         sb.foot_len[s] = m;
         if (m == 0) {
             sb.foot_off[s].alloc(sb.ntiles + 1);
@@ -839,6 +879,50 @@ void Inspector::footprints(int first, int nl, SubSched &sb) {
         sb.acc[s] = std::move(b2);
         offsets_by_high(k2, m, sb.ntiles, sb.foot_off[s], st);
     }
+}
+
+void Inspector::dependences(SubSched &sb, const DBuf<uint64_t> *keys, const int64_t *len) {
+    hipStream_t st = stream;
+    const int32_t nt = sb.ntiles;
+    std::vector<DBuf<uint64_t>> parts;
+    std::vector<int64_t> lens;
+    DBuf<int32_t> bad(1);
+    DGT_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), st));
+    int64_t total = 0;
+    for (int s = 0; s < chain.nsets; ++s) {
+        const int64_t m = len[s];
+        if (m < 2) continue;
+        DBuf<int64_t> cnt(m + 1), pos(m + 1);
+        DGT_HIP(hipMemsetAsync(cnt.p + m, 0, sizeof(int64_t), st));
+        k_dep_count<<<blocks_for(m, 256), 256, 0, st>>>(keys[s].p, m, cnt.p);
+        exclusive_scan_i64(cnt.p, pos.p, m + 1, st);
+        int64_t np = 0;
+        DGT_HIP(hipMemcpyAsync(&np, pos.p + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        DGT_HIP(hipStreamSynchronize(st));
+        if (np == 0) continue;
+        DBuf<uint64_t> out(np);
+        k_dep_emit<<<blocks_for(m, 256), 256, 0, st>>>(keys[s].p, m, pos.p, sb.color.p, out.p, bad.p);
+        parts.push_back(std::move(out));
+        lens.push_back(np);
+        total += np;
+    }
+    DBuf<uint64_t> edges(total > 0 ? total : 1);
+    int64_t w = 0;
+    for (size_t i = 0; i < parts.size(); ++i) {
+        DGT_HIP(hipMemcpyAsync(edges.p + w, parts[i].p, sizeof(uint64_t) * lens[i], hipMemcpyDeviceToDevice, st));
+        w += lens[i];
+    }
+    parts.clear();
+    sort_keys(edges, total, st);
+    const int64_t ne = unique_keys(edges, total, st);
+    DGT_REQUIRE(bad.download(st)[0] == 0, DGT_ESTATE, "two tiles of one colour share an element");
+    sb.dep_edges = ne;
+    sb.dep_need.alloc(nt);
+    DGT_HIP(hipMemsetAsync(sb.dep_need.p, 0, sizeof(int32_t) * nt, st));
+    if (ne) k_low32_hist<<<blocks_for(ne, 256), 256, 0, st>>>(edges.p, ne, sb.dep_need.p);
+    offsets_by_high(edges, ne, nt, sb.dep_off, st);
+    sb.dep_succ.alloc(ne > 0 ? ne : 1);
+    if (ne) k_low32<<<blocks_for(ne, 256), 256, 0, st>>>(edges.p, ne, sb.dep_succ.p);
 }
 
 std::unique_ptr<Schedule> Inspector::run(int64_t ts, int partition, const double *xy_host, const double *xy_dev,

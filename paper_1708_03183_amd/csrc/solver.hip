@@ -35,7 +35,7 @@ struct SubPlan {
     int o0 = 0, nops = 0;  // chain kernel: operators of the sub-chain
     // dependence-driven schedule (built on first use)
     bool graph = false;
-    DBuf<int32_t> need, succ_off, succ, err;
+    DBuf<int32_t> err;
     DBuf<uint32_t> cnt, head;
     uint32_t epoch = 0;
     int slots = 0;  // workgroup size of the tile kernel
@@ -255,11 +255,16 @@ static void set_exec_order(dgt_solver *s, const std::vector<int32_t> &rank) {
     });
     // untiled maps in exec numbering; facets ordered by their lower exec cell
     const auto &M = *s->mesh;
-    std::vector<int64_t> ford(nf);
-    std::iota(ford.begin(), ford.end(), 0);
-    std::vector<int32_t> fkey(nf);
-    for (int64_t f = 0; f < nf; ++f) fkey[f] = std::min(rank[M.f2c[2 * f]], rank[M.f2c[2 * f + 1]]);
-    std::stable_sort(ford.begin(), ford.end(), [&](int64_t a, int64_t b) { return fkey[a] < fkey[b]; });
+    // (counting sorts by exec cell, stable in the mesh's facet order)
+    auto counting_order = [nc](int64_t n, auto key) {
+        std::vector<int64_t> start(nc + 1, 0), ord(n);
+        for (int64_t i = 0; i < n; ++i) start[key(i) + 1]++;
+        for (int64_t c = 0; c < nc; ++c) start[c + 1] += start[c];
+        for (int64_t i = 0; i < n; ++i) ord[start[key(i)]++] = i;
+        return ord;
+    };
+    const std::vector<int64_t> ford = counting_order(
+        nf, [&](int64_t f) { return std::min(rank[M.f2c[2 * f]], rank[M.f2c[2 * f + 1]]); });
     std::vector<int32_t> ef2c(2 * std::max<int64_t>(nf, 1)), c2f(3 * std::max<int64_t>(nc, 1), INT32_MIN);
     std::vector<uint8_t> ef2l(std::max<int64_t>(nf, 1));
     for (int64_t e = 0; e < nf; ++e) {
@@ -271,9 +276,7 @@ static void set_exec_order(dgt_solver *s, const std::vector<int32_t> &rank) {
         c2f[(int64_t)M.f2l[2 * f] * nc + x0] = (int32_t)(2 * e);
         c2f[(int64_t)M.f2l[2 * f + 1] * nc + x1] = (int32_t)(2 * e + 1);
     }
-    std::vector<int64_t> bord(nb);
-    std::iota(bord.begin(), bord.end(), 0);
-    std::stable_sort(bord.begin(), bord.end(), [&](int64_t a, int64_t b) { return rank[M.b2c[a]] < rank[M.b2c[b]]; });
+    const std::vector<int64_t> bord = counting_order(nb, [&](int64_t b) { return rank[M.b2c[b]]; });
     std::vector<int32_t> eb2c(std::max<int64_t>(nb, 1));
     std::vector<uint8_t> eb2l(std::max<int64_t>(nb, 1));
     for (int64_t e = 0; e < nb; ++e) {
@@ -647,50 +650,11 @@ static void step_untiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &laun
     }
 }
 
-// Dependence graph of a sub-chain's tiles for the dependence-driven schedule: tile a
-// precedes tile b when their footprints share an element of any set and a has the
-// lower colour (tiles of one colour never share one).  Built on the host from the
-// schedule's footprints; counters start at zero.
+// Counters of the dependence-driven schedule of one sub-chain (the dependence graph
+// itself comes with the inspector's schedule); they start at zero.
 static void build_graph(dgt_solver *s, int b, SubPlan &P) {
     hipStream_t st = s->st;
-    const dgt::Schedule &S = *s->sched->s;
-    const SubSched &sb = S.sub[b];
-    const auto col = sb.color.download(st, sb.ntiles);
-    std::vector<uint64_t> pairs, edges;
-    for (int set = 0; set < s->sched->chain->nsets; ++set) {
-        const int64_t m = sb.foot_len[set];
-        if (m <= 0) continue;
-        const auto off = sb.foot_off[set].download(st, sb.ntiles + 1);
-        const auto el = sb.foot[set].download(st, m);
-        pairs.assign(m, 0);
-        for (int t = 0; t < sb.ntiles; ++t)
-            for (int64_t q = off[t]; q < off[t + 1]; ++q) pairs[q] = ((uint64_t)(uint32_t)el[q] << 32) | (uint32_t)t;
-        std::sort(pairs.begin(), pairs.end());
-        for (size_t i = 0; i < pairs.size();) {
-            size_t j = i;
-            while (j < pairs.size() && (pairs[j] >> 32) == (pairs[i] >> 32)) ++j;
-            for (size_t u = i; u < j; ++u)
-                for (size_t v = u + 1; v < j; ++v) {
-                    uint32_t x = (uint32_t)pairs[u], y = (uint32_t)pairs[v];
-                    DGT_REQUIRE(col[x] != col[y], DGT_ESTATE, "two tiles of one colour share an element");
-                    if (col[x] > col[y]) std::swap(x, y);
-                    edges.push_back(((uint64_t)x << 32) | y);
-                }
-            i = j;
-        }
-    }
-    std::sort(edges.begin(), edges.end());
-    edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
-    std::vector<int32_t> need(sb.ntiles, 0), off(sb.ntiles + 1, 0), succ(std::max<size_t>(edges.size(), 1));
-    for (uint64_t e : edges) {
-        off[(e >> 32) + 1]++;
-        need[(uint32_t)e]++;
-    }
-    for (int t = 0; t < sb.ntiles; ++t) off[t + 1] += off[t];
-    for (size_t i = 0; i < edges.size(); ++i) succ[i] = (int32_t)(uint32_t)edges[i];  // edges sorted by source
-    P.need.upload(need, st);
-    P.succ_off.upload(off, st);
-    P.succ.upload(succ, st);
+    const SubSched &sb = s->sched->s->sub[b];
     P.cnt.alloc(sb.ntiles);
     P.head.alloc(1);
     P.err.alloc(1);
@@ -726,7 +690,8 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
                           st, P.args, TA_ATTR);
     for (int64_t n = 0; n < nsteps; ++n) {
         const double th = t0 + ((double)n + 0.5) * dt;
-        for (auto &P : s->plan) {
+        for (size_t b = 0; b < s->plan.size(); ++b) {
+            SubPlan &P = s->plan[b];
             TileArgs A = P.args;
             A.dt = dt;
             A.src_cell = s->has_src ? (int32_t)s->src_exec : -1;
@@ -735,9 +700,10 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
                 A.persist = 1;
                 A.ntiles = P.ntiles;
                 A.tile_base = 0;
-                A.need = P.need.p;
-                A.succ_off = P.succ_off.p;
-                A.succ = P.succ.p;
+                const SubSched &sb = s->sched->s->sub[b];
+                A.need = sb.dep_need.p;
+                A.succ_off = sb.dep_off.p;
+                A.succ = sb.dep_succ.p;
                 A.cnt = P.cnt.p;
                 A.head = P.head.p;
                 A.err = P.err.p;
