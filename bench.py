@@ -47,6 +47,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-untiled", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--workload", choices=["single", "batched"], default="single",
+                    help="batched: 64 Ricker shots on 6 uneven meshes (P2 FP32), the batched form against "
+                         "the same shots run one at a time")
+    ap.add_argument("--shots", type=int, default=64)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched workload: use the fixed P2 FP32 tile size and schedule instead of the autotuner")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain elementwise pass over 256 MiB (torch.neg: 256 MiB read, 256 MiB "
                          "written) for scaling HBM byte counters")
@@ -92,12 +98,196 @@ def measured_traffic(workload, dtype, ts, splits, schedule):
     return None
 
 
+def cfl_dt(m, lam, mu, rho, k):
+    """CFL time step: 0.2 h_min / ((2k+1) c_p,max), h = 4|K| / perimeter."""
+    import numpy as np
+    p = m.xy[m.c2v]
+    e = [np.hypot(*(p[:, (i + 1) % 3] - p[:, i]).T) for i in range(3)]
+    area = 0.5 * ((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1]) - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1]))
+    hmin = float(np.min(4.0 * area / (e[0] + e[1] + e[2])))
+    cmax = float(np.max(np.sqrt((lam + 2 * mu) / rho)))
+    return 0.2 * hmin / ((2 * k + 1) * cmax)
+
+
+BATCH_MESHES = (181, 239, 315, 416, 549, 724)
+TUNE_TILE_SIZES = (64, 96, 128, 192, 256, 384, 512)
+
+
+def batched(a):
+    """64 Ricker shots at seeded positions (uniform in [0.1, 0.9]^2), shot i on mesh
+    i mod 6 of six jittered renumbered meshes (n = 181 ... 724 squares per side, 65,522
+    to 1,048,352 cells), DG P2, FP32, three-layer material, upwind.  Batched form: one
+    solver per mesh holding all of its shots, the six advanced on six streams at once.
+    Plain form: the same shots one at a time on one-shot solvers.  Every shot of the
+    batched run is compared with its plain run: bit-equal when both run the same
+    configuration, else (the autotuner may pick different tile sizes, hence tile
+    kernels, for the two forms) the relative L2 difference is reported."""
+    import numpy as np
+    import torch
+
+    from paper_1708_03183_amd import dgtile as D
+    from paper_1708_03183_amd import inputs as I
+
+    k, prec = 2, 1
+    npk = (k + 1) * (k + 2) // 2
+    ts, splits, schedule = DEFAULTS[(k, "fp32")]
+    if a.tile_size:
+        ts = a.tile_size
+    if a.schedule is not None:
+        schedule = a.schedule
+    rng = np.random.default_rng(64)
+    xy = rng.uniform(0.1, 0.9, size=(a.shots, 2))
+    t0 = time.time()
+    meshes = []
+    for i, n in enumerate(BATCH_MESHES):
+        m = I.square_mesh(n, jitter=0.2, jitter_seed=10 + i, renumber_seed=20 + i)
+        lam, mu, rho = I.layered_material(m)
+        meshes.append((m, lam, mu, rho, cfl_dt(m, lam, mu, rho, k), D.Mesh.from_mesh(m)))
+    t_gen = time.time() - t0
+    shots_of = [[q for q in range(a.shots) if q % len(meshes) == i] for i in range(len(meshes))]
+    streams = [torch.cuda.Stream() for _ in meshes]
+
+    tuned = {"batched": [], "plain": []}
+
+    def make(i, form, stream=None):
+        """A solver for mesh i holding its shots (batched) or one shot (plain), tuned by
+        the autotuner (tile size and schedule by trial steps) unless --no-autotune."""
+        m, lam, mu, rho, dt, gm = meshes[i]
+        s = D.Solver(gm, lam, mu, rho, degree=k, flux=1, time_order=4, precision=prec, free_sides=0x8, dt=dt,
+                     stream=stream)
+        q = shots_of[i]
+        if form == "batched":
+            s.set_shots(len(q), xy[q])
+        else:
+            s.set_source(*xy[q[0]])
+        if a.no_autotune:
+            s.inspect(ts, partition=1, splits=splits)
+            s.set_schedule(schedule)
+            tuned[form].append({"tile_size": ts, "schedule": schedule})
+        else:
+            r = s.autotune(TUNE_TILE_SIZES, splits=splits, partition=1, trial_steps=3)
+            tuned[form].append({"tile_size": r["tile_size"], "schedule": r["schedule"],
+                                "trial_ms_per_step": r["ms_per_step"], "timed": r["timed"]})
+        return s
+
+    # batched
+    ti = time.time()
+    bat = []
+    for i in range(len(meshes)):
+        if not shots_of[i]:
+            continue
+        bat.append((i, make(i, "batched", streams[i])))
+    torch.cuda.synchronize()
+    t_insp = time.time() - ti
+    states = {}
+    for i, s in bat:
+        states[i] = s.zeros()
+    torch.cuda.synchronize()  # the zeros come from torch's stream, the solvers run on their own
+    for i, s in bat:
+        v, st = states[i]
+        s.upload(v, st)
+        s.step(a.warmup, mode=1, t0=0.0)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    for i, s in bat:
+        s.step(a.steps, mode=1, t0=a.warmup * meshes[i][4])
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - tb
+    for i, s in bat:
+        s.download(*states[i])
+    torch.cuda.synchronize()
+    dofs_step = sum(5 * npk * meshes[i][0].nc * len(shots_of[i]) for i in range(len(meshes)))
+
+    # plain: one shot at a time
+    wall_p = 0.0
+    equal = True
+    diff = 0.0
+    for i, _ in bat:
+        s = make(i, "plain")
+        for j, q in enumerate(shots_of[i]):
+            s.set_source(*xy[q])
+            v, st = s.zeros()
+            s.upload(v, st)
+            s.step(a.warmup, mode=1, t0=0.0)
+            torch.cuda.synchronize()
+            tp = time.perf_counter()
+            s.step(a.steps, mode=1, t0=a.warmup * meshes[i][4])
+            torch.cuda.synchronize()
+            wall_p += time.perf_counter() - tp
+            s.download(v, st)
+            torch.cuda.synchronize()
+            bv, bs = states[i][0][j], states[i][1][j]
+            equal &= bool(torch.equal(v, bv) and torch.equal(st, bs))
+            num = ((v.double() - bv.double()) ** 2).sum() + ((st.double() - bs.double()) ** 2).sum()
+            den = (bv.double() ** 2).sum() + (bs.double() ** 2).sum()
+            diff = max(diff, math.sqrt(num.item() / den.item()) if den.item() > 0 else 0.0)
+        del s
+
+    # the FP32 batched state of shot 0 (mesh 0), two more steps against the FP64 oracle
+    err = None
+    if not a.no_cpu_baseline:
+        import oracle as O
+        m, lam, mu, rho, dt, gm = meshes[0]
+        om = O.OMesh.from_mesh(m)
+        od = O.ODG(om, k, lam, mu, rho, flux=1, order=4, dt=dt, free_sides=0x8)
+        od.set_source(*xy[0], 5.0, 0.2, 1.0)
+        v = states[0][0][0].double().cpu().numpy().copy()
+        s_ = states[0][1][0].double().cpu().numpy().copy()
+        tstart = (a.warmup + a.steps) * dt
+        od.step(v, s_, 2, t0=tstart)
+        i0, sb = bat[0]
+        sb.upload(*states[i0])
+        sb.step(2, mode=1, t0=tstart)
+        sb.download(*states[i0])
+        torch.cuda.synchronize()
+        gv = states[i0][0][0].double().cpu().numpy()
+        gs = states[i0][1][0].double().cpu().numpy()
+        num = math.sqrt(((gv - v) ** 2).sum() + ((gs - s_) ** 2).sum())
+        den = math.sqrt((v ** 2).sum() + (s_ ** 2).sum())
+        err = num / den if den > 0 else 0.0
+
+    rate_b = dofs_step * a.steps / wall_b
+    rate_p = dofs_step * a.steps / wall_p
+    out = {
+        "metric": "DG dof-updates/s, batched forward shots on uneven meshes, 1 MI355X",
+        "value": rate_b,
+        "unit": "dof-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * wall_b / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batched: {a.shots} Ricker shots on {len(meshes)} jittered renumbered meshes "
+                               f"(n = {', '.join(map(str, BATCH_MESHES))}), DG P2, 3-layer, upwind, order-4 leapfrog",
+                   "cells": [mm[0].nc for mm in meshes], "shots_per_mesh": [len(x) for x in shots_of],
+                   "dofs_per_step": dofs_step, "splits": list(splits),
+                   "tuning": "fixed" if a.no_autotune else "autotuner"},
+        "tuned": tuned,
+        "plain": {"value": rate_p, "ms_per_step": 1e3 * wall_p / a.steps,
+                  "form": "the same shots one at a time, one-shot solvers"},
+        "speedup_batched_vs_plain": rate_b / rate_p,
+        "batched_equals_plain_bitwise": equal,
+        "max_rel_l2_diff_batched_vs_plain": diff,
+        "err_fp32_run_vs_fp64_oracle_rel_l2": err,
+        "inspect_and_tune_wall_s": t_insp,
+        "mesh_gen_s": t_gen,
+    }
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this build",
                           "n_gpus": a.gpus}))
         sys.exit(2)
+    if a.workload == "batched":
+        batched(a)
+        return
     import numpy as np
     import torch
 
@@ -120,13 +310,7 @@ def main():
     t_gen = time.time() - t0
     k = a.degree
     npk = (k + 1) * (k + 2) // 2
-    # CFL time step: 0.2 h_min / ((2k+1) c_p,max), h = 4|K| / perimeter
-    p = m.xy[m.c2v]
-    e = [np.hypot(*(p[:, (i + 1) % 3] - p[:, i]).T) for i in range(3)]
-    area = 0.5 * ((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1]) - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1]))
-    hmin = float(np.min(4.0 * area / (e[0] + e[1] + e[2])))
-    cmax = float(np.max(np.sqrt((lam + 2 * mu) / rho)))
-    dt = 0.2 * hmin / ((2 * k + 1) * cmax)
+    dt = cfl_dt(m, lam, mu, rho, k)
 
     mesh = D.Mesh.from_mesh(m)
     dofs = 5 * npk * mesh.nc

@@ -191,13 +191,59 @@ dgt_status dgt_solver_create(const dgt_mesh *m, const double *lam, const double 
  * returned, and dgt_step in tiled mode then fails with DGT_EUNSUPPORTED
  * (smaller tile_size or more splits needed).  Synchronises the stream. */
 dgt_status dgt_solver_inspect(dgt_solver *s, const dgt_inspect_params *p);
+/* Autotuner: picks the seed tile size (from tile_sizes) and the executor
+ * schedule (0 or 1, see dgt_solver_set_schedule) by timing trial steps, and
+ * leaves the solver inspected and scheduled with the fastest pair.  Each
+ * candidate is inspected; those whose tiles exceed the LDS budget are skipped.
+ * A footprint model orders the rest: the cells every tile gathers, summed over
+ * tiles and sub-chains and divided by the mesh's cells (the data a step moves
+ * per cell, larger for smaller tiles, in the spirit of the paper's estimates of
+ * tile footprints and reuse); with prune > 0 a candidate whose model cost
+ * exceeds prune times the lowest is dropped untimed.  Every remaining candidate
+ * runs one step and then trial_steps timed steps (HIP events) with each
+ * schedule its kernels support, from a zero state with the solver's sources
+ * and shots.  The caller's state is kept (restored afterwards); without an
+ * uploaded state the fields are zero afterwards.  Synchronises the stream.
+ * EINVAL for bad parameters, EUNSUPPORTED when no candidate fits. */
+typedef struct {
+    const int32_t *tile_sizes;  /* host [ntile_sizes] candidate seed tile sizes, >= 1 */
+    int32_t ntile_sizes;        /* 1..64 */
+    const int32_t *splits;      /* fusion scheme, as in dgt_inspect_params */
+    int32_t nsplits;
+    int32_t partition;          /* 0 or 1, as in dgt_inspect_params */
+    int32_t trial_steps;        /* timed steps per candidate and schedule, 1..1000 */
+    double prune;               /* model cost cut-off (multiple of the lowest); 0: time all */
+} dgt_autotune_params;
+typedef struct {
+    int32_t tile_size;  /* chosen seed tile size */
+    int32_t schedule;   /* chosen schedule */
+    double ms_per_step; /* its trial time */
+    int32_t timed;      /* (tile size, schedule) pairs timed */
+    int32_t skipped;    /* tile sizes not timed (LDS budget or model) */
+} dgt_autotune_result;
+dgt_status dgt_solver_autotune(dgt_solver *s, const dgt_autotune_params *p, dgt_autotune_result *out);
 /* The schedule of the last dgt_solver_inspect (borrowed; NULL before). */
 dgt_status dgt_solver_schedule(const dgt_solver *s, const dgt_schedule **out);
 /* Ricker point source on sxx and syy: r(t) = amp (1 - 2 a) exp(-a),
- * a = (pi f0 (t - t0))^2, placed in the lowest-id cell containing (x, y). */
+ * a = (pi f0 (t - t0))^2, placed in the lowest-id cell containing (x, y); with
+ * several shots, every shot gets this source. */
 dgt_status dgt_set_source(dgt_solver *s, double x, double y, double f0, double t0, double amp);
+/* Shots: nshots (1..65536) independent states advanced together on this mesh
+ * (the batched forward run; one shot is the default).  Each shot has its own
+ * Ricker point source at (xy[2q], xy[2q+1]) (host, [nshots*2]) with the common
+ * wavelet f0, t0, amp, placed as by dgt_set_source; xy NULL: no sources.  The
+ * state of every shot is reset to zero and must be uploaded again; the schedule
+ * and plan stay (shots share the mesh, its tiles and geometry).  A tiled step
+ * runs every (tile, shot) pair as one work item, with the shots of a tile next
+ * to each other in the launch order; dgt_step mode 0 runs the shots one after
+ * another.  Results of a shot do not depend on the other shots.  EINVAL for a
+ * bad count, a non-finite position or one outside the mesh (the solver then has
+ * no sources).  Synchronises the stream. */
+dgt_status dgt_solver_set_shots(dgt_solver *s, int32_t nshots, const double *xy, double f0, double t0,
+                                double amp);
 /* Copy the state into / out of the solver (device pointers, caller layout
- * v[2][Np][nc], s[3][Np][nc] in the solver precision; enqueued on the stream). */
+ * v[nshots][2][Np][nc], s[nshots][3][Np][nc] in the solver precision; enqueued on
+ * the stream). */
 dgt_status dgt_state_upload(dgt_solver *s, const void *v, const void *sig);
 dgt_status dgt_state_download(dgt_solver *s, void *v, void *sig);
 /* Advance nsteps time steps starting at time t0 (sigma at t0, v at t0 - dt/2).
@@ -205,8 +251,8 @@ dgt_status dgt_state_download(dgt_solver *s, void *v, void *sig);
  * executor (requires dgt_solver_inspect).  Enqueued on the stream. */
 dgt_status dgt_step(dgt_solver *s, int64_t nsteps, int32_t mode, double t0);
 /* Discrete energy 1/2 v'M_rho v + 1/2 sum_K int sig_new : C^-1 sig_old, reduced
- * in FP64 on the GPU.  v, sig_new, sig_old: device, caller layout, solver
- * precision.  Synchronises the stream. */
+ * in FP64 on the GPU.  v, sig_new, sig_old: device, caller layout of one shot,
+ * solver precision.  Synchronises the stream. */
 dgt_status dgt_energy(dgt_solver *s, const void *v, const void *sig_new, const void *sig_old, double *out);
 /* Schedule of the tiled executor (default 0).  0: one kernel launch per colour
  * of every sub-chain (Alg. 2's colour loop).  1: sub-chains that run on the
@@ -234,8 +280,9 @@ dgt_status dgt_solver_profile(dgt_solver *s, int32_t on);
  * kernel_ms the sum of the tile kernels' durations when per-launch timing was
  * on for a tiled call, else equal to total_ms; launches: kernels launched. */
 dgt_status dgt_last_step_timing(const dgt_solver *s, double *total_ms, double *kernel_ms, int64_t *launches);
-/* Per-step algorithmic HBM bytes of the fused step (state read and written
- * once, cell invariants read once) and the LDS bytes per tile slot. */
+/* Per-step algorithmic HBM bytes of the fused step (the state of every shot
+ * read and written once, cell invariants read once) and the LDS bytes per tile
+ * slot. */
 dgt_status dgt_solver_info(const dgt_solver *s, int64_t *np, int64_t *bytes_per_step, int64_t *lds_bytes);
 void dgt_solver_destroy(dgt_solver *s);
 

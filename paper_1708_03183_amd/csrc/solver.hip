@@ -65,12 +65,16 @@ struct dgt_solver {
     bool state_valid = false;
     int sched_mode = 0;  // tiled executor: 0 one launch per colour, 1 dependence-driven
     uint32_t wait_limit = 1u << 20;  // polls before a dependence wait gives up
-    // source
+    // shots: independent states on this mesh, each with its own point source (one
+    // Ricker wavelet for all) or none
+    int32_t nshots = 1;
     bool has_src = false;
-    int64_t src_in = -1, src_exec = -1;
+    std::vector<int64_t> src_in;       // [nshots] mesh cell holding each source
+    std::vector<int32_t> src_exec_h;   // [nshots] its exec id
     double sf0 = 0, st0 = 0, samp = 0;
-    std::vector<double> src_vec_h;
-    dgt::DBuf<char> src_vec;
+    dgt::DBuf<char> src_vec;           // [nshots][Np] inverse mass times the basis at the source
+    dgt::DBuf<int32_t> src_cells;      // [nshots] exec ids, -1 without sources
+    int64_t fshot(int f) const { return (int64_t)dgt::field_ncomp(f) * E.np * nc; }
     // chain, schedule, plan
     std::vector<dgt::GLoop> loops;
     dgt_chain chain;
@@ -212,29 +216,48 @@ static void build_loops(dgt_solver *s) {
 
 // ------------------------------------------------------------ exec order
 
+// caller layout v[nshots][2][Np][nc], sg[nshots][3][Np][nc] in the mesh's numbering
 static void to_caller(dgt_solver *s, void *v, void *sg) {
     dispatch(s, [&]<int K, typename T>() {
         constexpr int NP = np_of(K);
-        k_permute_rows<T><<<blocks_for(2 * NP * s->nc, 256), 256, 0, s->st>>>(
-            (const T *)s->fld[F_V].p, (T *)v, s->rank.p, 2 * NP, s->nc, 0);
-        k_permute_rows<T><<<blocks_for(3 * NP * s->nc, 256), 256, 0, s->st>>>(
-            (const T *)s->fld[F_S].p, (T *)sg, s->rank.p, 3 * NP, s->nc, 0);
+        const int64_t nv = 2 * NP * s->nc, ns = 3 * NP * s->nc;
+        for (int q = 0; q < s->nshots; ++q) {
+            k_permute_rows<T><<<blocks_for(nv, 256), 256, 0, s->st>>>(
+                (const T *)s->fld[F_V].p + q * nv, (T *)v + q * nv, s->rank.p, 2 * NP, s->nc, 0);
+            k_permute_rows<T><<<blocks_for(ns, 256), 256, 0, s->st>>>(
+                (const T *)s->fld[F_S].p + q * ns, (T *)sg + q * ns, s->rank.p, 3 * NP, s->nc, 0);
+        }
     });
 }
 
 static void from_caller(dgt_solver *s, const void *v, const void *sg) {
     dispatch(s, [&]<int K, typename T>() {
         constexpr int NP = np_of(K);
-        k_permute_rows<T><<<blocks_for(2 * NP * s->nc, 256), 256, 0, s->st>>>(
-            (const T *)v, (T *)s->fld[F_V].p, s->rank.p, 2 * NP, s->nc, 1);
-        k_permute_rows<T><<<blocks_for(3 * NP * s->nc, 256), 256, 0, s->st>>>(
-            (const T *)sg, (T *)s->fld[F_S].p, s->rank.p, 3 * NP, s->nc, 1);
+        const int64_t nv = 2 * NP * s->nc, ns = 3 * NP * s->nc;
+        for (int q = 0; q < s->nshots; ++q) {
+            k_permute_rows<T><<<blocks_for(nv, 256), 256, 0, s->st>>>(
+                (const T *)v + q * nv, (T *)s->fld[F_V].p + q * nv, s->rank.p, 2 * NP, s->nc, 1);
+            k_permute_rows<T><<<blocks_for(ns, 256), 256, 0, s->st>>>(
+                (const T *)sg + q * ns, (T *)s->fld[F_S].p + q * ns, s->rank.p, 3 * NP, s->nc, 1);
+        }
     });
 }
 
+// exec ids of the source cells (the executors compare a cell's exec id with them)
 static void set_source_exec(dgt_solver *s) {
-    if (!s->has_src) return;
-    s->src_exec = s->rank_h[s->src_in];
+    s->src_exec_h.assign(s->nshots, -1);
+    if (s->has_src)
+        for (int q = 0; q < s->nshots; ++q) s->src_exec_h[q] = s->rank_h[s->src_in[q]];
+    s->src_cells.upload(s->src_exec_h, s->st);
+    DGT_HIP(hipStreamSynchronize(s->st));
+}
+
+// fields for every shot, zeroed
+static void alloc_fields(dgt_solver *s) {
+    for (int f = 0; f < F_COUNT; ++f) {
+        s->fld[f].alloc((size_t)s->fshot(f) * s->nshots * s->esz);
+        DGT_HIP(hipMemsetAsync(s->fld[f].p, 0, s->fld[f].n, s->st));
+    }
 }
 
 static void set_exec_order(dgt_solver *s, const std::vector<int32_t> &rank) {
@@ -244,8 +267,8 @@ static void set_exec_order(dgt_solver *s, const std::vector<int32_t> &rank) {
     // keep any state across the renumbering
     DBuf<char> keep;
     if (s->state_valid) {
-        keep.alloc(5 * np * nc * s->esz);
-        to_caller(s, keep.p, keep.p + 2 * np * nc * s->esz);
+        keep.alloc(5 * np * nc * s->esz * s->nshots);
+        to_caller(s, keep.p, keep.p + 2 * np * nc * s->esz * s->nshots);
     }
     s->rank_h = rank;
     s->rank.upload(rank, st);
@@ -296,7 +319,7 @@ static void set_exec_order(dgt_solver *s, const std::vector<int32_t> &rank) {
     s->c2f.upload(c2f, st);
     DGT_HIP(hipStreamSynchronize(st));
     set_source_exec(s);
-    if (s->state_valid) from_caller(s, keep.p, keep.p + 2 * np * nc * s->esz);
+    if (s->state_valid) from_caller(s, keep.p, keep.p + 2 * np * nc * s->esz * s->nshots);
     DGT_HIP(hipStreamSynchronize(st));
 }
 
@@ -458,6 +481,9 @@ static void build_plan(dgt_solver *s) {
         A.nc = s->nc;
         A.stride = std::max(P.max_foot, 1);
         A.src_vec = s->src_vec.p;
+        A.src_cells = s->src_cells.p;
+        A.nshots = s->nshots;
+        for (int f = 0; f < F_COUNT; ++f) A.fshot[f] = s->fshot(f);
         // neighbour tables: for each tile, facet group, local facet and footprint slot, the
         // neighbour's slot and local facet (interior) or the boundary kind (exterior)
         {
@@ -577,14 +603,14 @@ static void build_plan(dgt_solver *s) {
 // ------------------------------------------------------------ steps
 
 template <int K, typename T>
-static void apply_untiled(dgt_solver *s, bool vel, int in, int out, double scale, int pen, double pscale,
+static void apply_untiled(dgt_solver *s, int shot, bool vel, int in, int out, double scale, int pen, double pscale,
                           int64_t &launches) {
     hipStream_t st = s->st;
     const int64_t nc = s->nc, nf = s->nf, nb = s->nb;
     constexpr int NP = np_of(K), NFP = K + 1;
-    const T *fin = (const T *)s->fld[in].p;
-    T *fout = (T *)s->fld[out].p;
-    const T *fpen = pen >= 0 ? (const T *)s->fld[pen].p : nullptr;
+    const T *fin = (const T *)s->fld[in].p + shot * s->fshot(in);
+    T *fout = (T *)s->fld[out].p + shot * s->fshot(out);
+    const T *fpen = pen >= 0 ? (const T *)s->fld[pen].p + shot * s->fshot(pen) : nullptr;
     const T *geo = (const T *)s->geo.p;
     T *G = (T *)s->G.p, *Gx = (T *)s->Gx.p;
     const T sc = (T)scale, ps = (T)pscale;
@@ -623,30 +649,32 @@ static void step_untiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &laun
     const int64_t nc = s->nc;
     const double dt = s->p.dt, c3 = dt * dt * dt / 24.0;
     const int penv = s->haspen ? F_V : -1, pens = s->haspen ? F_S : -1;
-    T *V = (T *)s->fld[F_V].p, *Sg = (T *)s->fld[F_S].p, *U = (T *)s->fld[F_U].p, *X = (T *)s->fld[F_X].p,
-      *Z = (T *)s->fld[F_Z].p;
+    for (int q = 0; q < s->nshots; ++q) {  // shots one after another
+    T *V = (T *)s->fld[F_V].p + q * s->fshot(F_V), *Sg = (T *)s->fld[F_S].p + q * s->fshot(F_S),
+      *U = (T *)s->fld[F_U].p + q * s->fshot(F_U), *X = (T *)s->fld[F_X].p + q * s->fshot(F_X),
+      *Z = (T *)s->fld[F_Z].p + q * s->fshot(F_Z);
+    const T *sv = (const T *)s->src_vec.p + q * NP;
     for (int64_t n = 0; n < nsteps; ++n) {
         const double th = t0 + ((double)n + 0.5) * dt;
         const double amp = s->has_src ? dt * ricker(th, s->sf0, s->st0, s->samp) : 0.0;
-        const int64_t src = s->has_src ? s->src_exec : -1;
+        const int64_t src = s->src_exec_h[q];
         if (s->p.time_order == 4) {
-            apply_untiled<K, T>(s, true, F_S, F_U, 1.0, -1, 0.0, launches);
-            apply_untiled<K, T>(s, false, F_U, F_X, 1.0, -1, 0.0, launches);
-            apply_untiled<K, T>(s, true, F_X, F_Z, c3, penv, dt, launches);
+            apply_untiled<K, T>(s, q, true, F_S, F_U, 1.0, -1, 0.0, launches);
+            apply_untiled<K, T>(s, q, false, F_U, F_X, 1.0, -1, 0.0, launches);
+            apply_untiled<K, T>(s, q, true, F_X, F_Z, c3, penv, dt, launches);
             k_upd_v<T><<<blocks_for(2 * NP * nc, 256), 256, 0, st>>>(V, U, Z, 2 * NP * nc, (T)dt);
-            apply_untiled<K, T>(s, false, F_V, F_X, 1.0, -1, 0.0, launches);
-            apply_untiled<K, T>(s, true, F_X, F_U, 1.0, -1, 0.0, launches);
-            apply_untiled<K, T>(s, false, F_U, F_Z, c3, pens, dt, launches);
-            k_upd_s<K, T><<<blocks_for(3 * NP * nc, 256), 256, 0, st>>>(Sg, X, Z, nc, (T)dt, src, (T)amp,
-                                                                       (const T *)s->src_vec.p);
+            apply_untiled<K, T>(s, q, false, F_V, F_X, 1.0, -1, 0.0, launches);
+            apply_untiled<K, T>(s, q, true, F_X, F_U, 1.0, -1, 0.0, launches);
+            apply_untiled<K, T>(s, q, false, F_U, F_Z, c3, pens, dt, launches);
+            k_upd_s<K, T><<<blocks_for(3 * NP * nc, 256), 256, 0, st>>>(Sg, X, Z, nc, (T)dt, src, (T)amp, sv);
         } else {
-            apply_untiled<K, T>(s, true, F_S, F_Z, dt, penv, dt, launches);
+            apply_untiled<K, T>(s, q, true, F_S, F_Z, dt, penv, dt, launches);
             k_upd_v<T><<<blocks_for(2 * NP * nc, 256), 256, 0, st>>>(V, nullptr, Z, 2 * NP * nc, (T)dt);
-            apply_untiled<K, T>(s, false, F_V, F_Z, dt, pens, dt, launches);
-            k_upd_s<K, T><<<blocks_for(3 * NP * nc, 256), 256, 0, st>>>(Sg, nullptr, Z, nc, (T)dt, src, (T)amp,
-                                                                       (const T *)s->src_vec.p);
+            apply_untiled<K, T>(s, q, false, F_V, F_Z, dt, pens, dt, launches);
+            k_upd_s<K, T><<<blocks_for(3 * NP * nc, 256), 256, 0, st>>>(Sg, nullptr, Z, nc, (T)dt, src, (T)amp, sv);
         }
         launches += 2;
+    }
     }
 }
 
@@ -655,10 +683,10 @@ static void step_untiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &laun
 static void build_graph(dgt_solver *s, int b, SubPlan &P) {
     hipStream_t st = s->st;
     const SubSched &sb = s->sched->s->sub[b];
-    P.cnt.alloc(sb.ntiles);
+    P.cnt.alloc((size_t)sb.ntiles * s->nshots);
     P.head.alloc(1);
     P.err.alloc(1);
-    DGT_HIP(hipMemsetAsync(P.cnt.p, 0, sizeof(uint32_t) * sb.ntiles, st));
+    DGT_HIP(hipMemsetAsync(P.cnt.p, 0, sizeof(uint32_t) * sb.ntiles * s->nshots, st));
     DGT_HIP(hipMemsetAsync(P.head.p, 0, sizeof(uint32_t), st));
     DGT_HIP(hipMemsetAsync(P.err.p, 0, sizeof(int32_t), st));
     P.epoch = 0;
@@ -672,7 +700,7 @@ static void check_graphs(dgt_solver *s) {
         if (!P.graph) continue;
         if (P.err.download(s->st)[0] != 0) {
             bad = true;
-            DGT_HIP(hipMemsetAsync(P.cnt.p, 0, sizeof(uint32_t) * P.ntiles, s->st));
+            DGT_HIP(hipMemsetAsync(P.cnt.p, 0, sizeof(uint32_t) * P.ntiles * s->nshots, s->st));
             DGT_HIP(hipMemsetAsync(P.head.p, 0, sizeof(uint32_t), s->st));
             DGT_HIP(hipMemsetAsync(P.err.p, 0, sizeof(int32_t), s->st));
             P.epoch = 0;
@@ -693,8 +721,14 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
         for (size_t b = 0; b < s->plan.size(); ++b) {
             SubPlan &P = s->plan[b];
             TileArgs A = P.args;
+            for (int f = 0; f < F_COUNT; ++f) {
+                A.F[f] = s->fld[f].p;
+                A.fshot[f] = s->fshot(f);
+            }
+            A.nshots = s->nshots;
+            A.src_cells = s->src_cells.p;
+            A.src_vec = s->src_vec.p;
             A.dt = dt;
-            A.src_cell = s->has_src ? (int32_t)s->src_exec : -1;
             A.src_amp = s->has_src ? dt * ricker(th, s->sf0, s->st0, s->samp) : 0.0;
             if (s->sched_mode == 1 && P.kind == TK_CHAIN) {  // one launch for all colours
                 A.persist = 1;
@@ -707,7 +741,7 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
                 A.cnt = P.cnt.p;
                 A.head = P.head.p;
                 A.err = P.err.p;
-                A.head_base = P.epoch * (uint32_t)(P.ntiles + P.slots);
+                A.head_base = P.epoch * (uint32_t)(P.ntiles * s->nshots + P.slots);
                 A.epoch = ++P.epoch;
                 A.spin_limit = s->wait_limit;
                 s->mark();
@@ -722,8 +756,8 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
                 if (ntiles == 0) continue;
                 A.tile_base = P.color_off[c];
                 s->mark();
-                tile_launch<K, T>(P.kind, P.threads, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, ntiles,
-                                  P.lds_bytes, st, A, TA_LAUNCH);
+                tile_launch<K, T>(P.kind, P.threads, s->upw, s->haspen, s->p.time_order, P.o0, P.nops,
+                                  ntiles * s->nshots, P.lds_bytes, st, A, TA_LAUNCH);
                 s->mark();
                 ++launches;
             }
@@ -820,14 +854,12 @@ dgt_status dgt_solver_create(const dgt_mesh *m, const double *lam, const double 
         s->rho.upload(rho, M.nc, st);
         const int np = s->E.np, nfp = s->E.nfp;
         s->geo.alloc((size_t)(G_NROWS + 1) * M.nc * s->esz);
-        for (int f = 0; f < F_COUNT; ++f) {
-            s->fld[f].alloc((size_t)field_ncomp(f) * np * M.nc * s->esz);
-            DGT_HIP(hipMemsetAsync(s->fld[f].p, 0, s->fld[f].n, st));
-        }
+        alloc_fields(s.get());
         s->G.alloc((size_t)2 * 3 * nfp * std::max<int64_t>(M.nf, 1) * s->esz);
         s->Gx.alloc((size_t)3 * nfp * std::max<int64_t>(M.nb, 1) * s->esz);
         s->src_vec.alloc((size_t)np * s->esz);
         DGT_HIP(hipMemsetAsync(s->src_vec.p, 0, s->src_vec.n, st));
+        s->src_in.assign(1, -1);
         std::vector<int32_t> id(M.nc);
         std::iota(id.begin(), id.end(), 0);
         set_exec_order(s.get(), id);
@@ -836,6 +868,61 @@ dgt_status dgt_solver_create(const dgt_mesh *m, const double *lam, const double 
         DGT_HIP(hipEventCreate(&s->ev1));
         *out = s.release();
     });
+}
+
+// Point sources of every shot: the lowest-id cell containing (x, y) and the vector
+// inverse reference mass times the basis at the point, divided by |det J| (the
+// projection of a point force onto the cell's polynomial space).
+static void set_sources(dgt_solver *s, const double *xy, double f0, double t0, double amp) {
+    const Mesh &M = *s->mesh;
+    const int np = s->E.np;
+    std::vector<int64_t> cells(s->nshots, -1);
+    std::vector<double> svs((size_t)s->nshots * np);
+    for (int q = 0; q < s->nshots; ++q) {
+        const double x = xy[2 * q], y = xy[2 * q + 1];
+        DGT_REQUIRE(std::isfinite(x) && std::isfinite(y), DGT_EINVAL, "source position is not finite");
+        int64_t cell = -1;
+        double rs = 0, ss = 0;
+        for (int64_t c = 0; c < M.nc && cell < 0; ++c) {
+            const double *p0 = &M.xy[2 * M.c2v[3 * c]], *p1 = &M.xy[2 * M.c2v[3 * c + 1]],
+                         *p2 = &M.xy[2 * M.c2v[3 * c + 2]];
+            const double xr = p1[0] - p0[0], xs = p2[0] - p0[0], yr = p1[1] - p0[1], ys = p2[1] - p0[1];
+            const double det = xr * ys - xs * yr;
+            const double r = (ys * (x - p0[0]) - xs * (y - p0[1])) / det;
+            const double sv = (-yr * (x - p0[0]) + xr * (y - p0[1])) / det;
+            if (r >= -1e-12 && sv >= -1e-12 && 1.0 - r - sv >= -1e-12) {
+                cell = c;
+                rs = r;
+                ss = sv;
+            }
+        }
+        DGT_REQUIRE(cell >= 0, DGT_EINVAL, "source outside the mesh");
+        std::vector<double> phi(np);
+        s->E.phi(rs, ss, phi.data());
+        const double *p0 = &M.xy[2 * M.c2v[3 * cell]], *p1 = &M.xy[2 * M.c2v[3 * cell + 1]],
+                     *p2 = &M.xy[2 * M.c2v[3 * cell + 2]];
+        const double det = (p1[0] - p0[0]) * (p2[1] - p0[1]) - (p2[0] - p0[0]) * (p1[1] - p0[1]);
+        for (int i = 0; i < np; ++i) {
+            double a = 0;
+            for (int j = 0; j < np; ++j) a += s->E.Minv[i * np + j] * phi[j];
+            svs[(size_t)q * np + i] = a / det;
+        }
+        cells[q] = cell;
+    }
+    s->src_vec.alloc(svs.size() * s->esz);
+    if (s->fp32) {
+        std::vector<float> f(svs.begin(), svs.end());
+        DGT_HIP(hipMemcpyAsync(s->src_vec.p, f.data(), 4 * f.size(), hipMemcpyHostToDevice, s->st));
+    } else {
+        DGT_HIP(hipMemcpyAsync(s->src_vec.p, svs.data(), 8 * svs.size(), hipMemcpyHostToDevice, s->st));
+    }
+    DGT_HIP(hipStreamSynchronize(s->st));
+    s->has_src = true;
+    s->src_in = cells;
+    s->sf0 = f0;
+    s->st0 = t0;
+    s->samp = amp;
+    set_source_exec(s);
 }
 
 // workgroups of a sub-chain's tile kernel that the whole GPU holds at once
@@ -851,6 +938,19 @@ static int plan_slots(dgt_solver *s, const SubPlan &P) {
     hipDeviceProp_t prop;
     DGT_HIP(hipGetDeviceProperties(&prop, dev));
     return occ * prop.multiProcessorCount;
+}
+
+// Counters and workgroup counts of the dependence-driven schedule (schedule 1).
+static void prepare_tiled(dgt_solver *s) {
+    if (s->sched_mode != 1) return;
+    check_graphs(s);  // synchronises: reports a wait that timed out earlier
+    for (size_t b = 0; b < s->plan.size(); ++b) {
+        SubPlan &P = s->plan[b];
+        if (P.kind != TK_CHAIN) continue;
+        if (!P.graph) build_graph(s, (int)b, P);
+        if (!P.slots) P.slots = plan_slots(s, P);
+        DGT_REQUIRE(P.slots > 0, DGT_EUNSUPPORTED, "the tile kernel does not fit on a compute unit");
+    }
 }
 
 static void solver_inspect_once(dgt_solver *s, const dgt_inspect_params *p, int cap) {
@@ -907,6 +1007,110 @@ dgt_status dgt_solver_inspect(dgt_solver *s, const dgt_inspect_params *p) {
     });
 }
 
+dgt_status dgt_solver_autotune(dgt_solver *s, const dgt_autotune_params *p, dgt_autotune_result *out) {
+    return guard([&] {
+        DGT_REQUIRE(s && p && out, DGT_EINVAL, "NULL argument");
+        DGT_REQUIRE(p->ntile_sizes >= 1 && p->ntile_sizes <= 64 && p->tile_sizes, DGT_EINVAL,
+                    "1..64 candidate tile sizes");
+        for (int i = 0; i < p->ntile_sizes; ++i)
+            DGT_REQUIRE(p->tile_sizes[i] >= 1, DGT_EINVAL, "tile sizes must be >= 1");
+        DGT_REQUIRE(p->partition == 0 || p->partition == 1, DGT_EINVAL, "partition must be 0 or 1");
+        DGT_REQUIRE(p->nsplits >= 0 && (p->nsplits == 0 || p->splits), DGT_EINVAL, "bad splits");
+        DGT_REQUIRE(p->trial_steps >= 1 && p->trial_steps <= 1000, DGT_EINVAL, "trial_steps must be 1..1000");
+        DGT_REQUIRE(p->prune >= 0, DGT_EINVAL, "prune must be >= 0");
+        hipStream_t st = s->st;
+        const int np = s->E.np;
+        // keep the caller's state (in the mesh's numbering: the trials renumber the cells)
+        DBuf<char> keep;
+        const bool had = s->state_valid;
+        if (had) {
+            keep.alloc((size_t)5 * np * s->nc * s->esz * s->nshots);
+            to_caller(s, keep.p, keep.p + (size_t)2 * np * s->nc * s->esz * s->nshots);
+        }
+        s->state_valid = false;
+        dgt_inspect_params ip{};
+        ip.partition = p->partition;
+        ip.max_conflict_rounds = 64;
+        ip.splits = p->splits;
+        ip.nsplits = p->nsplits;
+        struct Cand { int ts; double foot; };
+        std::vector<Cand> cands;
+        int skipped = 0, timed = 0;
+        // footprint model: the cells a tile gathers over all its sub-chains, summed over
+        // tiles and divided by the mesh's cells, is the data a step moves per cell
+        // (the halo grows as tiles shrink); candidates whose tiles fit are timed in
+        // ascending model cost, and with prune > 0 a candidate whose cost exceeds
+        // prune times the lowest is dropped untimed
+        for (int i = 0; i < p->ntile_sizes; ++i) {
+            ip.tile_size = p->tile_sizes[i];
+            solver_inspect_once(s, &ip, 0);
+            if (s->plan_status != DGT_OK) {
+                ++skipped;
+                continue;
+            }
+            double f = 0;
+            for (const auto &sb : s->sched->s->sub) f += (double)sb.foot_len[0];
+            cands.push_back({p->tile_sizes[i], f / (double)s->nc});
+        }
+        DGT_REQUIRE(!cands.empty(), DGT_EUNSUPPORTED, "no candidate tile size fits the LDS budget");
+        std::stable_sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.foot < b.foot; });
+        double best_ms = 1e300;
+        int best_ts = cands[0].ts, best_sched = 0;
+        const int keep_mode = s->sched_mode;
+        for (const Cand &c : cands) {
+            if (p->prune > 0 && c.foot > p->prune * cands[0].foot) {
+                ++skipped;
+                continue;
+            }
+            ip.tile_size = c.ts;
+            solver_inspect_once(s, &ip, 0);
+            bool chain = false;
+            for (const auto &P : s->plan) chain |= P.kind == TK_CHAIN;
+            for (int mode = 0; mode <= (chain ? 1 : 0); ++mode) {
+                s->sched_mode = mode;
+                for (int f = 0; f < F_COUNT; ++f) DGT_HIP(hipMemsetAsync(s->fld[f].p, 0, s->fld[f].n, st));
+                prepare_tiled(s);
+                int64_t launches = 0;
+                dispatch(s, [&]<int K, typename T>() {
+                    step_tiled<K, T>(s, 1, 0.0, launches);  // first launches: code and caches warm
+                    DGT_HIP(hipEventRecord(s->ev0, st));
+                    step_tiled<K, T>(s, p->trial_steps, s->p.dt, launches);
+                    DGT_HIP(hipEventRecord(s->ev1, st));
+                });
+                DGT_HIP(hipGetLastError());
+                DGT_HIP(hipEventSynchronize(s->ev1));
+                float ms = 0;
+                DGT_HIP(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+                check_graphs(s);
+                ++timed;
+                const double per = ms / p->trial_steps;
+                if (per < best_ms) {
+                    best_ms = per;
+                    best_ts = c.ts;
+                    best_sched = mode;
+                }
+            }
+        }
+        s->sched_mode = keep_mode;
+        ip.tile_size = best_ts;
+        solver_inspect_once(s, &ip, 0);
+        s->sched_mode = best_sched;
+        for (int f = 0; f < F_COUNT; ++f) DGT_HIP(hipMemsetAsync(s->fld[f].p, 0, s->fld[f].n, st));
+        if (had) {
+            from_caller(s, keep.p, keep.p + (size_t)2 * np * s->nc * s->esz * s->nshots);
+            s->state_valid = true;
+        }
+        DGT_HIP(hipStreamSynchronize(st));
+        s->last_ms = -1.0;
+        s->last_launches = 0;
+        out->tile_size = best_ts;
+        out->schedule = best_sched;
+        out->ms_per_step = best_ms;
+        out->timed = timed;
+        out->skipped = skipped;
+    });
+}
+
 dgt_status dgt_solver_schedule(const dgt_solver *s, const dgt_schedule **out) {
     return guard([&] {
         DGT_REQUIRE(s && out, DGT_EINVAL, "NULL argument");
@@ -917,48 +1121,33 @@ dgt_status dgt_solver_schedule(const dgt_solver *s, const dgt_schedule **out) {
 dgt_status dgt_set_source(dgt_solver *s, double x, double y, double f0, double t0, double amp) {
     return guard([&] {
         DGT_REQUIRE(s, DGT_EINVAL, "solver is NULL");
-        const Mesh &M = *s->mesh;
-        int64_t cell = -1;
-        double rs = 0, ss = 0;
-        for (int64_t c = 0; c < M.nc && cell < 0; ++c) {
-            const double *p0 = &M.xy[2 * M.c2v[3 * c]], *p1 = &M.xy[2 * M.c2v[3 * c + 1]],
-                         *p2 = &M.xy[2 * M.c2v[3 * c + 2]];
-            const double xr = p1[0] - p0[0], xs = p2[0] - p0[0], yr = p1[1] - p0[1], ys = p2[1] - p0[1];
-            const double det = xr * ys - xs * yr;
-            const double r = (ys * (x - p0[0]) - xs * (y - p0[1])) / det;
-            const double sv = (-yr * (x - p0[0]) + xr * (y - p0[1])) / det;
-            if (r >= -1e-12 && sv >= -1e-12 && 1.0 - r - sv >= -1e-12) {
-                cell = c;
-                rs = r;
-                ss = sv;
-            }
+        std::vector<double> xy;
+        for (int q = 0; q < s->nshots; ++q) {
+            xy.push_back(x);
+            xy.push_back(y);
         }
-        DGT_REQUIRE(cell >= 0, DGT_EINVAL, "source outside the mesh");
-        const int np = s->E.np;
-        std::vector<double> phi(np), sv(np);
-        s->E.phi(rs, ss, phi.data());
-        const double *p0 = &M.xy[2 * M.c2v[3 * cell]], *p1 = &M.xy[2 * M.c2v[3 * cell + 1]],
-                     *p2 = &M.xy[2 * M.c2v[3 * cell + 2]];
-        const double det = (p1[0] - p0[0]) * (p2[1] - p0[1]) - (p2[0] - p0[0]) * (p1[1] - p0[1]);
-        for (int i = 0; i < np; ++i) {
-            double a = 0;
-            for (int j = 0; j < np; ++j) a += s->E.Minv[i * np + j] * phi[j];
-            sv[i] = a / det;
-        }
-        s->src_vec_h = sv;
-        if (s->fp32) {
-            std::vector<float> f(sv.begin(), sv.end());
-            DGT_HIP(hipMemcpyAsync(s->src_vec.p, f.data(), 4 * np, hipMemcpyHostToDevice, s->st));
-        } else {
-            DGT_HIP(hipMemcpyAsync(s->src_vec.p, sv.data(), 8 * np, hipMemcpyHostToDevice, s->st));
-        }
+        set_sources(s, xy.data(), f0, t0, amp);
+    });
+}
+
+dgt_status dgt_solver_set_shots(dgt_solver *s, int32_t nshots, const double *xy, double f0, double t0,
+                                double amp) {
+    return guard([&] {
+        DGT_REQUIRE(s && nshots >= 1 && nshots <= 65536, DGT_EINVAL, "nshots must be 1..65536");
+        const int64_t words = (int64_t)5 * s->E.np * s->nc * nshots;
+        DGT_REQUIRE(words * (int64_t)s->esz < ((int64_t)1 << 40), DGT_EINVAL, "state of all shots exceeds 1 TiB");
         DGT_HIP(hipStreamSynchronize(s->st));
-        s->has_src = true;
-        s->src_in = cell;
-        s->sf0 = f0;
-        s->st0 = t0;
-        s->samp = amp;
-        set_source_exec(s);
+        check_graphs(s);
+        s->nshots = nshots;
+        alloc_fields(s);
+        s->state_valid = false;
+        for (auto &P : s->plan) P.graph = false;  // counters are per shot
+        s->has_src = false;
+        s->src_in.assign(nshots, -1);
+        s->src_vec.alloc((size_t)nshots * s->E.np * s->esz);
+        DGT_HIP(hipMemsetAsync(s->src_vec.p, 0, s->src_vec.n, s->st));
+        set_source_exec(s);  // no sources until set_sources succeeds
+        if (xy) set_sources(s, xy, f0, t0, amp);
     });
 }
 
@@ -985,16 +1174,7 @@ dgt_status dgt_step(dgt_solver *s, int64_t nsteps, int32_t mode, double t0) {
         DGT_REQUIRE(s->state_valid, DGT_ESTATE, "state not uploaded");
         DGT_REQUIRE(mode == 0 || mode == 1, DGT_EINVAL, "mode must be 0 or 1");
         DGT_REQUIRE(mode == 0 || s->plan_status == DGT_OK, s->plan_status, s->plan_error);
-        if (mode == 1 && s->sched_mode == 1) {
-            check_graphs(s);  // synchronises: reports a wait that timed out earlier
-            for (size_t b = 0; b < s->plan.size(); ++b) {
-                SubPlan &P = s->plan[b];
-                if (P.kind != TK_CHAIN) continue;
-                if (!P.graph) build_graph(s, (int)b, P);
-                if (!P.slots) P.slots = plan_slots(s, P);
-                DGT_REQUIRE(P.slots > 0, DGT_EUNSUPPORTED, "the tile kernel does not fit on a compute unit");
-            }
-        }
+        if (mode == 1) prepare_tiled(s);
         int64_t launches = 0;
         s->npev = 0;
         DGT_HIP(hipEventRecord(s->ev0, s->st));
@@ -1071,7 +1251,8 @@ dgt_status dgt_solver_info(const dgt_solver *s, int64_t *np, int64_t *bytes_per_
         DGT_REQUIRE(s, DGT_EINVAL, "solver is NULL");
         if (np) *np = s->E.np;
         // state read and written once, per-cell invariants (9 geometry rows) read once
-        if (bytes_per_step) *bytes_per_step = (int64_t)(2 * 5 * s->E.np + G_NROWS) * (int64_t)s->esz * s->nc;
+        if (bytes_per_step)
+            *bytes_per_step = (int64_t)(2 * 5 * s->E.np * s->nshots + G_NROWS) * (int64_t)s->esz * s->nc;
         size_t mx = 0;
         for (auto &P : s->plan) mx = std::max(mx, P.lds_bytes);
         if (lds_bytes) *lds_bytes = (int64_t)mx;

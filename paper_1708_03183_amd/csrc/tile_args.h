@@ -36,9 +36,14 @@ struct TileArgs {
     int32_t nrow;              // LDS elements per slot (odd), geometry in the last G_NROWS
     int32_t stride;            // slot capacity (largest footprint of the sub-chain)
     int32_t nfl;               // facet loops with a neighbour table
-    int32_t src_cell;          // exec id of the source cell or -1
-    double dt, src_amp;        // src_amp = dt * r(t^{n+1/2})
-    const void *src_vec;
+    // shots: independent states on the same mesh; a work item is a (tile, shot) pair,
+    // item i taking tile i / nshots and shot i % nshots, so consecutive workgroups share
+    // a tile's metadata and geometry
+    int32_t nshots;
+    int64_t fshot[F_COUNT];     // elements between two shots' copies of a field
+    const int32_t *src_cells;   // [nshots] exec id of each shot's source cell, or -1
+    double dt, src_amp;         // src_amp = dt * r(t^{n+1/2}), the same wavelet for every shot
+    const void *src_vec;        // [nshots][Np] inverse mass times the basis at each source
     // dependence-driven schedule (chain kernel): one launch per sub-chain; workgroups take
     // tiles in colour order from a ticket counter, and a tile starts once every
     // lower-colour tile whose footprint meets its own has finished
@@ -47,7 +52,7 @@ struct TileArgs {
     const int32_t *need;        // [ntiles] predecessors per tile
     const int32_t *succ_off;    // [ntiles+1] successors (CSR)
     const int32_t *succ;
-    uint32_t *cnt;              // [ntiles] finished predecessors, counted across launches
+    uint32_t *cnt;              // [nshots][ntiles] finished predecessors, counted across launches
     uint32_t *head;             // ticket counter, counted across launches
     int32_t *err;               // set when a wait times out
     uint32_t epoch;             // launches of this plan so far (this one included)

@@ -101,7 +101,8 @@ struct CellRegs {
 
 template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int O>
 __device__ __forceinline__ void chain_op(CellRegs<K, T> &r, const TileArgs &a, T *__restrict__ lds, int NR, bool act,
-                                         int s, uint32_t acc, uint16_t fl, const uint32_t (&nb)[3], int64_t x) {
+                                         int s, uint32_t acc, uint16_t fl, const uint32_t (&nb)[3], int64_t x,
+                                         int shot) {
     constexpr int NP = np_of(K), NFP = K + 1;
     constexpr OpDesc D = op_desc(ORDER, O);
     constexpr int NI = D.vel ? 3 : 2, NO = D.vel ? 2 : 3;
@@ -119,7 +120,7 @@ __device__ __forceinline__ void chain_op(CellRegs<K, T> &r, const TileArgs &a, T
 #pragma unroll
         for (int f = 0; f < F_COUNT; ++f) {
             if (field_first_op(ORDER, O0, NOPS, f) != O || !((fl >> f) & 1)) continue;
-            const T *F = reinterpret_cast<const T *>(a.F[f]);
+            const T *F = reinterpret_cast<const T *>(a.F[f]) + shot * a.fshot[f];
             const bool coh = a.persist;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -313,8 +314,8 @@ __device__ __forceinline__ void chain_op(CellRegs<K, T> &r, const TileArgs &a, T
         if (ju < a.nloops && ((acc >> ju) & 1u)) {
             T(&q)[3][NP] = r.f[D.vel ? F_V : F_S];
             const T dt = (T)a.dt;
-            const bool src = !D.vel && x == a.src_cell;
-            const T *sv = reinterpret_cast<const T *>(a.src_vec);
+            const bool src = !D.vel && x == a.src_cells[shot];
+            const T *sv = reinterpret_cast<const T *>(a.src_vec) + shot * NP;
 #pragma unroll
             for (int c = 0; c < NO; ++c)
 #pragma unroll
@@ -330,7 +331,7 @@ __device__ __forceinline__ void chain_op(CellRegs<K, T> &r, const TileArgs &a, T
 #pragma unroll
     for (int f = 0; f < F_COUNT; ++f) {
         if (field_last_write(ORDER, O0, NOPS, f) != O || !((fl >> (8 + f)) & 1)) continue;
-        T *F = reinterpret_cast<T *>(a.F[f]);
+        T *F = reinterpret_cast<T *>(a.F[f]) + shot * a.fshot[f];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             if (c >= field_ncomp(f)) break;
@@ -341,7 +342,7 @@ __device__ __forceinline__ void chain_op(CellRegs<K, T> &r, const TileArgs &a, T
 }
 
 template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS>
-__device__ __forceinline__ void chain_tile(const TileArgs &a, T *__restrict__ lds, int tile) {
+__device__ __forceinline__ void chain_tile(const TileArgs &a, T *__restrict__ lds, int tile, int shot) {
     constexpr int NP = np_of(K);
     const int f0 = a.foot_off[tile];
     const int nfoot = a.foot_off[tile + 1] - f0;
@@ -385,22 +386,25 @@ __device__ __forceinline__ void chain_tile(const TileArgs &a, T *__restrict__ ld
     }
     // fields are gathered at their first use and written back after their last write
     [&]<int... Q>(std::integer_sequence<int, Q...>) {
-        (chain_op<K, T, UPW, ORDER, O0, NOPS, O0 + Q>(r, a, lds, a.nrow, act, s, acc, fl, nb[Q], x), ...);
+        (chain_op<K, T, UPW, ORDER, O0, NOPS, O0 + Q>(r, a, lds, a.nrow, act, s, acc, fl, nb[Q], x, shot), ...);
     }(std::make_integer_sequence<int, NOPS>{});
 }
 
-// Dependence-driven schedule, thread 0 of a workgroup: take the next ticket (tiles
-// in colour order) and wait until every predecessor of its tile has finished.
-// Predecessors have lower colours, hence lower tickets, so they were taken by
-// workgroups already running: the wait ends unless a counter is wrong, and the
-// poll limit ends it then too (the error flag tells the host).  -1: no tile left.
-__device__ __forceinline__ int next_tile(const TileArgs &a) {
+// Dependence-driven schedule, thread 0 of a workgroup: take the next ticket ((tile,
+// shot) items with tiles in colour order) and wait until every predecessor of its
+// tile has finished for the same shot.  Predecessors have lower colours, hence lower
+// tickets, so they were taken by workgroups already running: the wait ends unless a
+// counter is wrong, and the poll limit ends it then too (the error flag tells the
+// host).  -1: no item left.
+__device__ __forceinline__ int next_tile(const TileArgs &a, int &shot) {
     const uint32_t ticket = atomicAdd(a.head, 1u) - a.head_base;
-    if (ticket >= (uint32_t)a.ntiles) return -1;
-    const int tile = a.tiles[ticket];
+    if (ticket >= (uint32_t)a.ntiles * (uint32_t)a.nshots) return -1;
+    const int tile = a.tiles[ticket / (uint32_t)a.nshots];
+    shot = (int)(ticket % (uint32_t)a.nshots);
     const uint32_t need = (uint32_t)a.need[tile], base = (a.epoch - 1u) * need;
+    const uint32_t *cnt = a.cnt + (int64_t)shot * a.ntiles + tile;
     uint32_t polls = 0;
-    while (__hip_atomic_load(a.cnt + tile, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - base < need) {
+    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - base < need) {
         if (++polls > a.spin_limit) {
             atomicExch(a.err, 1);
             return -1;
@@ -413,25 +417,27 @@ __device__ __forceinline__ int next_tile(const TileArgs &a) {
 template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int NT>
 __global__ __launch_bounds__(NT) void k_tile_chain(const TileArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_next;
+    __shared__ int s_next, s_shot;
     T *lds = reinterpret_cast<T *>(smem);
     if (!a.persist) {  // one launch per colour
-        chain_tile<K, T, UPW, ORDER, O0, NOPS>(a, lds, a.tiles[a.tile_base + blockIdx.x]);
+        chain_tile<K, T, UPW, ORDER, O0, NOPS>(a, lds, a.tiles[a.tile_base + (int)blockIdx.x / a.nshots],
+                                               (int)blockIdx.x % a.nshots);
         return;
     }
     for (;;) {
-        if (threadIdx.x == 0) s_next = next_tile(a);
+        if (threadIdx.x == 0) s_next = next_tile(a, s_shot);
         __syncthreads();
-        const int tile = s_next;
+        const int tile = s_next, shot = s_shot;
         if (tile < 0) return;
-        chain_tile<K, T, UPW, ORDER, O0, NOPS>(a, lds, tile);
+        chain_tile<K, T, UPW, ORDER, O0, NOPS>(a, lds, tile, shot);
         // every wave waits for its coherent field stores to complete, so once the barrier
         // is passed the whole tile is visible at device scope and its successors may start
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (threadIdx.x == 0)
             for (int k = a.succ_off[tile]; k < a.succ_off[tile + 1]; ++k)
-                __hip_atomic_fetch_add(a.cnt + a.succ[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(a.cnt + (int64_t)shot * a.ntiles + a.succ[k], 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

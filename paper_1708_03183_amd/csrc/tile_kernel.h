@@ -20,10 +20,11 @@
 namespace dgt {
 
 template <int K, typename T, int F>
-__device__ __forceinline__ void stage_field(T *__restrict__ row, const TileArgs &a, int64_t x, uint16_t fl, bool in) {
+__device__ __forceinline__ void stage_field(T *__restrict__ row, const TileArgs &a, int64_t x, uint16_t fl, bool in,
+                                            int shot) {
     constexpr int NV = field_ncomp(F) * np_of(K);
     if (a.lds_row[F] < 0) return;
-    T *f = reinterpret_cast<T *>(a.F[F]);
+    T *f = reinterpret_cast<T *>(a.F[F]) + shot * a.fshot[F];
     if (in) {
         if (!((fl >> F) & 1)) return;
         T v[NV];
@@ -44,7 +45,8 @@ __global__ __launch_bounds__(NT) void k_tile(const TileArgs a) {
     constexpr int NG = K <= 2 ? 1 : (K == 3 ? 2 : 3);  // node groups per cell
     constexpr int NPG = (NP + NG - 1) / NG;             // nodes per group
     extern __shared__ __align__(16) unsigned char smem[];
-    const int tile = a.tiles[a.tile_base + blockIdx.x];
+    const int tile = a.tiles[a.tile_base + (int)blockIdx.x / a.nshots];
+    const int shot = (int)blockIdx.x % a.nshots;
     const int f0 = a.foot_off[tile];
     const int nfoot = a.foot_off[tile + 1] - f0;
     const int S = a.stride, NR = a.nrow;
@@ -89,11 +91,11 @@ __global__ __launch_bounds__(NT) void k_tile(const TileArgs a) {
             T gv[G_NROWS];
 #pragma unroll
             for (int r = 0; r < G_NROWS; ++r) gv[r] = geo[(int64_t)r * nc + x];
-            stage_field<K, T, 0>(row, a, x, fl, true);
-            stage_field<K, T, 1>(row, a, x, fl, true);
-            stage_field<K, T, 2>(row, a, x, fl, true);
-            stage_field<K, T, 3>(row, a, x, fl, true);
-            stage_field<K, T, 4>(row, a, x, fl, true);
+            stage_field<K, T, 0>(row, a, x, fl, true, shot);
+            stage_field<K, T, 1>(row, a, x, fl, true, shot);
+            stage_field<K, T, 2>(row, a, x, fl, true, shot);
+            stage_field<K, T, 3>(row, a, x, fl, true, shot);
+            stage_field<K, T, 4>(row, a, x, fl, true, shot);
 #pragma unroll
             for (int r = 0; r < G_NROWS; ++r) row[GR + r] = gv[r];
         }
@@ -278,8 +280,8 @@ __global__ __launch_bounds__(NT) void k_tile(const TileArgs a) {
                 T *Sg = row + a.lds_row[F_S];
                 const T *Z = row + a.lds_row[F_Z];
                 const T *X = row + (o4 ? a.lds_row[F_X] : 0);
-                const bool src = sfoot[s] == a.src_cell;
-                const T *sv = reinterpret_cast<const T *>(a.src_vec);
+                const bool src = sfoot[s] == a.src_cells[shot];
+                const T *sv = reinterpret_cast<const T *>(a.src_vec) + shot * NP;
 #pragma unroll
                 for (int ii = 0; ii < NPG; ++ii) {
                     const int i = g * NPG + ii;
@@ -303,11 +305,11 @@ __global__ __launch_bounds__(NT) void k_tile(const TileArgs a) {
         const int64_t x = sfoot[s];
         const uint16_t fl = flags[s];
         T *row = lds + (size_t)s * NR;
-        stage_field<K, T, 0>(row, a, x, fl, false);
-        stage_field<K, T, 1>(row, a, x, fl, false);
-        stage_field<K, T, 2>(row, a, x, fl, false);
-        stage_field<K, T, 3>(row, a, x, fl, false);
-        stage_field<K, T, 4>(row, a, x, fl, false);
+        stage_field<K, T, 0>(row, a, x, fl, false, shot);
+        stage_field<K, T, 1>(row, a, x, fl, false, shot);
+        stage_field<K, T, 2>(row, a, x, fl, false, shot);
+        stage_field<K, T, 3>(row, a, x, fl, false, shot);
+        stage_field<K, T, 4>(row, a, x, fl, false, shot);
     }
 }
 

@@ -25,6 +25,17 @@ class DgtError(RuntimeError):
         self.status = status
 
 
+class _AutotuneParams(C.Structure):
+    _fields_ = [("tile_sizes", C.c_void_p), ("ntile_sizes", C.c_int32), ("splits", C.c_void_p),
+                ("nsplits", C.c_int32), ("partition", C.c_int32), ("trial_steps", C.c_int32),
+                ("prune", C.c_double)]
+
+
+class _AutotuneResult(C.Structure):
+    _fields_ = [("tile_size", C.c_int32), ("schedule", C.c_int32), ("ms_per_step", C.c_double),
+                ("timed", C.c_int32), ("skipped", C.c_int32)]
+
+
 class _Desc(C.Structure):
     _fields_ = [("map", C.c_int32), ("mode", C.c_int32), ("data", C.c_int32)]
 
@@ -70,6 +81,8 @@ _SIGS = {
     "dgt_solver_inspect": [_p, C.POINTER(_InspectParams)],
     "dgt_solver_schedule": [_p, C.POINTER(_p)],
     "dgt_set_source": [_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double],
+    "dgt_solver_set_shots": [_p, C.c_int32, _p, C.c_double, C.c_double, C.c_double],
+    "dgt_solver_autotune": [_p, _p, _p],
     "dgt_state_upload": [_p, _p, _p],
     "dgt_state_download": [_p, _p, _p],
     "dgt_step": [_p, C.c_int64, C.c_int32, C.c_double],
@@ -269,7 +282,8 @@ class Mesh:
 
 
 class Solver:
-    """DG velocity-stress solver; state tensors v[2,Np,nc], s[3,Np,nc] on the GPU."""
+    """DG velocity-stress solver; state tensors v[2,Np,nc], s[3,Np,nc] on the GPU
+    (v[S,2,Np,nc], s[S,3,Np,nc] with S > 1 shots)."""
 
     def __init__(self, mesh: Mesh, lam, mu, rho, degree=2, flux=1, time_order=4, precision=0,
                  free_sides=0xF, dt=None, stream=None):
@@ -285,21 +299,38 @@ class Solver:
         _check(lib().dgt_solver_create(mesh.h, *[_np_ptr(a) for a in self._mat], C.byref(prm),
                                        _stream_handle(stream), C.byref(h)))
         self.h = h
+        self.nshots = 1
 
     @property
     def dtype(self):
         import torch
         return torch.float32 if self.precision == 1 else torch.float64
 
+    def _shape(self, comps):
+        return (comps, self.np, self.mesh.nc) if self.nshots == 1 else (self.nshots, comps, self.np, self.mesh.nc)
+
     def zeros(self, device="cuda"):
         import torch
-        return (torch.zeros((2, self.np, self.mesh.nc), dtype=self.dtype, device=device),
-                torch.zeros((3, self.np, self.mesh.nc), dtype=self.dtype, device=device))
+        return (torch.zeros(self._shape(2), dtype=self.dtype, device=device),
+                torch.zeros(self._shape(3), dtype=self.dtype, device=device))
 
     def inspect(self, tile_size, partition=1, max_rounds=64, splits=(), max_colour_tiles=0):
         """max_colour_tiles: 0 none, > 0 cap per colour class, -1 the GPU's resident tile count."""
         p, keep = _inspect_params(tile_size, partition, None, max_rounds, splits, max_colour_tiles)
         _check(lib().dgt_solver_inspect(self.h, C.byref(p)))
+
+    def autotune(self, tile_sizes=(64, 96, 128, 192, 256, 384, 512), splits=(), partition=1, trial_steps=5,
+                 prune=0.0) -> dict:
+        """Pick the seed tile size and schedule by timing trial steps; the solver is left
+        inspected and scheduled with the fastest pair."""
+        ts = np.ascontiguousarray(tile_sizes, np.int32)
+        sp = np.ascontiguousarray(splits, np.int32)
+        p = _AutotuneParams(_np_ptr(ts), len(ts), _np_ptr(sp) if len(sp) else None, len(sp), int(partition),
+                            int(trial_steps), float(prune))
+        r = _AutotuneResult()
+        _check(lib().dgt_solver_autotune(self.h, C.byref(p), C.byref(r)))
+        return dict(tile_size=r.tile_size, schedule=r.schedule, ms_per_step=r.ms_per_step, timed=r.timed,
+                    skipped=r.skipped)
 
     def schedule(self) -> Schedule:
         h = C.c_void_p()
@@ -316,20 +347,35 @@ class Solver:
     def set_source(self, x, y, f0=5.0, t0=0.2, amp=1.0):
         _check(lib().dgt_set_source(self.h, x, y, f0, t0, amp))
 
+    def set_shots(self, nshots: int, xy=None, f0=5.0, t0=0.2, amp=1.0):
+        """nshots independent states on this mesh, shot q with a Ricker source at xy[q]
+        (or none); the state is reset to zero."""
+        keep = None
+        if xy is not None:
+            keep = np.ascontiguousarray(xy, np.float64).reshape(-1)
+            assert keep.size == 2 * nshots
+        _check(lib().dgt_solver_set_shots(self.h, int(nshots), None if keep is None else _np_ptr(keep),
+                                          float(f0), float(t0), float(amp)))
+        self.nshots = int(nshots)
+
     def upload(self, v, s):
         assert v.dtype == self.dtype and s.dtype == self.dtype and v.is_contiguous() and s.is_contiguous()
-        assert tuple(v.shape) == (2, self.np, self.mesh.nc) and tuple(s.shape) == (3, self.np, self.mesh.nc)
+        assert tuple(v.shape) == self._shape(2) and tuple(s.shape) == self._shape(3)
         _check(lib().dgt_state_upload(self.h, C.c_void_p(v.data_ptr()), C.c_void_p(s.data_ptr())))
 
     def download(self, v, s):
         assert v.dtype == self.dtype and s.dtype == self.dtype and v.is_contiguous() and s.is_contiguous()
-        assert tuple(v.shape) == (2, self.np, self.mesh.nc) and tuple(s.shape) == (3, self.np, self.mesh.nc)
+        assert tuple(v.shape) == self._shape(2) and tuple(s.shape) == self._shape(3)
         _check(lib().dgt_state_download(self.h, C.c_void_p(v.data_ptr()), C.c_void_p(s.data_ptr())))
 
     def step(self, nsteps: int, mode: int = 1, t0: float = 0.0):
         _check(lib().dgt_step(self.h, int(nsteps), int(mode), float(t0)))
 
     def energy(self, v, s_new, s_old) -> float:
+        """Energy of one shot's state (tensors of one shot, contiguous)."""
+        assert tuple(v.shape) == (2, self.np, self.mesh.nc) and v.is_contiguous()
+        assert tuple(s_new.shape) == (3, self.np, self.mesh.nc) and s_new.is_contiguous()
+        assert tuple(s_old.shape) == (3, self.np, self.mesh.nc) and s_old.is_contiguous()
         out = C.c_double()
         _check(lib().dgt_energy(self.h, C.c_void_p(v.data_ptr()), C.c_void_p(s_new.data_ptr()),
                                 C.c_void_p(s_old.data_ptr()), C.byref(out)))
