@@ -70,21 +70,12 @@ __device__ uint64_t hilbert16(uint32_t x, uint32_t y) {
     return d;
 }
 
-__global__ void k_minmax2(const double *__restrict__ xy, int64_t n, double *__restrict__ out4) {
-    // one block; deterministic (min/max are exact)
+// bounding box of n points: each block reduces a grid-stride share of the points to
+// (min x, max x, min y, max y) in part[4 * block]; k_minmax_final reduces the parts
+// (min and max are exact, so the result does not depend on the grid)
+__device__ __forceinline__ void minmax_block(double (&v)[4]) {
     __shared__ double s[4][256];
-    double lo0 = INFINITY, lo1 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const double a = xy[2 * i], b = xy[2 * i + 1];
-        lo0 = fmin(lo0, a);
-        hi0 = fmax(hi0, a);
-        lo1 = fmin(lo1, b);
-        hi1 = fmax(hi1, b);
-    }
-    s[0][threadIdx.x] = lo0;
-    s[1][threadIdx.x] = hi0;
-    s[2][threadIdx.x] = lo1;
-    s[3][threadIdx.x] = hi1;
+    for (int q = 0; q < 4; ++q) s[q][threadIdx.x] = v[q];
     __syncthreads();
     for (int w = blockDim.x / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
@@ -95,12 +86,34 @@ __global__ void k_minmax2(const double *__restrict__ xy, int64_t n, double *__re
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        out4[0] = s[0][0];
-        out4[1] = s[1][0];
-        out4[2] = s[2][0];
-        out4[3] = s[3][0];
+    for (int q = 0; q < 4; ++q) v[q] = s[q][0];
+}
+
+__global__ __launch_bounds__(256) void k_minmax_part(const double *__restrict__ xy, int64_t n,
+                                                     double *__restrict__ part) {
+    double v[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double a = xy[2 * i], b = xy[2 * i + 1];
+        v[0] = fmin(v[0], a);
+        v[1] = fmax(v[1], a);
+        v[2] = fmin(v[2], b);
+        v[3] = fmax(v[3], b);
     }
+    minmax_block(v);
+    if (threadIdx.x < 4) part[4 * blockIdx.x + threadIdx.x] = v[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_minmax_final(const double *__restrict__ part, int nparts,
+                                                      double *__restrict__ out4) {
+    double v[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+        v[0] = fmin(v[0], part[4 * b]);
+        v[1] = fmax(v[1], part[4 * b + 1]);
+        v[2] = fmin(v[2], part[4 * b + 2]);
+        v[3] = fmax(v[3], part[4 * b + 3]);
+    }
+    minmax_block(v);
+    if (threadIdx.x < 4) out4[threadIdx.x] = v[threadIdx.x];
 }
 
 __device__ uint32_t quantise16(double v, double lo, double hi) {
@@ -150,9 +163,16 @@ __global__ void k_low32(const uint64_t *__restrict__ keys, int64_t n, int32_t *_
     if (i < n) out[i] = (int32_t)(keys[i] & 0xffffffffull);
 }
 
-__global__ void k_high32_hist(const uint64_t *__restrict__ keys, int64_t n, int32_t *__restrict__ count) {
+// CSR offsets of keys sorted by their high word (each < ngroups): off[g] is the first
+// position whose high word is >= g.  Thread i (0..n) writes the offsets of the groups
+// that start at i, so every offset is written once, without atomics.
+__global__ void k_sorted_offsets(const uint64_t *__restrict__ keys, int64_t n, int64_t ngroups,
+                                 int32_t *__restrict__ off) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) atomicAdd(&count[(int32_t)(keys[i] >> 32)], 1);
+    if (i > n) return;
+    const int64_t lo = i == 0 ? 0 : (int64_t)(keys[i - 1] >> 32) + 1;
+    const int64_t hi = i == n ? ngroups : min((int64_t)(keys[i] >> 32), ngroups);  // stays in bounds
+    for (int64_t g = lo; g <= hi; ++g) off[g] = (int32_t)i;
 }
 
 // tile pairs through a map into the seed set: all pairs of slots of one source
@@ -467,10 +487,8 @@ static void counts_to_offsets(DBuf<int32_t> &cnt, int64_t n, DBuf<int32_t> &off,
 // CSR offsets of sorted (high32 << 32 | low32) keys grouped by the high word
 static void offsets_by_high(const DBuf<uint64_t> &keys, int64_t n, int64_t ngroups, DBuf<int32_t> &off,
                             hipStream_t st) {
-    DBuf<int32_t> cnt(ngroups + 1);
-    DGT_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (ngroups + 1), st));
-    if (n) k_high32_hist<<<blocks_for(n, 256), 256, 0, st>>>(keys.p, n, cnt.p);
-    counts_to_offsets(cnt, ngroups, off, st);
+    off.alloc(ngroups + 1);
+    k_sorted_offsets<<<blocks_for(n + 1, 256), 256, 0, st>>>(keys.p, n, ngroups, off.p);
 }
 
 // ----------------------------------------------------------------- host driver
@@ -525,7 +543,12 @@ void Inspector::seed_partition(int seedset, int64_t ts, int partition, const dou
         xy = xy_owned.p;
     }
     DBuf<double> box(4);
-    k_minmax2<<<1, 256, 0, st>>>(xy, n0, box.p);
+    {
+        const int nparts = (int)std::min<int64_t>(1024, blocks_for(n0, 256));
+        DBuf<double> part(4 * nparts);
+        k_minmax_part<<<nparts, 256, 0, st>>>(xy, n0, part.p);
+        k_minmax_final<<<1, 256, 0, st>>>(part.p, nparts, box.p);
+    }
     DBuf<uint64_t> keys(n0);
     k_hilbert_keys<<<blocks_for(n0, 256), 256, 0, st>>>(xy, n0, box.p, keys.p);
     sort_keys(keys, n0, st);
