@@ -254,6 +254,36 @@ dgt_status dgt_step(dgt_solver *s, int64_t nsteps, int32_t mode, double t0);
  * in FP64 on the GPU.  v, sig_new, sig_old: device, caller layout of one shot,
  * solver precision.  Synchronises the stream. */
 dgt_status dgt_energy(dgt_solver *s, const void *v, const void *sig_new, const void *sig_old, double *out);
+/* Full-waveform inversion (an extension beyond the paper's forward chain).
+ * Receivers are velocity sensors: receiver r reads sum_i phi_i(x_r) v_i of the
+ * lowest-id cell containing x_r, after every time step.  Both calls start from
+ * rest at t = 0 with the solver's shots and sources (dgt_solver_set_shots /
+ * dgt_set_source), run nsteps steps with the untiled chain (mode 0) or the tiled
+ * executor (mode 1, after dgt_solver_inspect, with the solver's schedule), and
+ * overwrite the solver's state.  Enqueued on the stream; synchronise on return. */
+typedef struct {
+    int32_t nrec;           /* receivers, >= 1 */
+    const double *rec_xy;   /* host [nrec*2] receiver positions inside the mesh */
+    int64_t nsteps;         /* time steps, >= 1 */
+    int32_t nsnap;          /* checkpoints of the reversal (dgt_fwi_gradient), >= 1 */
+    int32_t mode;           /* 0 untiled, 1 tiled */
+} dgt_fwi_params;
+/* Receiver traces of the forward run: traces device [nshots][nsteps][nrec][2]
+ * FP64 (vx, vy), caller-owned.  EINVAL for bad parameters or a receiver outside
+ * the mesh, ESTATE for mode 1 without a usable inspection. */
+dgt_status dgt_fwi_forward(dgt_solver *s, const dgt_fwi_params *p, double *traces);
+/* Misfit J = 1/2 sum_shots sum_steps sum_receivers |r - d|^2 against observed
+ * (device, layout of dgt_fwi_forward) and its gradient with respect to each
+ * cell's lambda, mu, rho: g_lam, g_mu, g_rho device [nc] FP64 in the mesh's cell
+ * numbering, caller-owned, summed over the shots.  Discrete adjoint of the
+ * time-stepped chain: the reversed chain runs the same loops with -dt on a
+ * second solver (same inspection and schedule); forward states are recomputed
+ * from nsnap checkpoints by a binomial reversal schedule; the per-cell terms are
+ * accumulated in FP64.  EUNSUPPORTED unless the flux is central and every
+ * exterior facet is a free surface (or the mesh is periodic): the adjoint is the
+ * reversed step only for that energy-conserving discretisation.  *misfit host. */
+dgt_status dgt_fwi_gradient(dgt_solver *s, const dgt_fwi_params *p, const double *observed, double *misfit,
+                            double *g_lam, double *g_mu, double *g_rho);
 /* Schedule of the tiled executor (default 0).  0: one kernel launch per colour
  * of every sub-chain (Alg. 2's colour loop).  1: sub-chains that run on the
  * chain kernel (whole operator applications) launch once; workgroups take tiles

@@ -3,7 +3,9 @@
 TEST INFRASTRUCTURE ONLY.  Nothing in the product path (``libdgtile`` and the
 ``paper_1708_03183_amd`` binding) imports or loads this package; the tests, the
 smoke check and the benchmark's CPU-baseline leg do.  The C sources next to this
-file hold the arithmetic; this module only marshals NumPy arrays to them.
+file hold the arithmetic; this module marshals NumPy arrays to them, apart from
+the receiver sampling and misfit of full-waveform inversion (plain NumPy on top
+of the C time step, at the end of this file).
 """
 from __future__ import annotations
 
@@ -364,3 +366,142 @@ class OSched:
         if getattr(self, "h", None) and _lib is not None:
             _lib.or_sched_free(self.h)
             self.h = None
+
+
+# ----------------------------------------------------------------- FWI misfit
+# (the paper runs the forward chain only; these helpers define the receiver
+# sampling and the misfit whose gradient the library's adjoint computes)
+
+def locate(om: OMesh, x, y):
+    """Lowest-id cell containing (x, y), within 1e-12 in the reference coordinates
+    (r, s) of the affine map from the cell's first vertex, and those coordinates."""
+    p = om.xy[om.c2v]
+    xr, xs = p[:, 1, 0] - p[:, 0, 0], p[:, 2, 0] - p[:, 0, 0]
+    yr, ys = p[:, 1, 1] - p[:, 0, 1], p[:, 2, 1] - p[:, 0, 1]
+    det = xr * ys - xs * yr
+    r = (ys * (x - p[:, 0, 0]) - xs * (y - p[:, 0, 1])) / det
+    s = (-yr * (x - p[:, 0, 0]) + xr * (y - p[:, 0, 1])) / det
+    inside = np.flatnonzero((r >= -1e-12) & (s >= -1e-12) & (1.0 - r - s >= -1e-12))
+    if not len(inside):
+        raise ValueError("point outside the mesh")
+    c = int(inside[0])
+    return c, float(r[c]), float(s[c])
+
+
+def fwi_traces(od: ODG, rec_xy, shots_xy, nsteps, f0=5.0, t0=0.2, amp=1.0):
+    """Velocity traces [nshots, nsteps, nrec, 2]: each shot runs from rest with its
+    Ricker source; after step n receiver r reads sum_i phi_i(x_r) v_i of its cell."""
+    rec = [locate(od.om, x, y) for x, y in np.asarray(rec_xy, np.float64).reshape(-1, 2)]
+    phis = [basis(od.k, r, s) for _, r, s in rec]
+    shots = np.asarray(shots_xy, np.float64).reshape(-1, 2)
+    out = np.zeros((len(shots), nsteps, len(rec), 2))
+    for q, (x, y) in enumerate(shots):
+        od.set_source(x, y, f0, t0, amp)
+        v, s = od.zeros()
+        for n in range(nsteps):
+            od.step(v, s, 1, t0=n * od.dt)
+            for k, ((c, _, _), phi) in enumerate(zip(rec, phis)):
+                out[q, n, k] = v[:, :, c] @ phi
+    return out
+
+
+def fwi_misfit(od: ODG, rec_xy, shots_xy, nsteps, observed, f0=5.0, t0=0.2, amp=1.0):
+    """J = 1/2 sum over shots, steps, receivers and components of (r - d)^2."""
+    r = fwi_traces(od, rec_xy, shots_xy, nsteps, f0, t0, amp)
+    return 0.5 * float(((r - observed) ** 2).sum())
+
+
+
+def fwi_gradient_adjoint(od: ODG, od_rev: ODG, order, rec_xy, shots_xy, nsteps, observed, f0=5.0, t0=0.2, amp=1.0):
+    """Misfit and its gradient (g_lam, g_mu, g_rho per cell) by the discrete adjoint,
+    storing every forward state.  Valid for the central flux with free-surface or
+    periodic boundaries, where the transpose of a step is T^-1 Phi(-dt) T with
+    T = blockdiag(M_J^-1 / rho, M_J^-1 C) per cell; od_rev is the same solver built
+    with -dt.  A = velocity operator, B = stress operator (od.rate with the other
+    field zero); per step, with alpha the adjoint in T-variables,
+      g_rho -= |J| [(dt av + c A B av) . M^ (A s_n) + av . M^ (c A B A s_n)
+                    - c (A as) . M^ (A B v')]
+      g_lam += |J| [(dt as + c B A as) . (M^ x S_lam) (B v') + as . (M^ x S_lam) (c B A B v')
+                    - c (B av) . (M^ x S_lam) (B A s_n)]
+    with av the velocity part of alpha after the reversed step, as its stress part
+    before it, v' the velocity after the step, c = dt^3/24 (0 at order 2),
+    S_m = C^-1 (dC/dm) C^-1."""
+    om, k = od.om, od.k
+    npk, nc, dt = od.np, om.nc, od.dt
+    c3 = dt ** 3 / 24.0 if order == 4 else 0.0
+    R = refelem(k)
+    M, Minv = R["M"], R["Minv"]
+    p = om.xy[om.c2v]
+    det = (p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1]) - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1])
+    lam, mu, rho = od.lam, od.mu, od.rho
+    cA, cB, cC = (lam + 2 * mu) / (4 * mu * (lam + mu)), -lam / (4 * mu * (lam + mu)), 1.0 / mu
+    rec = [locate(om, x, y) for x, y in np.asarray(rec_xy, np.float64).reshape(-1, 2)]
+    phis = [basis(k, r, s) for _, r, s in rec]
+    zv, zs = od.zeros()
+
+    def A(s):
+        return od.rate(zv, s)[0]
+
+    def B(v):
+        return od.rate(v, zs)[1]
+
+    def cinv(x):  # C^-1 on (xx, yy, xy) per node
+        return np.stack([cA * x[0] + cB * x[1], cB * x[0] + cA * x[1], cC * x[2]])
+
+    def mdot(a, b):  # per cell: sum_ij a_i M_ij b_j
+        return np.einsum("in,ij,jn->n", a, M, b)
+
+    shots = np.asarray(shots_xy, np.float64).reshape(-1, 2)
+    g = np.zeros((3, nc))
+    J = 0.0
+    for q, (x, y) in enumerate(shots):
+        od.set_source(x, y, f0, t0, amp)
+        v, s = od.zeros()
+        states = [(v.copy(), s.copy())]
+        for n in range(nsteps):
+            od.step(v, s, 1, t0=n * dt)
+            states.append((v.copy(), s.copy()))
+
+        def residual(n):  # observation after step n - 1, from state n
+            vn = states[n][0]
+            return [vn[:, :, c] @ phi - observed[q, n - 1, kk] for kk, ((c, _, _), phi) in enumerate(zip(rec, phis))]
+
+        def inject(av, res):
+            for (c, _, _), phi, r in zip(rec, phis, res):
+                av[:, :, c] += np.outer(r, Minv @ phi) / (rho[c] * det[c])
+
+        for n in range(1, nsteps + 1):
+            J += 0.5 * sum(float(r @ r) for r in residual(n))
+        av, as_ = od.zeros()
+        inject(av, residual(nsteps))
+        for n in range(nsteps - 1, -1, -1):
+            v0, s0 = states[n]
+            v1 = states[n + 1][0]
+            U = A(s0)
+            X1 = B(v1)
+            Z = c3 * A(B(U)) if order == 4 else None
+            V2 = c3 * B(A(X1)) if order == 4 else None
+            as_before = as_.copy()
+            od_rev.step(av, as_, 1, t0=0.0)
+            def lm(b, e):  # (b . (M^ x S_lam) e, b . (M^ x S_mu) e) with b, e already through C^-1
+                return (mdot(b[0] + b[1], e[0] + e[1]),
+                        2 * (mdot(b[0], e[0]) + mdot(b[1], e[1])) + mdot(b[2], e[2]))
+
+            a = dt * av + (c3 * A(B(av)) if order == 4 else 0.0)
+            gr = sum(mdot(a[c], U[c]) for c in range(2))
+            P = dt * as_before + (c3 * B(A(as_before)) if order == 4 else 0.0)
+            gl, gm = lm(cinv(P), cinv(X1))
+            if order == 4:
+                # the velocity half's c A B A holds C, the stress half's c B A B holds 1/rho
+                gr = gr + sum(mdot(av[c], Z[c]) for c in range(2))
+                Ya = A(as_before)
+                gr = gr - c3 * sum(mdot(Ya[c], A(X1)[c]) for c in range(2))
+                l2, m2 = lm(cinv(as_before), cinv(V2))
+                l3, m3 = lm(cinv(B(av)), cinv(B(U)))
+                gl, gm = gl + l2 - c3 * l3, gm + m2 - c3 * m3
+            g[0] += det * gl
+            g[1] += det * gm
+            g[2] -= det * gr
+            if n >= 1:
+                inject(av, residual(n))
+    return J, g

@@ -1,0 +1,473 @@
+// Full-waveform-inversion gradient of libdgtile (included at the end of solver.hip;
+// the paper runs the forward chain only, so this part follows the survey's
+// extension of the method rather than a passage of the paper).
+//
+// Forward: u_{n+1} = Phi(u_n) + s_n with u_n = (v^{n-1/2}, sigma^n), one step of the
+// DG loop chain.  Receivers sample the velocity after every step, r_n = R u_{n+1};
+// the misfit is J = 1/2 sum_n sum_r |r_n - d_n|^2.
+//
+// Adjoint: with the central flux and free-surface (or periodic) boundaries the
+// semi-discrete operator is skew-adjoint in the discrete energy inner product, so
+// Phi^T = T^-1 Phi(-dt) T with T = blockdiag(M_J^-1 P, M_J^-1 C) per cell (M_J the
+// cell mass |J| M^, P = 1/rho, C the stiffness).  In the variables alpha = T a the
+// adjoint recursion a_n = Phi^T a_{n+1} + R^T (r_{n-1} - d_{n-1}) is the forward
+// chain run with -dt (on a second solver, tiled by the same inspector) plus the
+// injection T R^T (r - d).  Per step the gradient needs the forward operator outputs
+// (U = A sigma_n, X' = B U, Z = A X' of the velocity half, X1 = B v^{n+1/2}, Y = A X1,
+// V2 = B Y of the stress half) and, at order 4, W = A B alpha_v, W' = B A alpha_s and
+// their first halves; they come from single operator applications (untiled kernels).  With dA/drho_K =
+// -(1/rho_K) E_K A and dB/dlam_K = C_lam C^-1 E_K B (E_K the restriction to cell K):
+//   g_rho_K -= |J_K| sum [(dt av + c W) . M^ U + av . M^ (c Z) - c (A as) . M^ Y]
+//   g_lam_K += |J_K| sum [(dt as + c W') . (M^ x S_lam) X1 + as . (M^ x S_lam) (c V2)
+//                         - c (B av) . (M^ x S_lam) X']
+// (and g_mu with S_mu), S_m = C^-1 C_m C^-1, c = dt^3/24 (0 at order 2), av the
+// velocity part of alpha after the reversed step, as its stress part before it; the
+// last terms of each line come from the material inside the other half's c A B A
+// or c B A B.
+// Forward states are recomputed from checkpoints by a binomial (revolve-style)
+// reversal schedule.
+
+namespace dgt {
+
+// receiver r at step n of shot q: out[((q * nsteps + n) * nrec + r) * 2 + c]
+template <int K, typename T>
+__global__ __launch_bounds__(256) void k_fwi_sample(const T *__restrict__ v, int64_t nc, int64_t vsh, int nrec,
+                                                    const int32_t *__restrict__ cell, const double *__restrict__ phi,
+                                                    int64_t nsteps, int64_t n, const double *__restrict__ obs,
+                                                    double *__restrict__ trace, double *__restrict__ res,
+                                                    double *__restrict__ jacc) {
+    constexpr int NP = np_of(K);
+    __shared__ double red[256];
+    const int q = blockIdx.x;
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < 2 * nrec; t += blockDim.x) {
+        const int k = t >> 1, c = t & 1;
+        const int64_t x = cell[k];
+        double r = 0.0;
+        for (int i = 0; i < NP; ++i) r += phi[k * NP + i] * (double)v[q * vsh + (int64_t)(c * NP + i) * nc + x];
+        const int64_t o = (((int64_t)q * nsteps + n) * nrec + k) * 2 + c;
+        if (trace) trace[o] = r;
+        if (obs) {
+            const double d = r - obs[o];
+            res[((int64_t)q * nrec + k) * 2 + c] = d;
+            acc += d * d;
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && jacc) jacc[q] += 0.5 * red[0];
+}
+
+// alpha_v += T R^T res: per receiver the weights (1/rho_K) M^-1 phi(x_r) / |J_K|.  One
+// thread per (shot, component, node) runs over the receivers in order (receivers
+// sharing a cell never race).
+template <int K, typename T>
+__global__ __launch_bounds__(256) void k_fwi_inject(T *__restrict__ av, int64_t nc, int64_t vsh, int nshots, int nrec,
+                                                    const int32_t *__restrict__ cell, const double *__restrict__ mphi,
+                                                    const T *__restrict__ geo, const double *__restrict__ res) {
+    constexpr int NP = np_of(K);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nshots * 2 * NP) return;
+    const int q = t / (2 * NP), c = (t / NP) % 2, i = t % NP;
+    for (int k = 0; k < nrec; ++k) {
+        const int64_t x = cell[k];
+        const double w = mphi[k * NP + i] * (double)geo[G_IRHO * nc + x] / (double)geo[G_DET * nc + x];
+        T &a = av[q * vsh + (int64_t)(c * NP + i) * nc + x];
+        a = (T)((double)a + w * res[((int64_t)q * nrec + k) * 2 + c]);
+    }
+}
+
+// v1 = v0 + (dt U + Z), the velocity update of the untiled chain
+template <typename T>
+__global__ __launch_bounds__(256) void k_fwi_vnext(T *__restrict__ v1, const T *__restrict__ v0,
+                                                   const T *__restrict__ U, const T *__restrict__ Z, int64_t n, T dt) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    v1[t] = v0[t] + (dt * U[t] + (Z ? Z[t] : T(0)));
+}
+
+// per-cell gradient terms of one step, summed over the shots in order (FP64).
+// 2-component fields (stride vsh per shot): av, U, Zs = c A B U, W = A B av,
+// tV = A as, Y = A X1; 3-component (stride ssh): as, X1, V2s = c B A X1,
+// Wp = B A as, tS = B av, Xp = B U.  The order-4 fields are null at order 2.
+template <int K, typename T>
+__device__ __forceinline__ double fwi_m(const T *a, const T *b, int64_t o, int64_t nc, int c, int i, int j) {
+    return (double)a[o + (int64_t)(c * np_of(K) + i) * nc] * (double)b[o + (int64_t)(c * np_of(K) + j) * nc];
+}
+
+template <int K, typename T>
+__global__ __launch_bounds__(256) void k_fwi_grad(int64_t nc, int nshots, const T *__restrict__ geo,
+                                                  const T *__restrict__ av, const T *__restrict__ U,
+                                                  const T *__restrict__ Zs, const T *__restrict__ W,
+                                                  const T *__restrict__ tV, const T *__restrict__ Y, int64_t vsh,
+                                                  const T *__restrict__ as, const T *__restrict__ X1,
+                                                  const T *__restrict__ V2s, const T *__restrict__ Wp,
+                                                  const T *__restrict__ tS, const T *__restrict__ Xp, int64_t ssh,
+                                                  double dt, double c3, double *__restrict__ g) {
+    constexpr int NP = np_of(K);
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nc) return;
+    const auto &Rf = R<K, T>();
+    const double lam = geo[G_LAM * nc + x], mu = geo[G_MU * nc + x], det = geo[G_DET * nc + x];
+    // C^-1 on (xx, yy, xy): [[cA, cB, 0], [cB, cA, 0], [0, 0, 1/mu]]
+    const double cA = (lam + 2 * mu) / (4 * mu * (lam + mu)), cB = -lam / (4 * mu * (lam + mu)), cC = 1.0 / mu;
+    const bool o4 = W != nullptr;
+    double gr = 0.0, gl = 0.0, gm = 0.0;
+    // b . (M^ x S_lam) e and b . (M^ x S_mu) e for 3-component nodal vectors already through C^-1
+    auto lm = [&](const double (&b)[3], const double (&e)[3], double M, double w) {
+        gl += w * M * (b[0] + b[1]) * (e[0] + e[1]);
+        gm += w * M * (2 * (b[0] * e[0] + b[1] * e[1]) + b[2] * e[2]);
+    };
+    auto through_cinv = [&](const T *f, int64_t o, int i, double sc, const T *f2, double sc2, double (&r)[3]) {
+        double p[3];
+        for (int c = 0; c < 3; ++c) {
+            p[c] = sc * (double)f[o + (int64_t)(c * NP + i) * nc];
+            if (f2) p[c] += sc2 * (double)f2[o + (int64_t)(c * NP + i) * nc];
+        }
+        r[0] = cA * p[0] + cB * p[1];
+        r[1] = cB * p[0] + cA * p[1];
+        r[2] = cC * p[2];
+    };
+    for (int q = 0; q < nshots; ++q) {
+        const int64_t ov = q * vsh + x, os = q * ssh + x;
+        for (int i = 0; i < NP; ++i) {
+            double bP[3], bA[3], bS[3];
+            through_cinv(as, os, i, dt, o4 ? Wp : nullptr, c3, bP);  // C^-1 (dt as + c W')
+            if (o4) {
+                through_cinv(as, os, i, 1.0, nullptr, 0.0, bA);       // C^-1 as
+                through_cinv(tS, os, i, 1.0, nullptr, 0.0, bS);       // C^-1 B av
+            }
+            for (int j = 0; j < NP; ++j) {
+                const double M = (double)Rf.M[i * NP + j];
+                double tr = 0.0;
+                for (int c = 0; c < 2; ++c) {
+                    double a = dt * (double)av[ov + (int64_t)(c * NP + i) * nc];
+                    if (o4) a += c3 * (double)W[ov + (int64_t)(c * NP + i) * nc];
+                    tr += a * (double)U[ov + (int64_t)(c * NP + j) * nc];
+                    if (o4) tr += fwi_m<K, T>(av, Zs, ov, nc, c, i, j) - c3 * fwi_m<K, T>(tV, Y, ov, nc, c, i, j);
+                }
+                gr += M * tr;
+                double e[3];
+                through_cinv(X1, os, j, 1.0, nullptr, 0.0, e);
+                lm(bP, e, M, 1.0);
+                if (o4) {
+                    through_cinv(V2s, os, j, 1.0, nullptr, 0.0, e);
+                    lm(bA, e, M, 1.0);
+                    through_cinv(Xp, os, j, 1.0, nullptr, 0.0, e);
+                    lm(bS, e, M, -c3);
+                }
+            }
+        }
+    }
+    g[x] += det * gl;
+    g[nc + x] += det * gm;
+    g[2 * nc + x] -= det * gr;
+}
+
+struct FwiReceivers {
+    int nrec = 0;
+    DBuf<int32_t> cell;  // exec id of each receiver's cell
+    DBuf<double> phi;    // [nrec][Np] basis at the receiver
+    DBuf<double> mphi;   // [nrec][Np] reference inverse mass times phi
+};
+
+static void fwi_receivers(dgt_solver *s, int nrec, const double *xy, FwiReceivers &R) {
+    const int np = s->E.np;
+    std::vector<int32_t> cell(nrec);
+    std::vector<double> phi((size_t)nrec * np), mphi((size_t)nrec * np);
+    for (int k = 0; k < nrec; ++k) {
+        DGT_REQUIRE(std::isfinite(xy[2 * k]) && std::isfinite(xy[2 * k + 1]), DGT_EINVAL,
+                    "receiver position is not finite");
+        double rs = 0, ss = 0;
+        const int64_t c = locate_point(s, xy[2 * k], xy[2 * k + 1], rs, ss);
+        DGT_REQUIRE(c >= 0, DGT_EINVAL, "receiver outside the mesh");
+        cell[k] = s->rank_h[c];
+        s->E.phi(rs, ss, &phi[(size_t)k * np]);
+        for (int i = 0; i < np; ++i) {
+            double a = 0;
+            for (int j = 0; j < np; ++j) a += s->E.Minv[i * np + j] * phi[(size_t)k * np + j];
+            mphi[(size_t)k * np + i] = a;
+        }
+    }
+    R.nrec = nrec;
+    R.cell.upload(cell, s->st);
+    R.phi.upload(phi, s->st);
+    R.mphi.upload(mphi, s->st);
+}
+
+static void fwi_check(dgt_solver *s, const dgt_fwi_params *p) {
+    DGT_REQUIRE(p->nrec >= 1 && p->rec_xy, DGT_EINVAL, "at least one receiver");
+    DGT_REQUIRE(p->nsteps >= 1, DGT_EINVAL, "nsteps must be >= 1");
+    DGT_REQUIRE(p->mode == 0 || p->mode == 1, DGT_EINVAL, "mode must be 0 or 1");
+    DGT_REQUIRE(p->mode == 0 || (s->plan_status == DGT_OK && s->inspected), DGT_ESTATE,
+                "tiled mode needs a successful dgt_solver_inspect");
+}
+
+template <int K, typename T>
+static void fwi_advance(dgt_solver *s, int64_t n0, int64_t nsteps, int mode) {
+    if (nsteps <= 0) return;
+    int64_t launches = 0;
+    // one call per step, so that every replay computes the source times alike
+    for (int64_t n = n0; n < n0 + nsteps; ++n) {
+        if (mode == 0) step_untiled<K, T>(s, 1, (double)n * s->p.dt, launches);
+        else step_tiled<K, T>(s, 1, (double)n * s->p.dt, launches);
+    }
+}
+
+// number of steps a binomial reversal reverses with `snaps` free checkpoints and
+// `sweeps` forward sweeps: C(snaps + sweeps, snaps), capped
+static int64_t binom_steps(int snaps, int sweeps, int64_t cap) {
+    double b = 1.0;
+    for (int i = 1; i <= snaps; ++i) {
+        b = b * (double)(sweeps + i) / (double)i;
+        if (b > (double)cap) return cap + 1;
+    }
+    return (int64_t)(b + 0.5);
+}
+
+template <int K, typename T>
+struct FwiRun {
+    dgt_solver *f = nullptr, *a = nullptr;  // forward (dt) and reversed (-dt) solvers
+    const dgt_fwi_params *p = nullptr;
+    const FwiReceivers *R = nullptr;
+    const double *obs = nullptr;
+    int S = 1;
+    int64_t vsh = 0, ssh = 0, advanced = 0, reversed = 0;
+    std::vector<DBuf<char>> snap;
+    DBuf<T> U, Xp, Zs, V1, X1, Y, V2s, W, Wp, tV, tS, As;
+    DBuf<double> res, g;
+
+    void store(int slot) {
+        const size_t bv = (size_t)vsh * S * sizeof(T), bs = (size_t)ssh * S * sizeof(T);
+        if (snap[slot].n < bv + bs) snap[slot].alloc(bv + bs);
+        DGT_HIP(hipMemcpyAsync(snap[slot].p, f->fld[F_V].p, bv, hipMemcpyDeviceToDevice, f->st));
+        DGT_HIP(hipMemcpyAsync(snap[slot].p + bv, f->fld[F_S].p, bs, hipMemcpyDeviceToDevice, f->st));
+    }
+    void restore(int slot) {
+        const size_t bv = (size_t)vsh * S * sizeof(T), bs = (size_t)ssh * S * sizeof(T);
+        DGT_HIP(hipMemcpyAsync(f->fld[F_V].p, snap[slot].p, bv, hipMemcpyDeviceToDevice, f->st));
+        DGT_HIP(hipMemcpyAsync(f->fld[F_S].p, snap[slot].p + bv, bs, hipMemcpyDeviceToDevice, f->st));
+    }
+    void advance(int64_t n0, int64_t n) {
+        fwi_advance<K, T>(f, n0, n, p->mode);
+        advanced += n;
+    }
+    // residual of the receivers at the forward state held (the observation after
+    // step n - 1), injected into the adjoint velocity
+    void inject(int64_t n) {
+        if (n < 1) return;
+        hipStream_t st = f->st;
+        k_fwi_sample<K, T><<<S, 256, 0, st>>>((const T *)f->fld[F_V].p, f->nc, vsh, R->nrec, R->cell.p, R->phi.p,
+                                            p->nsteps, n - 1, obs, nullptr, res.p, nullptr);
+        constexpr int NP = np_of(K);
+        k_fwi_inject<K, T><<<blocks_for((int64_t)S * 2 * NP, 256), 256, 0, st>>>(
+            (T *)a->fld[F_V].p, f->nc, vsh, S, R->nrec, R->cell.p, R->mphi.p, (const T *)f->geo.p, res.p);
+    }
+    // the forward state u_n is in f, alpha_{n+1} in a
+    void step_back(int64_t n) {
+        hipStream_t st = f->st;
+        const int64_t nc = f->nc;
+        const bool o4 = f->p.time_order == 4;
+        const double dt = f->p.dt, c3 = o4 ? dt * dt * dt / 24.0 : 0.0;
+        int64_t launches = 0;
+        const T *v0 = (const T *)f->fld[F_V].p, *s0 = (const T *)f->fld[F_S].p;
+        for (int q = 0; q < S; ++q) {
+            const int64_t ov = q * vsh, os = q * ssh;
+            apply_op<K, T>(f, true, s0 + os, U.p + ov, 1.0, nullptr, 0.0, launches);
+            if (o4) {
+                apply_op<K, T>(f, false, U.p + ov, Xp.p + os, 1.0, nullptr, 0.0, launches);
+                apply_op<K, T>(f, true, Xp.p + os, Zs.p + ov, c3, nullptr, 0.0, launches);
+            }
+            k_fwi_vnext<T><<<blocks_for(vsh, 256), 256, 0, st>>>(V1.p + ov, v0 + ov, U.p + ov,
+                                                                o4 ? Zs.p + ov : nullptr, vsh, (T)dt);
+            apply_op<K, T>(f, false, V1.p + ov, X1.p + os, 1.0, nullptr, 0.0, launches);
+            if (o4) {
+                apply_op<K, T>(f, true, X1.p + os, Y.p + ov, 1.0, nullptr, 0.0, launches);
+                apply_op<K, T>(f, false, Y.p + ov, V2s.p + os, c3, nullptr, 0.0, launches);
+            }
+        }
+        // alpha_s before the reversed step, then the step itself
+        DGT_HIP(hipMemcpyAsync(As.p, a->fld[F_S].p, (size_t)ssh * S * sizeof(T), hipMemcpyDeviceToDevice, st));
+        fwi_advance<K, T>(a, 0, 1, p->mode);
+        ++reversed;
+        const T *av = (const T *)a->fld[F_V].p;
+        if (o4) {
+            for (int q = 0; q < S; ++q) {
+                const int64_t ov = q * vsh, os = q * ssh;
+                apply_op<K, T>(f, false, av + ov, tS.p + os, 1.0, nullptr, 0.0, launches);
+                apply_op<K, T>(f, true, tS.p + os, W.p + ov, 1.0, nullptr, 0.0, launches);
+                apply_op<K, T>(f, true, As.p + os, tV.p + ov, 1.0, nullptr, 0.0, launches);
+                apply_op<K, T>(f, false, tV.p + ov, Wp.p + os, 1.0, nullptr, 0.0, launches);
+            }
+        }
+        k_fwi_grad<K, T><<<blocks_for(nc, 256), 256, 0, st>>>(
+            nc, S, (const T *)f->geo.p, av, U.p, o4 ? Zs.p : nullptr, o4 ? W.p : nullptr, o4 ? tV.p : nullptr,
+            o4 ? Y.p : nullptr, vsh, As.p, X1.p, o4 ? V2s.p : nullptr, o4 ? Wp.p : nullptr, o4 ? tS.p : nullptr,
+            o4 ? Xp.p : nullptr, ssh, dt, c3, g.p);
+        inject(n);
+    }
+    // reverse steps [l, r): u_l is in checkpoint `slot`, `free` checkpoints above it
+    void reverse(int64_t l, int64_t r, int slot, int free) {
+        if (r - l == 1) {
+            restore(slot);
+            step_back(l);
+            return;
+        }
+        if (free == 0) {
+            for (int64_t j = r - 1; j >= l; --j) {
+                restore(slot);
+                advance(l, j - l);
+                step_back(j);
+            }
+            return;
+        }
+        const int64_t n = r - l;
+        int t = 1;
+        while (binom_steps(free, t, n) < n) ++t;
+        int64_t right = binom_steps(free - 1, t, n);
+        right = std::max<int64_t>(1, std::min<int64_t>(right, n - 1));
+        const int64_t m = r - right;
+        restore(slot);
+        advance(l, m - l);
+        store(slot + 1);
+        reverse(m, r, slot + 1, free - 1);
+        reverse(l, m, slot, free);
+    }
+};
+
+// a second solver on the same mesh and material running the chain with -dt, the
+// same shots (no sources) and the same inspection and schedule
+static std::unique_ptr<dgt_solver> fwi_adjoint_solver(dgt_solver *s, const dgt_mesh *mh) {
+    const int64_t nc = s->nc;
+    std::vector<double> lam(nc), mu(nc), rho(nc);
+    DGT_HIP(hipMemcpyAsync(lam.data(), s->lam.p, 8 * nc, hipMemcpyDeviceToHost, s->st));
+    DGT_HIP(hipMemcpyAsync(mu.data(), s->mu.p, 8 * nc, hipMemcpyDeviceToHost, s->st));
+    DGT_HIP(hipMemcpyAsync(rho.data(), s->rho.p, 8 * nc, hipMemcpyDeviceToHost, s->st));
+    DGT_HIP(hipStreamSynchronize(s->st));
+    dgt_solver_params q = s->p;
+    q.dt = -s->p.dt;
+    auto a = new_solver(mh, lam.data(), mu.data(), rho.data(), &q, (void *)s->st);
+    if (s->nshots > 1) {
+        a->nshots = s->nshots;
+        alloc_fields(a.get());
+        a->src_in.assign(s->nshots, -1);
+        a->src_vec.alloc((size_t)s->nshots * s->E.np * s->esz);
+        DGT_HIP(hipMemsetAsync(a->src_vec.p, 0, a->src_vec.n, s->st));
+        set_source_exec(a.get());
+    }
+    if (s->inspected) {
+        dgt_inspect_params ip = s->last_ip;
+        ip.splits = s->last_splits.data();
+        ip.nsplits = (int32_t)s->last_splits.size();
+        solver_inspect_once(a.get(), &ip, s->last_cap);
+        DGT_REQUIRE(a->plan_status == DGT_OK && a->rank_h == s->rank_h, DGT_ESTATE,
+                    "the reversed chain's inspection differs from the forward one");
+        a->sched_mode = s->sched_mode;
+    } else {
+        DGT_REQUIRE(a->rank_h == s->rank_h, DGT_ESTATE, "cell orders differ");
+    }
+    return a;
+}
+
+template <int K, typename T>
+static void fwi_forward_run(dgt_solver *s, const dgt_fwi_params *p, const FwiReceivers &R, const double *obs,
+                            double *trace, double *jacc) {
+    const int64_t vsh = s->fshot(F_V);
+    for (int f = 0; f < F_COUNT; ++f) DGT_HIP(hipMemsetAsync(s->fld[f].p, 0, s->fld[f].n, s->st));
+    DBuf<double> res((size_t)s->nshots * R.nrec * 2);
+    for (int64_t n = 0; n < p->nsteps; ++n) {
+        fwi_advance<K, T>(s, n, 1, p->mode);
+        k_fwi_sample<K, T><<<s->nshots, 256, 0, s->st>>>((const T *)s->fld[F_V].p, s->nc, vsh, R.nrec, R.cell.p,
+                                                       R.phi.p, p->nsteps, n, obs, trace, res.p, jacc);
+    }
+}
+
+}  // namespace dgt
+
+extern "C" {
+
+dgt_status dgt_fwi_forward(dgt_solver *s, const dgt_fwi_params *p, double *traces) {
+    return guard([&] {
+        DGT_REQUIRE(s && p && traces, DGT_EINVAL, "NULL argument");
+        fwi_check(s, p);
+        FwiReceivers R;
+        fwi_receivers(s, p->nrec, p->rec_xy, R);
+        if (p->mode == 1) prepare_tiled(s);
+        dispatch(s, [&]<int K, typename T>() { fwi_forward_run<K, T>(s, p, R, nullptr, traces, nullptr); });
+        DGT_HIP(hipGetLastError());
+        DGT_HIP(hipStreamSynchronize(s->st));
+        if (p->mode == 1) check_graphs(s);
+        s->state_valid = true;  // the state after the run
+    });
+}
+
+dgt_status dgt_fwi_gradient(dgt_solver *s, const dgt_fwi_params *p, const double *observed, double *misfit,
+                            double *g_lam, double *g_mu, double *g_rho) {
+    return guard([&] {
+        DGT_REQUIRE(s && p && observed && misfit && g_lam && g_mu && g_rho, DGT_EINVAL, "NULL argument");
+        fwi_check(s, p);
+        DGT_REQUIRE(p->nsnap >= 1, DGT_EINVAL, "nsnap must be >= 1");
+        DGT_REQUIRE(!s->upw && !s->haspen, DGT_EUNSUPPORTED,
+                    "the adjoint needs the central flux and free-surface or periodic boundaries");
+        FwiReceivers R;
+        fwi_receivers(s, p->nrec, p->rec_xy, R);
+        auto adj = fwi_adjoint_solver(s, s->mesh_handle);
+        hipStream_t st = s->st;
+        const int S = s->nshots;
+        const int64_t nc = s->nc;
+        DBuf<double> jacc(S);
+        DGT_HIP(hipMemsetAsync(jacc.p, 0, 8 * S, st));
+        if (p->mode == 1) {
+            prepare_tiled(s);
+            prepare_tiled(adj.get());
+        }
+        double J = 0;
+        dispatch(s, [&]<int K, typename T>() {
+            FwiRun<K, T> run;
+            run.f = s;
+            run.a = adj.get();
+            run.p = p;
+            run.R = &R;
+            run.obs = observed;
+            run.S = S;
+            run.vsh = s->fshot(F_V);
+            run.ssh = s->fshot(F_S);
+            const size_t nv = (size_t)run.vsh * S, ns = (size_t)run.ssh * S;
+            for (auto *b : {&run.U, &run.Zs, &run.V1, &run.Y, &run.W, &run.tV}) b->alloc(nv);
+            for (auto *b : {&run.Xp, &run.X1, &run.V2s, &run.Wp, &run.tS, &run.As}) b->alloc(ns);
+            run.res.alloc((size_t)S * R.nrec * 2);
+            run.g.alloc((size_t)3 * nc);
+            DGT_HIP(hipMemsetAsync(run.g.p, 0, 8 * 3 * nc, st));
+            run.snap.resize(p->nsnap);
+            // forward sweep from rest: misfit; the start state is the first checkpoint
+            for (int f = 0; f < F_COUNT; ++f) DGT_HIP(hipMemsetAsync(s->fld[f].p, 0, s->fld[f].n, st));
+            run.store(0);
+            fwi_forward_run<K, T>(s, p, R, observed, nullptr, jacc.p);
+            run.advanced += p->nsteps;
+            // adjoint start: alpha_N = T R^T (r_{N-1} - d_{N-1}), from the final state
+            for (int f = 0; f < F_COUNT; ++f) DGT_HIP(hipMemsetAsync(adj->fld[f].p, 0, adj->fld[f].n, st));
+            run.inject(p->nsteps);
+            run.reverse(0, p->nsteps, 0, p->nsnap - 1);
+            // gradient into the mesh numbering
+            for (int m = 0; m < 3; ++m)
+                k_permute_rows<double><<<blocks_for(nc, 256), 256, 0, st>>>(
+                    run.g.p + m * nc, m == 0 ? g_lam : (m == 1 ? g_mu : g_rho), s->rank.p, 1, nc, 0);
+            s->last_launches = run.advanced + run.reversed;
+        });
+        DGT_HIP(hipGetLastError());
+        const auto jh = jacc.download(st);
+        for (int q = 0; q < S; ++q) J += jh[q];
+        if (p->mode == 1) {
+            check_graphs(s);
+            check_graphs(adj.get());
+        }
+        *misfit = J;
+        s->state_valid = false;  // the fields hold the reversal's last forward state
+    });
+}
+
+}  // extern "C"

@@ -45,6 +45,7 @@ struct SubPlan {
 
 struct dgt_solver {
     const dgt::Mesh *mesh = nullptr;
+    const dgt_mesh *mesh_handle = nullptr;
     dgt_solver_params p{};
     hipStream_t st = nullptr;
     dgt::RefElem E;
@@ -81,6 +82,11 @@ struct dgt_solver {
     dgt_schedule *sched = nullptr;
     std::vector<dgt::SubPlan> plan;
     dgt_status plan_status = DGT_ESTATE;  // why the tiled executor cannot run (DGT_OK when it can)
+    // parameters of the last inspection (the FWI adjoint solver repeats it)
+    bool inspected = false;
+    dgt_inspect_params last_ip{};
+    std::vector<int32_t> last_splits;
+    int last_cap = 0;
     std::string plan_error = "tiled mode needs dgt_solver_inspect";
     // timing of the last step
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -602,15 +608,14 @@ static void build_plan(dgt_solver *s) {
 
 // ------------------------------------------------------------ steps
 
+// One operator application of the untiled chain (volume, facet and lift kernels):
+// fout = scale * op(fin) (+ the upwind penalty of fpen scaled by pscale).
 template <int K, typename T>
-static void apply_untiled(dgt_solver *s, int shot, bool vel, int in, int out, double scale, int pen, double pscale,
-                          int64_t &launches) {
+static void apply_op(dgt_solver *s, bool vel, const T *fin, T *fout, double scale, const T *fpen, double pscale,
+                     int64_t &launches) {
     hipStream_t st = s->st;
     const int64_t nc = s->nc, nf = s->nf, nb = s->nb;
     constexpr int NP = np_of(K), NFP = K + 1;
-    const T *fin = (const T *)s->fld[in].p + shot * s->fshot(in);
-    T *fout = (T *)s->fld[out].p + shot * s->fshot(out);
-    const T *fpen = pen >= 0 ? (const T *)s->fld[pen].p + shot * s->fshot(pen) : nullptr;
     const T *geo = (const T *)s->geo.p;
     T *G = (T *)s->G.p, *Gx = (T *)s->Gx.p;
     const T sc = (T)scale, ps = (T)pscale;
@@ -640,6 +645,13 @@ static void apply_untiled(dgt_solver *s, int shot, bool vel, int in, int out, do
         k_lift<K, T, false><<<blocks_for(nc * NP, 256), 256, 0, st>>>(fout, s->c2f.p, G, Gx, nc, nf, nb);
     }
     ++launches;
+}
+
+template <int K, typename T>
+static void apply_untiled(dgt_solver *s, int shot, bool vel, int in, int out, double scale, int pen, double pscale,
+                          int64_t &launches) {
+    apply_op<K, T>(s, vel, (const T *)s->fld[in].p + shot * s->fshot(in), (T *)s->fld[out].p + shot * s->fshot(out),
+                   scale, pen >= 0 ? (const T *)s->fld[pen].p + shot * s->fshot(pen) : nullptr, pscale, launches);
 }
 
 template <int K, typename T>
@@ -805,16 +817,19 @@ dgt_status dgt_mesh_maps(const dgt_mesh *m, int32_t *f2c, int8_t *f2l, int32_t *
 
 void dgt_mesh_destroy(dgt_mesh *m) { delete m; }
 
-dgt_status dgt_solver_create(const dgt_mesh *m, const double *lam, const double *mu, const double *rho,
-                             const dgt_solver_params *p, void *stream, dgt_solver **out) {
-    return guard([&] {
-        DGT_REQUIRE(m && p && out, DGT_EINVAL, "NULL argument");
-        *out = nullptr;
+}  // extern "C"
+
+namespace dgt {
+
+// The solver without the sign check of dt: the FWI adjoint runs the chain backward
+// in time (dt < 0) on a solver of its own.
+static std::unique_ptr<dgt_solver> new_solver(const dgt_mesh *m, const double *lam, const double *mu,
+                                              const double *rho, const dgt_solver_params *p, void *stream) {
         DGT_REQUIRE(p->degree >= 1 && p->degree <= 4, DGT_EINVAL, "degree must be 1..4");
         DGT_REQUIRE(p->flux == 0 || p->flux == 1, DGT_EINVAL, "flux must be 0 or 1");
         DGT_REQUIRE(p->time_order == 2 || p->time_order == 4, DGT_EINVAL, "time_order must be 2 or 4");
         DGT_REQUIRE(p->precision == 0 || p->precision == 1, DGT_EINVAL, "precision must be 0 or 1");
-        DGT_REQUIRE(p->dt > 0 && std::isfinite(p->dt), DGT_EINVAL, "dt must be positive");
+        DGT_REQUIRE(p->dt != 0 && std::isfinite(p->dt), DGT_EINVAL, "dt must be finite and nonzero");
         const Mesh &M = m->m;
         DGT_REQUIRE(M.nc > 0, DGT_EINVAL, "empty mesh");
         DGT_REQUIRE(lam && mu && rho, DGT_EINVAL, "material is NULL");
@@ -822,6 +837,7 @@ dgt_status dgt_solver_create(const dgt_mesh *m, const double *lam, const double 
             DGT_REQUIRE(lam[c] > 0 && mu[c] > 0 && rho[c] > 0, DGT_EINVAL, "material must be positive");
         auto s = std::make_unique<dgt_solver>();
         s->mesh = &M;
+        s->mesh_handle = m;
         s->p = *p;
         s->st = (hipStream_t)stream;
         s->K = p->degree;
@@ -866,8 +882,41 @@ dgt_status dgt_solver_create(const dgt_mesh *m, const double *lam, const double 
         build_loops(s.get());
         DGT_HIP(hipEventCreate(&s->ev0));
         DGT_HIP(hipEventCreate(&s->ev1));
-        *out = s.release();
+        return s;
+}
+
+}  // namespace dgt
+
+extern "C" {
+
+dgt_status dgt_solver_create(const dgt_mesh *m, const double *lam, const double *mu, const double *rho,
+                             const dgt_solver_params *p, void *stream, dgt_solver **out) {
+    return guard([&] {
+        DGT_REQUIRE(m && p && out, DGT_EINVAL, "NULL argument");
+        *out = nullptr;
+        DGT_REQUIRE(p->dt > 0 && std::isfinite(p->dt), DGT_EINVAL, "dt must be positive");
+        *out = new_solver(m, lam, mu, rho, p, stream).release();
     });
+}
+
+// The lowest-id cell containing (x, y) (with a 1e-12 tolerance in reference
+// coordinates) and the point's reference coordinates; -1 when none does.
+static int64_t locate_point(const dgt_solver *s, double x, double y, double &rs, double &ss) {
+    const Mesh &M = *s->mesh;
+    for (int64_t c = 0; c < M.nc; ++c) {
+        const double *p0 = &M.xy[2 * M.c2v[3 * c]], *p1 = &M.xy[2 * M.c2v[3 * c + 1]],
+                     *p2 = &M.xy[2 * M.c2v[3 * c + 2]];
+        const double xr = p1[0] - p0[0], xs = p2[0] - p0[0], yr = p1[1] - p0[1], ys = p2[1] - p0[1];
+        const double det = xr * ys - xs * yr;
+        const double r = (ys * (x - p0[0]) - xs * (y - p0[1])) / det;
+        const double sv = (-yr * (x - p0[0]) + xr * (y - p0[1])) / det;
+        if (r >= -1e-12 && sv >= -1e-12 && 1.0 - r - sv >= -1e-12) {
+            rs = r;
+            ss = sv;
+            return c;
+        }
+    }
+    return -1;
 }
 
 // Point sources of every shot: the lowest-id cell containing (x, y) and the vector
@@ -881,21 +930,8 @@ static void set_sources(dgt_solver *s, const double *xy, double f0, double t0, d
     for (int q = 0; q < s->nshots; ++q) {
         const double x = xy[2 * q], y = xy[2 * q + 1];
         DGT_REQUIRE(std::isfinite(x) && std::isfinite(y), DGT_EINVAL, "source position is not finite");
-        int64_t cell = -1;
         double rs = 0, ss = 0;
-        for (int64_t c = 0; c < M.nc && cell < 0; ++c) {
-            const double *p0 = &M.xy[2 * M.c2v[3 * c]], *p1 = &M.xy[2 * M.c2v[3 * c + 1]],
-                         *p2 = &M.xy[2 * M.c2v[3 * c + 2]];
-            const double xr = p1[0] - p0[0], xs = p2[0] - p0[0], yr = p1[1] - p0[1], ys = p2[1] - p0[1];
-            const double det = xr * ys - xs * yr;
-            const double r = (ys * (x - p0[0]) - xs * (y - p0[1])) / det;
-            const double sv = (-yr * (x - p0[0]) + xr * (y - p0[1])) / det;
-            if (r >= -1e-12 && sv >= -1e-12 && 1.0 - r - sv >= -1e-12) {
-                cell = c;
-                rs = r;
-                ss = sv;
-            }
-        }
+        const int64_t cell = locate_point(s, x, y, rs, ss);
         DGT_REQUIRE(cell >= 0, DGT_EINVAL, "source outside the mesh");
         std::vector<double> phi(np);
         s->E.phi(rs, ss, phi.data());
@@ -955,6 +991,11 @@ static void prepare_tiled(dgt_solver *s) {
 
 static void solver_inspect_once(dgt_solver *s, const dgt_inspect_params *p, int cap) {
     hipStream_t st = s->st;
+    s->inspected = false;
+    s->last_ip = *p;
+    s->last_splits.assign(p->splits, p->splits + p->nsplits);
+    s->last_ip.splits = nullptr;
+    s->last_cap = cap;
     delete s->sched;
     s->sched = nullptr;
     s->plan.clear();
@@ -977,6 +1018,7 @@ static void solver_inspect_once(dgt_solver *s, const dgt_inspect_params *p, int 
     try {
         build_plan(s);
         s->plan_status = DGT_OK;
+        s->inspected = true;
     } catch (const Error &e) {
         if (e.st != DGT_EUNSUPPORTED) throw;
         s->plan.clear();
@@ -1262,3 +1304,5 @@ dgt_status dgt_solver_info(const dgt_solver *s, int64_t *np, int64_t *bytes_per_
 void dgt_solver_destroy(dgt_solver *s) { delete s; }
 
 }  // extern "C"
+
+#include "fwi_impl.h"

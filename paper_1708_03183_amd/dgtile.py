@@ -31,6 +31,11 @@ class _AutotuneParams(C.Structure):
                 ("prune", C.c_double)]
 
 
+class _FwiParams(C.Structure):
+    _fields_ = [("nrec", C.c_int32), ("rec_xy", C.c_void_p), ("nsteps", C.c_int64), ("nsnap", C.c_int32),
+                ("mode", C.c_int32)]
+
+
 class _AutotuneResult(C.Structure):
     _fields_ = [("tile_size", C.c_int32), ("schedule", C.c_int32), ("ms_per_step", C.c_double),
                 ("timed", C.c_int32), ("skipped", C.c_int32)]
@@ -83,6 +88,8 @@ _SIGS = {
     "dgt_set_source": [_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double],
     "dgt_solver_set_shots": [_p, C.c_int32, _p, C.c_double, C.c_double, C.c_double],
     "dgt_solver_autotune": [_p, _p, _p],
+    "dgt_fwi_forward": [_p, _p, _p],
+    "dgt_fwi_gradient": [_p, _p, _p, _p, _p, _p, _p],
     "dgt_state_upload": [_p, _p, _p],
     "dgt_state_download": [_p, _p, _p],
     "dgt_step": [_p, C.c_int64, C.c_int32, C.c_double],
@@ -331,6 +338,33 @@ class Solver:
         _check(lib().dgt_solver_autotune(self.h, C.byref(p), C.byref(r)))
         return dict(tile_size=r.tile_size, schedule=r.schedule, ms_per_step=r.ms_per_step, timed=r.timed,
                     skipped=r.skipped)
+
+    def _fwi_params(self, rec_xy, nsteps, nsnap, mode):
+        xy = np.ascontiguousarray(rec_xy, np.float64).reshape(-1)
+        assert xy.size >= 2 and xy.size % 2 == 0
+        return _FwiParams(xy.size // 2, _np_ptr(xy), int(nsteps), int(nsnap), int(mode)), xy
+
+    def fwi_forward(self, rec_xy, nsteps: int, mode: int = 1):
+        """Receiver traces [nshots, nsteps, nrec, 2] (FP64, on the GPU) of a run from rest."""
+        import torch
+        p, keep = self._fwi_params(rec_xy, nsteps, 1, mode)
+        out = torch.empty((self.nshots, int(nsteps), p.nrec, 2), dtype=torch.float64, device="cuda")
+        _check(lib().dgt_fwi_forward(self.h, C.byref(p), C.c_void_p(out.data_ptr())))
+        return out
+
+    def fwi_gradient(self, rec_xy, nsteps: int, observed, nsnap: int = 32, mode: int = 1):
+        """Misfit 1/2 sum |r - d|^2 and its gradient w.r.t. per-cell lambda, mu, rho
+        (FP64 tensors [nc] on the GPU, mesh numbering)."""
+        import torch
+        p, keep = self._fwi_params(rec_xy, nsteps, nsnap, mode)
+        assert observed.dtype == torch.float64 and observed.is_cuda and observed.is_contiguous()
+        assert tuple(observed.shape) == (self.nshots, int(nsteps), p.nrec, 2)
+        g = torch.zeros((3, self.mesh.nc), dtype=torch.float64, device="cuda")
+        J = C.c_double()
+        _check(lib().dgt_fwi_gradient(self.h, C.byref(p), C.c_void_p(observed.data_ptr()), C.byref(J),
+                                      C.c_void_p(g[0].data_ptr()), C.c_void_p(g[1].data_ptr()),
+                                      C.c_void_p(g[2].data_ptr())))
+        return J.value, g[0], g[1], g[2]
 
     def schedule(self) -> Schedule:
         h = C.c_void_p()

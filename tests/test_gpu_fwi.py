@@ -1,0 +1,151 @@
+"""GPU: full-waveform-inversion misfit and gradient (dgt_fwi_forward / dgt_fwi_gradient).
+
+The library's receiver traces, misfit and per-cell gradient (lambda, mu, rho)
+match the FP64 oracle's traces, misfit and discrete-adjoint gradient (itself
+pinned to finite differences on the CPU), for both time orders, untiled and tiled
+reversal, both schedules, several checkpoint counts and batched shots.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1708_03183_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SHOTS = np.array([[0.3, 0.6], [0.7, 0.4]])
+RECS = np.array([[0.2, 0.9], [0.5, 0.95], [0.8, 0.7], [0.45, 0.1]])
+
+
+@pytest.fixture(scope="module")
+def D():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1708_03183_amd import dgtile
+    dgtile.lib()
+    return dgtile
+
+
+def _case(D, n, k, order, prec=0, per=0, nsteps=14, shots=SHOTS):
+    m = I.square_mesh(n, jitter=0.2, renumber_seed=3, periodic=per)
+    lam, mu, rho = I.layered_material(m)
+    om = O.OMesh.from_mesh(m)
+    dt = O.cfl_dt(om, k, lam, mu, rho)
+    free = 0x0 if per else 0xF
+
+    def mk(l, u, r, d=dt):
+        return O.ODG(om, k, l, u, r, flux=0, order=order, dt=d, free_sides=free)
+
+    obs = O.fwi_traces(mk(lam * 1.1, mu * 0.95, rho * 1.05), RECS, shots, nsteps, f0=8.0, t0=0.05)
+    J, g = O.fwi_gradient_adjoint(mk(lam, mu, rho), mk(lam, mu, rho, -dt), order, RECS, shots, nsteps, obs,
+                                  f0=8.0, t0=0.05)
+    gm = D.Mesh.from_mesh(m)
+
+    def solver(nshots=len(shots), xy=shots):
+        s = D.Solver(gm, lam, mu, rho, degree=k, flux=0, time_order=order, precision=prec, free_sides=free, dt=dt)
+        s.set_shots(nshots, np.asarray(xy).reshape(-1, 2), 8.0, 0.05, 1.0)
+        return s
+
+    return dict(m=m, mk=mk, obs=obs, J=J, g=g, solver=solver, nsteps=nsteps, lam=lam, mu=mu, rho=rho)
+
+
+def _rel(a, b):
+    return float(np.sqrt(((a - b) ** 2).sum()) / np.sqrt((b ** 2).sum()))
+
+
+FWI_CASES = [
+    # n, k, order, prec, periodic, mode, schedule, ts, splits, nsnap
+    (6, 1, 2, 0, 0, 0, 0, 0, (), 3),
+    (6, 1, 4, 0, 0, 1, 0, 10, (13,), 2),
+    (6, 2, 4, 0, 0, 1, 1, 10, (13,), 4),
+    (6, 2, 2, 0, 3, 1, 1, 12, (), 5),
+    (5, 3, 4, 0, 0, 1, 0, 8, (4, 8, 12, 13, 17, 21, 25), 3),
+    (6, 2, 4, 1, 0, 1, 1, 10, (13,), 4),
+]
+
+
+@pytest.mark.parametrize("n,k,order,prec,per,mode,schedule,ts,splits,nsnap", FWI_CASES)
+def test_fwi_gradient_matches_oracle_adjoint(D, n, k, order, prec, per, mode, schedule, ts, splits, nsnap):
+    c = _case(D, n, k, order, prec, per)
+    s = c["solver"]()
+    if mode == 1:
+        s.inspect(ts, partition=1, splits=splits)
+        s.set_schedule(schedule)
+    tr = s.fwi_forward(RECS, c["nsteps"], mode=mode)
+    own = O.fwi_traces(c["mk"](c["lam"], c["mu"], c["rho"]), RECS, SHOTS, c["nsteps"], f0=8.0, t0=0.05)
+    err_tr = _rel(tr.cpu().numpy(), own)
+    obs = torch.from_numpy(c["obs"]).cuda().contiguous()
+    J, gl, gm, gr = s.fwi_gradient(RECS, c["nsteps"], obs, nsnap=nsnap, mode=mode)
+    g = np.stack([x.cpu().numpy() for x in (gl, gm, gr)])
+    err_J = abs(J - c["J"]) / c["J"]
+    err_g = _rel(g, c["g"])
+    print(f"FWI n={n} k={k} order={order} {'fp32' if prec else 'fp64'} periodic={per} mode={mode} "
+          f"schedule={schedule} nsnap={nsnap}: traces {err_tr:.2e}, misfit {err_J:.2e}, gradient {err_g:.2e} "
+          f"(rel L2 vs the FP64 oracle)")
+    tol = 1e-4 if prec else 1e-10
+    assert err_tr <= (1e-5 if prec else 1e-12)
+    assert err_J <= tol and err_g <= tol
+
+
+def test_fwi_gradient_independent_of_checkpoints_and_shot_batching(D):
+    c = _case(D, 6, 2, 4)
+    obs = torch.from_numpy(c["obs"]).cuda().contiguous()
+    grads = []
+    for nsnap in (1, 3, c["nsteps"]):
+        s = c["solver"]()
+        s.inspect(10, partition=1, splits=(13,))
+        s.set_schedule(1)
+        J, *g = s.fwi_gradient(RECS, c["nsteps"], obs, nsnap=nsnap, mode=1)
+        grads.append((J, torch.stack(g)))
+    for J, g in grads[1:]:  # the replays recompute the forward states bit for bit
+        assert J == grads[0][0] and torch.equal(g, grads[0][1])
+    # two shots in one batch = the sum of the two one-shot gradients
+    parts = []
+    for q in range(2):
+        s = c["solver"](1, SHOTS[q])
+        s.inspect(10, partition=1, splits=(13,))
+        J, *g = s.fwi_gradient(RECS, c["nsteps"], obs[q:q + 1].contiguous(), nsnap=3, mode=1)
+        parts.append((J, torch.stack(g)))
+    Jsum = parts[0][0] + parts[1][0]
+    gsum = parts[0][1] + parts[1][1]
+    assert abs(grads[0][0] - Jsum) <= 1e-13 * Jsum
+    assert float((grads[0][1] - gsum).norm() / gsum.norm()) <= 1e-12
+
+
+def test_fwi_autograd_function(D):
+    from paper_1708_03183_amd import fwi as F
+    c = _case(D, 6, 1, 4)
+    setup = F.FwiSetup(mesh=D.Mesh.from_mesh(c["m"]), degree=1, dt=c["mk"](c["lam"], c["mu"], c["rho"]).dt,
+                       shots_xy=SHOTS, rec_xy=RECS, nsteps=c["nsteps"],
+                       observed=torch.from_numpy(c["obs"]).cuda().contiguous(), nsnap=4, mode=1, tile_size=10,
+                       splits=(13,), f0=8.0, t0=0.05)
+    lam, mu, rho = [torch.tensor(a, dtype=torch.float64, requires_grad=True) for a in (c["lam"], c["mu"], c["rho"])]
+    J = F.misfit(lam, mu, rho, setup)
+    J.backward()
+    g = np.stack([t.grad.numpy() for t in (lam, mu, rho)])
+    assert abs(J.detach().item() - c["J"]) <= 1e-10 * c["J"]
+    assert _rel(g, c["g"]) <= 1e-10
+
+
+def test_fwi_errors(D):
+    c = _case(D, 5, 1, 2, nsteps=4)
+    obs = torch.from_numpy(c["obs"]).cuda().contiguous()
+    s = c["solver"]()
+    with pytest.raises(D.DgtError) as e:  # tiled mode needs an inspection
+        s.fwi_gradient(RECS, 4, obs, mode=1)
+    assert e.value.status == D.DGT_ESTATE
+    with pytest.raises(D.DgtError) as e:
+        s.fwi_gradient(RECS, 4, obs, nsnap=0, mode=0)
+    assert e.value.status == D.DGT_EINVAL
+    with pytest.raises(D.DgtError) as e:
+        s.fwi_gradient(np.array([[0.5, 2.0]] * 4), 4, obs, mode=0)
+    assert e.value.status == D.DGT_EINVAL
+    m = c["m"]
+    gm = D.Mesh.from_mesh(m)
+    for flux, free in ((1, 0xF), (0, 0x8)):  # upwind flux; absorbing sides
+        u = D.Solver(gm, c["lam"], c["mu"], c["rho"], degree=1, flux=flux, time_order=2, free_sides=free, dt=1e-3)
+        u.set_shots(2, SHOTS)
+        with pytest.raises(D.DgtError) as e:
+            u.fwi_gradient(RECS, 4, obs, mode=0)
+        assert e.value.status == D.DGT_EUNSUPPORTED
