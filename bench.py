@@ -47,9 +47,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-untiled", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
-    ap.add_argument("--workload", choices=["single", "batched"], default="single",
+    ap.add_argument("--workload", choices=["single", "batched", "fwi"], default="single",
                     help="batched: 64 Ricker shots on 6 uneven meshes (P2 FP32), the batched form against "
-                         "the same shots run one at a time")
+                         "the same shots run one at a time; fwi: misfit gradient of 16 shots on a 256x256 "
+                         "mesh (P2, FP32 state, FP64 gradient)")
+    ap.add_argument("--fwi-steps", type=int, default=2000)
+    ap.add_argument("--fwi-snapshots", type=int, default=32)
     ap.add_argument("--shots", type=int, default=64)
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched workload: use the fixed P2 FP32 tile size and schedule instead of the autotuner")
@@ -279,6 +282,104 @@ def batched(a):
     print(json.dumps(out))
 
 
+def fwi(a):
+    """Full-waveform-inversion gradient: 256x256 jittered renumbered mesh (131,072
+    cells), DG P2, 16 Ricker shots at seeded positions, 128 velocity receivers along
+    the top edge, observed data from the 3-layer true model, gradient at a
+    homogeneous starting model (the true model's means), central flux and free
+    surfaces (the discretisation whose adjoint is the reversed chain), order-4
+    leapfrog, FP32 state, FP64 gradient, 32 checkpoints, tiled executor (tile size and
+    schedule by the autotuner).  Reports the wall time of one gradient, of one
+    forward run of the same shots, and the FP32 gradient's difference from an FP64
+    gradient of the first shot alone."""
+    import numpy as np
+    import torch
+
+    from paper_1708_03183_amd import dgtile as D
+    from paper_1708_03183_amd import inputs as I
+
+    k, n, nshots, nrec = 2, 256, 16, 128
+    m = I.square_mesh(n, jitter=0.2, jitter_seed=30, renumber_seed=31)
+    lam_t, mu_t, rho_t = I.layered_material(m)
+    lam0, mu0, rho0 = [np.full(m.nc, float(x.mean())) for x in (lam_t, mu_t, rho_t)]
+    dt = min(cfl_dt(m, lam_t, mu_t, rho_t, k), cfl_dt(m, lam0, mu0, rho0, k))
+    rng = np.random.default_rng(16)
+    shots = rng.uniform(0.1, 0.9, size=(nshots, 2))
+    recs = np.stack([(np.arange(nrec) + 0.5) / nrec, np.ones(nrec)], axis=1)
+    gm = D.Mesh.from_mesh(m)
+    npk = (k + 1) * (k + 2) // 2
+
+    def make(lam, mu, rho, prec, ns=nshots, tune=True):
+        s = D.Solver(gm, lam, mu, rho, degree=k, flux=0, time_order=4, precision=prec, free_sides=0xF, dt=dt)
+        s.set_shots(ns, shots[:ns])
+        if tune:
+            r = s.autotune((64, 128, 256, 512), splits=(13,), partition=1, trial_steps=3)
+        else:
+            s.inspect(128, partition=1, splits=(13,))
+            r = None
+        return s, r
+
+    nsteps, nsnap = a.fwi_steps, a.fwi_snapshots
+    true, _ = make(lam_t, mu_t, rho_t, 1, tune=False)
+    obs = true.fwi_forward(recs, nsteps, mode=1)
+    torch.cuda.synchronize()
+    del true
+    ti = time.time()
+    sol, tuned = make(lam0, mu0, rho0, 1)
+    torch.cuda.synchronize()
+    t_tune = time.time() - ti
+    t = time.perf_counter()
+    sol.fwi_forward(recs, nsteps, mode=1)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t
+    t = time.perf_counter()
+    J, gl, gm_, gr = sol.fwi_gradient(recs, nsteps, obs, nsnap=nsnap, mode=1)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t
+    gnorm = float(torch.sqrt((gl ** 2).sum() + (gm_ ** 2).sum() + (gr ** 2).sum()))
+
+    # FP32 against FP64 on one shot over all steps (the waves reach the receivers late)
+    ws, wq = nsteps, 1
+    err = None
+    if not a.no_cpu_baseline:
+        g32, g64 = [], []
+        for prec, out in ((1, g32), (0, g64)):
+            s_, _ = make(lam0, mu0, rho0, prec, wq, tune=False)
+            o = obs[:wq].contiguous()
+            _, *g = s_.fwi_gradient(recs, ws, o, nsnap=8, mode=1)
+            out.append(torch.stack(g))
+            del s_
+        err = float((g32[0] - g64[0]).norm() / g64[0].norm())
+
+    out = {
+        "metric": "FWI gradient time, 1 MI355X",
+        "value": t_grad,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": nsteps,
+        "warmup": 0,
+        "ms_per_step": 1e3 * t_grad / nsteps,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 state, f64 gradient",
+        "data": "synthetic",
+        "config": {"workload": f"fwi256_p2: {n}x{n} jittered renumbered triangulation, {m.nc} cells, DG P2, "
+                               f"{nshots} shots, {nrec} receivers at y = 1, 3-layer true model, homogeneous start, "
+                               f"central flux, free surfaces, order-4 leapfrog",
+                   "cells": m.nc, "shots": nshots, "receivers": nrec, "snapshots": nsnap,
+                   "dofs_per_step_all_shots": 5 * npk * m.nc * nshots, "tuned": tuned},
+        "forward_s": t_fwd,
+        "gradient_over_forward": t_grad / t_fwd,
+        "misfit": J,
+        "gradient_norm": gnorm,
+        "err_fp32_vs_fp64_gradient_rel_l2": err,
+        "err_window": f"{ws} steps, shot 0 alone",
+        "tune_s": t_tune,
+    }
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -287,6 +388,9 @@ def main():
         sys.exit(2)
     if a.workload == "batched":
         batched(a)
+        return
+    if a.workload == "fwi":
+        fwi(a)
         return
     import numpy as np
     import torch

@@ -21,14 +21,18 @@
 namespace dgt {
 
 // ------------------------------------------------------------ untiled kernels (one per loop)
+// blockIdx.y selects a shot: every field and facet buffer is offset by its shot stride
 
 // volume term of the velocity (VEL) or stress operator: out = scale * vol(in)
 template <int K, typename T, bool VEL>
 __global__ __launch_bounds__(256) void k_vol(const T *__restrict__ in, T *__restrict__ out,
-                                             const T *__restrict__ geo, int64_t nc, T scale) {
+                                             const T *__restrict__ geo, int64_t nc, T scale, int64_t ish,
+                                             int64_t osh) {
     constexpr int NP = np_of(K);
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nc * NP) return;
+    in += blockIdx.y * ish;
+    out += blockIdx.y * osh;
     const int64_t c = t / NP;  // nodes of one cell are adjacent lanes: its inputs are read once
     const int i = (int)(t - c * NP);
     const auto &Rf = R<K, T>();
@@ -70,10 +74,14 @@ template <int K, typename T, bool VEL, bool UPW, bool PEN>
 __global__ __launch_bounds__(256) void k_flux_int(const T *__restrict__ in, const T *__restrict__ pin,
                                                   const int32_t *__restrict__ f2c, const uint8_t *__restrict__ f2l,
                                                   const T *__restrict__ geo, int64_t nc, int64_t nf, T scale,
-                                                  T pscale, T *__restrict__ G) {
+                                                  T pscale, T *__restrict__ G, int64_t ish, int64_t psh,
+                                                  int64_t gsh) {
     constexpr int NP = np_of(K), NFP = K + 1, NCO = VEL ? 2 : 3;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nf * NFP) return;
+    in += blockIdx.y * ish;
+    if (PEN) pin += blockIdx.y * psh;
+    G += blockIdx.y * gsh;
     const int m = (int)(t / nf);
     const int64_t f = t - (int64_t)m * nf;
     const auto &Rf = R<K, T>();
@@ -133,10 +141,14 @@ template <int K, typename T, bool VEL, bool UPW, bool PEN>
 __global__ __launch_bounds__(256) void k_flux_ext(const T *__restrict__ in, const T *__restrict__ pin,
                                                   const int32_t *__restrict__ b2c, const uint8_t *__restrict__ b2l,
                                                   const T *__restrict__ geo, int64_t nc, int64_t nb, T scale,
-                                                  T pscale, T *__restrict__ G) {
+                                                  T pscale, T *__restrict__ G, int64_t ish, int64_t psh,
+                                                  int64_t gsh) {
     constexpr int NP = np_of(K), NFP = K + 1, NCO = VEL ? 2 : 3;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nb * NFP) return;
+    in += blockIdx.y * ish;
+    if (PEN) pin += blockIdx.y * psh;
+    G += blockIdx.y * gsh;
     const int m = (int)(t / nb);
     const int64_t b = t - (int64_t)m * nb;
     const auto &Rf = R<K, T>();
@@ -177,10 +189,13 @@ __global__ __launch_bounds__(256) void k_flux_ext(const T *__restrict__ in, cons
 template <int K, typename T, bool VEL>
 __global__ __launch_bounds__(256) void k_lift(T *__restrict__ out, const int32_t *__restrict__ c2f,
                                               const T *__restrict__ G, const T *__restrict__ Gx, int64_t nc,
-                                              int64_t nf, int64_t nb) {
+                                              int64_t nf, int64_t nb, int64_t osh, int64_t gsh, int64_t gxsh) {
     constexpr int NP = np_of(K), NFP = K + 1, NCO = VEL ? 2 : 3;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nc * NP) return;
+    out += blockIdx.y * osh;
+    G += blockIdx.y * gsh;
+    Gx += blockIdx.y * gxsh;
     const int64_t c = t / NP;
     const int i = (int)(t - c * NP);
     const auto &Rf = R<K, T>();

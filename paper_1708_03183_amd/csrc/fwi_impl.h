@@ -275,20 +275,19 @@ struct FwiRun {
         const double dt = f->p.dt, c3 = o4 ? dt * dt * dt / 24.0 : 0.0;
         int64_t launches = 0;
         const T *v0 = (const T *)f->fld[F_V].p, *s0 = (const T *)f->fld[F_S].p;
-        for (int q = 0; q < S; ++q) {
-            const int64_t ov = q * vsh, os = q * ssh;
-            apply_op<K, T>(f, true, s0 + os, U.p + ov, 1.0, nullptr, 0.0, launches);
-            if (o4) {
-                apply_op<K, T>(f, false, U.p + ov, Xp.p + os, 1.0, nullptr, 0.0, launches);
-                apply_op<K, T>(f, true, Xp.p + os, Zs.p + ov, c3, nullptr, 0.0, launches);
-            }
-            k_fwi_vnext<T><<<blocks_for(vsh, 256), 256, 0, st>>>(V1.p + ov, v0 + ov, U.p + ov,
-                                                                o4 ? Zs.p + ov : nullptr, vsh, (T)dt);
-            apply_op<K, T>(f, false, V1.p + ov, X1.p + os, 1.0, nullptr, 0.0, launches);
-            if (o4) {
-                apply_op<K, T>(f, true, X1.p + os, Y.p + ov, 1.0, nullptr, 0.0, launches);
-                apply_op<K, T>(f, false, Y.p + ov, V2s.p + os, c3, nullptr, 0.0, launches);
-            }
+        // every operator application covers all shots in one launch per kernel
+        auto vop = [&](const T *in, T *out, double sc) { apply_op<K, T>(f, true, in, out, sc, nullptr, 0.0, launches, S, ssh, vsh); };
+        auto sop = [&](const T *in, T *out, double sc) { apply_op<K, T>(f, false, in, out, sc, nullptr, 0.0, launches, S, vsh, ssh); };
+        vop(s0, U.p, 1.0);
+        if (o4) {
+            sop(U.p, Xp.p, 1.0);
+            vop(Xp.p, Zs.p, c3);
+        }
+        k_fwi_vnext<T><<<blocks_for(vsh * S, 256), 256, 0, st>>>(V1.p, v0, U.p, o4 ? Zs.p : nullptr, vsh * S, (T)dt);
+        sop(V1.p, X1.p, 1.0);
+        if (o4) {
+            vop(X1.p, Y.p, 1.0);
+            sop(Y.p, V2s.p, c3);
         }
         // alpha_s before the reversed step, then the step itself
         DGT_HIP(hipMemcpyAsync(As.p, a->fld[F_S].p, (size_t)ssh * S * sizeof(T), hipMemcpyDeviceToDevice, st));
@@ -296,13 +295,10 @@ struct FwiRun {
         ++reversed;
         const T *av = (const T *)a->fld[F_V].p;
         if (o4) {
-            for (int q = 0; q < S; ++q) {
-                const int64_t ov = q * vsh, os = q * ssh;
-                apply_op<K, T>(f, false, av + ov, tS.p + os, 1.0, nullptr, 0.0, launches);
-                apply_op<K, T>(f, true, tS.p + os, W.p + ov, 1.0, nullptr, 0.0, launches);
-                apply_op<K, T>(f, true, As.p + os, tV.p + ov, 1.0, nullptr, 0.0, launches);
-                apply_op<K, T>(f, false, tV.p + ov, Wp.p + os, 1.0, nullptr, 0.0, launches);
-            }
+            sop(av, tS.p, 1.0);
+            vop(tS.p, W.p, 1.0);
+            vop(As.p, tV.p, 1.0);
+            sop(tV.p, Wp.p, 1.0);
         }
         k_fwi_grad<K, T><<<blocks_for(nc, 256), 256, 0, st>>>(
             nc, S, (const T *)f->geo.p, av, U.p, o4 ? Zs.p : nullptr, o4 ? W.p : nullptr, o4 ? tV.p : nullptr,

@@ -608,29 +608,36 @@ static void build_plan(dgt_solver *s) {
 
 // ------------------------------------------------------------ steps
 
-// One operator application of the untiled chain (volume, facet and lift kernels):
+// One operator application of the untiled chain (volume, facet and lift kernels)
+// for `shots` fields at once (strides ish, osh, psh between them):
 // fout = scale * op(fin) (+ the upwind penalty of fpen scaled by pscale).
 template <int K, typename T>
 static void apply_op(dgt_solver *s, bool vel, const T *fin, T *fout, double scale, const T *fpen, double pscale,
-                     int64_t &launches) {
+                     int64_t &launches, int shots = 1, int64_t ish = 0, int64_t osh = 0, int64_t psh = 0) {
     hipStream_t st = s->st;
     const int64_t nc = s->nc, nf = s->nf, nb = s->nb;
     constexpr int NP = np_of(K), NFP = K + 1;
+    // facet buffers: one copy per shot
+    const int64_t gsh = (int64_t)2 * 3 * NFP * std::max<int64_t>(nf, 1), gxsh = (int64_t)3 * NFP * std::max<int64_t>(nb, 1);
+    if (s->G.n < (size_t)(gsh * shots) * sizeof(T)) s->G.alloc((size_t)(gsh * shots) * sizeof(T));
+    if (s->Gx.n < (size_t)(gxsh * shots) * sizeof(T)) s->Gx.alloc((size_t)(gxsh * shots) * sizeof(T));
     const T *geo = (const T *)s->geo.p;
     T *G = (T *)s->G.p, *Gx = (T *)s->Gx.p;
     const T sc = (T)scale, ps = (T)pscale;
-    if (vel) k_vol<K, T, true><<<blocks_for(nc * NP, 256), 256, 0, st>>>(fin, fout, geo, nc, sc);
-    else k_vol<K, T, false><<<blocks_for(nc * NP, 256), 256, 0, st>>>(fin, fout, geo, nc, sc);
+    const dim3 gc(blocks_for(nc * NP, 256), shots), gf(blocks_for(nf * NFP, 256), shots),
+        gb(blocks_for(nb * NFP, 256), shots);
+    if (vel) k_vol<K, T, true><<<gc, 256, 0, st>>>(fin, fout, geo, nc, sc, ish, osh);
+    else k_vol<K, T, false><<<gc, 256, 0, st>>>(fin, fout, geo, nc, sc, ish, osh);
     ++launches;
     auto fi = [&]<bool VEL, bool UPW, bool PEN>() {
         if (nf) {
-            k_flux_int<K, T, VEL, UPW, PEN><<<blocks_for(nf * NFP, 256), 256, 0, st>>>(
-                fin, fpen, s->ef2c.p, s->ef2l.p, geo, nc, nf, sc, ps, G);
+            k_flux_int<K, T, VEL, UPW, PEN><<<gf, 256, 0, st>>>(fin, fpen, s->ef2c.p, s->ef2l.p, geo, nc, nf, sc, ps,
+                                                                G, ish, psh, gsh);
             ++launches;
         }
         if (nb) {
-            k_flux_ext<K, T, VEL, UPW, PEN><<<blocks_for(nb * NFP, 256), 256, 0, st>>>(
-                fin, fpen, s->eb2c.p, s->eb2l.p, geo, nc, nb, sc, ps, Gx);
+            k_flux_ext<K, T, VEL, UPW, PEN><<<gb, 256, 0, st>>>(fin, fpen, s->eb2c.p, s->eb2l.p, geo, nc, nb, sc, ps,
+                                                                Gx, ish, psh, gxsh);
             ++launches;
         }
     };
@@ -638,11 +645,11 @@ static void apply_op(dgt_solver *s, bool vel, const T *fin, T *fout, double scal
     if (vel) {
         if (s->upw) { if (pn) fi.template operator()<true, true, true>(); else fi.template operator()<true, true, false>(); }
         else { if (pn) fi.template operator()<true, false, true>(); else fi.template operator()<true, false, false>(); }
-        k_lift<K, T, true><<<blocks_for(nc * NP, 256), 256, 0, st>>>(fout, s->c2f.p, G, Gx, nc, nf, nb);
+        k_lift<K, T, true><<<gc, 256, 0, st>>>(fout, s->c2f.p, G, Gx, nc, nf, nb, osh, gsh, gxsh);
     } else {
         if (s->upw) { if (pn) fi.template operator()<false, true, true>(); else fi.template operator()<false, true, false>(); }
         else { if (pn) fi.template operator()<false, false, true>(); else fi.template operator()<false, false, false>(); }
-        k_lift<K, T, false><<<blocks_for(nc * NP, 256), 256, 0, st>>>(fout, s->c2f.p, G, Gx, nc, nf, nb);
+        k_lift<K, T, false><<<gc, 256, 0, st>>>(fout, s->c2f.p, G, Gx, nc, nf, nb, osh, gsh, gxsh);
     }
     ++launches;
 }
