@@ -284,8 +284,8 @@ def batched(a):
 
 def fwi(a):
     """Full-waveform-inversion gradient: 256x256 jittered renumbered mesh (131,072
-    cells), DG P2, 16 Ricker shots at seeded positions, 128 velocity receivers along
-    the top edge, observed data from the 3-layer true model, gradient at a
+    cells), DG P2, 16 Ricker shots at seeded positions just below the top edge, 128
+    velocity receivers along the top edge, observed data from the 3-layer true model, gradient at a
     homogeneous starting model (the true model's means), central flux and free
     surfaces (the discretisation whose adjoint is the reversed chain), order-4
     leapfrog, FP32 state, FP64 gradient, 32 checkpoints, tiled executor (tile size and
@@ -303,15 +303,19 @@ def fwi(a):
     lam_t, mu_t, rho_t = I.layered_material(m)
     lam0, mu0, rho0 = [np.full(m.nc, float(x.mean())) for x in (lam_t, mu_t, rho_t)]
     dt = min(cfl_dt(m, lam_t, mu_t, rho_t, k), cfl_dt(m, lam0, mu0, rho0, k))
+    # a surface survey sized to the window: 2000 steps span 2000 dt = 0.03 time units, in
+    # which P waves (c_p = 2) travel 0.06, so the sources sit just below the receivers
+    # and the Ricker wavelet (f0 = 100, t0 = 0.012) fits three periods into the window
     rng = np.random.default_rng(16)
-    shots = rng.uniform(0.1, 0.9, size=(nshots, 2))
+    shots = np.stack([rng.uniform(0.1, 0.9, nshots), rng.uniform(0.96, 0.99, nshots)], axis=1)
     recs = np.stack([(np.arange(nrec) + 0.5) / nrec, np.ones(nrec)], axis=1)
+    f0, t0 = 100.0, 0.012
     gm = D.Mesh.from_mesh(m)
     npk = (k + 1) * (k + 2) // 2
 
     def make(lam, mu, rho, prec, ns=nshots, tune=True):
         s = D.Solver(gm, lam, mu, rho, degree=k, flux=0, time_order=4, precision=prec, free_sides=0xF, dt=dt)
-        s.set_shots(ns, shots[:ns])
+        s.set_shots(ns, shots[:ns], f0, t0, 1.0)
         if tune:
             r = s.autotune((64, 128, 256, 512), splits=(13,), partition=1, trial_steps=3)
         else:
@@ -365,7 +369,8 @@ def fwi(a):
         "dtype": "f32 state, f64 gradient",
         "data": "synthetic",
         "config": {"workload": f"fwi256_p2: {n}x{n} jittered renumbered triangulation, {m.nc} cells, DG P2, "
-                               f"{nshots} shots, {nrec} receivers at y = 1, 3-layer true model, homogeneous start, "
+                               f"{nshots} shots at y in [0.96, 0.99] (Ricker f0 = {f0}, t0 = {t0}), {nrec} receivers at y = 1, "
+                               f"3-layer true model, homogeneous start, "
                                f"central flux, free surfaces, order-4 leapfrog",
                    "cells": m.nc, "shots": nshots, "receivers": nrec, "snapshots": nsnap,
                    "dofs_per_step_all_shots": 5 * npk * m.nc * nshots, "tuned": tuned},

@@ -90,15 +90,11 @@ __global__ __launch_bounds__(256) void k_fwi_vnext(T *__restrict__ v1, const T *
     v1[t] = v0[t] + (dt * U[t] + (Z ? Z[t] : T(0)));
 }
 
-// per-cell gradient terms of one step, summed over the shots in order (FP64).
+// per-cell gradient terms of one step and one shot (blockIdx.y), in FP64, stored per
+// shot in part[shot][3][nc]; k_fwi_grad_sum adds the shots in order (deterministic).
 // 2-component fields (stride vsh per shot): av, U, Zs = c A B U, W = A B av,
 // tV = A as, Y = A X1; 3-component (stride ssh): as, X1, V2s = c B A X1,
 // Wp = B A as, tS = B av, Xp = B U.  The order-4 fields are null at order 2.
-template <int K, typename T>
-__device__ __forceinline__ double fwi_m(const T *a, const T *b, int64_t o, int64_t nc, int c, int i, int j) {
-    return (double)a[o + (int64_t)(c * np_of(K) + i) * nc] * (double)b[o + (int64_t)(c * np_of(K) + j) * nc];
-}
-
 template <int K, typename T>
 __global__ __launch_bounds__(256) void k_fwi_grad(int64_t nc, int nshots, const T *__restrict__ geo,
                                                   const T *__restrict__ av, const T *__restrict__ U,
@@ -107,65 +103,108 @@ __global__ __launch_bounds__(256) void k_fwi_grad(int64_t nc, int nshots, const 
                                                   const T *__restrict__ as, const T *__restrict__ X1,
                                                   const T *__restrict__ V2s, const T *__restrict__ Wp,
                                                   const T *__restrict__ tS, const T *__restrict__ Xp, int64_t ssh,
-                                                  double dt, double c3, double *__restrict__ g) {
+                                                  double dt, double c3, double *__restrict__ part) {
     constexpr int NP = np_of(K);
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= nc) return;
+    const int q = blockIdx.y;
     const auto &Rf = R<K, T>();
     const double lam = geo[G_LAM * nc + x], mu = geo[G_MU * nc + x], det = geo[G_DET * nc + x];
     // C^-1 on (xx, yy, xy): [[cA, cB, 0], [cB, cA, 0], [0, 0, 1/mu]]
     const double cA = (lam + 2 * mu) / (4 * mu * (lam + mu)), cB = -lam / (4 * mu * (lam + mu)), cC = 1.0 / mu;
     const bool o4 = W != nullptr;
+    auto ld = [&](const T *f, int64_t o, int c, int i) { return (double)f[o + (int64_t)(c * NP + i) * nc]; };
     double gr = 0.0, gl = 0.0, gm = 0.0;
-    // b . (M^ x S_lam) e and b . (M^ x S_mu) e for 3-component nodal vectors already through C^-1
-    auto lm = [&](const double (&b)[3], const double (&e)[3], double M, double w) {
-        gl += w * M * (b[0] + b[1]) * (e[0] + e[1]);
-        gm += w * M * (2 * (b[0] * e[0] + b[1] * e[1]) + b[2] * e[2]);
-    };
-    auto through_cinv = [&](const T *f, int64_t o, int i, double sc, const T *f2, double sc2, double (&r)[3]) {
-        double p[3];
-        for (int c = 0; c < 3; ++c) {
-            p[c] = sc * (double)f[o + (int64_t)(c * NP + i) * nc];
-            if (f2) p[c] += sc2 * (double)f2[o + (int64_t)(c * NP + i) * nc];
-        }
-        r[0] = cA * p[0] + cB * p[1];
-        r[1] = cB * p[0] + cA * p[1];
-        r[2] = cC * p[2];
-    };
-    for (int q = 0; q < nshots; ++q) {
+    {
         const int64_t ov = q * vsh + x, os = q * ssh + x;
+        // left factors per node, read once: velocity (a = dt av + c W, av, -c A as) and
+        // stress through C^-1 (dt as + c W', as, -c B av), the last two at order 4 only
+        T la[2][NP], lb[2][NP], lc[2][NP], lp[3][NP], lg[3][NP], ls[3][NP];
+#pragma unroll
         for (int i = 0; i < NP; ++i) {
-            double bP[3], bA[3], bS[3];
-            through_cinv(as, os, i, dt, o4 ? Wp : nullptr, c3, bP);  // C^-1 (dt as + c W')
-            if (o4) {
-                through_cinv(as, os, i, 1.0, nullptr, 0.0, bA);       // C^-1 as
-                through_cinv(tS, os, i, 1.0, nullptr, 0.0, bS);       // C^-1 B av
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                la[c][i] = (T)(dt * ld(av, ov, c, i) + (o4 ? c3 * ld(W, ov, c, i) : 0.0));
+                lb[c][i] = o4 ? (T)ld(av, ov, c, i) : T(0);
+                lc[c][i] = o4 ? (T)(-c3 * ld(tV, ov, c, i)) : T(0);
             }
-            for (int j = 0; j < NP; ++j) {
+            double p[3], h[3], t[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                p[c] = dt * ld(as, os, c, i) + (o4 ? c3 * ld(Wp, os, c, i) : 0.0);
+                h[c] = o4 ? ld(as, os, c, i) : 0.0;
+                t[c] = o4 ? -c3 * ld(tS, os, c, i) : 0.0;
+            }
+            lp[0][i] = (T)(cA * p[0] + cB * p[1]); lp[1][i] = (T)(cB * p[0] + cA * p[1]); lp[2][i] = (T)(cC * p[2]);
+            lg[0][i] = (T)(cA * h[0] + cB * h[1]); lg[1][i] = (T)(cB * h[0] + cA * h[1]); lg[2][i] = (T)(cC * h[2]);
+            ls[0][i] = (T)(cA * t[0] + cB * t[1]); ls[1][i] = (T)(cB * t[0] + cA * t[1]); ls[2][i] = (T)(cC * t[2]);
+        }
+        // right factors streamed node by node: sum_i left_i M_ij right_j
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            double mla[2] = {0, 0}, mlb[2] = {0, 0}, mlc[2] = {0, 0}, mlp[3] = {0, 0, 0}, mlg[3] = {0, 0, 0},
+                   mls[3] = {0, 0, 0};
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
                 const double M = (double)Rf.M[i * NP + j];
-                double tr = 0.0;
+#pragma unroll
                 for (int c = 0; c < 2; ++c) {
-                    double a = dt * (double)av[ov + (int64_t)(c * NP + i) * nc];
-                    if (o4) a += c3 * (double)W[ov + (int64_t)(c * NP + i) * nc];
-                    tr += a * (double)U[ov + (int64_t)(c * NP + j) * nc];
-                    if (o4) tr += fwi_m<K, T>(av, Zs, ov, nc, c, i, j) - c3 * fwi_m<K, T>(tV, Y, ov, nc, c, i, j);
+                    mla[c] += M * (double)la[c][i];
+                    if (o4) {
+                        mlb[c] += M * (double)lb[c][i];
+                        mlc[c] += M * (double)lc[c][i];
+                    }
                 }
-                gr += M * tr;
-                double e[3];
-                through_cinv(X1, os, j, 1.0, nullptr, 0.0, e);
-                lm(bP, e, M, 1.0);
-                if (o4) {
-                    through_cinv(V2s, os, j, 1.0, nullptr, 0.0, e);
-                    lm(bA, e, M, 1.0);
-                    through_cinv(Xp, os, j, 1.0, nullptr, 0.0, e);
-                    lm(bS, e, M, -c3);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    mlp[c] += M * (double)lp[c][i];
+                    if (o4) {
+                        mlg[c] += M * (double)lg[c][i];
+                        mls[c] += M * (double)ls[c][i];
+                    }
                 }
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                gr += mla[c] * ld(U, ov, c, j);
+                if (o4) gr += mlb[c] * ld(Zs, ov, c, j) + mlc[c] * ld(Y, ov, c, j);
+            }
+            // strains E = C^-1 (field): lam term (b_xx + b_yy)(e_xx + e_yy), mu term
+            // 2 (b_xx e_xx + b_yy e_yy) + b_xy e_xy
+            auto strain = [&](const T *f, double (&e)[3]) {
+                const double f0 = ld(f, os, 0, j), f1 = ld(f, os, 1, j), f2 = ld(f, os, 2, j);
+                e[0] = cA * f0 + cB * f1;
+                e[1] = cB * f0 + cA * f1;
+                e[2] = cC * f2;
+            };
+            auto acc = [&](const double (&b)[3], const double (&e)[3]) {
+                gl += (b[0] + b[1]) * (e[0] + e[1]);
+                gm += 2 * (b[0] * e[0] + b[1] * e[1]) + b[2] * e[2];
+            };
+            double e[3];
+            strain(X1, e);
+            acc(mlp, e);
+            if (o4) {
+                strain(V2s, e);
+                acc(mlg, e);
+                strain(Xp, e);
+                acc(mls, e);
             }
         }
     }
-    g[x] += det * gl;
-    g[nc + x] += det * gm;
-    g[2 * nc + x] -= det * gr;
+    double *o = part + (int64_t)q * 3 * nc;
+    o[x] = det * gl;
+    o[nc + x] = det * gm;
+    o[2 * nc + x] = -det * gr;
+}
+
+__global__ __launch_bounds__(256) void k_fwi_grad_sum(int64_t nc, int nshots, const double *__restrict__ part,
+                                                      double *__restrict__ g) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * nc) return;
+    double a = 0.0;
+    for (int q = 0; q < nshots; ++q) a += part[(int64_t)q * 3 * nc + t];
+    g[t] += a;
 }
 
 struct FwiReceivers {
@@ -239,7 +278,7 @@ struct FwiRun {
     int64_t vsh = 0, ssh = 0, advanced = 0, reversed = 0;
     std::vector<DBuf<char>> snap;
     DBuf<T> U, Xp, Zs, V1, X1, Y, V2s, W, Wp, tV, tS, As;
-    DBuf<double> res, g;
+    DBuf<double> res, g, part;
 
     void store(int slot) {
         const size_t bv = (size_t)vsh * S * sizeof(T), bs = (size_t)ssh * S * sizeof(T);
@@ -300,10 +339,11 @@ struct FwiRun {
             vop(As.p, tV.p, 1.0);
             sop(tV.p, Wp.p, 1.0);
         }
-        k_fwi_grad<K, T><<<blocks_for(nc, 256), 256, 0, st>>>(
+        k_fwi_grad<K, T><<<dim3(blocks_for(nc, 256), S), 256, 0, st>>>(
             nc, S, (const T *)f->geo.p, av, U.p, o4 ? Zs.p : nullptr, o4 ? W.p : nullptr, o4 ? tV.p : nullptr,
             o4 ? Y.p : nullptr, vsh, As.p, X1.p, o4 ? V2s.p : nullptr, o4 ? Wp.p : nullptr, o4 ? tS.p : nullptr,
-            o4 ? Xp.p : nullptr, ssh, dt, c3, g.p);
+            o4 ? Xp.p : nullptr, ssh, dt, c3, part.p);
+        k_fwi_grad_sum<<<blocks_for(3 * nc, 256), 256, 0, st>>>(nc, S, part.p, g.p);
         inject(n);
     }
     // reverse steps [l, r): u_l is in checkpoint `slot`, `free` checkpoints above it
@@ -437,6 +477,7 @@ dgt_status dgt_fwi_gradient(dgt_solver *s, const dgt_fwi_params *p, const double
             for (auto *b : {&run.Xp, &run.X1, &run.V2s, &run.Wp, &run.tS, &run.As}) b->alloc(ns);
             run.res.alloc((size_t)S * R.nrec * 2);
             run.g.alloc((size_t)3 * nc);
+            run.part.alloc((size_t)3 * nc * S);
             DGT_HIP(hipMemsetAsync(run.g.p, 0, 8 * 3 * nc, st));
             run.snap.resize(p->nsnap);
             // forward sweep from rest: misfit; the start state is the first checkpoint
