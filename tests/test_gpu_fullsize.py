@@ -1,0 +1,150 @@
+"""GPU parity at the workloads' full sizes, in the launch configurations bench.py times.
+
+The oracle cannot run a 0.5-2 M cell mesh in seconds, but one step of the chain
+only reaches a bounded neighbourhood: every operator application has one facet
+loop, so a cell's state after s order-4 steps depends only on cells at most 6 s
+facet-neighbour layers away.  For sampled cells (random ones, the source cell, the
+free-surface edge and the corners) the oracle runs the same steps on the patch of
+cells within 6 s + 1 layers (same geometry, material, state and source, cells kept
+in their mesh order so the source lands in the same cell) and the sampled cells'
+values are compared with the GPU's full-mesh run.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1708_03183_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+OPS = (4, 8, 13, 17, 21)
+
+
+@pytest.fixture(scope="module")
+def D():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1708_03183_amd import dgtile
+    dgtile.lib()
+    return dgtile
+
+
+def _cfl_dt(m, lam, mu, rho, k):
+    p = m.xy[m.c2v]
+    e = [np.hypot(*(p[:, (i + 1) % 3] - p[:, i]).T) for i in range(3)]
+    area = 0.5 * ((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1]) - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1]))
+    hmin = float(np.min(4.0 * area / (e[0] + e[1] + e[2])))
+    return 0.2 * hmin / ((2 * k + 1) * float(np.max(np.sqrt((lam + 2 * mu) / rho))))
+
+
+def _adjacency(m):
+    f2c = O.OMesh.from_mesh(m).maps()["f2c"].astype(np.int64)
+    a = np.concatenate([f2c[:, 0], f2c[:, 1]])
+    b = np.concatenate([f2c[:, 1], f2c[:, 0]])
+    order = np.argsort(a, kind="stable")
+    off = np.zeros(m.nc + 1, np.int64)
+    np.add.at(off, a + 1, 1)
+    return np.cumsum(off), b[order]
+
+
+def _patch(off, nb, c, layers):
+    seen = {int(c)}
+    front = [int(c)]
+    for _ in range(layers):
+        nxt = []
+        for x in front:
+            for y in nb[off[x]:off[x + 1]]:
+                y = int(y)
+                if y not in seen:
+                    seen.add(y)
+                    nxt.append(y)
+        front = nxt
+    return np.array(sorted(seen), np.int64)
+
+
+def _samples(m, rng, nrand, src):
+    cen = m.xy[m.c2v].mean(axis=1)
+    picks = list(rng.choice(m.nc, nrand, replace=False))
+    for target in (src, (0.5, 0.999), (0.001, 0.001), (0.999, 0.999), (0.001, 0.5)):
+        picks.append(int(np.argmin(((cen - np.asarray(target)) ** 2).sum(axis=1))))
+    return sorted(set(int(x) for x in picks))
+
+
+def _oracle_on_patch(m, cells, lam, mu, rho, k, order, dt, v, s, steps, src, t0):
+    c2v = m.c2v[cells]
+    verts, inv = np.unique(c2v.ravel(), return_inverse=True)
+    om = O.OMesh(m.xy[verts], inv.reshape(-1, 3).astype(np.int32))
+    od = O.ODG(om, k, lam[cells], mu[cells], rho[cells], flux=1, order=order, dt=dt, free_sides=0x8)
+    try:
+        od.set_source(*src)
+    except ValueError:
+        pass  # the source lies outside the patch and cannot reach its centre in `steps` steps
+    pv = np.ascontiguousarray(v[:, :, cells])
+    ps = np.ascontiguousarray(s[:, :, cells])
+    od.step(pv, ps, steps, t0=t0)
+    return pv, ps
+
+
+FULL_CASES = [
+    # name, n, k, prec, tile size, splits, schedule, steps, shots
+    ("jitter512_p2_fp64", 512, 2, 0, 128, (13,), 1, 2, 1),
+    ("jitter512_p2_fp32", 512, 2, 1, 128, (13,), 1, 2, 1),
+    ("jitter1024_p3_fp32", 1024, 3, 1, 64, OPS, 0, 1, 1),
+    ("jitter416_p2_fp32_11shots", 416, 2, 1, 256, (13,), 0, 2, 11),
+]
+
+
+@pytest.mark.parametrize("name,n,k,prec,ts,splits,schedule,steps,shots", FULL_CASES)
+def test_full_size_sampled_cells_match_oracle(D, name, n, k, prec, ts, splits, schedule, steps, shots):
+    print(f"case {name}: building the mesh", flush=True)
+    m = I.square_mesh(n, jitter=0.2, jitter_seed=1, renumber_seed=2)
+    lam, mu, rho = I.layered_material(m)
+    dt = _cfl_dt(m, lam, mu, rho, k)
+    npk = (k + 1) * (k + 2) // 2
+    rng = np.random.default_rng(7)
+    srcs = [(0.5, 0.5)] + [tuple(x) for x in rng.uniform(0.1, 0.9, size=(shots - 1, 2))]
+    # random start states (FP64 values rounded to the solver precision, used by both sides)
+    dtype = torch.float32 if prec else torch.float64
+    v = np.stack([I.random_state((2, npk, m.nc), 11 + 2 * q) for q in range(shots)])
+    s = np.stack([I.random_state((3, npk, m.nc), 12 + 2 * q) for q in range(shots)])
+    if prec:
+        v, s = v.astype(np.float32).astype(np.float64), s.astype(np.float32).astype(np.float64)
+    gm = D.Mesh.from_mesh(m)
+    g = D.Solver(gm, lam, mu, rho, degree=k, flux=1, time_order=4, precision=prec, free_sides=0x8, dt=dt)
+    if shots > 1:
+        g.set_shots(shots, np.array(srcs))
+    else:
+        g.set_source(*srcs[0])
+    g.inspect(ts, partition=1, splits=splits)
+    g.set_schedule(schedule)
+    gv = torch.from_numpy(v if shots > 1 else v[0]).to(dtype).cuda().contiguous()
+    gs = torch.from_numpy(s if shots > 1 else s[0]).to(dtype).cuda().contiguous()
+    g.upload(gv, gs)
+    t0 = 0.1
+    g.step(steps, mode=1, t0=t0)
+    g.download(gv, gs)
+    torch.cuda.synchronize()
+    rv = gv.double().cpu().numpy().reshape(shots, 2, npk, m.nc)
+    rs = gs.double().cpu().numpy().reshape(shots, 3, npk, m.nc)
+    off, nb = _adjacency(m)
+    num = den = 0.0
+    worst = 0.0
+    for q in ([0, shots - 1] if shots > 1 else [0]):
+        cells = _samples(m, rng, 16, srcs[q])
+        for c in cells:
+            patch = _patch(off, nb, c, 6 * steps + 1)
+            pv, ps = _oracle_on_patch(m, patch, lam, mu, rho, k, 4, dt, v[q], s[q], steps, srcs[q], t0)
+            j = int(np.searchsorted(patch, c))
+            dv = rv[q][:, :, c] - pv[:, :, j]
+            ds = rs[q][:, :, c] - ps[:, :, j]
+            e = float((dv ** 2).sum() + (ds ** 2).sum())
+            r = float((pv[:, :, j] ** 2).sum() + (ps[:, :, j] ** 2).sum())
+            num += e
+            den += r
+            worst = max(worst, np.sqrt(e / r))
+    err = np.sqrt(num / den)
+    print(f"{name}: {m.nc} cells, ts={ts}, splits={splits}, schedule={schedule}, {steps} steps, {shots} shot(s): "
+          f"sampled cells rel L2 err vs FP64 oracle {err:.3e} (worst cell {worst:.3e})")
+    tol = 1e-5 if prec else 1e-12
+    assert err <= tol and worst <= 10 * tol
