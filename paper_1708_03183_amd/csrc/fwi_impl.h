@@ -275,6 +275,7 @@ struct FwiRun {
     const FwiReceivers *R = nullptr;
     const double *obs = nullptr;
     int S = 1;
+    bool rec = false;  // intermediates from recorded tiled steps
     int64_t vsh = 0, ssh = 0, advanced = 0, reversed = 0;
     std::vector<DBuf<char>> snap;
     DBuf<T> U, Xp, Zs, V1, X1, Y, V2s, W, Wp, tV, tS, As;
@@ -296,15 +297,57 @@ struct FwiRun {
         advanced += n;
     }
     // residual of the receivers at the forward state held (the observation after
-    // step n - 1), injected into the adjoint velocity
-    void inject(int64_t n) {
+    // step n - 1), then its injection into the adjoint velocity
+    void sample(int64_t n) {
         if (n < 1) return;
-        hipStream_t st = f->st;
-        k_fwi_sample<K, T><<<S, 256, 0, st>>>((const T *)f->fld[F_V].p, f->nc, vsh, R->nrec, R->cell.p, R->phi.p,
-                                            p->nsteps, n - 1, obs, nullptr, res.p, nullptr);
+        k_fwi_sample<K, T><<<S, 256, 0, f->st>>>((const T *)f->fld[F_V].p, f->nc, vsh, R->nrec, R->cell.p, R->phi.p,
+                                               p->nsteps, n - 1, obs, nullptr, res.p, nullptr);
+    }
+    void add_residual(int64_t n) {
+        if (n < 1) return;
         constexpr int NP = np_of(K);
-        k_fwi_inject<K, T><<<blocks_for((int64_t)S * 2 * NP, 256), 256, 0, st>>>(
+        k_fwi_inject<K, T><<<blocks_for((int64_t)S * 2 * NP, 256), 256, 0, f->st>>>(
             (T *)a->fld[F_V].p, f->nc, vsh, S, R->nrec, R->cell.p, R->mphi.p, (const T *)f->geo.p, res.p);
+    }
+    void inject(int64_t n) {
+        sample(n);
+        add_residual(n);
+    }
+    // copy a field of every shot (ncomp components) into a buffer of shot stride dsh
+    void copy_field(T *dst, int64_t dsh, const dgt_solver *s, int fld, int ncomp) {
+        const int64_t w = (int64_t)ncomp * np_of(K) * s->nc;
+        DGT_HIP(hipMemcpy2DAsync(dst, dsh * sizeof(T), s->fld[fld].p, s->fshot(fld) * sizeof(T), w * sizeof(T), S,
+                                 hipMemcpyDeviceToDevice, s->st));
+    }
+    // Both half steps keep U, X, Z when the chain is split at the end of the velocity
+    // half (loop 13 of the order-4 chain) and runs tiled: one forward step and one
+    // reversed step then give every intermediate of the gradient, instead of ten
+    // untiled operator applications.
+    bool recordable() const {
+        if (p->mode != 1 || f->p.time_order != 4) return false;
+        for (const dgt_solver *s : {f, a}) {
+            bool half = false;
+            for (const auto &P : s->plan) half |= P.first + P.n == 13;
+            if (!half) return false;
+        }
+        return true;
+    }
+    // one tiled step of solver s from time t0; after the velocity half its fields U, X, Z
+    // go to vel[0], vel[1], vel[2], after the stress half to str[0..2] (null: not kept)
+    void record_step(dgt_solver *s, double t0, T *const (&vel)[3], T *const (&str)[3]) {
+        int64_t launches = 0;
+        const std::function<void(size_t)> after = [&](size_t b) {
+            const auto &P = s->plan[b];
+            const int end = P.first + P.n;
+            if (end != 13 && end != 26) return;
+            T *const(&d)[3] = end == 13 ? vel : str;
+            // velocity half: U = A s, X = B U, Z = c A X (2 components); stress half:
+            // X = B v, U = A X, Z = c B U (3 components)
+            if (d[0]) copy_field(d[0], vsh, s, F_U, 2);
+            if (d[1]) copy_field(d[1], ssh, s, F_X, 3);
+            if (d[2]) copy_field(d[2], end == 13 ? vsh : ssh, s, F_Z, end == 13 ? 2 : 3);
+        };
+        step_tiled<K, T>(s, 1, t0, launches, (1 << F_U) | (1 << F_X) | (1 << F_Z), &after);
     }
     // the forward state u_n is in f, alpha_{n+1} in a
     void step_back(int64_t n) {
@@ -313,6 +356,23 @@ struct FwiRun {
         const bool o4 = f->p.time_order == 4;
         const double dt = f->p.dt, c3 = o4 ? dt * dt * dt / 24.0 : 0.0;
         int64_t launches = 0;
+        if (rec) {
+            sample(n);  // from u_n, before the recorded step advances the forward state
+            // forward step: velocity half U = A s_n, X = B U, Z = c A X; stress half X = B v',
+            // U = A X, Z = c B U  (record_step's slots: U, X, Z fields)
+            record_step(f, (double)n * dt, {U.p, Xp.p, Zs.p}, {Y.p, X1.p, V2s.p});
+            DGT_HIP(hipMemcpyAsync(As.p, a->fld[F_S].p, (size_t)ssh * S * sizeof(T), hipMemcpyDeviceToDevice, st));
+            // reversed step: velocity half U = A as, X = B A as; stress half X = B av,
+            // U = A B av
+            record_step(a, 0.0, {tV.p, Wp.p, nullptr}, {W.p, tS.p, nullptr});
+            ++reversed;
+            k_fwi_grad<K, T><<<dim3(blocks_for(nc, 256), S), 256, 0, st>>>(
+                nc, S, (const T *)f->geo.p, (const T *)a->fld[F_V].p, U.p, Zs.p, W.p, tV.p, Y.p, vsh, As.p, X1.p,
+                V2s.p, Wp.p, tS.p, Xp.p, ssh, dt, c3, part.p);
+            k_fwi_grad_sum<<<blocks_for(3 * nc, 256), 256, 0, st>>>(nc, S, part.p, g.p);
+            add_residual(n);
+            return;
+        }
         const T *v0 = (const T *)f->fld[F_V].p, *s0 = (const T *)f->fld[F_S].p;
         // every operator application covers all shots in one launch per kernel
         auto vop = [&](const T *in, T *out, double sc) { apply_op<K, T>(f, true, in, out, sc, nullptr, 0.0, launches, S, ssh, vsh); };
@@ -480,6 +540,7 @@ dgt_status dgt_fwi_gradient(dgt_solver *s, const dgt_fwi_params *p, const double
             run.part.alloc((size_t)3 * nc * S);
             DGT_HIP(hipMemsetAsync(run.g.p, 0, 8 * 3 * nc, st));
             run.snap.resize(p->nsnap);
+            run.rec = run.recordable() && !std::getenv("DGT_FWI_UNTILED_INTERMEDIATES");
             // forward sweep from rest: misfit; the start state is the first checkpoint
             for (int f = 0; f < F_COUNT; ++f) DGT_HIP(hipMemsetAsync(s->fld[f].p, 0, s->fld[f].n, st));
             run.store(0);

@@ -728,8 +728,12 @@ static void check_graphs(dgt_solver *s) {
     DGT_REQUIRE(!bad, DGT_ESTATE, "a dependence wait of the tiled executor timed out; its results are invalid");
 }
 
+// extra_persist: fields written back for every cell that writes them (the FWI
+// reversal keeps the intermediates U, X, Z this way); after: called once a
+// sub-chain's launches are enqueued, with its plan index
 template <int K, typename T>
-static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launches) {
+static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launches, int32_t extra_persist = 0,
+                       const std::function<void(size_t)> *after = nullptr) {
     hipStream_t st = s->st;
     const double dt = s->p.dt;
     for (auto &P : s->plan)
@@ -747,6 +751,7 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
             A.nshots = s->nshots;
             A.src_cells = s->src_cells.p;
             A.src_vec = s->src_vec.p;
+            A.persistent_mask |= extra_persist;
             A.dt = dt;
             A.src_amp = s->has_src ? dt * ricker(th, s->sf0, s->st0, s->samp) : 0.0;
             if (s->sched_mode == 1 && P.kind == TK_CHAIN) {  // one launch for all colours
@@ -768,6 +773,7 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
                                   P.lds_bytes, st, A, TA_LAUNCH);
                 s->mark();
                 ++launches;
+                if (after) (*after)(b);
                 continue;
             }
             for (int c = 0; c < P.ncolors; ++c) {
@@ -780,6 +786,7 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
                 s->mark();
                 ++launches;
             }
+            if (after) (*after)(b);
         }
     }
 }
