@@ -578,6 +578,9 @@ static void build_plan(dgt_solver *s) {
             known = known && chain_built(s->K, nops);
             const int cap = s->K == 4 && s->esz == 8 ? TILE_NT[1] : TILE_NT[2];
             const char *env = std::getenv("DGT_TILE_OP");
+            // at P1/P2 the chain kernel also holds the reference element in static LDS
+            const size_t refb =
+                s->K <= 2 ? (size_t)(3 * np * np + 3 * np * (s->K + 1)) * s->esz + 3 * (s->K + 1) * 4 + 16 : 0;
             if (ok && j == end && known && A.nfl == nops && P.max_foot <= cap && !(env && std::atoi(env) == 0)) {
                 int w = 0;
                 for (int q = first_op; q < first_op + nops; ++q) {
@@ -585,12 +588,14 @@ static void build_plan(dgt_solver *s) {
                     const bool pn = D.pen >= 0 && s->loops[op_first_loop(order, q) + 1].pen >= 0;
                     w = std::max(w, np * (D.vel ? 3 : 2) + (pn ? np * (D.vel ? 2 : 3) : 0));
                 }
-                A.nrow = 2 + w;
-                if (!(A.nrow & 1)) ++A.nrow;
-                P.kind = TK_CHAIN;
-                P.o0 = first_op;
-                P.nops = nops;
-                P.lds_bytes = (size_t)A.nrow * A.stride * s->esz;
+                const int nrow = (2 + w) | 1;
+                if ((size_t)nrow * A.stride * s->esz + refb <= budget) {
+                    A.nrow = nrow;
+                    P.kind = TK_CHAIN;
+                    P.o0 = first_op;
+                    P.nops = nops;
+                    P.lds_bytes = (size_t)A.nrow * A.stride * s->esz;
+                }
             }
         }
         DGT_REQUIRE(P.lds_bytes <= budget, DGT_EUNSUPPORTED,

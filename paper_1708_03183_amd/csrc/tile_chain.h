@@ -100,7 +100,8 @@ struct CellRegs {
 };
 
 template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int O>
-__device__ __forceinline__ void chain_op(CellRegs<K, T> &r, const TileArgs &a, T *__restrict__ lds, int NR, bool act,
+__device__ __forceinline__ void chain_op(const RefC<K, T> &Rf, CellRegs<K, T> &r, const TileArgs &a,
+                                         T *__restrict__ lds, int NR, bool act,
                                          int s, uint32_t acc, uint16_t fl, const uint32_t (&nb)[3], int64_t x,
                                          int shot) {
     constexpr int NP = np_of(K), NFP = K + 1;
@@ -109,7 +110,6 @@ __device__ __forceinline__ void chain_op(CellRegs<K, T> &r, const TileArgs &a, T
     constexpr int j0 = op_first_loop(ORDER, O) - op_first_loop(ORDER, O0);
     constexpr int ju = op_upd_loop(ORDER, O) - op_first_loop(ORDER, O0);
     constexpr int PO = 2 + NP * NI;  // penalty traces in a row; impedances at 0 and 1
-    const auto &Rf = R<K, T>();
     const bool pen = D.pen >= 0 && a.loops[j0 + 1].pen >= 0;
     T(&vin)[3][NP] = r.f[D.in];
     T(&o)[3][NP] = r.f[D.out];
@@ -342,7 +342,8 @@ __device__ __forceinline__ void chain_op(CellRegs<K, T> &r, const TileArgs &a, T
 }
 
 template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS>
-__device__ __forceinline__ void chain_tile(const TileArgs &a, T *__restrict__ lds, int tile, int shot) {
+__device__ __forceinline__ void chain_tile(const RefC<K, T> &Rf, const TileArgs &a, T *__restrict__ lds, int tile,
+                                           int shot) {
     constexpr int NP = np_of(K);
     const int f0 = a.foot_off[tile];
     const int nfoot = a.foot_off[tile + 1] - f0;
@@ -386,7 +387,7 @@ __device__ __forceinline__ void chain_tile(const TileArgs &a, T *__restrict__ ld
     }
     // fields are gathered at their first use and written back after their last write
     [&]<int... Q>(std::integer_sequence<int, Q...>) {
-        (chain_op<K, T, UPW, ORDER, O0, NOPS, O0 + Q>(r, a, lds, a.nrow, act, s, acc, fl, nb[Q], x, shot), ...);
+        (chain_op<K, T, UPW, ORDER, O0, NOPS, O0 + Q>(Rf, r, a, lds, a.nrow, act, s, acc, fl, nb[Q], x, shot), ...);
     }(std::make_integer_sequence<int, NOPS>{});
 }
 
@@ -415,12 +416,11 @@ __device__ __forceinline__ int next_tile(const TileArgs &a, int &shot) {
 }
 
 template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int NT>
-__global__ __launch_bounds__(NT) void k_tile_chain(const TileArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void chain_kernel_body(const RefC<K, T> &Rf, const TileArgs &a, unsigned char *smem) {
     __shared__ int s_next, s_shot;
     T *lds = reinterpret_cast<T *>(smem);
     if (!a.persist) {  // one launch per colour
-        chain_tile<K, T, UPW, ORDER, O0, NOPS>(a, lds, a.tiles[a.tile_base + (int)blockIdx.x / a.nshots],
+        chain_tile<K, T, UPW, ORDER, O0, NOPS>(Rf, a, lds, a.tiles[a.tile_base + (int)blockIdx.x / a.nshots],
                                                (int)blockIdx.x % a.nshots);
         return;
     }
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(NT) void k_tile_chain(const TileArgs a) {
         __syncthreads();
         const int tile = s_next, shot = s_shot;
         if (tile < 0) return;
-        chain_tile<K, T, UPW, ORDER, O0, NOPS>(a, lds, tile, shot);
+        chain_tile<K, T, UPW, ORDER, O0, NOPS>(Rf, a, lds, tile, shot);
         // every wave waits for its coherent field stores to complete, so once the barrier
         // is passed the whole tile is visible at device scope and its successors may start
         __builtin_amdgcn_s_waitcnt(0);
@@ -438,6 +438,25 @@ __global__ __launch_bounds__(NT) void k_tile_chain(const TileArgs a) {
             for (int k = a.succ_off[tile]; k < a.succ_off[tile + 1]; ++k)
                 __hip_atomic_fetch_add(a.cnt + (int64_t)shot * a.ntiles + a.succ[k], 1u, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int NT>
+__global__ __launch_bounds__(NT) void k_tile_chain(const TileArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    if constexpr (K <= 2) {
+        // P1/P2: the reference matrices in LDS; every lane reads the same word (a
+        // broadcast), so the operators no longer hold them in scalar registers, which
+        // the compiler spilled to vector lanes (P3/P4 keep constant memory: their
+        // small tiles lose more to the extra LDS than they gain)
+        __shared__ __align__(16) RefC<K, T> sref;
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(&R<K, T>());
+        uint32_t *dst = reinterpret_cast<uint32_t *>(&sref);
+        for (int i = threadIdx.x; i < (int)(sizeof(RefC<K, T>) / 4); i += NT) dst[i] = src[i];
+        __syncthreads();
+        chain_kernel_body<K, T, UPW, ORDER, O0, NOPS, NT>(sref, a, smem);
+    } else {
+        chain_kernel_body<K, T, UPW, ORDER, O0, NOPS, NT>(R<K, T>(), a, smem);
     }
 }
 
