@@ -44,6 +44,10 @@ def parse():
                     help="tiles per colour class: -1 the GPU's resident tile workgroups, 0 uncapped")
     ap.add_argument("--schedule", type=int, default=None,
                     help="tiled executor: 0 one launch per colour, 1 dependence-driven (one launch per sub-chain)")
+    ap.add_argument("--partition", type=int, choices=[0, 1], default=1,
+                    help="seed partition: 1 Hilbert order of the cell centroids, 0 chunks of the mesh numbering")
+    ap.add_argument("--mesh-order", choices=["renumbered", "natural"], default="renumbered",
+                    help="cell numbering of the mesh: seeded random renumbering, or the generator's row-major order")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-untiled", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
@@ -414,7 +418,7 @@ def main():
         splits = () if a.splits in ("", "none") else tuple(int(x) for x in a.splits.split(","))
 
     t0 = time.time()
-    m = I.square_mesh(a.n, jitter=0.2, jitter_seed=1, renumber_seed=2)
+    m = I.square_mesh(a.n, jitter=0.2, jitter_seed=1, renumber_seed=2 if a.mesh_order == "renumbered" else None)
     lam, mu, rho = I.layered_material(m)
     t_gen = time.time() - t0
     k = a.degree
@@ -441,7 +445,7 @@ def main():
     sol = make(prec)
     torch.cuda.synchronize()
     ti0 = time.time()
-    sol.inspect(ts, partition=1, splits=splits, max_colour_tiles=a.colour_cap)
+    sol.inspect(ts, partition=a.partition, splits=splits, max_colour_tiles=a.colour_cap)
     sol.set_schedule(schedule)
     torch.cuda.synchronize()
     t_insp_wall = time.time() - ti0
@@ -504,7 +508,8 @@ def main():
     achieved = bytes_launch / avg_launch_s / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic(f"jitter{a.n}_p{k}", "f32" if prec else "f64", ts, splits, schedule),
+                "traffic": (measured_traffic(f"jitter{a.n}_p{k}", "f32" if prec else "f64", ts, splits, schedule)
+                            if a.partition == 1 and a.mesh_order == "renumbered" else None),
                 "kernel": "k_tile_chain",
                 "bytes_per_launch": bytes_launch, "avg_launch_us": avg_launch_s * 1e6,
                 "avg_launch_us_event_pairs": ker_p / launches_p * 1e3}
@@ -531,7 +536,7 @@ def main():
                          f"({tcpu:.1f} s, FP64, single thread)"}
         # GPU FP64 tiled from the same state, compared with the oracle
         chk = make(0)
-        chk.inspect(ts, partition=1, splits=splits, max_colour_tiles=a.colour_cap)
+        chk.inspect(ts, partition=a.partition, splits=splits, max_colour_tiles=a.colour_cap)
         chk.set_schedule(schedule)
         gv = torch.from_numpy(np.ascontiguousarray(vt.double().cpu().numpy())).cuda()
         gs = torch.from_numpy(np.ascontiguousarray(st_.double().cpu().numpy())).cuda()
@@ -565,10 +570,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec else "f64",
         "data": "synthetic",
-        "config": {"workload": f"jitter{a.n}_p{k}: {a.n}x{a.n} jittered renumbered triangulation, "
+        "config": {"workload": f"jitter{a.n}_p{k}: {a.n}x{a.n} jittered "
+                               f"{'renumbered' if a.mesh_order == 'renumbered' else 'row-major'} triangulation, "
                                f"{mesh.nc} cells, DG P{k}, 3-layer, upwind, order-4 leapfrog",
                    "cells": mesh.nc, "dofs_per_step": dofs, "tile_size": ts, "splits": list(splits),
-                   "partition": "hilbert", "colour_cap": a.colour_cap,
+                   "partition": "hilbert" if a.partition == 1 else "chunks of the mesh numbering",
+                   "mesh_order": a.mesh_order, "colour_cap": a.colour_cap,
                    "schedule": "dependence-driven" if schedule == 1 else "colour launches"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -843,65 +843,65 @@ namespace dgt {
 // The solver without the sign check of dt: the FWI adjoint runs the chain backward
 // in time (dt < 0) on a solver of its own.
 static std::unique_ptr<dgt_solver> new_solver(const dgt_mesh *m, const double *lam, const double *mu,
-                                              const double *rho, const dgt_solver_params *p, void *stream) {
-        DGT_REQUIRE(p->degree >= 1 && p->degree <= 4, DGT_EINVAL, "degree must be 1..4");
-        DGT_REQUIRE(p->flux == 0 || p->flux == 1, DGT_EINVAL, "flux must be 0 or 1");
-        DGT_REQUIRE(p->time_order == 2 || p->time_order == 4, DGT_EINVAL, "time_order must be 2 or 4");
-        DGT_REQUIRE(p->precision == 0 || p->precision == 1, DGT_EINVAL, "precision must be 0 or 1");
-        DGT_REQUIRE(p->dt != 0 && std::isfinite(p->dt), DGT_EINVAL, "dt must be finite and nonzero");
-        const Mesh &M = m->m;
-        DGT_REQUIRE(M.nc > 0, DGT_EINVAL, "empty mesh");
-        DGT_REQUIRE(lam && mu && rho, DGT_EINVAL, "material is NULL");
-        for (int64_t c = 0; c < M.nc; ++c)
-            DGT_REQUIRE(lam[c] > 0 && mu[c] > 0 && rho[c] > 0, DGT_EINVAL, "material must be positive");
-        auto s = std::make_unique<dgt_solver>();
-        s->mesh = &M;
-        s->mesh_handle = m;
-        s->p = *p;
-        s->st = (hipStream_t)stream;
-        s->K = p->degree;
-        s->fp32 = p->precision;
-        s->esz = p->precision ? 4 : 8;
-        s->upw = p->flux == 1;
-        s->nc = M.nc;
-        s->nf = M.nf;
-        s->nb = M.nb;
-        s->haspen = s->upw;
-        for (int64_t b = 0; b < M.nb; ++b)
-            if (!(M.bside[b] >= 0 && ((p->free_sides >> M.bside[b]) & 1))) s->haspen = 1;
-        s->E = make_refelem(p->degree);
-        hipStream_t st = s->st;
-        dispatch(s.get(), [&]<int K, typename T>() {
-            upload_ref<K, T>(s->E, st);
-            tile_upload_ref<K, T>(s->E, st);
-        });
-        s->xy.upload(M.xy, st);
-        s->c2v.upload(M.c2v, st);
-        s->f2c.upload(M.f2c.empty() ? std::vector<int32_t>{0, 0} : M.f2c, st);
-        s->f2l.upload(M.f2l.empty() ? std::vector<int8_t>{0, 0} : M.f2l, st);
-        s->b2c.upload(M.b2c.empty() ? std::vector<int32_t>{0} : M.b2c, st);
-        s->b2l.upload(M.b2l.empty() ? std::vector<int8_t>{0} : M.b2l, st);
-        std::vector<uint8_t> bfree(std::max<int64_t>(M.nb, 1), 0);
-        for (int64_t b = 0; b < M.nb; ++b) bfree[b] = M.bside[b] >= 0 && ((p->free_sides >> M.bside[b]) & 1);
-        s->bfree.upload(bfree, st);
-        s->lam.upload(lam, M.nc, st);
-        s->mu.upload(mu, M.nc, st);
-        s->rho.upload(rho, M.nc, st);
-        const int np = s->E.np, nfp = s->E.nfp;
-        s->geo.alloc((size_t)(G_NROWS + 1) * M.nc * s->esz);
-        alloc_fields(s.get());
-        s->G.alloc((size_t)2 * 3 * nfp * std::max<int64_t>(M.nf, 1) * s->esz);
-        s->Gx.alloc((size_t)3 * nfp * std::max<int64_t>(M.nb, 1) * s->esz);
-        s->src_vec.alloc((size_t)np * s->esz);
-        DGT_HIP(hipMemsetAsync(s->src_vec.p, 0, s->src_vec.n, st));
-        s->src_in.assign(1, -1);
-        std::vector<int32_t> id(M.nc);
-        std::iota(id.begin(), id.end(), 0);
-        set_exec_order(s.get(), id);
-        build_loops(s.get());
-        DGT_HIP(hipEventCreate(&s->ev0));
-        DGT_HIP(hipEventCreate(&s->ev1));
-        return s;
+                                          const double *rho, const dgt_solver_params *p, void *stream) {
+    DGT_REQUIRE(p->degree >= 1 && p->degree <= 4, DGT_EINVAL, "degree must be 1..4");
+    DGT_REQUIRE(p->flux == 0 || p->flux == 1, DGT_EINVAL, "flux must be 0 or 1");
+    DGT_REQUIRE(p->time_order == 2 || p->time_order == 4, DGT_EINVAL, "time_order must be 2 or 4");
+    DGT_REQUIRE(p->precision == 0 || p->precision == 1, DGT_EINVAL, "precision must be 0 or 1");
+    DGT_REQUIRE(p->dt != 0 && std::isfinite(p->dt), DGT_EINVAL, "dt must be finite and nonzero");
+    const Mesh &M = m->m;
+    DGT_REQUIRE(M.nc > 0, DGT_EINVAL, "empty mesh");
+    DGT_REQUIRE(lam && mu && rho, DGT_EINVAL, "material is NULL");
+    for (int64_t c = 0; c < M.nc; ++c)
+        DGT_REQUIRE(lam[c] > 0 && mu[c] > 0 && rho[c] > 0, DGT_EINVAL, "material must be positive");
+    auto s = std::make_unique<dgt_solver>();
+    s->mesh = &M;
+    s->mesh_handle = m;
+    s->p = *p;
+    s->st = (hipStream_t)stream;
+    s->K = p->degree;
+    s->fp32 = p->precision;
+    s->esz = p->precision ? 4 : 8;
+    s->upw = p->flux == 1;
+    s->nc = M.nc;
+    s->nf = M.nf;
+    s->nb = M.nb;
+    s->haspen = s->upw;
+    for (int64_t b = 0; b < M.nb; ++b)
+        if (!(M.bside[b] >= 0 && ((p->free_sides >> M.bside[b]) & 1))) s->haspen = 1;
+    s->E = make_refelem(p->degree);
+    hipStream_t st = s->st;
+    dispatch(s.get(), [&]<int K, typename T>() {
+        upload_ref<K, T>(s->E, st);
+        tile_upload_ref<K, T>(s->E, st);
+    });
+    s->xy.upload(M.xy, st);
+    s->c2v.upload(M.c2v, st);
+    s->f2c.upload(M.f2c.empty() ? std::vector<int32_t>{0, 0} : M.f2c, st);
+    s->f2l.upload(M.f2l.empty() ? std::vector<int8_t>{0, 0} : M.f2l, st);
+    s->b2c.upload(M.b2c.empty() ? std::vector<int32_t>{0} : M.b2c, st);
+    s->b2l.upload(M.b2l.empty() ? std::vector<int8_t>{0} : M.b2l, st);
+    std::vector<uint8_t> bfree(std::max<int64_t>(M.nb, 1), 0);
+    for (int64_t b = 0; b < M.nb; ++b) bfree[b] = M.bside[b] >= 0 && ((p->free_sides >> M.bside[b]) & 1);
+    s->bfree.upload(bfree, st);
+    s->lam.upload(lam, M.nc, st);
+    s->mu.upload(mu, M.nc, st);
+    s->rho.upload(rho, M.nc, st);
+    const int np = s->E.np, nfp = s->E.nfp;
+    s->geo.alloc((size_t)(G_NROWS + 1) * M.nc * s->esz);
+    alloc_fields(s.get());
+    s->G.alloc((size_t)2 * 3 * nfp * std::max<int64_t>(M.nf, 1) * s->esz);
+    s->Gx.alloc((size_t)3 * nfp * std::max<int64_t>(M.nb, 1) * s->esz);
+    s->src_vec.alloc((size_t)np * s->esz);
+    DGT_HIP(hipMemsetAsync(s->src_vec.p, 0, s->src_vec.n, st));
+    s->src_in.assign(1, -1);
+    std::vector<int32_t> id(M.nc);
+    std::iota(id.begin(), id.end(), 0);
+    set_exec_order(s.get(), id);
+    build_loops(s.get());
+    DGT_HIP(hipEventCreate(&s->ev0));
+    DGT_HIP(hipEventCreate(&s->ev1));
+    return s;
 }
 
 }  // namespace dgt
