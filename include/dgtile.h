@@ -111,6 +111,10 @@ typedef struct {
                                      workgroups.  -1 (dgt_solver_inspect only): the
                                      solver picks the number of tile workgroups the
                                      GPU holds at once when a class exceeds it. */
+    const int32_t *sub_tile_sizes; /* host [nsplits+1]: the seed tile size of each
+                                     sub-chain (a fusion scheme fixes one per
+                                     sub-chain, Sec. 7.2), each >= 1; NULL:
+                                     tile_size for all */
 } dgt_inspect_params;
 
 /* Run the inspector on the GPU (Alg. 1 with Alg. 3 projections and Alg. 4

@@ -84,7 +84,7 @@ def _declare(L):
     L.or_chain_map.argtypes = [_p, C.c_int, C.c_int, C.c_int, _i32p]
     L.or_chain_loop.argtypes = [_p, C.c_int, C.c_int, _i32p, _i32p, _i32p]
     L.or_chain_nloops.argtypes = [_p]
-    L.or_inspect.argtypes = [_p, C.c_int64, C.c_int, _p, C.c_int, C.c_int, _p, C.c_int, C.POINTER(_p)]
+    L.or_inspect.argtypes = [_p, C.c_int64, C.c_int, _p, C.c_int, C.c_int, _p, C.c_int, _p, C.POINTER(_p)]
     L.or_sched_free.argtypes = [_p]
     L.or_sched_nsub.argtypes = [_p]
     L.or_sched_sub_info.argtypes = [_p, C.c_int] + [C.POINTER(C.c_int32)] * 5
@@ -268,12 +268,18 @@ class OChain:
     def nloops(self):
         return lib().or_chain_nloops(self.h)
 
-    def inspect(self, ts, partition=0, seed_xy=None, max_rounds=64, splits=(), max_colour_tiles=0):
+    def inspect(self, ts, partition=0, seed_xy=None, max_rounds=64, splits=(), max_colour_tiles=0,
+                sub_tile_sizes=None):
+        """sub_tile_sizes: one seed tile size per sub-chain (len(splits) + 1), else ts for all."""
         xy = None if seed_xy is None else np.ascontiguousarray(seed_xy, np.float64)
         sp = np.ascontiguousarray(np.array(splits, np.int32))
+        st = None
+        if sub_tile_sizes is not None:
+            st = np.ascontiguousarray(np.array(sub_tile_sizes, np.int32))
+            assert st.size == len(sp) + 1
         h = C.c_void_p()
         rc = lib().or_inspect(self.h, ts, partition, _ptr(xy), max_rounds, max_colour_tiles,
-                              _ptr(sp) if len(sp) else None, len(sp), C.byref(h))
+                              _ptr(sp) if len(sp) else None, len(sp), _ptr(st), C.byref(h))
         if rc:
             raise RuntimeError(f"or_inspect -> {rc}")
         return OSched(h, self)

@@ -623,9 +623,12 @@ static int inspect_sub(const or_chain *c, or_sched *s, sub_t *sb, int64_t ts, in
 }
 
 int or_inspect(const or_chain *c, int64_t ts, int partition, const double *seed_xy, int max_rounds,
-               int max_colour_tiles, const int32_t *splits, int nsplits, or_sched **out) {
+               int max_colour_tiles, const int32_t *splits, int nsplits, const int32_t *sub_ts, or_sched **out) {
     *out = NULL;
     if (ts < 1 || c->nloops == 0 || max_rounds < 1 || max_colour_tiles < 0) return -1;
+    if (sub_ts)
+        for (int i = 0; i <= nsplits; i++)
+            if (sub_ts[i] < 1) return -1;
     or_sched *s = calloc(1, sizeof(*s));
     s->nloops = c->nloops;
     for (int j = 0; j < c->nloops; j++) {
@@ -640,7 +643,8 @@ int or_inspect(const or_chain *c, int64_t ts, int partition, const double *seed_
         sb->first = start;
         sb->n = end - start;
         for (int j = start; j < end; j++) s->sub_of[j] = s->nsub - 1;
-        int rc = inspect_sub(c, s, sb, ts, partition, seed_xy, max_rounds, max_colour_tiles);
+        /* a fusion scheme gives each sub-chain its own seed tile size (Sec. 7.2) */
+        int rc = inspect_sub(c, s, sb, sub_ts ? sub_ts[i] : ts, partition, seed_xy, max_rounds, max_colour_tiles);
         if (rc) { or_sched_free(s); return rc; }
         start = end;
     }

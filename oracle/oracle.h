@@ -85,7 +85,8 @@ int or_chain_nloops(const or_chain *c);
 /* Alg. 1 with readings C10-C17; splits = loop indices starting new sub-chains;
  * max_colour_tiles > 0 caps every colour class after each colouring (R5b in chain.c). */
 int or_inspect(const or_chain *c, int64_t ts, int partition, const double *seed_xy,
-               int max_rounds, int max_colour_tiles, const int32_t *splits, int nsplits, or_sched **out);
+               int max_rounds, int max_colour_tiles, const int32_t *splits, int nsplits,
+               const int32_t *sub_ts, or_sched **out);
 void or_sched_free(or_sched *s);
 int or_sched_nsub(const or_sched *s);
 /* per sub-chain: loop range, ntiles, ncolors, rounds used */

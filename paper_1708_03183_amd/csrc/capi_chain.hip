@@ -22,7 +22,7 @@ extern "C" {
 
 const char *dgt_last_error(void) { return g_last_error.c_str(); }
 
-int dgt_version(void) { return 102; }
+int dgt_version(void) { return 103; }
 
 dgt_status dgt_chain_create(dgt_chain **out) {
     return guard([&] {
@@ -97,8 +97,10 @@ dgt_status dgt_inspect(const dgt_chain *c, const dgt_inspect_params *p, void *st
         Inspector insp(sch->chain_copy, st);
         std::vector<int32_t> splits(p->splits, p->splits + p->nsplits);
         DGT_REQUIRE(p->max_colour_tiles >= 0, DGT_EINVAL, "max_colour_tiles must be >= 0");
+        std::vector<int32_t> sub_ts;
+        if (p->sub_tile_sizes) sub_ts.assign(p->sub_tile_sizes, p->sub_tile_sizes + p->nsplits + 1);
         sch->s = insp.run(p->tile_size, p->partition, p->seed_xy, nullptr, p->max_conflict_rounds,
-                          p->max_colour_tiles, splits);
+                          p->max_colour_tiles, splits, sub_ts);
         *out = sch.release();
     });
 }

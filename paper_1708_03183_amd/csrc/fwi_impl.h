@@ -459,6 +459,7 @@ static std::unique_ptr<dgt_solver> fwi_adjoint_solver(dgt_solver *s, const dgt_m
         dgt_inspect_params ip = s->last_ip;
         ip.splits = s->last_splits.data();
         ip.nsplits = (int32_t)s->last_splits.size();
+        ip.sub_tile_sizes = s->last_sub_ts.empty() ? nullptr : s->last_sub_ts.data();
         solver_inspect_once(a.get(), &ip, s->last_cap);
         DGT_REQUIRE(a->plan_status == DGT_OK && a->rank_h == s->rank_h, DGT_ESTATE,
                     "the reversed chain's inspection differs from the forward one");

@@ -63,7 +63,8 @@ class Inspector {
    public:
     Inspector(const ChainDesc &c, hipStream_t st);
     std::unique_ptr<Schedule> run(int64_t ts, int partition, const double *xy_host, const double *xy_dev,
-                                  int max_rounds, int cap, const std::vector<int32_t> &splits);
+                                  int max_rounds, int cap, const std::vector<int32_t> &splits,
+                                  const std::vector<int32_t> &sub_ts = {});
     const ChainDesc &chain;
     hipStream_t stream;
     DBuf<int32_t> dmap[kMaxMaps], inv_off[kMaxMaps], inv_val[kMaxMaps];

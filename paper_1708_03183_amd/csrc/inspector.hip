@@ -949,9 +949,13 @@ void Inspector::dependences(SubSched &sb, const DBuf<uint64_t> *keys, const int6
 }
 
 std::unique_ptr<Schedule> Inspector::run(int64_t ts, int partition, const double *xy_host, const double *xy_dev,
-                                         int max_rounds, int cap, const std::vector<int32_t> &splits) {
+                                         int max_rounds, int cap, const std::vector<int32_t> &splits,
+                                         const std::vector<int32_t> &sub_ts) {
     hipStream_t st = stream;
     DGT_REQUIRE(ts >= 1, DGT_EINVAL, "tile_size must be >= 1");
+    DGT_REQUIRE(sub_ts.empty() || sub_ts.size() == splits.size() + 1, DGT_EINVAL,
+                "sub_tile_sizes needs one tile size per sub-chain");
+    for (int32_t t : sub_ts) DGT_REQUIRE(t >= 1, DGT_EINVAL, "sub-chain tile sizes must be >= 1");
     DGT_REQUIRE(cap >= 0, DGT_EINVAL, "max_colour_tiles must be >= 0");
     DGT_REQUIRE(max_rounds >= 1, DGT_EINVAL, "max_conflict_rounds must be >= 1");
     DGT_REQUIRE(chain.nloops >= 1, DGT_EINVAL, "empty loop chain");
@@ -980,7 +984,8 @@ std::unique_ptr<Schedule> Inspector::run(int64_t ts, int partition, const double
         sb.first = start;
         sb.n = end - start;
         for (int j = start; j < end; ++j) S->sub_of[j] = (int)S->sub.size() - 1;
-        run_sub(*S, sb, ts, partition, xy_host, xy_dev, max_rounds, cap);
+        // a fusion scheme gives each sub-chain its own seed tile size (Sec. 7.2)
+        run_sub(*S, sb, sub_ts.empty() ? ts : sub_ts[i], partition, xy_host, xy_dev, max_rounds, cap);
         start = end;
     }
     DGT_HIP(hipEventRecord(e1, st));

@@ -85,7 +85,7 @@ struct dgt_solver {
     // parameters of the last inspection (the FWI adjoint solver repeats it)
     bool inspected = false;
     dgt_inspect_params last_ip{};
-    std::vector<int32_t> last_splits;
+    std::vector<int32_t> last_splits, last_sub_ts;
     int last_cap = 0;
     std::string plan_error = "tiled mode needs dgt_solver_inspect";
     // timing of the last step
@@ -1014,6 +1014,9 @@ static void solver_inspect_once(dgt_solver *s, const dgt_inspect_params *p, int 
     s->last_ip = *p;
     s->last_splits.assign(p->splits, p->splits + p->nsplits);
     s->last_ip.splits = nullptr;
+    if (p->sub_tile_sizes) s->last_sub_ts.assign(p->sub_tile_sizes, p->sub_tile_sizes + p->nsplits + 1);
+    else s->last_sub_ts.clear();
+    s->last_ip.sub_tile_sizes = nullptr;
     s->last_cap = cap;
     delete s->sched;
     s->sched = nullptr;
@@ -1027,7 +1030,8 @@ static void solver_inspect_once(dgt_solver *s, const dgt_inspect_params *p, int 
     sch->chain = &sch->chain_copy;
     Inspector insp(sch->chain_copy, st);
     std::vector<int32_t> splits(p->splits, p->splits + p->nsplits);
-    sch->s = insp.run(p->tile_size, p->partition, nullptr, cxy.p, p->max_conflict_rounds, cap, splits);
+    sch->s = insp.run(p->tile_size, p->partition, nullptr, cxy.p, p->max_conflict_rounds, cap, splits,
+                      s->last_sub_ts);
     s->sched = sch.release();
     // executor layout follows the seed order of the schedule
     auto rank = s->sched->s->seed_rank.download(st, s->nc);

@@ -48,7 +48,7 @@ class _Desc(C.Structure):
 class _InspectParams(C.Structure):
     _fields_ = [("tile_size", C.c_int64), ("partition", C.c_int32), ("seed_xy", C.c_void_p),
                 ("max_conflict_rounds", C.c_int32), ("splits", C.c_void_p), ("nsplits", C.c_int32),
-                ("max_colour_tiles", C.c_int32)]
+                ("max_colour_tiles", C.c_int32), ("sub_tile_sizes", C.c_void_p)]
 
 
 class _SolverParams(C.Structure):
@@ -145,12 +145,17 @@ def _stream_handle(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
-def _inspect_params(tile_size, partition, seed_xy, max_rounds, splits, max_colour_tiles=0):
+def _inspect_params(tile_size, partition, seed_xy, max_rounds, splits, max_colour_tiles=0, sub_tile_sizes=None):
     sp = np.ascontiguousarray(np.array(list(splits), np.int32))
     xy = None if seed_xy is None else np.ascontiguousarray(seed_xy, np.float64)
+    st = None
+    if sub_tile_sizes is not None:
+        st = np.ascontiguousarray(np.array(list(sub_tile_sizes), np.int32))
+        if st.size != len(sp) + 1:
+            raise ValueError("sub_tile_sizes needs one tile size per sub-chain (len(splits) + 1)")
     p = _InspectParams(int(tile_size), int(partition), _np_ptr(xy), int(max_rounds),
-                       _np_ptr(sp) if len(sp) else None, len(sp), int(max_colour_tiles))
-    return p, (sp, xy)
+                       _np_ptr(sp) if len(sp) else None, len(sp), int(max_colour_tiles), _np_ptr(st))
+    return p, (sp, xy, st)
 
 
 # --------------------------------------------------------------- tier 1
@@ -184,8 +189,8 @@ class Chain:
         return out.value
 
     def inspect(self, tile_size, partition=0, seed_xy=None, max_rounds=64, splits=(), stream=None,
-                max_colour_tiles=0) -> "Schedule":
-        p, keep = _inspect_params(tile_size, partition, seed_xy, max_rounds, splits, max_colour_tiles)
+                max_colour_tiles=0, sub_tile_sizes=None) -> "Schedule":
+        p, keep = _inspect_params(tile_size, partition, seed_xy, max_rounds, splits, max_colour_tiles, sub_tile_sizes)
         h = C.c_void_p()
         _check(lib().dgt_inspect(self.h, C.byref(p), _stream_handle(stream), C.byref(h)))
         return Schedule(h, owner=True, loop_sizes=[self.sizes[s] for s in self.loop_sets])
@@ -321,9 +326,10 @@ class Solver:
         return (torch.zeros(self._shape(2), dtype=self.dtype, device=device),
                 torch.zeros(self._shape(3), dtype=self.dtype, device=device))
 
-    def inspect(self, tile_size, partition=1, max_rounds=64, splits=(), max_colour_tiles=0):
-        """max_colour_tiles: 0 none, > 0 cap per colour class, -1 the GPU's resident tile count."""
-        p, keep = _inspect_params(tile_size, partition, None, max_rounds, splits, max_colour_tiles)
+    def inspect(self, tile_size, partition=1, max_rounds=64, splits=(), max_colour_tiles=0, sub_tile_sizes=None):
+        """max_colour_tiles: 0 none, > 0 cap per colour class, -1 the GPU's resident tile count;
+        sub_tile_sizes: one seed tile size per sub-chain (else tile_size for all)."""
+        p, keep = _inspect_params(tile_size, partition, None, max_rounds, splits, max_colour_tiles, sub_tile_sizes)
         _check(lib().dgt_solver_inspect(self.h, C.byref(p)))
 
     def autotune(self, tile_sizes=(64, 96, 128, 192, 256, 384, 512), splits=(), partition=1, trial_steps=5,

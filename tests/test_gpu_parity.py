@@ -397,3 +397,35 @@ def test_errors_are_reported(D):
         gd.step(1, mode=1)  # not inspected
     with pytest.raises(D.DgtError):
         gd.inspect(0)
+
+
+@pytest.mark.parametrize("k,sub_ts,schedule", [(2, (12, 30), 1), (1, (40, 9), 0), (3, (6, 10, 7, 12, 8, 9), 0)])
+def test_sub_chain_tile_sizes_schedule_and_executor(D, k, sub_ts, schedule):
+    """Each sub-chain of a fusion scheme with its own seed tile size: the GPU schedule
+    equals the oracle's byte for byte, and the tiled executor matches the oracle."""
+    splits = (13,) if len(sub_ts) == 2 else (4, 8, 13, 17, 21)
+    n = 12 if k < 3 else 10
+    m, om, od, gm, gd = _dg_pair(D, n, k, 4, 1, 0x8, 5)
+    gd.inspect(8, partition=1, splits=splits, sub_tile_sizes=sub_ts)
+    gs = gd.schedule()
+    os_ = od.chain().inspect(8, partition=1, seed_xy=m.centroids(), splits=splits, sub_tile_sizes=sub_ts)
+    sizes = {0: om.nc, 1: om.nf, 2: om.nb}
+    pat = ([0, 1, 2, 0] * 3 + [0]) * 2
+    _compare_schedules(gs, os_, [sizes[s] for s in pat], [om.nc, om.nf, om.nb], len(splits) + 1)
+    assert os_.check() == 0
+    od.set_source(0.43, 0.52)
+    gd.set_source(0.43, 0.52)
+    v, s = od.zeros()
+    if k <= 2:
+        v[:] = I.random_state(v.shape, 3)
+        s[:] = I.random_state(s.shape, 4)
+    gv, gsg = torch.from_numpy(v.copy()).cuda(), torch.from_numpy(s.copy()).cuda()
+    od.step(v, s, 5, t0=0.1)
+    gd.set_schedule(schedule)
+    gd.upload(gv, gsg)
+    gd.step(5, mode=1, t0=0.1)
+    gd.download(gv, gsg)
+    torch.cuda.synchronize()
+    err = rel_l2([gv.cpu().numpy(), gsg.cpu().numpy()], [v, s])
+    print(f"sub-chain tile sizes {sub_ts} k={k} schedule={schedule}: schedule byte-equal, rel L2 err {err:.3e}")
+    assert err <= 1e-12

@@ -254,3 +254,33 @@ def test_colour_class_cap_greedy_order():
     col = s.colors(0)
     assert all(col[t] != col[t + 1] for t in range(len(col) - 1))
     assert s.check() == 0
+
+
+def test_sub_chains_with_their_own_tile_sizes():
+    """A fusion scheme gives each sub-chain its own seed tile size: each sub-chain's
+    schedule equals that of an inspection with its tile size for all sub-chains, the
+    whole schedule is legal, and the tiled chain equals the untiled one."""
+    m, om, d = _dg(12, k=2, order=4, flux=1, free=0x8, ren=5)
+    d.set_source(0.43, 0.52)
+    ch = d.chain()
+    xy = m.centroids()
+    mixed = ch.inspect(8, partition=1, seed_xy=xy, splits=(13,), sub_tile_sizes=(12, 30))
+    assert mixed.check() == 0
+    sizes = [om.nc, om.nf, om.nb, om.nc] * 3 + [om.nc]
+    sizes = sizes + sizes
+    for sub, ts in ((0, 12), (1, 30)):
+        ref = ch.inspect(ts, partition=1, seed_xy=xy, splits=(13,))
+        assert mixed.sub_info(sub) == ref.sub_info(sub)
+        assert np.array_equal(mixed.colors(sub), ref.colors(sub))
+        first, n = ref.sub_info(sub)["first"], ref.sub_info(sub)["nloops"]
+        for j in range(first, first + n):
+            assert np.array_equal(mixed.sigma(j, sizes[j]), ref.sigma(j, sizes[j]))
+    assert mixed.sub_info(0)["ntiles"] == -(-om.nc // 12) and mixed.sub_info(1)["ntiles"] == -(-om.nc // 30)
+    v, sg = d.zeros()
+    v[:] = I.random_state(v.shape, 1)
+    sg[:] = I.random_state(sg.shape, 2)
+    v2, s2 = v.copy(), sg.copy()
+    d.step(v, sg, 3, t0=0.1)
+    d.step_tiled(mixed, v2, s2, 3, t0=0.1)
+    err = np.sqrt(((v - v2) ** 2).sum() + ((sg - s2) ** 2).sum()) / np.sqrt((v ** 2).sum() + (sg ** 2).sum())
+    assert err <= 1e-14
