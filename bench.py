@@ -5,7 +5,7 @@ Workload (default): 512x512 jittered (0.2h) and randomly renumbered unit-square
 triangulation, 524288 cells, DG P2 velocity-stress elastic, three-layer
 material, upwind flux, free surface on top and absorbing elsewhere, Ricker
 source at (0.5, 0.5), 4th-order Taylor leapfrog (26 loops per step), tiles
-grown from 128 seed cells in Hilbert order, the chain fused per half step,
+grown from 256 seed cells in Hilbert order, the chain fused per half step,
 tiles of a half step started by dependence counters in one launch.
 
 Prints ONE JSON line.  `value` is the tiled-fused rate in dof-updates/s (5
@@ -71,7 +71,7 @@ def parse():
 OPS = (4, 8, 13, 17, 21)
 DEFAULTS = {
     (1, "fp64"): (256, (13,), 1),
-    (2, "fp64"): (128, (13,), 1),
+    (2, "fp64"): (256, (13,), 1),
     (2, "fp32"): (128, (13,), 1),
     (3, "fp32"): (64, OPS, 0),
     (4, "fp32"): (32, OPS, 0),
