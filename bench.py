@@ -73,8 +73,8 @@ DEFAULTS = {
     (1, "fp64"): (256, (13,), 1),
     (2, "fp64"): (256, (13,), 1),
     (2, "fp32"): (128, (13,), 1),
-    (3, "fp32"): (64, OPS, 0),
-    (4, "fp32"): (32, OPS, 0),
+    (3, "fp32"): (192, OPS, 1),
+    (4, "fp32"): (192, OPS, 0),
 }
 
 

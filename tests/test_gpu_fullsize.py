@@ -88,9 +88,10 @@ def _oracle_on_patch(m, cells, lam, mu, rho, k, order, dt, v, s, steps, src, t0)
 
 FULL_CASES = [
     # name, n, k, prec, tile size, splits, schedule, steps, shots
-    ("jitter512_p2_fp64", 512, 2, 0, 128, (13,), 1, 2, 1),
+    ("jitter512_p2_fp64", 512, 2, 0, 256, (13,), 1, 2, 1),
     ("jitter512_p2_fp32", 512, 2, 1, 128, (13,), 1, 2, 1),
-    ("jitter1024_p3_fp32", 1024, 3, 1, 64, OPS, 0, 1, 1),
+    ("jitter1024_p3_fp32", 1024, 3, 1, 192, OPS, 1, 1, 1),
+    ("jitter1024_p4_fp32", 1024, 4, 1, 192, OPS, 0, 1, 1),
     ("jitter416_p2_fp32_11shots", 416, 2, 1, 256, (13,), 0, 2, 11),
 ]
 
