@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--tile-size", type=int, default=None)
     ap.add_argument("--splits", type=str, default=None, help="comma-separated loop indices, or 'none'")
+    ap.add_argument("--sub-tile-sizes", type=str, default=None,
+                    help="comma-separated seed tile size of each sub-chain (one more than the splits)")
     ap.add_argument("--colour-cap", type=int, default=0,
                     help="tiles per colour class: -1 the GPU's resident tile workgroups, 0 uncapped")
     ap.add_argument("--schedule", type=int, default=None,
@@ -67,12 +69,13 @@ def parse():
 
 
 # tuned defaults per (degree, precision): seed tile size, fusion splits (13: half steps;
-# 4,8,13,17,21: one operator per sub-chain) and schedule (1: dependence-driven)
+# 4,8,13,17,21: one operator per sub-chain), schedule (1: dependence-driven) and,
+# optionally, a seed tile size per sub-chain
 OPS = (4, 8, 13, 17, 21)
 DEFAULTS = {
     (1, "fp64"): (256, (13,), 1),
     (2, "fp64"): (256, (13,), 1),
-    (2, "fp32"): (128, (13,), 1),
+    (2, "fp32"): (128, (13,), 1, (256, 128)),
     (3, "fp32"): (192, OPS, 1),
     (4, "fp32"): (192, OPS, 0),
 }
@@ -137,7 +140,7 @@ def batched(a):
 
     k, prec = 2, 1
     npk = (k + 1) * (k + 2) // 2
-    ts, splits, schedule = DEFAULTS[(k, "fp32")]
+    ts, splits, schedule, *_ = DEFAULTS[(k, "fp32")]
     if a.tile_size:
         ts = a.tile_size
     if a.schedule is not None:
@@ -409,7 +412,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     prec = 1 if a.precision == "fp32" else 0
-    ts, splits, schedule = DEFAULTS.get((a.degree, a.precision), (64, OPS, 0))
+    ts, splits, schedule, *rest = DEFAULTS.get((a.degree, a.precision), (64, OPS, 0))
+    default_sub_ts = rest[0] if rest and not (a.tile_size or a.splits) else None
     if a.schedule is not None:
         schedule = a.schedule
     if a.tile_size:
@@ -445,7 +449,8 @@ def main():
     sol = make(prec)
     torch.cuda.synchronize()
     ti0 = time.time()
-    sol.inspect(ts, partition=a.partition, splits=splits, max_colour_tiles=a.colour_cap)
+    sub_ts = tuple(int(x) for x in a.sub_tile_sizes.split(",")) if a.sub_tile_sizes else default_sub_ts
+    sol.inspect(ts, partition=a.partition, splits=splits, max_colour_tiles=a.colour_cap, sub_tile_sizes=sub_ts)
     sol.set_schedule(schedule)
     torch.cuda.synchronize()
     t_insp_wall = time.time() - ti0
@@ -515,7 +520,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": (measured_traffic(f"jitter{a.n}_p{k}", "f32" if prec else "f64", ts, splits, schedule)
-                            if a.partition == 1 and a.mesh_order == "renumbered" else None),
+                            if a.partition == 1 and a.mesh_order == "renumbered" and not sub_ts else None),
                 "kernel": "k_tile_chain",
                 "bytes_per_launch": bytes_launch, "avg_launch_us": avg_launch_s * 1e6,
                 "avg_launch_us_event_pairs": ker_p / launches_p * 1e3}
@@ -591,7 +596,7 @@ def main():
         den = math.sqrt((vr ** 2).sum() + (sr ** 2).sum())
         # GPU FP64 tiled from the same state, compared with the oracle
         chk = make(0)
-        chk.inspect(ts, partition=a.partition, splits=splits, max_colour_tiles=a.colour_cap)
+        chk.inspect(ts, partition=a.partition, splits=splits, max_colour_tiles=a.colour_cap, sub_tile_sizes=sub_ts)
         chk.set_schedule(schedule)
         gv = torch.from_numpy(np.ascontiguousarray(v0)).cuda()
         gs = torch.from_numpy(np.ascontiguousarray(s0)).cuda()
@@ -629,6 +634,7 @@ def main():
                                f"{'renumbered' if a.mesh_order == 'renumbered' else 'row-major'} triangulation, "
                                f"{mesh.nc} cells, DG P{k}, 3-layer, upwind, order-4 leapfrog",
                    "cells": mesh.nc, "dofs_per_step": dofs, "tile_size": ts, "splits": list(splits),
+                   "sub_tile_sizes": list(sub_ts) if sub_ts else None,
                    "partition": "hilbert" if a.partition == 1 else "chunks of the mesh numbering",
                    "mesh_order": a.mesh_order, "colour_cap": a.colour_cap,
                    "schedule": "dependence-driven" if schedule == 1 else "colour launches"},

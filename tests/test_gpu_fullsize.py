@@ -87,9 +87,9 @@ def _oracle_on_patch(m, cells, lam, mu, rho, k, order, dt, v, s, steps, src, t0)
 
 
 FULL_CASES = [
-    # name, n, k, prec, tile size, splits, schedule, steps, shots
+    # name, n, k, prec, tile size (or one per sub-chain), splits, schedule, steps, shots
     ("jitter512_p2_fp64", 512, 2, 0, 256, (13,), 1, 2, 1),
-    ("jitter512_p2_fp32", 512, 2, 1, 128, (13,), 1, 2, 1),
+    ("jitter512_p2_fp32", 512, 2, 1, (256, 128), (13,), 1, 2, 1),
     ("jitter1024_p3_fp32", 1024, 3, 1, 192, OPS, 1, 1, 1),
     ("jitter1024_p4_fp32", 1024, 4, 1, 192, OPS, 0, 1, 1),
     ("jitter416_p2_fp32_11shots", 416, 2, 1, 256, (13,), 0, 2, 11),
@@ -117,7 +117,10 @@ def test_full_size_sampled_cells_match_oracle(D, name, n, k, prec, ts, splits, s
         g.set_shots(shots, np.array(srcs))
     else:
         g.set_source(*srcs[0])
-    g.inspect(ts, partition=1, splits=splits)
+    if isinstance(ts, tuple):
+        g.inspect(ts[0], partition=1, splits=splits, sub_tile_sizes=ts)
+    else:
+        g.inspect(ts, partition=1, splits=splits)
     g.set_schedule(schedule)
     gv = torch.from_numpy(v if shots > 1 else v[0]).to(dtype).cuda().contiguous()
     gs = torch.from_numpy(s if shots > 1 else s[0]).to(dtype).cuda().contiguous()
