@@ -1,6 +1,7 @@
-// Full-waveform-inversion gradient of libdgtile (included at the end of solver.hip;
-// the paper runs the forward chain only, so this part follows the survey's
-// extension of the method rather than a passage of the paper).
+// Full-waveform-inversion gradient of libdgtile (included at the end of solver.hip).
+// The paper runs the forward chain only; this part extends the method to the
+// gradient of a receiver misfit with respect to the per-cell material, and cites no
+// passage of the paper.
 //
 // Forward: u_{n+1} = Phi(u_n) + s_n with u_n = (v^{n-1/2}, sigma^n), one step of the
 // DG loop chain.  Receivers sample the velocity after every step, r_n = R u_{n+1};
