@@ -578,9 +578,11 @@ static void build_plan(dgt_solver *s) {
             known = known && chain_built(s->K, nops);
             const int cap = s->K == 4 && s->esz == 8 ? TILE_NT[1] : TILE_NT[2];
             const char *env = std::getenv("DGT_TILE_OP");
-            // at P1/P2 the chain kernel also holds the reference element in static LDS
-            const size_t refb =
-                s->K <= 2 ? (size_t)(3 * np * np + 3 * np * (s->K + 1)) * s->esz + 3 * (s->K + 1) * 4 + 16 : 0;
+            // at P1/P2 with the upwind flux the chain kernel also holds the reference
+            // element in static LDS
+            const size_t refb = s->K <= 2 && s->upw
+                                    ? (size_t)(3 * np * np + 3 * np * (s->K + 1)) * s->esz + 3 * (s->K + 1) * 4 + 16
+                                    : 0;
             if (ok && j == end && known && A.nfl == nops && P.max_foot <= cap && !(env && std::atoi(env) == 0)) {
                 int w = 0;
                 for (int q = first_op; q < first_op + nops; ++q) {

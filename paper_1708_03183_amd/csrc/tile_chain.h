@@ -444,11 +444,12 @@ __device__ __forceinline__ void chain_kernel_body(const RefC<K, T> &Rf, const Ti
 template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int NT>
 __global__ __launch_bounds__(NT) void k_tile_chain(const TileArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    if constexpr (K <= 2) {
-        // P1/P2: the reference matrices in LDS; every lane reads the same word (a
-        // broadcast), so the operators no longer hold them in scalar registers, which
-        // the compiler spilled to vector lanes (P3/P4 keep constant memory: their
-        // small tiles lose more to the extra LDS than they gain)
+    if constexpr (K <= 2 && UPW) {
+        // P1/P2 upwind: the reference matrices in LDS; every lane reads the same word
+        // (a broadcast), so the operators no longer hold them in scalar registers,
+        // which the compiler spilled to vector lanes.  P3/P4 keep constant memory
+        // (their small tiles lose more to the extra LDS than they gain), and so does
+        // the central flux (its lighter operators lose more to the LDS reads)
         __shared__ __align__(16) RefC<K, T> sref;
         const uint32_t *src = reinterpret_cast<const uint32_t *>(&R<K, T>());
         uint32_t *dst = reinterpret_cast<uint32_t *>(&sref);
