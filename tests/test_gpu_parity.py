@@ -211,6 +211,53 @@ def test_tiled_fp64_tile_sizes_and_splits(D, ts, part, splits):
     assert err <= 1e-12
 
 
+DEGENERATE_CASES = [
+    # n, k, order, flux, free, ren, steps, ts, splits, schedule
+    (1, 2, 4, 1, 0x8, 3, 6, 1, (13,), 1),       # two-cell mesh, one tile per cell, dependence-driven
+    (1, 2, 4, 1, 0x8, 3, 6, 8, (), 0),          # two-cell mesh, one tile for the whole step chain
+    (2, 1, 2, 0, 0xF, None, 8, 1, (), 1),       # eight cells, order 2, one tile per cell
+    (6, 2, 4, 1, 0x8, 3, 5, 1000, (13,), 1),    # one tile holding the whole mesh: no dependences
+    (6, 1, 4, 1, 0x8, 3, 5, 1, (13,), 1),       # one tile per cell: 72 tiles, 10 colours per half step
+]
+
+
+@pytest.mark.parametrize("n,k,order,flux,free,ren,steps,ts,splits,schedule", DEGENERATE_CASES)
+def test_degenerate_tilings_match_oracle(D, n, k, order, flux, free, ren, steps, ts, splits, schedule):
+    """Smallest meshes, tiles of a single seed cell and a single tile for the whole
+    mesh, under both schedules."""
+    err = _run_pair(D, n, k, order, flux, free, ren, steps, mode=1, ts=ts, splits=splits, schedule=schedule)
+    print(f"degenerate tiling n={n} k={k} order={order} ts={ts} splits={splits} schedule={schedule}: "
+          f"rel L2 err {err:.3e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("mode,schedule", [(0, 0), (1, 0), (1, 1)])
+def test_zero_steps_leave_state_unchanged(D, mode, schedule):
+    m, om, od, gm, gd = _dg_pair(D, 6, 2, 4, 1, 0x8, 3)
+    gd.set_source(0.43, 0.52)
+    v, s = od.zeros()
+    v[:] = I.random_state(v.shape, 5)
+    s[:] = I.random_state(s.shape, 6)
+    if mode == 1:
+        gd.inspect(10, partition=1, splits=(13,))
+        gd.set_schedule(schedule)
+    gv, gs = torch.from_numpy(v.copy()).cuda(), torch.from_numpy(s.copy()).cuda()
+    gd.upload(gv, gs)
+    gd.step(0, mode=mode, t0=0.1)
+    gv.zero_()
+    gs.zero_()
+    gd.download(gv, gs)
+    torch.cuda.synchronize()
+    assert np.array_equal(gv.cpu().numpy(), v) and np.array_equal(gs.cpu().numpy(), s)
+    if mode == 1:  # the dependence counters stay consistent for the next call
+        gd.step(2, mode=1, t0=0.1)
+        gd.download(gv, gs)
+        torch.cuda.synchronize()
+        od.set_source(0.43, 0.52)
+        od.step(v, s, 2, t0=0.1)
+        assert rel_l2([gv.cpu().numpy(), gs.cpu().numpy()], [v, s]) <= 1e-12
+
+
 OP_CASES = [
     # n, k, order, flux, free, ren, steps, ts, splits: one operator application per sub-chain,
     # with the update fused into the operator before it (chain kernel, one operator)
