@@ -121,7 +121,9 @@ __device__ __forceinline__ void chain_op(const RefC<K, T> &Rf, CellRegs<K, T> &r
         for (int f = 0; f < F_COUNT; ++f) {
             if (field_first_op(ORDER, O0, NOPS, f) != O || !((fl >> f) & 1)) continue;
             const T *F = reinterpret_cast<const T *>(a.F[f]) + shot * a.fshot[f];
-            const bool coh = a.persist;
+            // only fields the sub-chain writes can change during the launch; the others
+            // were written by earlier launches and need no device-scope coherence
+            const bool coh = a.persist && field_last_write(ORDER, O0, NOPS, f) >= 0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 if (c >= field_ncomp(f)) break;
