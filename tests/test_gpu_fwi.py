@@ -172,3 +172,56 @@ def test_fwi_intermediates_from_tiled_steps_match_untiled(D, monkeypatch, k, pre
           f"intermediates {err_rec:.2e}, untiled {err_unt:.2e}; between them {diff:.2e}")
     tol = 1e-4 if prec else 1e-10
     assert err_rec <= tol and err_unt <= tol and diff <= tol
+
+
+def _cfl_dt(m, lam, mu, rho, k):
+    p = m.xy[m.c2v]
+    e = [np.hypot(*(p[:, (i + 1) % 3] - p[:, i]).T) for i in range(3)]
+    area = 0.5 * ((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1]) - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1]))
+    hmin = float(np.min(4.0 * area / (e[0] + e[1] + e[2])))
+    return 0.2 * hmin / ((2 * k + 1) * float(np.max(np.sqrt((lam + 2 * mu) / rho))))
+
+
+def test_fwi_gradient_full_size_directional_derivative(D):
+    """At the FWI workload's size (256x256 mesh, 131,072 cells, P2, surface survey,
+    2000 steps; 4 of its 16 shots, FP64 state, tiled at 256 seeds, dependence-driven)
+    the oracle cannot run, but the discrete adjoint gradient is exact for the discrete
+    misfit at any size: its inner product with a perturbation of (lambda, mu, rho)
+    equals the central difference of the misfit along it, up to O(eps^2)."""
+    print("case fwi256 full size: building the mesh and the observed data", flush=True)
+    k, n, nrec, nsteps = 2, 256, 128, 2000
+    m = I.square_mesh(n, jitter=0.2, jitter_seed=30, renumber_seed=31)
+    lam_t, mu_t, rho_t = I.layered_material(m)
+    lam0, mu0, rho0 = [np.full(m.nc, float(x.mean())) for x in (lam_t, mu_t, rho_t)]
+    dt = min(_cfl_dt(m, lam_t, mu_t, rho_t, k), _cfl_dt(m, lam0, mu0, rho0, k))
+    rng = np.random.default_rng(16)
+    shots = np.stack([rng.uniform(0.1, 0.9, 16), rng.uniform(0.96, 0.99, 16)], axis=1)[:4]
+    recs = np.stack([(np.arange(nrec) + 0.5) / nrec, np.ones(nrec)], axis=1)
+    gm = D.Mesh.from_mesh(m)
+
+    def make(lam, mu, rho):
+        s = D.Solver(gm, lam, mu, rho, degree=k, flux=0, time_order=4, precision=0, free_sides=0xF, dt=dt)
+        s.set_shots(len(shots), shots, 100.0, 0.012, 1.0)
+        s.inspect(256, partition=1, splits=(13,))
+        s.set_schedule(1)
+        return s
+
+    obs = make(lam_t, mu_t, rho_t).fwi_forward(recs, nsteps, mode=1)
+    J, gl, gmu, gr = make(lam0, mu0, rho0).fwi_gradient(recs, nsteps, obs, nsnap=32, mode=1)
+    g = np.stack([x.cpu().numpy() for x in (gl, gmu, gr)])
+    prng = np.random.default_rng(2024)
+    dm = np.stack([b * prng.uniform(-1.0, 1.0, m.nc) for b in (lam0, mu0, rho0)])
+
+    def misfit(eps):
+        tr = make(*(base + eps * d for base, d in zip((lam0, mu0, rho0), dm))).fwi_forward(recs, nsteps, mode=1)
+        return 0.5 * float(((tr - obs) ** 2).sum())
+
+    J0 = misfit(0.0)
+    eps = 1e-4
+    fd = (misfit(eps) - misfit(-eps)) / (2 * eps)
+    ad = float((g * dm).sum())
+    err_J, err_d = abs(J0 - J) / J, abs(fd - ad) / abs(ad)
+    print(f"fwi256 full size, 4 shots, {nsteps} steps: misfit {J:.6e} (from traces: rel diff {err_J:.1e}); "
+          f"directional derivative adjoint {ad:.10e}, central difference {fd:.10e}, rel diff {err_d:.2e}")
+    assert err_J <= 1e-12
+    assert err_d <= 1e-6
