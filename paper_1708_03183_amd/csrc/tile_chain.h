@@ -78,9 +78,11 @@ __host__ __device__ constexpr int field_last_write(int order, int o0, int n, int
     return last;
 }
 
-// Field accesses of the dependence-driven schedule are coherent at device scope
-// (they neither hit a stale line of another XCD's L2 nor stay dirty in one), so
-// no cache write-back or invalidation is needed between dependent tiles.
+// Field accesses that can meet another tile's data within one launch of the
+// dependence-driven schedule (every write-back, and the gathers of fields the
+// sub-chain writes) are coherent at device scope: they neither hit a stale line of
+// another XCD's L2 nor stay dirty in one, so no cache write-back or invalidation is
+// needed between dependent tiles.
 template <typename T>
 __device__ __forceinline__ T load_field(const T *p, bool coherent) {
     return coherent ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
