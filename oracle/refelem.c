@@ -18,51 +18,88 @@
 
 int or_np(int k) { return (k + 1) * (k + 2) / 2; }
 
-/* Gauss-Legendre rule with n points on [0,1] (Newton on P_n). */
-static void gauss_legendre01(int n, double *x, double *w) {
+/*
+ * Precision.  Every table of the element (quadrature rules, monomial
+ * coefficients of the basis, mass matrices and their inverse, derivative
+ * matrices) is computed in IEEE binary128 (gcc's __float128: soft-float
+ * arithmetic, 113-bit significand) and rounded to double once, when it leaves
+ * this file.  In double precision the equispaced P4 Vandermonde and mass
+ * inversions lose about two digits, which put the tables 1e-14 away from the
+ * exact rationals; with 113 bits the rounding to double is the only error
+ * left in them.
+ */
+typedef __float128 qreal;
+
+static qreal qabs(qreal x) { return x < 0 ? -x : x; }
+
+/* Gauss-Legendre rule with n points on [0,1]: Newton on P_n from the
+ * Chebyshev-like guess cos(pi (i + 3/4) / (n + 1/2)), iterated in binary128. */
+static void gauss_legendre01_q(int n, qreal *x, qreal *w) {
     for (int i = 0; i < n; i++) {
-        double z = cos(M_PI * (i + 0.75) / (n + 0.5));
-        for (int it = 0; it < 100; it++) {
-            double p0 = 1.0, p1 = z;
+        qreal z = (qreal)cos(M_PI * (i + 0.75) / (n + 0.5));
+        qreal pn = 0, dp = 1;
+        for (int it = 0; it < 200; it++) {
+            qreal p0 = 1, p1 = z;
             for (int m = 2; m <= n; m++) {
-                double p2 = ((2.0 * m - 1.0) * z * p1 - (m - 1.0) * p0) / m;
+                qreal p2 = ((2 * m - 1) * z * p1 - (m - 1) * p0) / m;
                 p0 = p1;
                 p1 = p2;
             }
-            double pn = (n == 1) ? z : p1;
-            double pnm1 = (n == 1) ? 1.0 : p0;
-            double dp = n * (z * pn - pnm1) / (z * z - 1.0);
-            double dz = pn / dp;
+            pn = (n == 1) ? z : p1;
+            qreal pnm1 = (n == 1) ? 1 : p0;
+            dp = n * (z * pn - pnm1) / (z * z - 1);
+            qreal dz = pn / dp;
             z -= dz;
-            if (fabs(dz) < 1e-16) break;
+            if (qabs(dz) < (qreal)1e-33) break;
         }
-        double p0 = 1.0, p1 = z;
+        qreal p0 = 1, p1 = z;
         for (int m = 2; m <= n; m++) {
-            double p2 = ((2.0 * m - 1.0) * z * p1 - (m - 1.0) * p0) / m;
+            qreal p2 = ((2 * m - 1) * z * p1 - (m - 1) * p0) / m;
             p0 = p1;
             p1 = p2;
         }
-        double pn = (n == 1) ? z : p1, pnm1 = (n == 1) ? 1.0 : p0;
-        double dp = n * (z * pn - pnm1) / (z * z - 1.0);
-        x[i] = 0.5 * (1.0 - z);
-        w[i] = 1.0 / ((1.0 - z * z) * dp * dp); /* 2/((1-z^2)P'^2) scaled by 1/2 */
+        qreal pnm1 = (n == 1) ? 1 : p0;
+        pn = (n == 1) ? z : p1;
+        dp = n * (z * pn - pnm1) / (z * z - 1);
+        x[i] = (1 - z) / 2;
+        w[i] = 1 / ((1 - z * z) * dp * dp); /* 2/((1-z^2)P'^2) scaled by 1/2 */
     }
 }
 
-int or_tri_quad(int n, double *pts, double *w) {
-    double *u = malloc(sizeof(double) * n), *wu = malloc(sizeof(double) * n);
-    gauss_legendre01(n, u, wu);
+static void gauss_legendre01(int n, double *x, double *w) {
+    qreal xq[16], wq[16];
+    gauss_legendre01_q(n, xq, wq);
+    for (int i = 0; i < n; i++) {
+        x[i] = (double)xq[i];
+        w[i] = (double)wq[i];
+    }
+}
+
+/* collapsed (Duffy) product rule on the reference triangle, n*n points */
+static int tri_quad_q(int n, qreal *pts, qreal *w) {
+    qreal u[16], wu[16];
+    gauss_legendre01_q(n, u, wu);
     int q = 0;
     for (int a = 0; a < n; a++)
         for (int b = 0; b < n; b++) {
             /* (r, s) = (u_a, (1-u_a) u_b), Jacobian (1-u_a) */
             pts[2 * q] = u[a];
-            pts[2 * q + 1] = (1.0 - u[a]) * u[b];
-            w[q] = wu[a] * wu[b] * (1.0 - u[a]);
+            pts[2 * q + 1] = (1 - u[a]) * u[b];
+            w[q] = wu[a] * wu[b] * (1 - u[a]);
             q++;
         }
-    free(u);
-    free(wu);
+    return q;
+}
+
+int or_tri_quad(int n, double *pts, double *w) {
+    if (n < 1 || n > 16) return -1;
+    qreal pq[2 * 256], wq[256];
+    int q = tri_quad_q(n, pq, wq);
+    for (int i = 0; i < q; i++) {
+        pts[2 * i] = (double)pq[2 * i];
+        pts[2 * i + 1] = (double)pq[2 * i + 1];
+        w[i] = (double)wq[i];
+    }
     return q;
 }
 
@@ -77,78 +114,74 @@ static void mono_exps(int k, int *ea, int *eb) {
         }
 }
 
-static double ipow(double x, int e) {
-    double r = 1.0;
+static qreal ipow(qreal x, int e) {
+    qreal r = 1;
     for (int i = 0; i < e; i++) r *= x;
     return r;
 }
 
 /* Gauss-Jordan inverse with partial pivoting; returns 0 if singular. */
-static int invert(int n, const double *A, double *Ainv) {
-    double *a = malloc(sizeof(double) * n * 2 * n);
+static int invert(int n, const qreal *A, qreal *Ainv) {
+    qreal a[15 * 30];
     for (int i = 0; i < n; i++)
         for (int j = 0; j < 2 * n; j++)
-            a[i * 2 * n + j] = (j < n) ? A[i * n + j] : (j - n == i ? 1.0 : 0.0);
+            a[i * 2 * n + j] = (j < n) ? A[i * n + j] : (j - n == i ? 1 : 0);
     for (int c = 0; c < n; c++) {
         int p = c;
         for (int r = c + 1; r < n; r++)
-            if (fabs(a[r * 2 * n + c]) > fabs(a[p * 2 * n + c])) p = r;
-        if (fabs(a[p * 2 * n + c]) < 1e-300) {
-            free(a);
-            return 0;
-        }
+            if (qabs(a[r * 2 * n + c]) > qabs(a[p * 2 * n + c])) p = r;
+        if (qabs(a[p * 2 * n + c]) < (qreal)1e-300) return 0;
         if (p != c)
             for (int j = 0; j < 2 * n; j++) {
-                double t = a[c * 2 * n + j];
+                qreal t = a[c * 2 * n + j];
                 a[c * 2 * n + j] = a[p * 2 * n + j];
                 a[p * 2 * n + j] = t;
             }
-        double d = a[c * 2 * n + c];
+        qreal d = a[c * 2 * n + c];
         for (int j = 0; j < 2 * n; j++) a[c * 2 * n + j] /= d;
         for (int r = 0; r < n; r++) {
             if (r == c) continue;
-            double f = a[r * 2 * n + c];
-            if (f != 0.0)
+            qreal f = a[r * 2 * n + c];
+            if (f != 0)
                 for (int j = 0; j < 2 * n; j++) a[r * 2 * n + j] -= f * a[c * 2 * n + j];
         }
     }
     for (int i = 0; i < n; i++)
         for (int j = 0; j < n; j++) Ainv[i * n + j] = a[i * 2 * n + n + j];
-    free(a);
     return 1;
 }
 
-static void ref_nodes(int k, double *nodes) {
+static void ref_nodes(int k, qreal *nodes) {
     int m = 0;
     for (int j = 0; j <= k; j++)
         for (int i = 0; i <= k - j; i++) {
-            nodes[2 * m] = (double)i / k;
-            nodes[2 * m + 1] = (double)j / k;
+            nodes[2 * m] = (qreal)i / k;
+            nodes[2 * m + 1] = (qreal)j / k;
             m++;
         }
 }
 
 /* Coefficients C[m*Np+i] of phi_i in the monomial basis: C = V^{-1}. */
-static int lagrange_coeffs(int k, double *C) {
+static int lagrange_coeffs(int k, qreal *C) {
     int np = or_np(k);
     int ea[15], eb[15];
-    double nodes[30];
+    qreal nodes[30];
     mono_exps(k, ea, eb);
     ref_nodes(k, nodes);
-    double V[225];
+    qreal V[225];
     for (int n = 0; n < np; n++)
         for (int m = 0; m < np; m++) V[n * np + m] = ipow(nodes[2 * n], ea[m]) * ipow(nodes[2 * n + 1], eb[m]);
     return invert(np, V, C);
 }
 
-static void eval_basis(int k, const double *C, double r, double s, double *phi, double *dr, double *ds) {
+static void eval_basis(int k, const qreal *C, qreal r, qreal s, qreal *phi, qreal *dr, qreal *ds) {
     int np = or_np(k);
     int ea[15], eb[15];
     mono_exps(k, ea, eb);
     for (int i = 0; i < np; i++) {
-        double p = 0, pr = 0, ps = 0;
+        qreal p = 0, pr = 0, ps = 0;
         for (int m = 0; m < np; m++) {
-            double c = C[m * np + i];
+            qreal c = C[m * np + i];
             p += c * ipow(r, ea[m]) * ipow(s, eb[m]);
             if (ea[m] > 0) pr += c * ea[m] * ipow(r, ea[m] - 1) * ipow(s, eb[m]);
             if (eb[m] > 0) ps += c * eb[m] * ipow(r, ea[m]) * ipow(s, eb[m] - 1);
@@ -159,19 +192,28 @@ static void eval_basis(int k, const double *C, double r, double s, double *phi, 
     }
 }
 
+static void round_out(int n, const qreal *q, double *d) {
+    if (d)
+        for (int i = 0; i < n; i++) d[i] = (double)q[i];
+}
+
 int or_basis(int k, double r, double s, double *phi) {
     if (k < 1 || k > 4) return -1;
-    double C[225];
+    qreal C[225], p[15];
     if (!lagrange_coeffs(k, C)) return -2;
-    eval_basis(k, C, r, s, phi, NULL, NULL);
+    eval_basis(k, C, r, s, p, NULL, NULL);
+    round_out(or_np(k), p, phi);
     return 0;
 }
 
 /* Internal: basis values + derivatives (used by dg.c). */
 int or_basis_full(int k, double r, double s, double *phi, double *dr, double *ds) {
-    double C[225];
+    qreal C[225], p[15], pr[15], ps[15];
     if (!lagrange_coeffs(k, C)) return -2;
-    eval_basis(k, C, r, s, phi, dr, ds);
+    eval_basis(k, C, r, s, p, pr, ps);
+    round_out(or_np(k), p, phi);
+    round_out(or_np(k), pr, dr);
+    round_out(or_np(k), ps, ds);
     return 0;
 }
 
@@ -179,54 +221,57 @@ int or_refelem(int k, double *nodes, double *M, double *Minv, double *Dr, double
                int32_t *fnodes) {
     if (k < 1 || k > 4) return -1;
     int np = or_np(k), nfp = k + 1;
-    double C[225], nd[30];
+    qreal C[225], nd[30];
     if (!lagrange_coeffs(k, C)) return -2;
     ref_nodes(k, nd);
-    if (nodes) memcpy(nodes, nd, sizeof(double) * 2 * np);
-    double Mloc[225];
+    round_out(2 * np, nd, nodes);
+    qreal Mloc[225], Mi[225];
     {
         int nq1 = k + 2;
-        double pts[2 * 36], w[36], phi[15];
-        int nq = or_tri_quad(nq1, pts, w);
-        memset(Mloc, 0, sizeof(Mloc));
+        qreal pts[2 * 36], w[36], phi[15];
+        int nq = tri_quad_q(nq1, pts, w);
+        for (int i = 0; i < np * np; i++) Mloc[i] = 0;
         for (int q = 0; q < nq; q++) {
             eval_basis(k, C, pts[2 * q], pts[2 * q + 1], phi, NULL, NULL);
             for (int i = 0; i < np; i++)
                 for (int j = 0; j < np; j++) Mloc[i * np + j] += w[q] * phi[i] * phi[j];
         }
     }
-    if (M) memcpy(M, Mloc, sizeof(double) * np * np);
-    if (Minv && !invert(np, Mloc, Minv)) return -2;
+    round_out(np * np, Mloc, M);
+    if (Minv) {
+        if (!invert(np, Mloc, Mi)) return -2;
+        round_out(np * np, Mi, Minv);
+    }
     if (Dr || Ds) {
-        double phi[15], pr[15], ps[15];
+        qreal phi[15], pr[15], ps[15];
         for (int i = 0; i < np; i++) {
             eval_basis(k, C, nd[2 * i], nd[2 * i + 1], phi, pr, ps);
             for (int j = 0; j < np; j++) {
-                if (Dr) Dr[i * np + j] = pr[j];
-                if (Ds) Ds[i * np + j] = ps[j];
+                if (Dr) Dr[i * np + j] = (double)pr[j];
+                if (Ds) Ds[i * np + j] = (double)ps[j];
             }
         }
     }
     if (M1) {
         /* 1-D Lagrange basis on t_m = m/k, facet mass by Gauss-Legendre */
-        double V[25], Ci[25];
+        qreal V[25], Ci[25], x[8], w[8], Mf[25];
         for (int a = 0; a < nfp; a++)
-            for (int m = 0; m < nfp; m++) V[a * nfp + m] = ipow((double)a / k, m);
+            for (int m = 0; m < nfp; m++) V[a * nfp + m] = ipow((qreal)a / k, m);
         if (!invert(nfp, V, Ci)) return -2;
         int nq = k + 2;
-        double x[8], w[8];
-        gauss_legendre01(nq, x, w);
-        memset(M1, 0, sizeof(double) * nfp * nfp);
+        gauss_legendre01_q(nq, x, w);
+        for (int i = 0; i < nfp * nfp; i++) Mf[i] = 0;
         for (int q = 0; q < nq; q++) {
-            double psi[5];
+            qreal psi[5];
             for (int a = 0; a < nfp; a++) {
-                double p = 0;
+                qreal p = 0;
                 for (int m = 0; m < nfp; m++) p += Ci[m * nfp + a] * ipow(x[q], m);
                 psi[a] = p;
             }
             for (int a = 0; a < nfp; a++)
-                for (int b = 0; b < nfp; b++) M1[a * nfp + b] += w[q] * psi[a] * psi[b];
+                for (int b = 0; b < nfp; b++) Mf[a * nfp + b] += w[q] * psi[a] * psi[b];
         }
+        round_out(nfp * nfp, Mf, M1);
     }
     if (fnodes) {
         /* facet f joins local vertices f and f+1 (mod 3); its nodes run from the

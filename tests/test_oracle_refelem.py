@@ -64,3 +64,63 @@ def test_facet_nodes(k):
         a, b = verts[f], verts[(f + 1) % 3]
         for m in range(k + 1):
             assert np.allclose(nodes[fn[f, m]], a + (b - a) * m / k)
+
+
+def _exact_tables(k):
+    """The element's tables in exact rational arithmetic (Python fractions):
+    Lagrange basis from the monomial Vandermonde matrix, mass matrices from the
+    exact monomial moments int r^a s^b = a! b! / (a+b+2)! and int_0^1 t^e = 1/(e+1)."""
+    from fractions import Fraction as F
+
+    def inv(A):
+        n = len(A)
+        a = [list(row) + [F(int(i == j)) for j in range(n)] for i, row in enumerate(A)]
+        for c in range(n):
+            p = next(r for r in range(c, n) if a[r][c] != 0)
+            a[c], a[p] = a[p], a[c]
+            d = a[c][c]
+            a[c] = [x / d for x in a[c]]
+            for r in range(n):
+                if r != c and a[r][c] != 0:
+                    f = a[r][c]
+                    a[r] = [x - f * y for x, y in zip(a[r], a[c])]
+        return [row[n:] for row in a]
+
+    nodes = [(F(i, k), F(j, k)) for j in range(k + 1) for i in range(k + 1 - j)]
+    ex = [(d - b, b) for d in range(k + 1) for b in range(d + 1)]
+    n = len(nodes)
+    C = inv([[r ** a * s ** b for (a, b) in ex] for (r, s) in nodes])
+
+    def der(a, b, r, s, wrt_r):
+        if wrt_r:
+            return a * r ** (a - 1) * s ** b if a else F(0)
+        return b * r ** a * s ** (b - 1) if b else F(0)
+
+    Dr = [[sum(der(*ex[m], *nodes[i], True) * C[m][j] for m in range(n)) for j in range(n)] for i in range(n)]
+    Ds = [[sum(der(*ex[m], *nodes[i], False) * C[m][j] for m in range(n)) for j in range(n)] for i in range(n)]
+    mom = lambda a, b: F(math.factorial(a) * math.factorial(b), math.factorial(a + b + 2))
+    M = [[sum(C[p][i] * C[q][j] * mom(ex[p][0] + ex[q][0], ex[p][1] + ex[q][1]) for p in range(n) for q in range(n))
+          for j in range(n)] for i in range(n)]
+    C1 = inv([[F(a, k) ** e for e in range(k + 1)] for a in range(k + 1)])
+    M1 = [[sum(C1[e1][a] * C1[e2][b] * F(1, e1 + e2 + 1) for e1 in range(k + 1) for e2 in range(k + 1))
+           for b in range(k + 1)] for a in range(k + 1)]
+    return dict(Dr=Dr, Ds=Ds, M=M, Minv=inv(M), M1=M1)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_tables_are_the_exact_rationals_rounded_once(k):
+    """Every table equals the exact rational value rounded to the nearest double
+    (up to one unit in the last place: the tables are computed in binary128 and
+    rounded once, so double rounding may move a tie by one ulp); entries that are
+    exactly zero come out below 1e-30."""
+    r = O.refelem(k)
+    ex = _exact_tables(k)
+    for name, exact in ex.items():
+        got = r[name]
+        for i, row in enumerate(exact):
+            for j, e in enumerate(row):
+                g = got[i, j]
+                if e == 0:
+                    assert abs(g) < 1e-30, (name, i, j, g)
+                else:
+                    assert abs(g - float(e)) <= np.spacing(abs(float(e))), (name, i, j, g, float(e))
