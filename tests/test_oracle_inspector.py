@@ -284,3 +284,49 @@ def test_sub_chains_with_their_own_tile_sizes():
     d.step_tiled(mixed, v2, s2, 3, t0=0.1)
     err = np.sqrt(((v - v2) ** 2).sum() + ((sg - s2) ** 2).sum()) / np.sqrt((v ** 2).sum() + (sg ** 2).sum())
     assert err <= 1e-14
+
+
+def _hilbert_ranks(xy):
+    """Seed ranks of points under the Hilbert partition: one seed per tile, so the
+    tile of seed i is its rank along the curve."""
+    ch = O.OChain()
+    st = ch.set(len(xy))
+    ch.loop(st, [(-1, O.R, 0)])
+    s = ch.inspect(1, partition=1, seed_xy=np.ascontiguousarray(xy, np.float64))
+    return s.sigma(0, len(xy))
+
+
+# The order-2 Hilbert curve on a 4x4 grid, derived by hand from its construction:
+# the top level visits the quadrants (0,0) -> (0,1) -> (1,1) -> (1,0) (x right, y up);
+# the lower-left quadrant is the order-1 curve transposed (enter at (0,0), leave
+# upwards at (0,1)), the two upper quadrants repeat the order-1 curve unrotated,
+# and the lower-right quadrant is the order-1 curve reflected in the anti-diagonal
+# (enter at (3,1) from above, leave at (3,0)).
+HILBERT_ORDER2 = [(0, 0), (1, 0), (1, 1), (0, 1), (0, 2), (0, 3), (1, 3), (1, 2),
+                  (2, 2), (2, 3), (3, 3), (3, 2), (3, 1), (2, 1), (2, 0), (3, 0)]
+
+
+def test_hilbert_order2_curve_by_hand():
+    """Cell centres of a 4x4 grid, plus the two corners that fix the bounding box at
+    the unit square, ranked by the seed order: the 16 centres come in the order of
+    the hand-derived order-2 curve (the 2^16 curve visits each quarter-of-a-quarter
+    whole before the next)."""
+    pts = [((x + 0.5) / 4, (y + 0.5) / 4) for (x, y) in HILBERT_ORDER2[::-1]]  # listed backwards on purpose
+    xy = np.array(pts + [(0.0, 0.0), (1.0, 1.0)])
+    r = _hilbert_ranks(xy)
+    order = [int(i) for i in np.argsort(r) if i < 16]
+    assert [HILBERT_ORDER2[::-1][i] for i in order] == HILBERT_ORDER2
+
+
+def test_hilbert_curve_is_continuous_at_order4():
+    """On a 16x16 grid of cell centres consecutive seeds along the curve are edge
+    neighbours (a property of the Hilbert curve at every level; a wrong rotation
+    or reflection in any level breaks it), it starts in the lower-left cell and
+    ends in the lower-right one."""
+    g = [(x, y) for y in range(16) for x in range(16)]
+    xy = np.array([((x + 0.5) / 16, (y + 0.5) / 16) for (x, y) in g] + [(0.0, 0.0), (1.0, 1.0)])
+    r = _hilbert_ranks(xy)
+    walk = [g[i] for i in np.argsort(r) if i < 256]
+    assert walk[0] == (0, 0) and walk[-1] == (15, 0)
+    steps = [abs(a[0] - b[0]) + abs(a[1] - b[1]) for a, b in zip(walk, walk[1:])]
+    assert steps == [1] * 255

@@ -1,7 +1,8 @@
 """Pins of the oracle DG chain against mathematics the paper fixes or implies:
 exact discrete energy conservation (central flux), energy decay (upwind),
 plane-wave convergence, temporal order against the exact semi-discrete
-solution, Riemann-flux consistency and the injected source integral."""
+solution and the injected source integral.  The facet fluxes themselves are
+pinned against the exact Riemann problem in test_oracle_riemann.py."""
 import math
 
 import numpy as np
