@@ -320,6 +320,15 @@ dgt_status dgt_last_step_timing(const dgt_solver *s, double *total_ms, double *k
 dgt_status dgt_solver_info(const dgt_solver *s, int64_t *np, int64_t *bytes_per_step, int64_t *lds_bytes);
 void dgt_solver_destroy(dgt_solver *s);
 
+/* Host copies of the reference-element tables the kernels of degree `degree`
+ * (1..4) use (Sec. 7.1: nodal Lagrange P_k on the equispaced nodes of the
+ * reference triangle, exact integration; the tables are the exact rationals
+ * rounded to double once).  dr, ds: [Np*Np], D[i*Np+j] = d phi_j / dr (ds) at
+ * node i; minv: [Np*Np] inverse reference mass; lift: [3][Np][k+1], the inverse
+ * mass times facet f's mass matrix.  Any pointer may be NULL.  No device work;
+ * EINVAL for a degree outside 1..4. */
+dgt_status dgt_refelem(int32_t degree, double *dr, double *ds, double *minv, double *lift);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,8 +6,10 @@
 // function is built symbolically with Silvester's product formula in
 // barycentric coordinates, so derivatives are exact polynomial derivatives and
 // integrals use the exact monomial moments int r^a s^b = a! b! / (a+b+2)!.
-// The expanded P4 coefficients alternate in sign, so every step runs in x87
-// extended precision (64-bit mantissa) and is rounded to double once.
+// The expanded P4 coefficients alternate in sign and the equispaced P4 mass
+// matrix is ill-conditioned (about 1e5), so every step runs in IEEE binary128
+// (113-bit significand) and each table is rounded to double once: the tables
+// are then the exactly rounded values of the exact rationals.
 #include "refelem.h"
 
 #include <cmath>
@@ -17,7 +19,9 @@ namespace dgt {
 
 namespace {
 
-using xf = long double;
+using xf = __float128;
+
+xf xabs(xf v) { return v < 0 ? -v : v; }
 constexpr int D = 9;  // degree bound + 1 for products of two P4 polynomials
 
 struct Poly {  // sum c[a][b] r^a s^b
@@ -101,7 +105,7 @@ std::vector<xf> lu_inverse(const std::vector<xf> &A, int n) {
     for (int c = 0; c < n; ++c) {
         int p = c;
         for (int r = c + 1; r < n; ++r)
-            if (std::fabs(lu[r * n + c]) > std::fabs(lu[p * n + c])) p = r;
+            if (xabs(lu[r * n + c]) > xabs(lu[p * n + c])) p = r;
         if (lu[p * n + c] == 0) throw std::runtime_error("singular reference matrix");
         piv[c] = p;
         if (p != c)
@@ -127,7 +131,11 @@ std::vector<xf> lu_inverse(const std::vector<xf> &A, int n) {
     return inv;
 }
 
-std::vector<double> to_double(const std::vector<xf> &v) { return std::vector<double>(v.begin(), v.end()); }
+std::vector<double> to_double(const std::vector<xf> &v) {
+    std::vector<double> d(v.size());
+    for (size_t i = 0; i < v.size(); ++i) d[i] = (double)v[i];
+    return d;
+}
 
 }  // namespace
 
@@ -207,7 +215,7 @@ RefElem make_refelem(int k) {
                 E.lift[(f * np + i) * nfp + m] = (double)v;
             }
     E.phi = [phi](double r, double s, double *out) {
-        for (size_t i = 0; i < phi.size(); ++i) out[i] = (double)phi[i].eval(r, s);
+        for (size_t i = 0; i < phi.size(); ++i) out[i] = (double)phi[i].eval((xf)r, (xf)s);
     };
     return E;
 }

@@ -1328,6 +1328,18 @@ dgt_status dgt_solver_info(const dgt_solver *s, int64_t *np, int64_t *bytes_per_
 
 void dgt_solver_destroy(dgt_solver *s) { delete s; }
 
+dgt_status dgt_refelem(int32_t degree, double *dr, double *ds, double *minv, double *lift) {
+    return guard([&] {
+        DGT_REQUIRE(degree >= 1 && degree <= 4, DGT_EINVAL, "degree must be 1..4");
+        const RefElem E = make_refelem(degree);
+        const size_t n2 = (size_t)E.np * E.np;
+        if (dr) std::memcpy(dr, E.Dr.data(), n2 * sizeof(double));
+        if (ds) std::memcpy(ds, E.Ds.data(), n2 * sizeof(double));
+        if (minv) std::memcpy(minv, E.Minv.data(), n2 * sizeof(double));
+        if (lift) std::memcpy(lift, E.lift.data(), E.lift.size() * sizeof(double));
+    });
+}
+
 }  // extern "C"
 
 #include "fwi_impl.h"

@@ -100,6 +100,7 @@ _SIGS = {
     "dgt_solver_set_wait_limit": [_p, C.c_int64],
     "dgt_solver_info": [_p, _i64, _i64, _i64],
     "dgt_solver_destroy": [_p],
+    "dgt_refelem": [C.c_int32, _p, _p, _p, _p],
     "dgt_last_error": [],
     "dgt_version": [],
 }
@@ -159,6 +160,15 @@ def _inspect_params(tile_size, partition, seed_xy, max_rounds, splits, max_colou
 
 
 # --------------------------------------------------------------- tier 1
+def refelem(degree: int) -> dict:
+    """Host copies of the reference-element tables the degree-k kernels use."""
+    npn = (degree + 1) * (degree + 2) // 2
+    t = {n: np.zeros((npn, npn)) for n in ("Dr", "Ds", "Minv")}
+    t["lift"] = np.zeros((3, npn, degree + 1))
+    _check(lib().dgt_refelem(degree, _np_ptr(t["Dr"]), _np_ptr(t["Ds"]), _np_ptr(t["Minv"]), _np_ptr(t["lift"])))
+    return t
+
+
 class Chain:
     """Generic loop chain (sets, maps, loops with descriptors)."""
 

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(L, name), name
     assert set(declared) == set(D.exported_symbols())
-    assert L.dgt_version() == 103
+    assert L.dgt_version() == 104
 
 
 @pytest.mark.parametrize("n,jit,ren,per", [(1, 0, None, 0), (5, 0.2, 3, 0), (16, 0.2, 7, 0), (6, 0.0, None, 3),
@@ -65,3 +65,26 @@ def test_chain_validation_on_host():
     with pytest.raises(D.DgtError):
         ch.loop(v, [(mp, D.R)])  # map does not start at the loop set
     assert ch.loop(c, [(mp, D.INC), (-1, D.R)]) == 0
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_library_reference_tables_are_exact_rationals_rounded_once(k):
+    """The tables the library uploads to its kernels (derivative matrices, inverse
+    mass, lift) equal the exact rationals to one unit in the last place: the
+    library and the oracle then build the same element without sharing code."""
+    from test_oracle_refelem import _exact_tables
+    ex = _exact_tables(k)
+    got = D.refelem(k)
+    fn = O.refelem(k)["fnodes"]
+    npn = len(ex["Dr"])
+    lift = [[[sum(ex["Minv"][i][fn[f, q]] * ex["M1"][q][m] for q in range(k + 1)) for m in range(k + 1)]
+             for i in range(npn)] for f in range(3)]
+    for name, exact, g in [("Dr", ex["Dr"], got["Dr"]), ("Ds", ex["Ds"], got["Ds"]),
+                           ("Minv", ex["Minv"], got["Minv"])] + \
+            [(f"lift{f}", lift[f], got["lift"][f]) for f in range(3)]:
+        for i, row in enumerate(exact):
+            for j, e in enumerate(row):
+                if e == 0:  # binary128 rounding residue, far below an ulp of any nonzero entry
+                    assert abs(g[i, j]) < 1e-26, (name, i, j, g[i, j])
+                else:
+                    assert abs(g[i, j] - float(e)) <= np.spacing(abs(float(e))), (name, i, j, g[i, j], float(e))
