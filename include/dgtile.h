@@ -258,6 +258,18 @@ dgt_status dgt_step(dgt_solver *s, int64_t nsteps, int32_t mode, double t0);
  * in FP64 on the GPU.  v, sig_new, sig_old: device, caller layout of one shot,
  * solver precision.  Synchronises the stream. */
 dgt_status dgt_energy(dgt_solver *s, const void *v, const void *sig_new, const void *sig_old, double *out);
+/* dgt_energy without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same kernels and summation order, hence the same value
+ * bit for bit.  Its partial sums live in a fixed per-GPU array inside the
+ * library, whose address is looked up once per device
+ * when the first solver on that device is created; nothing is allocated per
+ * call.  Limit: the solver's mesh may have at most 4,194,304 (2^22) cells
+ * (the array holds 16,385 doubles, 128 KiB); beyond that DGT_EINVAL with a
+ * message.  Every call on one GPU shares that array: calls that overlap on a
+ * GPU (several streams or host threads) race and must be serialised by the
+ * caller.  Arguments as for dgt_energy; synchronises the stream. */
+dgt_status dgt_energy_noalloc(dgt_solver *s, const void *v, const void *sig_new, const void *sig_old, double *out);
 /* Full-waveform inversion (an extension beyond the paper's forward chain).
  * Receivers are velocity sensors: receiver r reads sum_i phi_i(x_r) v_i of the
  * lowest-id cell containing x_r, after every time step.  Both calls start from

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 
 #include "dg_device.h"
@@ -48,6 +49,7 @@ struct dgt_solver {
     const dgt_mesh *mesh_handle = nullptr;
     dgt_solver_params p{};
     hipStream_t st = nullptr;
+    int dev = 0;  // device current at creation (the stream's device)
     dgt::RefElem E;
     int K = 1, fp32 = 0, upw = 0, haspen = 0;
     int64_t nc = 0, nf = 0, nb = 0;
@@ -842,6 +844,36 @@ void dgt_mesh_destroy(dgt_mesh *m) { delete m; }
 
 namespace dgt {
 
+// Scratch of the allocation-free energy reduction: the per-workgroup partial
+// energies of k_energy and their sum, in a file-scope device array (one copy per
+// GPU, held until the process ends).  Host code never passes the array's name to
+// a kernel: each device's address is looked up once, with that device current,
+// when the first solver on it is created.
+constexpr int64_t ENERGY_NOALLOC_MAX_CELLS = int64_t(1) << 22;
+constexpr int64_t ENERGY_NOALLOC_BLOCKS = ENERGY_NOALLOC_MAX_CELLS / 256;
+static __device__ __align__(256) double scratch[ENERGY_NOALLOC_BLOCKS + 1];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// with device `dev` current
+static void energy_scratch_init(int dev) {
+    DGT_REQUIRE(dev >= 0 && dev < SCRATCH_MAX_DEVICES, DGT_EUNSUPPORTED, "device id beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return;
+    void *p = nullptr;
+    DGT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    DGT_REQUIRE(p != nullptr, DGT_EHIP, "hipGetSymbolAddress returned NULL for the energy scratch");
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+}
+
+static double *energy_scratch(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    double *p = dev >= 0 && dev < SCRATCH_MAX_DEVICES ? g_scratch_ptr[dev] : nullptr;
+    DGT_REQUIRE(p, DGT_ESTATE, "energy scratch of the solver's device was not set up");
+    return p;
+}
+
 // The solver without the sign check of dt: the FWI adjoint runs the chain backward
 // in time (dt < 0) on a solver of its own.
 static std::unique_ptr<dgt_solver> new_solver(const dgt_mesh *m, const double *lam, const double *mu,
@@ -857,6 +889,8 @@ static std::unique_ptr<dgt_solver> new_solver(const dgt_mesh *m, const double *l
     for (int64_t c = 0; c < M.nc; ++c)
         DGT_REQUIRE(lam[c] > 0 && mu[c] > 0 && rho[c] > 0, DGT_EINVAL, "material must be positive");
     auto s = std::make_unique<dgt_solver>();
+    DGT_HIP(hipGetDevice(&s->dev));
+    energy_scratch_init(s->dev);
     s->mesh = &M;
     s->mesh_handle = m;
     s->p = *p;
@@ -1310,6 +1344,29 @@ dgt_status dgt_energy(dgt_solver *s, const void *v, const void *sig_new, const v
         });
         k_sum_partials<<<1, 256, 0, s->st>>>(part.p, nblk, res.p);
         *out = res.download(s->st)[0];
+    });
+}
+
+dgt_status dgt_energy_noalloc(dgt_solver *s, const void *v, const void *sig_new, const void *sig_old, double *out) {
+    return guard([&] {
+        DGT_REQUIRE(s && v && sig_new && sig_old && out, DGT_EINVAL, "NULL argument");
+        const int64_t nc = s->nc;
+        DGT_REQUIRE(nc <= ENERGY_NOALLOC_MAX_CELLS, DGT_EINVAL,
+                    "dgt_energy_noalloc: " + std::to_string(nc) + " cells exceed its limit of " +
+                        std::to_string(ENERGY_NOALLOC_MAX_CELLS));
+        double *ptr = energy_scratch(s->dev);
+        const int64_t nblk = (nc + 255) / 256;
+        // every partial in [0, nblk) and the sum are written before they are read: nothing to clear
+        dispatch(s, [&]<int K, typename T>() {
+            k_energy<K, T><<<nblk, 256, 0, s->st>>>((const T *)v, (const T *)sig_new, (const T *)sig_old,
+                                                  (const T *)s->geo.p, s->rank.p, nc, ptr);
+        });
+        k_sum_partials<<<1, 256, 0, s->st>>>(ptr, nblk, ptr + ENERGY_NOALLOC_BLOCKS);
+        DGT_HIP(hipGetLastError());
+        double h = 0.0;
+        DGT_HIP(hipMemcpyAsync(&h, ptr + ENERGY_NOALLOC_BLOCKS, sizeof(double), hipMemcpyDeviceToHost, s->st));
+        DGT_HIP(hipStreamSynchronize(s->st));
+        *out = h;
     });
 }
 

@@ -94,6 +94,7 @@ _SIGS = {
     "dgt_state_download": [_p, _p, _p],
     "dgt_step": [_p, C.c_int64, C.c_int32, C.c_double],
     "dgt_energy": [_p, _p, _p, _p, C.POINTER(C.c_double)],
+    "dgt_energy_noalloc": [_p, _p, _p, _p, C.POINTER(C.c_double)],
     "dgt_last_step_timing": [_p, C.POINTER(C.c_double), C.POINTER(C.c_double), _i64],
     "dgt_solver_profile": [_p, C.c_int32],
     "dgt_solver_set_schedule": [_p, C.c_int32],
@@ -421,14 +422,16 @@ class Solver:
     def step(self, nsteps: int, mode: int = 1, t0: float = 0.0):
         _check(lib().dgt_step(self.h, int(nsteps), int(mode), float(t0)))
 
-    def energy(self, v, s_new, s_old) -> float:
-        """Energy of one shot's state (tensors of one shot, contiguous)."""
+    def energy(self, v, s_new, s_old, noalloc: bool = False) -> float:
+        """Energy of one shot's state (tensors of one shot, contiguous);
+        noalloc selects dgt_energy_noalloc."""
         assert tuple(v.shape) == (2, self.np, self.mesh.nc) and v.is_contiguous()
         assert tuple(s_new.shape) == (3, self.np, self.mesh.nc) and s_new.is_contiguous()
         assert tuple(s_old.shape) == (3, self.np, self.mesh.nc) and s_old.is_contiguous()
         out = C.c_double()
-        _check(lib().dgt_energy(self.h, C.c_void_p(v.data_ptr()), C.c_void_p(s_new.data_ptr()),
-                                C.c_void_p(s_old.data_ptr()), C.byref(out)))
+        fn = lib().dgt_energy_noalloc if noalloc else lib().dgt_energy
+        _check(fn(self.h, C.c_void_p(v.data_ptr()), C.c_void_p(s_new.data_ptr()), C.c_void_p(s_old.data_ptr()),
+                  C.byref(out)))
         return out.value
 
     def set_schedule(self, mode: int):
