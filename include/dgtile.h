@@ -305,7 +305,10 @@ dgt_status dgt_fwi_gradient(dgt_solver *s, const dgt_fwi_params *p, const double
  * chain kernel (whole operator applications) launch once; workgroups take tiles
  * in colour order from a ticket counter and a tile starts when every tile of a
  * lower colour whose footprint meets its own has finished (device-scope
- * counters, release/acquire), so no colour waits for a whole earlier colour.
+ * counters; field data that can cross tiles is read and written with
+ * device-coherent accesses, and each workgroup waits for its stores to
+ * complete before it counts its successors), so no colour waits for a whole
+ * earlier colour.
  * Every wait is bounded: if one gives up, the next dgt_step or
  * dgt_state_download returns DGT_ESTATE and the counters are reset.  In mode 1,
  * dgt_step synchronises the stream on entry.  mode: 0 or 1, else DGT_EINVAL. */
