@@ -335,6 +335,15 @@ dgt_status dgt_last_step_timing(const dgt_solver *s, double *total_ms, double *k
 dgt_status dgt_solver_info(const dgt_solver *s, int64_t *np, int64_t *bytes_per_step, int64_t *lds_bytes);
 void dgt_solver_destroy(dgt_solver *s);
 
+/* Tile kernel of each sub-chain of the current plan (after a successful
+ * dgt_solver_inspect; *nsub = 0 before): 0 the generic in-LDS executor, 1 the
+ * register-resident chain kernel (whole operator applications, one thread per
+ * footprint cell), 2 the matrix-core kernel (whole operator applications at
+ * degrees 3 and 4, per-cell contractions as 16x16x4 MFMA products).  kinds: host
+ * [*nsub] or NULL.  The environment variable DGT_TILE_OP read at inspection
+ * selects 0 (generic everywhere) or 1 (the chain kernel where it is built) instead
+ * of the default. */
+dgt_status dgt_solver_kernels(const dgt_solver *s, int32_t *nsub, int32_t *kinds);
 /* Host copies of the reference-element tables the kernels of degree `degree`
  * (1..4) use (Sec. 7.1: nodal Lagrange P_k on the equispaced nodes of the
  * reference triangle, exact integration; the tables are the exact rationals

@@ -2,6 +2,7 @@
 // loop chain handed to the GPU inspector, the executor plan, and the step,
 // state and energy entry points.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -577,15 +578,71 @@ static void build_plan(dgt_solver *s) {
             const int nops = o - first_op;
             bool known = false;
             for (const auto &c : TILE_CHAINS) known |= c[0] == order && c[1] == first_op && c[2] == nops;
-            known = known && chain_built(s->K, nops);
+            const bool whole = ok && j == end && known && A.nfl == nops;
             const int cap = s->K == 4 && s->esz == 8 ? TILE_NT[1] : TILE_NT[2];
+            // DGT_TILE_OP: 0 forces the generic kernel, 1 the register-resident chain kernel
+            // where it is built (at P3/P4 the matrix-core kernel is the default)
             const char *env = std::getenv("DGT_TILE_OP");
+            const int force = env ? std::atoi(env) : -1;
             // at P1/P2 with the upwind flux the chain kernel also holds the reference
             // element in static LDS
             const size_t refb = s->K <= 2 && s->upw
                                     ? (size_t)(3 * np * np + 3 * np * (s->K + 1)) * s->esz + 3 * (s->K + 1) * 4 + 16
                                     : 0;
-            if (ok && j == end && known && A.nfl == nops && P.max_foot <= cap && !(env && std::atoi(env) == 0)) {
+            if (whole && force != 0 && force != 1 && mfma_built(s->K, order, nops)) {
+                // matrix-core kernel: LDS regions [component][node][slot] for the fields an
+                // operator reads through a facet (operand, active penalty), a region reused
+                // once its field is dead; then the geometry rows and the per-slot words
+                int S16 = (std::max(P.max_foot, 1) + 15) & ~15;
+                if (S16 % 64 == 0) S16 += 16;  // consecutive node rows start in different banks
+                int first[F_COUNT], last[F_COUNT];
+                bool res[F_COUNT] = {};
+                for (int f = 0; f < F_COUNT; ++f) first[f] = -1, last[f] = -1;
+                for (int q = first_op; q < first_op + nops; ++q) {
+                    const OpDesc D = op_desc(order, q);
+                    const bool pn = D.pen >= 0 && s->loops[op_first_loop(order, q) + 1].pen >= 0;
+                    res[D.in] = true;
+                    if (pn) res[D.pen] = true;
+                    // fields the operator and its update touch (the penalty only when active)
+                    uint32_t m = (1u << D.in) | (1u << D.out);
+                    if (pn) m |= 1u << D.pen;
+                    if (D.upd) m |= 1u << (D.vel ? F_V : F_S);
+                    if (D.part >= 0) m |= 1u << D.part;
+                    for (int f = 0; f < F_COUNT; ++f) {
+                        if (!((m >> f) & 1)) continue;
+                        if (first[f] < 0) first[f] = q;
+                        last[f] = q;
+                    }
+                }
+                std::vector<std::array<int, 3>> regions;  // row offset, rows, free after op
+                int rows = 0;
+                for (int f = 0; f < F_COUNT; ++f) A.lds_row[f] = -1;
+                for (int q = first_op; q < first_op + nops; ++q)
+                    for (int f = 0; f < F_COUNT; ++f) {
+                        if (!res[f] || first[f] != q) continue;
+                        const int need = field_ncomp(f) * np;
+                        int pick = -1;
+                        for (size_t r = 0; r < regions.size(); ++r)
+                            if (regions[r][1] >= need && regions[r][2] < q) { pick = (int)r; break; }
+                        if (pick < 0) {
+                            regions.push_back({rows, need, last[f]});
+                            rows += need;
+                            pick = (int)regions.size() - 1;
+                        }
+                        regions[pick][2] = last[f];
+                        A.lds_row[f] = regions[pick][0] * S16;
+                    }
+                const size_t bytes = (size_t)(rows + G_NROWS) * S16 * s->esz + (size_t)S16 * (4 + 4 + 2) + 16;
+                if (bytes <= budget) {
+                    A.stride = S16;
+                    A.nrow = rows * S16;  // geometry rows start here
+                    P.kind = TK_MFMA;
+                    P.o0 = first_op;
+                    P.nops = nops;
+                    P.lds_bytes = bytes;
+                }
+            }
+            if (P.kind == TK_GENERIC && whole && chain_built(s->K, nops) && P.max_foot <= cap && force != 0) {
                 int w = 0;
                 for (int q = first_op; q < first_op + nops; ++q) {
                     const OpDesc D = op_desc(order, q);
@@ -610,6 +667,7 @@ static void build_plan(dgt_solver *s) {
         const int ng = P.kind == TK_CHAIN || s->K <= 2 ? 1 : (s->K == 3 ? 2 : 3);
         const int items = A.stride * ng;
         P.threads = items <= TILE_NT[0] ? TILE_NT[0] : (items <= TILE_NT[1] ? TILE_NT[1] : TILE_NT[2]);
+        if (P.kind == TK_MFMA) P.threads = MFMA_NT;
         if (const char *e = std::getenv("DGT_TILE_THREADS"); e && P.kind == TK_GENERIC) P.threads = std::atoi(e);
     }
     DGT_HIP(hipStreamSynchronize(st));
@@ -763,7 +821,7 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
             A.persistent_mask |= extra_persist;
             A.dt = dt;
             A.src_amp = s->has_src ? dt * ricker(th, s->sf0, s->st0, s->samp) : 0.0;
-            if (s->sched_mode == 1 && P.kind == TK_CHAIN) {  // one launch for all colours
+            if (s->sched_mode == 1 && P.kind != TK_GENERIC) {  // one launch for all colours
                 A.persist = 1;
                 A.ntiles = P.ntiles;
                 A.tile_base = 0;
@@ -1037,7 +1095,7 @@ static void prepare_tiled(dgt_solver *s) {
     check_graphs(s);  // synchronises: reports a wait that timed out earlier
     for (size_t b = 0; b < s->plan.size(); ++b) {
         SubPlan &P = s->plan[b];
-        if (P.kind != TK_CHAIN) continue;
+        if (P.kind == TK_GENERIC) continue;
         if (!P.graph) build_graph(s, (int)b, P);
         if (!P.slots) P.slots = plan_slots(s, P);
         DGT_REQUIRE(P.slots > 0, DGT_EUNSUPPORTED, "the tile kernel does not fit on a compute unit");
@@ -1166,7 +1224,7 @@ dgt_status dgt_solver_autotune(dgt_solver *s, const dgt_autotune_params *p, dgt_
             ip.tile_size = c.ts;
             solver_inspect_once(s, &ip, 0);
             bool chain = false;
-            for (const auto &P : s->plan) chain |= P.kind == TK_CHAIN;
+            for (const auto &P : s->plan) chain |= P.kind != TK_GENERIC;
             for (int mode = 0; mode <= (chain ? 1 : 0); ++mode) {
                 s->sched_mode = mode;
                 for (int f = 0; f < F_COUNT; ++f) DGT_HIP(hipMemsetAsync(s->fld[f].p, 0, s->fld[f].n, st));
@@ -1384,6 +1442,15 @@ dgt_status dgt_solver_info(const dgt_solver *s, int64_t *np, int64_t *bytes_per_
 }
 
 void dgt_solver_destroy(dgt_solver *s) { delete s; }
+
+dgt_status dgt_solver_kernels(const dgt_solver *s, int32_t *nsub, int32_t *kinds) {
+    return guard([&] {
+        DGT_REQUIRE(s && nsub, DGT_EINVAL, "NULL argument");
+        *nsub = (int32_t)s->plan.size();
+        if (kinds)
+            for (size_t b = 0; b < s->plan.size(); ++b) kinds[b] = (int32_t)s->plan[b].kind;
+    });
+}
 
 dgt_status dgt_refelem(int32_t degree, double *dr, double *ds, double *minv, double *lift) {
     return guard([&] {

@@ -8,7 +8,7 @@
 
 namespace dgt {
 
-enum TileKernel { TK_GENERIC = 0, TK_CHAIN = 1 };
+enum TileKernel { TK_GENERIC = 0, TK_CHAIN = 1, TK_MFMA = 2 };
 
 // operator sequences the chain kernel is built for: (time order, first operator, operators)
 constexpr int TILE_CHAINS[12][3] = {{4, 0, 3}, {4, 3, 3}, {4, 0, 6}, {2, 0, 2}, {4, 0, 1}, {4, 1, 1},
@@ -17,6 +17,13 @@ constexpr int TILE_CHAINS[12][3] = {{4, 0, 3}, {4, 3, 3}, {4, 0, 6}, {2, 0, 2}, 
 // Multi-operator chains hold every field of a cell in registers; from P3 on they
 // no longer fit (spills, one wave per SIMD), so only single operators are built.
 constexpr bool chain_built(int k, int nops) { return nops == 1 || k <= 2; }
+
+// The matrix-core kernel (P3/P4) keeps the fields neighbours read in LDS, so it
+// runs half steps of the fourth-order scheme too (a whole step's footprint would
+// not fit; in the two-operator second-order step the first update's field is the
+// second operator's operand, which the kernel does not keep in LDS).
+constexpr bool mfma_built(int k, int order, int nops) { return k >= 3 && (nops == 1 || (order == 4 && nops == 3)); }
+constexpr int MFMA_NT = 512;  // its workgroup size (eight waves)
 
 // Copies the reference element into the constant memory of the degree-K unit.
 template <int K, typename T>
@@ -30,7 +37,9 @@ enum TileAction { TA_LAUNCH = 0, TA_ATTR = 1, TA_OCCUPANCY = 2 };
 // items per tile.  Operator kernel: one operator application (vel selects the
 // velocity operator) with an optional trailing update; needs nt >= the
 // largest footprint.  Chain kernel: operators [o0, o0 + nops) of the order-`order`
-// step (one of TILE_CHAINS), nt >= the largest footprint.
+// step (one of TILE_CHAINS), nt >= the largest footprint.  Matrix-core kernel
+// (k >= 3): the same operator sequences, nt = MFMA_NT, any footprint that fits
+// the LDS plan.
 template <int K, typename T>
 void tile_launch(TileKernel kind, int nt, bool upw, bool pen, int order, int o0, int nops, int grid,
                  size_t lds, hipStream_t st, const TileArgs &A, TileAction act, int *occ = nullptr);

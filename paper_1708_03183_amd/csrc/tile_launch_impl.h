@@ -5,6 +5,7 @@
 #include "tile_exec.h"
 #include "tile_chain.h"
 #include "tile_kernel.h"
+#include "tile_mfma.h"
 
 namespace dgt {
 
@@ -47,6 +48,30 @@ static void tile_launch_chain(bool upw, int order, int o0, int nops, int grid, s
     else DGT_REQUIRE(false, DGT_EINVAL, "no chain kernel for this operator sequence");
 }
 
+template <int K, typename T>
+static void tile_launch_mfma(bool upw, int order, int o0, int nops, int grid, size_t lds, hipStream_t st,
+                             const TileArgs &A, TileAction act, int *occ) {
+    if constexpr (K >= 3) {
+        auto pick = [&]<int ORD, int O0, int N>() {
+            auto kern = upw ? k_tile_mfma<K, T, true, ORD, O0, N, MFMA_NT> : k_tile_mfma<K, T, false, ORD, O0, N, MFMA_NT>;
+            tile_go(kern, MFMA_NT, grid, lds, st, A, act, occ);
+        };
+        if (order == 4 && o0 == 0 && nops == 3) pick.template operator()<4, 0, 3>();
+        else if (order == 4 && o0 == 3 && nops == 3) pick.template operator()<4, 3, 3>();
+        else if (order == 4 && nops == 1 && o0 == 0) pick.template operator()<4, 0, 1>();
+        else if (order == 4 && nops == 1 && o0 == 1) pick.template operator()<4, 1, 1>();
+        else if (order == 4 && nops == 1 && o0 == 2) pick.template operator()<4, 2, 1>();
+        else if (order == 4 && nops == 1 && o0 == 3) pick.template operator()<4, 3, 1>();
+        else if (order == 4 && nops == 1 && o0 == 4) pick.template operator()<4, 4, 1>();
+        else if (order == 4 && nops == 1 && o0 == 5) pick.template operator()<4, 5, 1>();
+        else if (order == 2 && nops == 1 && o0 == 0) pick.template operator()<2, 0, 1>();
+        else if (order == 2 && nops == 1 && o0 == 1) pick.template operator()<2, 1, 1>();
+        else DGT_REQUIRE(false, DGT_EINVAL, "no matrix-core kernel for this operator sequence");
+    } else {
+        DGT_REQUIRE(false, DGT_EINVAL, "the matrix-core tile kernel is built for degrees 3 and 4");
+    }
+}
+
 template <int K, typename T, int NT>
 static void tile_launch_nt(bool upw, bool pen, int grid, size_t lds, hipStream_t st, const TileArgs &A, TileAction act,
                            int *occ) {
@@ -59,6 +84,11 @@ template <int K, typename T>
 static void tile_launch_any(TileKernel kind, int nt, bool upw, bool pen, int order, int o0, int nops,
                             int grid, size_t lds, hipStream_t st, const TileArgs &A, TileAction act, int *occ) {
     DGT_REQUIRE(nt == 128 || nt == 256 || nt == 512, DGT_EINVAL, "tile workgroup size must be 128, 256 or 512");
+    if (kind == TK_MFMA) {
+        DGT_REQUIRE(nt == MFMA_NT, DGT_EINVAL, "matrix-core tile kernel workgroup size mismatch");
+        tile_launch_mfma<K, T>(upw, order, o0, nops, grid, lds, st, A, act, occ);
+        return;
+    }
     if (kind == TK_CHAIN) {
         if (nt == 512) tile_launch_chain<K, T, 512>(upw, order, o0, nops, grid, lds, st, A, act, occ);
         else if (nt == 256) tile_launch_chain<K, T, 256>(upw, order, o0, nops, grid, lds, st, A, act, occ);

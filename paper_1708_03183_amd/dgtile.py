@@ -102,6 +102,7 @@ _SIGS = {
     "dgt_solver_info": [_p, _i64, _i64, _i64],
     "dgt_solver_destroy": [_p],
     "dgt_refelem": [C.c_int32, _p, _p, _p, _p],
+    "dgt_solver_kernels": [_p, _i32, _p],
     "dgt_last_error": [],
     "dgt_version": [],
 }
@@ -433,6 +434,14 @@ class Solver:
         _check(fn(self.h, C.c_void_p(v.data_ptr()), C.c_void_p(s_new.data_ptr()), C.c_void_p(s_old.data_ptr()),
                   C.byref(out)))
         return out.value
+
+    def kernels(self) -> list:
+        """Tile kernel per sub-chain: 0 generic, 1 register-resident chain, 2 matrix-core."""
+        n = C.c_int32()
+        _check(lib().dgt_solver_kernels(self.h, C.byref(n), None))
+        k = np.zeros(n.value, np.int32)
+        _check(lib().dgt_solver_kernels(self.h, C.byref(n), _np_ptr(k)))
+        return [int(v) for v in k]
 
     def set_schedule(self, mode: int):
         """0: one launch per colour; 1: dependence-driven tiles, one launch per sub-chain."""

@@ -169,6 +169,7 @@ def _run_pair(D, n, k, order, flux, free, ren, steps, mode, ts=24, part=1, split
     if mode == 1:
         gd.inspect(ts, partition=part, splits=splits, max_colour_tiles=cap)
         gd.set_schedule(schedule)
+        print(f"  [tile kernels per sub-chain {gd.kernels()}]")
     gd.upload(gv, gs)
     gd.step(steps, mode=mode, t0=0.1)
     gd.download(gv, gs)
@@ -301,14 +302,18 @@ CHAIN_CASES = [
 ]
 
 
-@pytest.mark.parametrize("kernel", ["generic", "specialised"])
+@pytest.mark.parametrize("kernel", ["generic", "specialised", "register"])
 @pytest.mark.parametrize("n,k,order,flux,free,ren,steps,ts,splits", CHAIN_CASES)
 def test_tiled_chain_kernels_fp64_match_oracle(D, monkeypatch, kernel, n, k, order, flux, free, ren, steps, ts,
                                                splits):
-    """The same schedule on the generic in-tile executor (every field in LDS)
-    and on the register-resident chain kernel."""
+    """The same schedule on the generic in-tile executor (every field in LDS),
+    on the default specialised kernel (register-resident chain kernel at P1/P2,
+    matrix-core kernel at P3/P4), and on the register-resident chain kernel
+    where it is built."""
     if kernel == "generic":
         monkeypatch.setenv("DGT_TILE_OP", "0")
+    elif kernel == "register":
+        monkeypatch.setenv("DGT_TILE_OP", "1")
     err = _run_pair(D, n, k, order, flux, free, ren, steps, mode=1, ts=ts, splits=splits)
     print(f"{kernel} tiled FP64 n={n} k={k} order={order} flux={flux} ts={ts} splits={splits}: err {err:.3e}")
     assert err <= 1e-12
@@ -478,3 +483,65 @@ def test_sub_chain_tile_sizes_schedule_and_executor(D, k, sub_ts, schedule):
     err = rel_err([gv.cpu().numpy(), gsg.cpu().numpy()], [v, s])
     print(f"sub-chain tile sizes {sub_ts} k={k} schedule={schedule}: schedule byte-equal, err {err:.3e}")
     assert err <= 1e-12
+
+
+MFMA_CASES = [
+    # k, prec, splits, schedule, ts: half steps and single operators at P3/P4
+    (3, 0, (13,), 0, 12), (3, 0, (13,), 1, 12), (4, 0, (13,), 0, 6), (4, 0, (13,), 1, 6),
+    (3, 0, (4, 8, 13, 17, 21), 0, 24), (4, 0, (4, 8, 13, 17, 21), 1, 16),
+    (4, 0, (4, 8, 12, 13, 17, 21, 25), 0, 16),
+    (3, 1, (13,), 0, 16), (3, 1, (13,), 1, 16), (4, 1, (13,), 1, 8), (4, 1, (4, 8, 13, 17, 21), 0, 24),
+]
+
+
+@pytest.mark.parametrize("k,prec,splits,schedule,ts", MFMA_CASES)
+def test_matrix_core_kernel_matches_oracle(D, k, prec, splits, schedule, ts):
+    """At P3/P4 the default kernel of whole operator applications is the
+    matrix-core one (derivative and lift contractions on MFMA), for half steps
+    and single operators, under both schedules; it matches the oracle element by
+    element from random states."""
+    m, om, od, gm, gd = _dg_pair(D, 12, k, 4, 1, 0x8, 5, prec)
+    od.set_source(0.43, 0.52)
+    gd.set_source(0.43, 0.52)
+    v, s = od.zeros()
+    v[:] = I.random_state(v.shape, 31)
+    s[:] = I.random_state(s.shape, 32)
+    dtype = torch.float32 if prec else torch.float64
+    gv = torch.from_numpy(v).to(dtype).cuda().contiguous()
+    gs = torch.from_numpy(s).to(dtype).cuda().contiguous()
+    od.step(v, s, 6, t0=0.1)
+    gd.inspect(ts, partition=1, splits=splits)
+    gd.set_schedule(schedule)
+    kinds = gd.kernels()
+    # every sub-chain of operator applications runs on it (an update alone is no operator)
+    whole = [b for b in range(len(splits) + 1) if not (b > 0 and splits[b - 1] in (12, 25))]
+    assert [kinds[b] for b in whole] == [2] * len(whole) and set(kinds) <= {0, 2}, kinds
+    gd.upload(gv, gs)
+    gd.step(6, mode=1, t0=0.1)
+    gd.download(gv, gs)
+    torch.cuda.synchronize()
+    err = rel_err([gv.double().cpu().numpy(), gs.double().cpu().numpy()], [v, s])
+    print(f"matrix-core k={k} prec={prec} splits={splits} schedule={schedule} ts={ts}: err {err:.3e}")
+    assert err <= (1e-5 if prec else 1e-12)
+
+
+def test_kernel_selection_follows_environment(D, monkeypatch):
+    """DGT_TILE_OP=1 selects the register-resident chain kernel where it is
+    built (single operators at P3), 0 the generic kernel; the default is the
+    matrix-core kernel, and P2 keeps the register-resident one."""
+    m, om, od, gm, gd = _dg_pair(D, 8, 3, 4, 1, 0x8, 5)
+    sp = (4, 8, 13, 17, 21)
+    gd.inspect(16, partition=1, splits=sp)
+    assert gd.kernels() == [2] * 6
+    monkeypatch.setenv("DGT_TILE_OP", "1")
+    gd.inspect(16, partition=1, splits=sp)
+    assert gd.kernels() == [1] * 6
+    gd.inspect(16, partition=1, splits=(13,))  # no register chain kernel for P3 half steps
+    assert gd.kernels() == [0, 0]
+    monkeypatch.setenv("DGT_TILE_OP", "0")
+    gd.inspect(16, partition=1, splits=sp)
+    assert gd.kernels() == [0] * 6
+    monkeypatch.delenv("DGT_TILE_OP")
+    m, om, od, gm, gd = _dg_pair(D, 8, 2, 4, 1, 0x8, 5)
+    gd.inspect(16, partition=1, splits=(13,))
+    assert gd.kernels() == [1, 1]
