@@ -632,8 +632,12 @@ static void build_plan(dgt_solver *s) {
                         regions[pick][2] = last[f];
                         A.lds_row[f] = regions[pick][0] * S16;
                     }
-                const size_t bytes = (size_t)(rows + G_NROWS) * S16 * s->esz + (size_t)S16 * (4 + 4 + 2) + 16;
-                if (bytes <= budget) {
+                // fields, geometry and facet normals, loop bits, cell ids, flags, neighbour tables
+                const size_t bytes = (size_t)(rows + G_NROWS + 9) * S16 * s->esz + (size_t)S16 * (4 + 4 + 2) +
+                                     (size_t)nops * 3 * S16 * 4 + 16;
+                // the kernel addresses a field's component-node rows with 32-bit offsets
+                const bool fits32 = (uint64_t)s->nc * 3 * np < (uint64_t)UINT32_MAX;
+                if (bytes <= budget && fits32) {
                     A.stride = S16;
                     A.nrow = rows * S16;  // geometry rows start here
                     P.kind = TK_MFMA;

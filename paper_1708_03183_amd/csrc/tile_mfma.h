@@ -88,6 +88,7 @@ struct MfmaTile {
     uint32_t *acc;     // [S] loop bits
     int32_t *x;        // [S] exec cell id
     uint16_t *fl;      // [S] gather (bits 0-7) and write-back (bits 8-15) flags per field
+    uint32_t *nb;      // [operator][local facet][S] neighbour codes of the tile's facet loops
     int S, nfoot, f0, tile, shot;
 };
 
@@ -105,6 +106,7 @@ __device__ __forceinline__ void mfma_op(const MfmaRef<K, T> &Ar, const TileArgs 
     const int S = tl.S, nfoot = tl.nfoot;
     const bool pen = D.pen >= 0 && a.loops[j0 + 1].pen >= 0;
     const int tid = threadIdx.x;
+    const uint32_t nc32 = (uint32_t)a.nc;  // component-node rows of a field fit in 32 bits (host check)
 
     // gather the LDS fields whose first use in the sub-chain is this operator
 #pragma unroll
@@ -116,11 +118,11 @@ __device__ __forceinline__ void mfma_op(const MfmaRef<K, T> &Ar, const TileArgs 
         T *dst = tl.f + a.lds_row[f];
         for (int s = tid; s < nfoot; s += NT) {
             if (!((tl.fl[s] >> f) & 1)) continue;
-            const int64_t x = tl.x[s];
+            const T *Fx = F + tl.x[s];
             T v[3 * NP];
 #pragma unroll
             for (int r = 0; r < 3 * NP; ++r)
-                if (r < nr) v[r] = load_field(F + (int64_t)r * a.nc + x, coh);
+                if (r < nr) v[r] = load_field(Fx + (uint32_t)r * nc32, coh);
 #pragma unroll
             for (int r = 0; r < 3 * NP; ++r)
                 if (r < nr) dst[(size_t)r * S + s] = v[r];
@@ -138,8 +140,18 @@ __device__ __forceinline__ void mfma_op(const MfmaRef<K, T> &Ar, const TileArgs 
     const T *gr = tl.f + a.nrow;  // geometry rows
     const T *fin = tl.f + a.lds_row[D.in];
     const T *fpn = tl.f + (pen ? a.lds_row[D.pen < 0 ? 0 : D.pen] : 0);
-    const int b0 = a.tnb_off[tl.tile];
     const T dt = (T)a.dt;
+
+    const T *nrm = gr + G_NROWS * S;  // per local facet: outward unit normal and |facet| / |J|
+    // the facet points this lane evaluates: q = 4 t + g -> local facet, node on it, cell node
+    int pt_p[KQ], pt_m[KQ], pt_n0[KQ];
+#pragma unroll
+    for (int t = 0; t < KQ; ++t) {
+        const int q = 4 * t + g;
+        pt_p[t] = q < NQ ? q / NFP : 3;
+        pt_m[t] = q < NQ ? q % NFP : 0;
+        pt_n0[t] = q < NQ ? fnode(K, pt_p[t], pt_m[t]) : 0;
+    }
 
     for (int grp = wave; grp < ngroups; grp += NW) {
         const int s = grp * 16 + jc;
@@ -150,6 +162,30 @@ __device__ __forceinline__ void mfma_op(const MfmaRef<K, T> &Ar, const TileArgs 
         const int64_t x = tl.x[sv];
         const bool vol = (acc >> j0) & 1u;
         const T rx = gr[G_RX * S + sv], ry = gr[G_RY * S + sv], sx = gr[G_SX * S + sv], sy = gr[G_SY * S + sv];
+
+        // operands of the update that are not in LDS, loaded now so that their latency
+        // hides behind the contractions
+        constexpr int NU = D.upd != 0 ? NO : 1;
+        T qpre[NU][4], ppre[NU][4];
+        bool upd = false;
+        if constexpr (D.upd != 0) {
+            upd = valid && ju < a.nloops && ((acc >> ju) & 1u);
+            const T *Q = reinterpret_cast<const T *>(a.F[QF]) + tl.shot * a.fshot[QF];
+            const T *PF = reinterpret_cast<const T *>(a.F[D.part < 0 ? 0 : D.part]) +
+                          tl.shot * a.fshot[D.part < 0 ? 0 : D.part];
+            const bool q_glob = a.lds_row[QF] < 0;
+            const bool p_glob = D.part >= 0 && a.lds_row[D.part < 0 ? 0 : D.part] < 0;
+            const bool p_coh = a.persist && D.part >= 0 && field_last_write(ORDER, O0, NOPS, D.part) >= 0;
+#pragma unroll
+            for (int c = 0; c < NU; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = Mfma<T>::row(g, r);
+                    const uint32_t gi = (uint32_t)(c * NP + (i < NP ? i : 0)) * nc32;
+                    qpre[c][r] = (upd && i < NP && q_glob) ? load_field(Q + x + gi, a.persist) : T(0);
+                    ppre[c][r] = (upd && i < NP && p_glob) ? load_field(PF + x + gi, p_coh) : T(0);
+                }
+        }
 
         // accumulators: one 16 x 16 block per output component, rows = nodes, columns = cells;
         // a cell whose volume loop is not in this tile starts from its partial sum
@@ -175,7 +211,7 @@ __device__ __forceinline__ void mfma_op(const MfmaRef<K, T> &Ar, const TileArgs 
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int i = Mfma<T>::row(g, r);
-                        if (i < NP && init) o[c][r] = load_field(F + (int64_t)(c * NP + i) * a.nc + x, coh);
+                        if (i < NP && init) o[c][r] = load_field(F + x + (uint32_t)(c * NP + i) * nc32, coh);
                     }
             }
         }
@@ -217,24 +253,20 @@ __device__ __forceinline__ void mfma_op(const MfmaRef<K, T> &Ar, const TileArgs 
 
         // facet loops of this tile: the flux at facet point q = 4 t + g of the column's cell
         // (its own side), lifted by LIFT (A) x flux (B)
-        uint32_t nb[3] = {0u, 0u, 0u};
-        if (valid) {
+        uint32_t nb[3];
 #pragma unroll
-            for (int p = 0; p < 3; ++p) nb[p] = a.tnb[b0 + ((O - O0) * 3 + p) * nfoot + s];
-        }
+        for (int p = 0; p < 3; ++p) nb[p] = tl.nb[((O - O0) * 3 + p) * S + sv];
         if (__ballot((nb[0] | nb[1] | nb[2]) & NB_VALID)) {
             const T zp0 = gr[G_ZP * S + sv], zs0 = gr[G_ZS * S + sv];
             const T irho = gr[G_IRHO * S + sv], lam = gr[G_LAM * S + sv], mu = gr[G_MU * S + sv];
 #pragma unroll
             for (int t = 0; t < KQ; ++t) {
-                const int q = 4 * t + g;
-                const int p = q < NQ ? q / NFP : 0, m = q < NQ ? q % NFP : 0;
-                const uint32_t code = q < NQ ? (p == 0 ? nb[0] : (p == 1 ? nb[1] : nb[2])) : 0u;
+                const int p = pt_p[t], m = pt_m[t];
+                const uint32_t code = p == 0 ? nb[0] : (p == 1 ? nb[1] : (p == 2 ? nb[2] : 0u));
                 T gq[3] = {0, 0, 0};
                 if (code & NB_VALID) {
-                    T nx, ny, fs;
-                    facet_normal<T>(p, rx, ry, sx, sy, nx, ny, fs);
-                    const int n0 = fnode(K, p, m);
+                    const T nx = nrm[(3 * p) * S + s], ny = nrm[(3 * p + 1) * S + s], fs = nrm[(3 * p + 2) * S + s];
+                    const int n0 = pt_n0[t];
                     T a0[NI], p0[NO];
 #pragma unroll
                     for (int c = 0; c < NI; ++c) a0[c] = fin[(size_t)(c * NP + n0) * S + s];
@@ -328,22 +360,16 @@ __device__ __forceinline__ void mfma_op(const MfmaRef<K, T> &Ar, const TileArgs 
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = Mfma<T>::row(g, r);
-                    if (i < NP) store_field(F + (int64_t)(c * NP + i) * a.nc + x, o[c][r], a.persist);
+                    if (i < NP) store_field(F + x + (uint32_t)(c * NP + i) * nc32, o[c][r], a.persist);
                 }
         }
 
         // the update consuming this operator's output (leapfrog, fourth or second order)
         if constexpr (D.upd != 0) {
-            const bool upd = valid && ju < a.nloops && ((acc >> ju) & 1u);
             if (__ballot(upd)) {
                 T *Q = reinterpret_cast<T *>(a.F[QF]) + tl.shot * a.fshot[QF];
-                const T *PF = D.part >= 0 ? reinterpret_cast<const T *>(a.F[D.part < 0 ? 0 : D.part]) +
-                                                tl.shot * a.fshot[D.part < 0 ? 0 : D.part]
-                                          : nullptr;
                 const bool q_lds = a.lds_row[QF] >= 0;
                 const bool p_lds = D.part >= 0 && a.lds_row[D.part < 0 ? 0 : D.part] >= 0;
-                const bool q_coh = a.persist;
-                const bool p_coh = a.persist && D.part >= 0 && field_last_write(ORDER, O0, NOPS, D.part) >= 0;
                 const bool wb_q = field_last_write(ORDER, O0, NOPS, QF) == O && ((fl >> (8 + QF)) & 1);
                 const bool src = !D.vel && x == a.src_cells[tl.shot];
                 const T *svec = reinterpret_cast<const T *>(a.src_vec) + tl.shot * NP;
@@ -354,18 +380,18 @@ __device__ __forceinline__ void mfma_op(const MfmaRef<K, T> &Ar, const TileArgs 
                         const int i = Mfma<T>::row(g, r);
                         if (i >= NP || !upd) continue;
                         const size_t li = (size_t)(c * NP + i) * S + s;
-                        const int64_t gi = (int64_t)(c * NP + i) * a.nc + x;
+                        const uint32_t gi = (uint32_t)(c * NP + i) * nc32;
                         T add = o[c][r];
                         if constexpr (D.upd == 1) {
-                            const T pv = p_lds ? tl.f[a.lds_row[D.part] + li] : load_field(PF + gi, p_coh);
+                            const T pv = p_lds ? tl.f[a.lds_row[D.part] + li] : ppre[c][r];
                             add = dt * pv + add;
                         }
                         if (src && c < 2) add += (T)a.src_amp * svec[i];
                         // the old value may sit in LDS (the operator's penalty field, which other
                         // waves still read as neighbour traces): the new one goes to HBM only
-                        T qv = q_lds ? tl.f[a.lds_row[QF] + li] : load_field(Q + gi, q_coh);
+                        T qv = q_lds ? tl.f[a.lds_row[QF] + li] : qpre[c][r];
                         qv += add;
-                        if (wb_q) store_field(Q + gi, qv, a.persist);
+                        if (wb_q) store_field(Q + x + gi, qv, a.persist);
                     }
             }
         }
@@ -379,9 +405,10 @@ __device__ __forceinline__ void mfma_tile(const MfmaRef<K, T> &Ar, const TileArg
     MfmaTile<T> tl;
     tl.S = a.stride;
     tl.f = reinterpret_cast<T *>(smem);
-    tl.acc = reinterpret_cast<uint32_t *>(tl.f + (size_t)a.nrow + (size_t)G_NROWS * tl.S);
+    tl.acc = reinterpret_cast<uint32_t *>(tl.f + (size_t)a.nrow + (size_t)(G_NROWS + 9) * tl.S);
     tl.x = reinterpret_cast<int32_t *>(tl.acc + tl.S);
     tl.fl = reinterpret_cast<uint16_t *>(tl.x + tl.S);
+    tl.nb = reinterpret_cast<uint32_t *>(tl.fl + tl.S + (tl.S & 1));
     tl.tile = tile;
     tl.shot = shot;
     tl.f0 = a.foot_off[tile];
@@ -410,12 +437,30 @@ __device__ __forceinline__ void mfma_tile(const MfmaRef<K, T> &Ar, const TileArg
             for (int r = 0; r < G_NROWS; ++r) gv[r] = geo[(int64_t)r * a.nc + x];
 #pragma unroll
             for (int r = 0; r < G_NROWS; ++r) gr[(size_t)r * tl.S + s] = gv[r];
+            // facet normals and scales, shared by the sub-chain's operators and by the four
+            // lanes that evaluate points of a facet
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                T nx, ny, fs;
+                facet_normal<T>(p, gv[G_RX], gv[G_RY], gv[G_SX], gv[G_SY], nx, ny, fs);
+                gr[(size_t)(G_NROWS + 3 * p) * tl.S + s] = nx;
+                gr[(size_t)(G_NROWS + 3 * p + 1) * tl.S + s] = ny;
+                gr[(size_t)(G_NROWS + 3 * p + 2) * tl.S + s] = fs;
+            }
         }
         // slots past the footprint in the last 16-cell group read as a valid empty cell
         for (int s = tl.nfoot + tid; s < ((tl.nfoot + 15) & ~15); s += NT) {
             tl.acc[s] = 0u;
             tl.x[s] = 0;
             tl.fl[s] = 0;
+#pragma unroll
+            for (int q = 0; q < 3 * NOPS; ++q) tl.nb[q * tl.S + s] = 0u;
+        }
+        // the neighbour tables of the tile's facet loops ([operator][facet][slot])
+        const int b0 = a.tnb_off[tile];
+        for (int i = tid; i < 3 * NOPS * tl.nfoot; i += NT) {
+            const int q = i / tl.nfoot, s = i - q * tl.nfoot;
+            tl.nb[q * tl.S + s] = a.tnb[b0 + i];
         }
     }
     [&]<int... Q>(std::integer_sequence<int, Q...>) {
