@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-untiled", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-cores", type=int, default=0,
+                    help="host cores of the multi-core oracle baseline (0: min(16, cpu count); 1: skip it)")
     ap.add_argument("--workload", choices=["single", "batched", "fwi"], default="single",
                     help="batched: 64 Ricker shots on 6 uneven meshes (P2 FP32), the batched form against "
                          "the same shots run one at a time; fwi: misfit gradient of 16 shots on a 256x256 "
@@ -62,6 +64,14 @@ def parse():
     ap.add_argument("--shots", type=int, default=64)
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched workload: use the fixed P2 FP32 tile size and schedule instead of the autotuner")
+    ap.add_argument("--material", choices=["auto", "layered", "lognormal"], default="auto",
+                    help="auto: three layers at P1/P2, the smooth lognormal fields (sigma 0.3) at P3/P4")
+    ap.add_argument("--no-horizon", action="store_true",
+                    help="skip the FP32-against-GPU-FP64 run over the whole step count")
+    ap.add_argument("--no-config3", action="store_true",
+                    help="skip the 1024x1024 P3/P4 FP32 extras of the default run")
+    ap.add_argument("--config3-steps", type=int, default=100)
+    ap.add_argument("--config3-horizon", type=int, default=500)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain elementwise pass over 256 MiB (torch.neg: 256 MiB read, 256 MiB "
                          "written) for scaling HBM byte counters")
@@ -76,9 +86,217 @@ DEFAULTS = {
     (1, "fp64"): (256, (13,), 1),
     (2, "fp64"): (256, (13,), 1),
     (2, "fp32"): (128, (13,), 1, (256, 128)),
-    (3, "fp32"): (192, OPS, 1),
-    (4, "fp32"): (192, OPS, 0),
+    (3, "fp32"): (256, OPS, 0),
+    (4, "fp32"): (256, OPS, 0),
+    (3, "fp64"): (192, OPS, 0),
+    (4, "fp64"): (128, OPS, 0),
 }
+# the register-resident (VALU) kernel's own best settings at P3/P4, for the A/B
+VALU_DEFAULTS = {3: (192, OPS, 1), 4: (192, OPS, 0)}
+
+
+def material(m, k, which):
+    from paper_1708_03183_amd import inputs as I
+    if which == "auto":
+        which = "lognormal" if k >= 3 else "layered"
+    return (I.lognormal_material(m) if which == "lognormal" else I.layered_material(m)), which
+
+
+def rel_errors(a, b):
+    """relative L2 and max-abs (over max |b|) errors of state pair a against b (torch tensors)"""
+    num = math.sqrt(sum(((x.double() - y.double()) ** 2).sum().item() for x, y in zip(a, b)))
+    den = math.sqrt(sum((y.double() ** 2).sum().item() for y in b))
+    mx = max((x.double() - y.double()).abs().max().item() for x, y in zip(a, b))
+    ref = max(y.double().abs().max().item() for y in b)
+    return (num / den if den > 0 else 0.0), (mx / ref if ref > 0 else 0.0)
+
+
+def horizon(D, make_solver, nsteps, k, ref_state, ref_prec, dt):
+    """The other precision's run of the same nsteps from rest (with the source),
+    against the reference precision's state: the measured FP32 error against GPU
+    FP64 over the whole run."""
+    import torch
+    other = 1 - ref_prec
+    ts, splits, schedule, *rest = DEFAULTS[(k, "fp32" if other else "fp64")]
+    s = make_solver(other)
+    s.inspect(ts, partition=1, splits=splits, sub_tile_sizes=rest[0] if rest else None)
+    s.set_schedule(schedule)
+    v, st = s.zeros()
+    s.upload(v, st)
+    t = time.perf_counter()
+    s.step(nsteps, mode=1, t0=0.0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    s.download(v, st)
+    torch.cuda.synchronize()
+    f32, f64 = ((v, st), ref_state) if other else (ref_state, (v, st))
+    l2, mx = rel_errors(f32, f64)
+    return {"steps": nsteps, "fp32_vs_gpu_fp64_rel_l2": l2, "fp32_vs_gpu_fp64_rel_max_abs": mx,
+            "other_precision_ms_per_step": 1e3 * wall / nsteps, "from": "rest, Ricker source at (0.5, 0.5)"}
+
+
+def oracle_patch(m, npk, cpu_steps, budget, centre):
+    """The whole mesh when cpu_steps oracle steps on it fit the budget of
+    dof-updates, else the cells within enough facet layers of the cell nearest to
+    centre; also the cells deeper than 6 cpu_steps layers inside that patch (a
+    cell's state after s steps depends only on cells within 6 s facet layers), and
+    the patch as a mesh."""
+    import numpy as np
+    import oracle as O
+    nc = m.c2v.shape[0]
+    if 5 * npk * nc * cpu_steps <= budget:
+        cells = np.arange(nc)
+        return cells, cells, m, f"the same {nc}-cell mesh"
+    f2c = O.OMesh.from_mesh(m).maps()["f2c"].astype(np.int64)
+    src_, dst_ = np.concatenate([f2c[:, 0], f2c[:, 1]]), np.concatenate([f2c[:, 1], f2c[:, 0]])
+    order = np.argsort(src_, kind="stable")
+    off = np.concatenate([[0], np.cumsum(np.bincount(src_, minlength=nc))])
+    nbr = dst_[order]
+    cen = m.xy[m.c2v].mean(axis=1)
+    depth = {int(np.argmin(((cen - np.asarray(centre)) ** 2).sum(axis=1))): 0}
+    front = list(depth)
+    want = budget / (5 * npk * cpu_steps)
+    layer = 0
+    while len(depth) < want or layer < 6 * cpu_steps + 1:
+        layer += 1
+        nxt = []
+        for x in front:
+            for y in nbr[off[x]:off[x + 1]]:
+                if int(y) not in depth:
+                    depth[int(y)] = layer
+                    nxt.append(int(y))
+        front = nxt
+    cells = np.array(sorted(depth), np.int64)
+    core = np.array([c for c in cells if depth[c] <= layer - 6 * cpu_steps - 1], np.int64)
+    verts, inv = np.unique(m.c2v[cells].ravel(), return_inverse=True)
+
+    class _Sub:
+        pass
+    sub = _Sub()
+    sub.xy, sub.c2v, sub.periodic = m.xy[verts], inv.reshape(-1, 3).astype(np.int32), 0
+    where = (f"a {len(cells)}-cell patch ({layer} facet layers around the centre) of the same "
+             f"{nc}-cell mesh, {len(core)} cells compared")
+    return cells, core, sub, where
+
+
+def _oracle_worker(args, barrier, queue):
+    """One host core's share of the multi-core oracle baseline: the oracle as it
+    stands (single-threaded FP64) on a patch of its own, started together with the
+    other workers."""
+    n, k, mat_name, cpu_steps, budget, centre, seed = args
+    import numpy as np
+    import oracle as O
+    from paper_1708_03183_amd import inputs as I
+    m = I.square_mesh(n, jitter=0.2, jitter_seed=1, renumber_seed=2)
+    (lam, mu, rho), _ = material(m, k, mat_name)
+    npk = (k + 1) * (k + 2) // 2
+    dt = cfl_dt(m, lam, mu, rho, k)
+    cells, _, sub, _ = oracle_patch(m, npk, cpu_steps, budget, centre)
+    om = O.OMesh(sub.xy, sub.c2v, sub.periodic)
+    od = O.ODG(om, k, lam[cells], mu[cells], rho[cells], flux=1, order=4, dt=dt, free_sides=0x8)
+    v, s = od.zeros()
+    v[:] = I.random_state(v.shape, seed)
+    s[:] = I.random_state(s.shape, seed + 1)
+    barrier.wait()
+    t0 = time.time()
+    od.step(v, s, cpu_steps, t0=0.0)
+    queue.put((5 * npk * len(cells) * cpu_steps, t0, time.time()))
+
+
+def oracle_multicore(n, k, mat_name, cpu_steps, budget, cores):
+    """Aggregate rate of `cores` concurrent oracle processes, each on its own patch
+    (the oracle itself is single-threaded and untuned): total dof-updates over the
+    span from the first start to the last finish."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(cores)
+    queue = ctx.Queue()
+    centres = [(0.2 + 0.6 * ((i * 0.618) % 1.0), 0.2 + 0.6 * ((i * 0.382 + 0.5) % 1.0)) for i in range(cores)]
+    procs = [ctx.Process(target=_oracle_worker, args=((n, k, mat_name, cpu_steps, budget, centres[i], 50 + 2 * i),
+                                                     barrier, queue)) for i in range(cores)]
+    for p in procs:
+        p.start()
+    res = [queue.get(timeout=600) for _ in procs]
+    for p in procs:
+        p.join(timeout=60)
+    work = sum(r[0] for r in res)
+    span = max(r[2] for r in res) - min(r[1] for r in res)
+    return work / span, span, work
+
+
+def config3(a):
+    """The 1024x1024 P3/P4 FP32 workload (lognormal material): tiled rates on the
+    matrix-core kernel (the default at P3/P4) and on the register-resident kernel,
+    the untiled chain, and FP32 against GPU FP64 after the workload's 500 steps."""
+    import torch
+    from paper_1708_03183_amd import dgtile as D
+    from paper_1708_03183_amd import inputs as I
+    t0 = time.time()
+    m = I.square_mesh(1024, jitter=0.2, jitter_seed=1, renumber_seed=2)
+    lam, mu, rho = I.lognormal_material(m)
+    mesh = D.Mesh.from_mesh(m)
+    out = {"workload": "jitter1024: 1024x1024 jittered renumbered triangulation, 2097152 cells, lognormal "
+                       "lambda, mu, rho (sigma 0.3), upwind, order-4 leapfrog, FP32",
+           "mesh_gen_s": time.time() - t0}
+
+    def timed(sol, mode, steps, warm, dt):
+        v, st = sol.zeros()
+        sol.upload(v, st)
+        sol.step(warm, mode=mode, t0=0.0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sol.step(steps, mode=mode, t0=warm * dt)
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t) / steps
+
+    for k in (3, 4):
+        npk = (k + 1) * (k + 2) // 2
+        dofs = 5 * npk * mesh.nc
+        dt = cfl_dt(m, lam, mu, rho, k)
+
+        def make(pr):
+            s = D.Solver(mesh, lam, mu, rho, degree=k, flux=1, time_order=4, precision=pr, free_sides=0x8, dt=dt)
+            s.set_source(0.5, 0.5, 5.0, 0.2, 1.0)
+            return s
+        r = {}
+        ts, splits, sch = DEFAULTS[(k, "fp32")]
+        s = make(1)
+        s.inspect(ts, partition=1, splits=splits)
+        s.set_schedule(sch)
+        ms = timed(s, 1, a.config3_steps, 10, dt)
+        r["mfma"] = {"value": dofs / ms * 1e3, "ms_per_step": ms, "tile_size": ts, "splits": list(splits),
+                     "schedule": sch, "kernels": s.kernels()}
+        ms_u = timed(s, 0, min(a.config3_steps, 50), 2, dt)
+        r["untiled"] = {"value": dofs / ms_u * 1e3, "ms_per_step": ms_u}
+        del s
+        ts, splits, sch = VALU_DEFAULTS[k]
+        os.environ["DGT_TILE_OP"] = "1"
+        try:
+            s = make(1)
+            s.inspect(ts, partition=1, splits=splits)
+        finally:
+            del os.environ["DGT_TILE_OP"]
+        s.set_schedule(sch)
+        ms = timed(s, 1, a.config3_steps, 10, dt)
+        r["valu"] = {"value": dofs / ms * 1e3, "ms_per_step": ms, "tile_size": ts, "splits": list(splits),
+                     "schedule": sch, "kernels": s.kernels()}
+        del s
+        if a.config3_horizon > 0:
+            ref = make(1)
+            ts, splits, sch = DEFAULTS[(k, "fp32")]
+            ref.inspect(ts, partition=1, splits=splits)
+            ref.set_schedule(sch)
+            v, st = ref.zeros()
+            ref.upload(v, st)
+            ref.step(a.config3_horizon, mode=1, t0=0.0)
+            ref.download(v, st)
+            torch.cuda.synchronize()
+            del ref
+            r["horizon"] = horizon(D, make, a.config3_horizon, k, (v, st), 1, dt)
+        out[f"p{k}"] = r
+        print(f"bench: config 3 P{k}: mfma {r['mfma']['ms_per_step']:.3f} ms, valu {r['valu']['ms_per_step']:.3f} "
+              f"ms, untiled {r['untiled']['ms_per_step']:.3f} ms", file=sys.stderr, flush=True)
+    return out
 
 
 TILE_SOURCES = ("tile_chain.h", "dg_kernels.h", "tile_args.h")
@@ -423,9 +641,9 @@ def main():
 
     t0 = time.time()
     m = I.square_mesh(a.n, jitter=0.2, jitter_seed=1, renumber_seed=2 if a.mesh_order == "renumbered" else None)
-    lam, mu, rho = I.layered_material(m)
-    t_gen = time.time() - t0
     k = a.degree
+    (lam, mu, rho), mat_name = material(m, k, a.material)
+    t_gen = time.time() - t0
     npk = (k + 1) * (k + 2) // 2
     dt = cfl_dt(m, lam, mu, rho, k)
 
@@ -540,41 +758,7 @@ def main():
         # layers (one facet loop per operator application), so the cells deeper than that
         # inside the patch are compared
         budget = 4e7
-        if dofs * a.cpu_steps <= budget:
-            cells = np.arange(mesh.nc)
-            core = cells
-            sub = m
-            where = f"the same {mesh.nc}-cell mesh"
-        else:
-            f2c = O.OMesh.from_mesh(m).maps()["f2c"].astype(np.int64)
-            src_, dst_ = np.concatenate([f2c[:, 0], f2c[:, 1]]), np.concatenate([f2c[:, 1], f2c[:, 0]])
-            order = np.argsort(src_, kind="stable")
-            off = np.concatenate([[0], np.cumsum(np.bincount(src_, minlength=mesh.nc))])
-            nbr = dst_[order]
-            cen = m.xy[m.c2v].mean(axis=1)
-            depth = {int(np.argmin(((cen - 0.5) ** 2).sum(axis=1))): 0}
-            front = list(depth)
-            want = budget / (5 * npk * a.cpu_steps)
-            layer = 0
-            while len(depth) < want or layer < 6 * a.cpu_steps + 1:
-                layer += 1
-                nxt = []
-                for x in front:
-                    for y in nbr[off[x]:off[x + 1]]:
-                        if int(y) not in depth:
-                            depth[int(y)] = layer
-                            nxt.append(int(y))
-                front = nxt
-            cells = np.array(sorted(depth), np.int64)
-            core = np.array([c for c in cells if depth[c] <= layer - 6 * a.cpu_steps - 1], np.int64)
-            verts, inv = np.unique(m.c2v[cells].ravel(), return_inverse=True)
-
-            class _Sub:
-                pass
-            sub = _Sub()
-            sub.xy, sub.c2v, sub.periodic = m.xy[verts], inv.reshape(-1, 3).astype(np.int32), 0
-            where = (f"a {len(cells)}-cell patch ({layer} facet layers around the centre) of the same "
-                     f"{mesh.nc}-cell mesh, {len(core)} cells compared")
+        cells, core, sub, where = oracle_patch(m, npk, a.cpu_steps, budget, (0.5, 0.5))
         print(f"cpu baseline: oracle on {where}, {a.cpu_steps} step(s)", file=sys.stderr, flush=True)
         om = O.OMesh(sub.xy, sub.c2v, sub.periodic)
         od = O.ODG(om, k, lam[cells], mu[cells], rho[cells], flux=1, order=4, dt=dt, free_sides=0x8)
@@ -591,6 +775,14 @@ def main():
                "kind": "oracle",
                "sample": f"{a.cpu_steps} step(s) of {where}, from the GPU's final state "
                          f"({tcpu:.1f} s, FP64, single thread)"}
+        if a.cpu_cores != 1:
+            ncores = a.cpu_cores or min(16, os.cpu_count() or 1)
+            progress(f"cpu baseline on {ncores} cores")
+            rate_mc, span, work = oracle_multicore(a.n, k, mat_name, a.cpu_steps, budget / 2, ncores)
+            cpu["all_cores"] = {"value": rate_mc, "unit": "dof-updates/s", "cores": ncores, "kind": "oracle",
+                                "sample": f"{ncores} concurrent processes, each the single-threaded oracle on a "
+                                          f"patch of its own of the same mesh ({work:.3g} dof-updates in "
+                                          f"{span:.1f} s)"}
         pos = np.searchsorted(cells, core)
         vr, sr = v[:, :, pos], s[:, :, pos]
         den = math.sqrt((vr ** 2).sum() + (sr ** 2).sum())
@@ -632,7 +824,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"jitter{a.n}_p{k}: {a.n}x{a.n} jittered "
                                f"{'renumbered' if a.mesh_order == 'renumbered' else 'row-major'} triangulation, "
-                               f"{mesh.nc} cells, DG P{k}, 3-layer, upwind, order-4 leapfrog",
+                               f"{mesh.nc} cells, DG P{k}, "
+                               f"{'3-layer' if mat_name == 'layered' else 'lognormal (sigma 0.3)'} material, "
+                               f"upwind, order-4 leapfrog",
+                   "material": mat_name,
                    "cells": mesh.nc, "dofs_per_step": dofs, "tile_size": ts, "splits": list(splits),
                    "sub_tile_sizes": list(sub_ts) if sub_ts else None,
                    "partition": "hilbert" if a.partition == 1 else "chunks of the mesh numbering",
@@ -649,6 +844,12 @@ def main():
         "mesh_gen_s": t_gen,
     }
     out.update(res)
+    if not a.no_horizon:
+        progress(f"FP32 against GPU FP64 over {a.warmup + a.steps} steps")
+        out["precision_horizon"] = horizon(D, make, a.warmup + a.steps, k, (vt, st_), prec, dt)
+    if not a.no_config3 and a.n == 512 and k == 2:
+        progress("config 3 extras (1024x1024 P3/P4 FP32)")
+        out["config3"] = config3(a)
     if "untiled" in res:
         gain = (res["untiled"]["ms_per_step"] - out["ms_per_step"]) / 1e3
         out["inspector"]["steps_to_amortise"] = (t_insp_wall / gain) if gain > 0 else None
