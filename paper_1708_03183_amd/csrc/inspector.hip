@@ -18,7 +18,10 @@
 //    or a map from the seed set sends two of their iterations to one element;
 //  * colouring priority is (fmix32(t), t), fmix32 the MurmurHash3 finaliser;
 //  * seed order 1 = Hilbert index of coordinates quantised to 2^16 per axis.
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_reduce_by_key.hpp>
+#include <rocprim/device/device_scan.hpp>
+#include <rocprim/device/device_select.hpp>
 
 #include <algorithm>
 #include <chrono>
@@ -419,9 +422,9 @@ void sort_keys(DBuf<uint64_t> &keys, int64_t n, hipStream_t st, int end_bit) {
     if (n <= 1) return;
     DBuf<uint64_t> out(n);
     size_t tmp = 0;
-    DGT_HIP(hipcub::DeviceRadixSort::SortKeys(nullptr, tmp, keys.p, out.p, (int)n, 0, end_bit, st));
+    DGT_HIP(rocprim::radix_sort_keys(nullptr, tmp, keys.p, out.p, (size_t)n, 0u, (unsigned)end_bit, st));
     DBuf<char> t(tmp);
-    DGT_HIP(hipcub::DeviceRadixSort::SortKeys(t.p, tmp, keys.p, out.p, (int)n, 0, end_bit, st));
+    DGT_HIP(rocprim::radix_sort_keys(t.p, tmp, keys.p, out.p, (size_t)n, 0u, (unsigned)end_bit, st));
     keys = std::move(out);
 }
 
@@ -430,9 +433,9 @@ void sort_pairs(DBuf<uint64_t> &keys, DBuf<uint32_t> &vals, int64_t n, hipStream
     DBuf<uint64_t> ko(n);
     DBuf<uint32_t> vo(n);
     size_t tmp = 0;
-    DGT_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, keys.p, ko.p, vals.p, vo.p, (int)n, 0, 64, st));
+    DGT_HIP(rocprim::radix_sort_pairs(nullptr, tmp, keys.p, ko.p, vals.p, vo.p, (size_t)n, 0u, 64u, st));
     DBuf<char> t(tmp);
-    DGT_HIP(hipcub::DeviceRadixSort::SortPairs(t.p, tmp, keys.p, ko.p, vals.p, vo.p, (int)n, 0, 64, st));
+    DGT_HIP(rocprim::radix_sort_pairs(t.p, tmp, keys.p, ko.p, vals.p, vo.p, (size_t)n, 0u, 64u, st));
     keys = std::move(ko);
     vals = std::move(vo);
 }
@@ -443,9 +446,9 @@ static int64_t unique_keys(DBuf<uint64_t> &keys, int64_t n, hipStream_t st) {
     DBuf<uint64_t> out(n);
     DBuf<int64_t> cnt(1);
     size_t tmp = 0;
-    DGT_HIP(hipcub::DeviceSelect::Unique(nullptr, tmp, keys.p, out.p, cnt.p, (int)n, st));
+    DGT_HIP(rocprim::unique(nullptr, tmp, keys.p, out.p, cnt.p, (size_t)n, rocprim::equal_to<uint64_t>(), st));
     DBuf<char> t(tmp);
-    DGT_HIP(hipcub::DeviceSelect::Unique(t.p, tmp, keys.p, out.p, cnt.p, (int)n, st));
+    DGT_HIP(rocprim::unique(t.p, tmp, keys.p, out.p, cnt.p, (size_t)n, rocprim::equal_to<uint64_t>(), st));
     int64_t m = cnt.download(st)[0];
     if (m > 0) {
         uint64_t last;
@@ -459,16 +462,16 @@ static int64_t unique_keys(DBuf<uint64_t> &keys, int64_t n, hipStream_t st) {
 
 static void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t st) {
     size_t tmp = 0;
-    DGT_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, in, out, (int)n, st));
+    DGT_HIP(rocprim::exclusive_scan(nullptr, tmp, in, out, int32_t(0), (size_t)n, rocprim::plus<int32_t>(), st));
     DBuf<char> t(tmp);
-    DGT_HIP(hipcub::DeviceScan::ExclusiveSum(t.p, tmp, in, out, (int)n, st));
+    DGT_HIP(rocprim::exclusive_scan(t.p, tmp, in, out, int32_t(0), (size_t)n, rocprim::plus<int32_t>(), st));
 }
 
 static void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t st) {
     size_t tmp = 0;
-    DGT_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, in, out, (int)n, st));
+    DGT_HIP(rocprim::exclusive_scan(nullptr, tmp, in, out, int64_t(0), (size_t)n, rocprim::plus<int64_t>(), st));
     DBuf<char> t(tmp);
-    DGT_HIP(hipcub::DeviceScan::ExclusiveSum(t.p, tmp, in, out, (int)n, st));
+    DGT_HIP(rocprim::exclusive_scan(t.p, tmp, in, out, int64_t(0), (size_t)n, rocprim::plus<int64_t>(), st));
 }
 
 // counts [n] -> offsets [n+1] (exclusive scan with total at the end)
@@ -818,10 +821,11 @@ int64_t Inspector::touches(int first, int nl, int s, DBuf<uint64_t> &keys, DBuf<
     DBuf<uint32_t> ub(total);
     DBuf<int64_t> cnt(1);
     size_t tmp = 0;
-    DGT_HIP(hipcub::DeviceReduce::ReduceByKey(nullptr, tmp, keys.p, uk.p, bits.p, ub.p, cnt.p, BitOr(), (int)total,
-                                              st));
+    DGT_HIP(rocprim::reduce_by_key(nullptr, tmp, keys.p, bits.p, (size_t)total, uk.p, ub.p, cnt.p, BitOr(),
+                                   rocprim::equal_to<uint64_t>(), st));
     DBuf<char> t(tmp);
-    DGT_HIP(hipcub::DeviceReduce::ReduceByKey(t.p, tmp, keys.p, uk.p, bits.p, ub.p, cnt.p, BitOr(), (int)total, st));
+    DGT_HIP(rocprim::reduce_by_key(t.p, tmp, keys.p, bits.p, (size_t)total, uk.p, ub.p, cnt.p, BitOr(),
+                                   rocprim::equal_to<uint64_t>(), st));
     const int64_t m = cnt.download(st)[0];
     keys = std::move(uk);
     bits = std::move(ub);
