@@ -122,6 +122,9 @@ __device__ __forceinline__ void chain_op(const RefC<K, T> &Rf, CellRegs<K, T> &r
 #pragma unroll
         for (int f = 0; f < F_COUNT; ++f) {
             if (field_first_op(ORDER, O0, NOPS, f) != O || !((fl >> f) & 1)) continue;
+            // (the dependence-driven schedule gathers the first operator's read-only fields
+            // before its dependence wait)
+            if (O == O0 && a.persist && field_last_write(ORDER, O0, NOPS, f) < 0) continue;
             const T *F = reinterpret_cast<const T *>(a.F[f]) + shot * a.fshot[f];
             // only fields the sub-chain writes can change during the launch; the others
             // were written by earlier launches and need no device-scope coherence
@@ -345,6 +348,40 @@ __device__ __forceinline__ void chain_op(const RefC<K, T> &Rf, CellRegs<K, T> &r
     }
 }
 
+// Dependence-driven schedule, thread 0 of a workgroup.  take_ticket: the next (tile,
+// shot) item, tiles in colour order; -1 when none is left.  wait_preds: wait until
+// every predecessor of the tile has finished for the same shot.  Predecessors have
+// lower colours, hence lower tickets, so they were taken by workgroups already
+// running: the wait ends unless a counter is wrong, and the poll limit ends it then
+// too (the error flag tells the host, and the tile's results are invalid).
+__device__ __forceinline__ int take_ticket(const TileArgs &a, int &shot) {
+    const uint32_t ticket = atomicAdd(a.head, 1u) - a.head_base;
+    if (ticket >= (uint32_t)a.ntiles * (uint32_t)a.nshots) return -1;
+    shot = (int)(ticket % (uint32_t)a.nshots);
+    return a.tiles[ticket / (uint32_t)a.nshots];
+}
+
+__device__ __forceinline__ bool wait_preds(const TileArgs &a, int tile, int shot) {
+    const uint32_t need = (uint32_t)a.need[tile], base = (a.epoch - 1u) * need;
+    const uint32_t *cnt = a.cnt + (int64_t)shot * a.ntiles + tile;
+    uint32_t polls = 0;
+    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - base < need) {
+        if (++polls > a.spin_limit) {
+            atomicExch(a.err, 1);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return true;
+}
+
+// both: -1 also when the wait gave up
+__device__ __forceinline__ int next_tile(const TileArgs &a, int &shot) {
+    const int tile = take_ticket(a, shot);
+    if (tile < 0 || !wait_preds(a, tile, shot)) return -1;
+    return tile;
+}
+
 template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS>
 __device__ __forceinline__ void chain_tile(const RefC<K, T> &Rf, const TileArgs &a, T *__restrict__ lds, int tile,
                                            int shot) {
@@ -389,34 +426,33 @@ __device__ __forceinline__ void chain_tile(const RefC<K, T> &Rf, const TileArgs 
         for (int p = 0; p < 3; ++p)
             facet_normal<T>(p, r.g[G_RX], r.g[G_RY], r.g[G_SX], r.g[G_SY], r.nrm[p][0], r.nrm[p][1], r.nrm[p][2]);
     }
+    if (a.persist) {
+        // dependence-driven schedule: the tile's metadata, geometry and the fields its first
+        // operator reads but no operator of the sub-chain writes (finished by earlier
+        // launches) do not depend on other tiles of this launch, so they are loaded before
+        // waiting for the tile's predecessors; only what follows is on the dependence path
+        if (act) {
+#pragma unroll
+            for (int f = 0; f < F_COUNT; ++f) {
+                if (field_first_op(ORDER, O0, NOPS, f) != O0 || field_last_write(ORDER, O0, NOPS, f) >= 0 ||
+                    !((fl >> f) & 1))
+                    continue;
+                const T *F = reinterpret_cast<const T *>(a.F[f]) + shot * a.fshot[f];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if (c >= field_ncomp(f)) break;
+#pragma unroll
+                    for (int i = 0; i < NP; ++i) r.f[f][c][i] = F[(int64_t)(c * NP + i) * a.nc + x];
+                }
+            }
+        }
+        if (threadIdx.x == 0) wait_preds(a, tile, shot);
+        __syncthreads();
+    }
     // fields are gathered at their first use and written back after their last write
     [&]<int... Q>(std::integer_sequence<int, Q...>) {
         (chain_op<K, T, UPW, ORDER, O0, NOPS, O0 + Q>(Rf, r, a, lds, a.nrow, act, s, acc, fl, nb[Q], x, shot), ...);
     }(std::make_integer_sequence<int, NOPS>{});
-}
-
-// Dependence-driven schedule, thread 0 of a workgroup: take the next ticket ((tile,
-// shot) items with tiles in colour order) and wait until every predecessor of its
-// tile has finished for the same shot.  Predecessors have lower colours, hence lower
-// tickets, so they were taken by workgroups already running: the wait ends unless a
-// counter is wrong, and the poll limit ends it then too (the error flag tells the
-// host).  -1: no item left.
-__device__ __forceinline__ int next_tile(const TileArgs &a, int &shot) {
-    const uint32_t ticket = atomicAdd(a.head, 1u) - a.head_base;
-    if (ticket >= (uint32_t)a.ntiles * (uint32_t)a.nshots) return -1;
-    const int tile = a.tiles[ticket / (uint32_t)a.nshots];
-    shot = (int)(ticket % (uint32_t)a.nshots);
-    const uint32_t need = (uint32_t)a.need[tile], base = (a.epoch - 1u) * need;
-    const uint32_t *cnt = a.cnt + (int64_t)shot * a.ntiles + tile;
-    uint32_t polls = 0;
-    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - base < need) {
-        if (++polls > a.spin_limit) {
-            atomicExch(a.err, 1);
-            return -1;
-        }
-        __builtin_amdgcn_s_sleep(2);
-    }
-    return tile;
 }
 
 template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int NT>
@@ -429,7 +465,7 @@ __device__ __forceinline__ void chain_kernel_body(const RefC<K, T> &Rf, const Ti
         return;
     }
     for (;;) {
-        if (threadIdx.x == 0) s_next = next_tile(a, s_shot);
+        if (threadIdx.x == 0) s_next = take_ticket(a, s_shot);  // chain_tile waits for the predecessors
         __syncthreads();
         const int tile = s_next, shot = s_shot;
         if (tile < 0) return;
