@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_vol(const T *__restrict__ in, T *__rest
             as[q] += ds * u;
         }
     }
-    if (VEL) {
+    if constexpr (VEL) {
         const T irho = geo[G_IRHO * nc + c];
         const T dxx = rx * ar[0] + sx * as[0];  // d/dx sxx
         const T dyy = ry * ar[1] + sy * as[1];  // d/dy syy
