@@ -22,7 +22,7 @@ extern "C" {
 
 const char *dgt_last_error(void) { return g_last_error.c_str(); }
 
-int dgt_version(void) { return 105; }
+int dgt_version(void) { return 106; }
 
 dgt_status dgt_chain_create(dgt_chain **out) {
     return guard([&] {

@@ -87,6 +87,7 @@ struct dgt_solver {
     dgt_status plan_status = DGT_ESTATE;  // why the tiled executor cannot run (DGT_OK when it can)
     // parameters of the last inspection (the FWI adjoint solver repeats it)
     bool inspected = false;
+    uint64_t gen = 0;  // counts inspections and field reallocations (batches built on this solver check it)
     dgt_inspect_params last_ip{};
     std::vector<int32_t> last_splits, last_sub_ts;
     int last_cap = 0;
@@ -263,6 +264,7 @@ static void set_source_exec(dgt_solver *s) {
 
 // fields for every shot, zeroed
 static void alloc_fields(dgt_solver *s) {
+    ++s->gen;
     for (int f = 0; f < F_COUNT; ++f) {
         s->fld[f].alloc((size_t)s->fshot(f) * s->nshots * s->esz);
         DGT_HIP(hipMemsetAsync(s->fld[f].p, 0, s->fld[f].n, s->st));
@@ -1109,6 +1111,7 @@ static void prepare_tiled(dgt_solver *s) {
 static void solver_inspect_once(dgt_solver *s, const dgt_inspect_params *p, int cap) {
     hipStream_t st = s->st;
     s->inspected = false;
+    ++s->gen;
     s->last_ip = *p;
     s->last_splits.assign(p->splits, p->splits + p->nsplits);
     s->last_ip.splits = nullptr;
@@ -1471,3 +1474,4 @@ dgt_status dgt_refelem(int32_t degree, double *dr, double *ds, double *minv, dou
 }  // extern "C"
 
 #include "fwi_impl.h"
+#include "batch_impl.h"

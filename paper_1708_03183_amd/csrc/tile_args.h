@@ -60,4 +60,24 @@ struct TileArgs {
     uint32_t spin_limit;        // polls before a wait gives up
 };
 
+// Several meshes in one launch per sub-chain (dependence-driven schedule): a work
+// queue over (mesh, tile, shot) items, segments of one mesh's tiles of one colour
+// ordered by colour, then mesh.
+struct BatchArgs {
+    const TileArgs *args;      // [nmesh] per-mesh launch arguments (device)
+    int32_t nseg;
+    const int32_t *seg_start;  // [nseg + 1] first ticket of each segment
+    const int32_t *seg_mesh;   // [nseg] mesh of the segment
+    const int32_t *seg_local;  // [nseg] the segment's first item in its mesh's own order
+    uint32_t *head;            // ticket counter, counted across launches
+    uint32_t head_base;        // tickets taken by earlier launches
+    uint32_t total;            // items of this launch
+    uint32_t epoch;            // launches of this sub-chain since the counters were cleared
+    // source amplitude of the step: amp_tab[mesh * amp_stride + (*amp_base) + amp_idx]
+    // (amp_base NULL: 0; graph replays move *amp_base between replays)
+    const double *amp_tab;
+    const int32_t *amp_base;
+    int32_t amp_idx, amp_stride;
+};
+
 }  // namespace dgt

@@ -105,7 +105,7 @@ template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int O>
 __device__ __forceinline__ void chain_op(const RefC<K, T> &Rf, CellRegs<K, T> &r, const TileArgs &a,
                                          T *__restrict__ lds, int NR, bool act,
                                          int s, uint32_t acc, uint16_t fl, const uint32_t (&nb)[3], int64_t x,
-                                         int shot) {
+                                         int shot, T amp) {
     constexpr int NP = np_of(K), NFP = K + 1;
     constexpr OpDesc D = op_desc(ORDER, O);
     constexpr int NI = D.vel ? 3 : 2, NO = D.vel ? 2 : 3;
@@ -329,7 +329,7 @@ __device__ __forceinline__ void chain_op(const RefC<K, T> &Rf, CellRegs<K, T> &r
                 for (int i = 0; i < NP; ++i) {
                     T add = o[c][i];
                     if constexpr (D.upd == 1) add = dt * r.f[D.part < 0 ? 0 : D.part][c][i] + add;
-                    if (src && c < 2) add += (T)a.src_amp * sv[i];
+                    if (src && c < 2) add += amp * sv[i];
                     q[c][i] += add;
                 }
         }
@@ -361,8 +361,8 @@ __device__ __forceinline__ int take_ticket(const TileArgs &a, int &shot) {
     return a.tiles[ticket / (uint32_t)a.nshots];
 }
 
-__device__ __forceinline__ bool wait_preds(const TileArgs &a, int tile, int shot) {
-    const uint32_t need = (uint32_t)a.need[tile], base = (a.epoch - 1u) * need;
+__device__ __forceinline__ bool wait_preds(const TileArgs &a, int tile, int shot, uint32_t epoch) {
+    const uint32_t need = (uint32_t)a.need[tile], base = (epoch - 1u) * need;
     const uint32_t *cnt = a.cnt + (int64_t)shot * a.ntiles + tile;
     uint32_t polls = 0;
     while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - base < need) {
@@ -378,13 +378,13 @@ __device__ __forceinline__ bool wait_preds(const TileArgs &a, int tile, int shot
 // both: -1 also when the wait gave up
 __device__ __forceinline__ int next_tile(const TileArgs &a, int &shot) {
     const int tile = take_ticket(a, shot);
-    if (tile < 0 || !wait_preds(a, tile, shot)) return -1;
+    if (tile < 0 || !wait_preds(a, tile, shot, a.epoch)) return -1;
     return tile;
 }
 
 template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS>
 __device__ __forceinline__ void chain_tile(const RefC<K, T> &Rf, const TileArgs &a, T *__restrict__ lds, int tile,
-                                           int shot) {
+                                           int shot, T amp, uint32_t epoch) {
     constexpr int NP = np_of(K);
     const int f0 = a.foot_off[tile];
     const int nfoot = a.foot_off[tile + 1] - f0;
@@ -446,12 +446,13 @@ __device__ __forceinline__ void chain_tile(const RefC<K, T> &Rf, const TileArgs 
                 }
             }
         }
-        if (threadIdx.x == 0) wait_preds(a, tile, shot);
+        if (threadIdx.x == 0) wait_preds(a, tile, shot, epoch);
         __syncthreads();
     }
     // fields are gathered at their first use and written back after their last write
     [&]<int... Q>(std::integer_sequence<int, Q...>) {
-        (chain_op<K, T, UPW, ORDER, O0, NOPS, O0 + Q>(Rf, r, a, lds, a.nrow, act, s, acc, fl, nb[Q], x, shot), ...);
+        (chain_op<K, T, UPW, ORDER, O0, NOPS, O0 + Q>(Rf, r, a, lds, a.nrow, act, s, acc, fl, nb[Q], x, shot, amp),
+         ...);
     }(std::make_integer_sequence<int, NOPS>{});
 }
 
@@ -461,7 +462,7 @@ __device__ __forceinline__ void chain_kernel_body(const RefC<K, T> &Rf, const Ti
     T *lds = reinterpret_cast<T *>(smem);
     if (!a.persist) {  // one launch per colour
         chain_tile<K, T, UPW, ORDER, O0, NOPS>(Rf, a, lds, a.tiles[a.tile_base + (int)blockIdx.x / a.nshots],
-                                               (int)blockIdx.x % a.nshots);
+                                               (int)blockIdx.x % a.nshots, (T)a.src_amp, a.epoch);
         return;
     }
     for (;;) {
@@ -469,7 +470,7 @@ __device__ __forceinline__ void chain_kernel_body(const RefC<K, T> &Rf, const Ti
         __syncthreads();
         const int tile = s_next, shot = s_shot;
         if (tile < 0) return;
-        chain_tile<K, T, UPW, ORDER, O0, NOPS>(Rf, a, lds, tile, shot);
+        chain_tile<K, T, UPW, ORDER, O0, NOPS>(Rf, a, lds, tile, shot, (T)a.src_amp, a.epoch);
         // every wave waits for its coherent field stores to complete, so once the barrier
         // is passed the whole tile is visible at device scope and its successors may start
         __builtin_amdgcn_s_waitcnt(0);

@@ -44,6 +44,12 @@ template <int K, typename T>
 void tile_launch(TileKernel kind, int nt, bool upw, bool pen, int order, int o0, int nops, int grid,
                  size_t lds, hipStream_t st, const TileArgs &A, TileAction act, int *occ = nullptr);
 
+// Launches one sub-chain of several meshes (the chain kernel's operator sequence
+// [o0, o0 + nops), P1/P2, dependence-driven), or queries it like tile_launch.
+template <int K, typename T>
+void tile_launch_batch(bool upw, int order, int o0, int nops, int nt, int grid, size_t lds, hipStream_t st,
+                       const BatchArgs &B, TileAction act, int *occ = nullptr);
+
 // workgroup sizes the tile kernels are built for
 constexpr int TILE_NT[3] = {128, 256, 512};
 

@@ -6,6 +6,7 @@
 #include "tile_chain.h"
 #include "tile_kernel.h"
 #include "tile_mfma.h"
+#include "tile_batch.h"
 
 namespace dgt {
 
@@ -46,6 +47,45 @@ static void tile_launch_chain(bool upw, int order, int o0, int nops, int grid, s
     else if (order == 2 && nops == 1 && o0 == 0) pick.template operator()<2, 0, 1>();
     else if (order == 2 && nops == 1 && o0 == 1) pick.template operator()<2, 1, 1>();
     else DGT_REQUIRE(false, DGT_EINVAL, "no chain kernel for this operator sequence");
+}
+
+template <typename Kern>
+static void batch_go(Kern kern, int nt, int grid, size_t lds, hipStream_t st, const BatchArgs &B, TileAction act,
+                     int *occ) {
+    if (act == TA_ATTR) {
+        DGT_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        return;
+    }
+    if (act == TA_OCCUPANCY) {
+        DGT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, kern, nt, lds));
+        return;
+    }
+    kern<<<grid, nt, lds, st>>>(B);
+}
+
+template <int K, typename T, int NT>
+static void batch_launch_nt(bool upw, int order, int o0, int nops, int grid, size_t lds, hipStream_t st,
+                            const BatchArgs &B, TileAction act, int *occ) {
+    auto pick = [&]<int ORD, int O0, int N>() {
+        auto kern = upw ? k_tile_chain_batch<K, T, true, ORD, O0, N, NT> : k_tile_chain_batch<K, T, false, ORD, O0, N, NT>;
+        batch_go(kern, NT, grid, lds, st, B, act, occ);
+    };
+    if (order == 4 && o0 == 0 && nops == 3) pick.template operator()<4, 0, 3>();
+    else if (order == 4 && o0 == 3 && nops == 3) pick.template operator()<4, 3, 3>();
+    else if (order == 2 && o0 == 0 && nops == 2) pick.template operator()<2, 0, 2>();
+    else DGT_REQUIRE(false, DGT_EINVAL, "batched launches are built for half steps and the order-2 step");
+}
+
+template <int K, typename T>
+static void tile_launch_batch_any(bool upw, int order, int o0, int nops, int nt, int grid, size_t lds, hipStream_t st,
+                                  const BatchArgs &B, TileAction act, int *occ) {
+    if constexpr (K <= 2) {
+        if (nt == 512) batch_launch_nt<K, T, 512>(upw, order, o0, nops, grid, lds, st, B, act, occ);
+        else if (nt == 256) batch_launch_nt<K, T, 256>(upw, order, o0, nops, grid, lds, st, B, act, occ);
+        else DGT_REQUIRE(false, DGT_EINVAL, "batched launches use workgroups of 256 or 512 threads");
+    } else {
+        DGT_REQUIRE(false, DGT_EINVAL, "batched launches are built for degrees 1 and 2");
+    }
 }
 
 template <int K, typename T>
@@ -110,6 +150,18 @@ template <>
 void tile_launch<DGT_TILE_K, float>(TileKernel kind, int nt, bool upw, bool pen, int order, int o0, int nops,
                                     int grid, size_t lds, hipStream_t st, const TileArgs &A, TileAction act, int *occ) {
     tile_launch_any<DGT_TILE_K, float>(kind, nt, upw, pen, order, o0, nops, grid, lds, st, A, act, occ);
+}
+
+template <>
+void tile_launch_batch<DGT_TILE_K, double>(bool upw, int order, int o0, int nops, int nt, int grid, size_t lds,
+                                           hipStream_t st, const BatchArgs &B, TileAction act, int *occ) {
+    tile_launch_batch_any<DGT_TILE_K, double>(upw, order, o0, nops, nt, grid, lds, st, B, act, occ);
+}
+
+template <>
+void tile_launch_batch<DGT_TILE_K, float>(bool upw, int order, int o0, int nops, int nt, int grid, size_t lds,
+                                          hipStream_t st, const BatchArgs &B, TileAction act, int *occ) {
+    tile_launch_batch_any<DGT_TILE_K, float>(upw, order, o0, nops, nt, grid, lds, st, B, act, occ);
 }
 
 template <>

@@ -103,10 +103,15 @@ _SIGS = {
     "dgt_solver_destroy": [_p],
     "dgt_refelem": [C.c_int32, _p, _p, _p, _p],
     "dgt_solver_kernels": [_p, _i32, _p],
+    "dgt_batch_create": [_p, C.c_int32, _p, C.POINTER(_p)],
+    "dgt_batch_set_graph": [_p, C.c_int32],
+    "dgt_batch_step": [_p, C.c_int64, _p],
+    "dgt_batch_timing": [_p, C.POINTER(C.c_double), _i64, _i64],
+    "dgt_batch_destroy": [_p],
     "dgt_last_error": [],
     "dgt_version": [],
 }
-_VOID = {"dgt_chain_destroy", "dgt_schedule_destroy", "dgt_mesh_destroy", "dgt_solver_destroy"}
+_VOID = {"dgt_chain_destroy", "dgt_schedule_destroy", "dgt_mesh_destroy", "dgt_solver_destroy", "dgt_batch_destroy"}
 
 
 def exported_symbols() -> list[str]:
@@ -468,4 +473,32 @@ class Solver:
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.dgt_solver_destroy(self.h)
+            self.h = None
+
+
+class Batch:
+    """Several inspected solvers advanced by one launch per sub-chain (dgt_batch_*)."""
+
+    def __init__(self, solvers, stream=None):
+        self.solvers = list(solvers)  # kept alive: members must outlive the batch
+        arr = (C.c_void_p * len(self.solvers))(*[s.h.value for s in self.solvers])
+        h = C.c_void_p()
+        _check(lib().dgt_batch_create(arr, len(self.solvers), _stream_handle(stream), C.byref(h)))
+        self.h = h
+
+    def set_graph(self, steps_per_graph: int):
+        _check(lib().dgt_batch_set_graph(self.h, int(steps_per_graph)))
+
+    def step(self, nsteps: int, t0):
+        t = np.ascontiguousarray(np.broadcast_to(np.asarray(t0, np.float64), (len(self.solvers),)))
+        _check(lib().dgt_batch_step(self.h, int(nsteps), _np_ptr(t)))
+
+    def timing(self):
+        ms, n, g = C.c_double(), C.c_int64(), C.c_int64()
+        _check(lib().dgt_batch_timing(self.h, C.byref(ms), C.byref(n), C.byref(g)))
+        return dict(ms=ms.value, launches=n.value, graph_launches=g.value)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.dgt_batch_destroy(self.h)
             self.h = None
