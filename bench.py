@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--fwi-steps", type=int, default=2000)
     ap.add_argument("--fwi-snapshots", type=int, default=32)
     ap.add_argument("--shots", type=int, default=64)
+    ap.add_argument("--graph-steps", type=int, default=10,
+                    help="batched workload: steps per HIP graph of the one-launch batch")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched workload: use the fixed P2 FP32 tile size and schedule instead of the autotuner")
     ap.add_argument("--material", choices=["auto", "layered", "lognormal"], default="auto",
@@ -426,6 +428,50 @@ def batched(a):
     torch.cuda.synchronize()
     dofs_step = sum(5 * npk * meshes[i][0].nc * len(shots_of[i]) for i in range(len(meshes)))
 
+    # the same solvers as ONE batch: shared launches for all six meshes (one per colour of a
+    # sub-chain, or one per sub-chain under the dependence-driven schedule), launched
+    # directly and replayed from a HIP graph of graph_steps steps
+    one = None
+    try:
+        batch = D.Batch([s for _, s in bat])
+    except D.DgtError as e:
+        one = {"error": str(e)}
+    if one is None:
+        one = {}
+        for mode, sched, g in (("colour_direct", 0, 0), ("colour_graph", 0, a.graph_steps),
+                               ("dependence_direct", 1, 0), ("dependence_graph", 1, a.graph_steps)):
+            batch.set_schedule(sched)
+            batch.set_graph(g)
+            for i, s in bat:
+                v, st = s.zeros()
+                torch.cuda.synchronize()
+                s.upload(v, st)
+            torch.cuda.synchronize()
+            batch.step(a.warmup, [0.0] * len(bat))
+            torch.cuda.synchronize()
+            tb1 = time.perf_counter()
+            batch.step(a.steps, [a.warmup * meshes[i][4] for i, _ in bat])
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - tb1
+            t = batch.timing()
+            worst = 0.0
+            for i, s in bat:
+                v, st = s.zeros()
+                torch.cuda.synchronize()
+                s.download(v, st)
+                torch.cuda.synchronize()
+                bv, bs = states[i]
+                num = ((v.double() - bv.double()) ** 2).sum() + ((st.double() - bs.double()) ** 2).sum()
+                den = (bv.double() ** 2).sum() + (bs.double() ** 2).sum()
+                worst = max(worst, math.sqrt(num.item() / den.item()) if den.item() > 0 else 0.0)
+            one[mode] = {"value": dofs_step * a.steps / wall, "ms_per_step": 1e3 * wall / a.steps,
+                         "event_ms_per_step": t["ms"] / a.steps, "launches_per_step": t["launches"] / a.steps,
+                         "graph_replays": t["graph_launches"], "steps_per_graph": g,
+                         "rel_l2_vs_six_streams": worst}
+            print(f"bench: one batch for all meshes ({mode}): {1e3 * wall / a.steps:.3f} ms/step, "
+                  f"{t['launches'] / a.steps:.0f} launches/step", file=sys.stderr, flush=True)
+        del batch
+
     # plain: one shot at a time
     wall_p = 0.0
     equal = True
@@ -495,6 +541,7 @@ def batched(a):
                    "dofs_per_step": dofs_step, "splits": list(splits),
                    "tuning": "fixed" if a.no_autotune else "autotuner"},
         "tuned": tuned,
+        "one_launch": one,
         "plain": {"value": rate_p, "ms_per_step": 1e3 * wall_p / a.steps,
                   "form": "the same shots one at a time, one-shot solvers"},
         "speedup_batched_vs_plain": rate_b / rate_p,

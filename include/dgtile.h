@@ -338,29 +338,34 @@ void dgt_solver_destroy(dgt_solver *s);
 /* ---- Several meshes in one launch (batched forward runs; an extension beyond
  * the paper, which runs one mesh at a time) ---- */
 typedef struct dgt_batch dgt_batch;
-/* A batch of solvers advanced together: every sub-chain of a step is ONE kernel
- * launch whose work queue holds the (tile, shot) items of all members, ordered by
- * colour and then member, each member's tiles in its own execution order; a
- * tile starts once its lower-colour neighbours of the same member have finished
- * (the dependence-driven schedule of dgt_solver_set_schedule mode 1, with the
+/* A batch of solvers advanced together by shared launches: one work queue over
+ * the (tile, shot) items of all members, ordered by colour and then member, each
+ * member's tiles in its own execution order.  Schedule 0 (default): one launch
+ * per colour of a sub-chain for all members (Alg. 2's colour loop across meshes),
+ * one item per workgroup.  Schedule 1: one launch per sub-chain, workgroups take
+ * items from a ticket counter and a tile starts once its lower-colour neighbours
+ * of the same member have finished (dgt_solver_set_schedule mode 1, with the
  * batch's own counters).  Members: host [n], 1 <= n <= 4096, distinct, each
  * inspected with a usable plan whose sub-chains all run on the register-resident
  * chain kernel (degrees 1 and 2), sharing degree, precision, flux, time order and
  * fusion scheme (half steps, or the whole order-2 step); they keep their own mesh,
  * material, dt, shots, sources and state and must outlive the batch.  Each item
  * runs the arithmetic of a member's own tiled step, so results equal stepping
- * each member alone (mode 1) to rounding (the batched kernel is compiled on its
- * own; multiply-adds may be contracted differently).  stream: hipStream_t or NULL; the batch
- * also owns a stream for graph replays, joined to it with events.  EINVAL for
- * mismatched members, ESTATE for an uninspected one, EUNSUPPORTED at degrees 3-4.
- * Synchronises the stream. *out owned by the caller (dgt_batch_destroy). */
+ * each member alone to rounding (the batched kernel is compiled on its own;
+ * multiply-adds may be contracted differently).  stream: hipStream_t or NULL; the
+ * batch also owns a stream for graph replays, joined to it with events.  EINVAL
+ * for mismatched members, ESTATE for an uninspected one, EUNSUPPORTED at degrees
+ * 3-4.  Synchronises the stream. *out owned by the caller (dgt_batch_destroy). */
 dgt_status dgt_batch_create(dgt_solver *const *solvers, int32_t n, void *stream, dgt_batch **out);
-/* Graph mode: steps_per_graph = G > 0 captures G steps (G x sub-chains kernel
- * nodes, no memory nodes) into a HIP graph at the next dgt_batch_step and replays
- * it floor(nsteps / G) times per call, the remaining steps launched directly;
- * before each replay the batch clears its counters and sets the replay's step
- * offset into the call's source amplitudes (outside the graph).  0 (default):
- * direct launches.  0 <= G <= 4096, else EINVAL. */
+/* Schedule of the batch's launches (default 0), as described above; mode 0 or 1,
+ * else EINVAL.  A change drops a captured graph. */
+dgt_status dgt_batch_set_schedule(dgt_batch *b, int32_t mode);
+/* Graph mode: steps_per_graph = G > 0 captures G steps (kernel nodes only, no
+ * memory nodes) into a HIP graph at the next dgt_batch_step and replays it
+ * floor(nsteps / G) times per call, the remaining steps launched directly; before
+ * each replay the batch sets the replay's step offset into the call's source
+ * amplitudes and, under schedule 1, clears its counters (outside the graph).
+ * 0 (default): direct launches.  0 <= G <= 4096, else EINVAL. */
 dgt_status dgt_batch_set_graph(dgt_batch *b, int32_t steps_per_graph);
 /* Advance every member nsteps steps, member i from its time t0[i] (host [n]),
  * like dgt_step(member, nsteps, 1, t0[i]).  Enqueued on the stream (the source

@@ -1,14 +1,15 @@
-// Several solvers in one launch per sub-chain, optionally replayed from a HIP
-// graph (included at the end of solver.hip).  The paper runs one mesh at a time;
+// Several solvers advanced by shared launches -- one per colour of a sub-chain, or
+// one per sub-chain under the dependence-driven schedule -- optionally replayed
+// from a HIP graph (included at the end of solver.hip).  The paper runs one mesh at a time;
 // the batched form serves many meshes and shots of the same discretisation, so
 // it cites no passage of the paper.
 //
 // Each member keeps its fields, schedule, plan and source; the batch owns the
 // work-queue segments and its own dependence and ticket counters, so members can
-// still be stepped alone.  Graph mode captures K steps (K x sub-chains kernel
-// nodes, nothing else) once and replays them: before each replay the counters are
-// cleared and the step offset of the source amplitudes is set, both outside the
-// graph, and the amplitudes of the whole call are uploaded at its start.
+// still be stepped alone.  Graph mode captures K steps (kernel nodes only) once and
+// replays them: before each replay the step offset of the source amplitudes is set
+// (and, for the dependence-driven schedule, the counters cleared), outside the
+// graph; the amplitudes of the whole call are uploaded at its start.
 
 struct dgt_batch {
     std::vector<dgt_solver *> m;        // members (not owned)
@@ -17,6 +18,7 @@ struct dgt_batch {
     hipStream_t gst = nullptr;          // own stream (graph capture and replay)
     hipEvent_t ev0 = nullptr, ev1 = nullptr, join = nullptr;
     int K = 0, fp32 = 0, upw = 0, order = 4, nsub = 0;
+    int sched = 0;  // 0: one launch per colour of a sub-chain; 1: dependence-driven, one per sub-chain
     struct Sub {
         int o0 = 0, nops = 0, nt = 0;
         size_t lds = 0;
@@ -28,6 +30,9 @@ struct dgt_batch {
         std::vector<dgt::DBuf<uint32_t>> cnt;  // [mesh] [nshots][ntiles]
         dgt::DBuf<uint32_t> head;
         dgt::DBuf<dgt::TileArgs> args;         // [mesh] launch arguments (fixed for the batch)
+        dgt::DBuf<dgt::TileArgs> args_c;       // the same for colour launches
+        std::vector<int32_t> cseg;             // [ncolours + 1] segments of each colour
+        std::vector<uint32_t> cstart;          // [ncolours + 1] first item of each colour
     };
     std::vector<Sub> sub;
     dgt::DBuf<int32_t> err;
@@ -45,7 +50,7 @@ struct dgt_batch {
     int64_t base_cap = 0;
     // timing of the last call
     double last_ms = 0;
-    int64_t launches = 0, graph_launches = 0;
+    int64_t launches = 0, graph_launches = 0, graph_nodes = 0;
     void drop_graph() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -80,7 +85,7 @@ static void dispatch_batch(const dgt_batch *b, F &&f) {
 // launch arguments of member `mi` for sub-chain `bi`: the dependence-driven form of
 // its own plan with the batch's counters (the epoch and source amplitude of a
 // launch come with the batch arguments)
-static TileArgs batch_member_args(dgt_batch *b, int bi, int mi) {
+static TileArgs batch_member_args(dgt_batch *b, int bi, int mi, int persist) {
     dgt_solver *s = b->m[mi];
     const SubPlan &P = s->plan[bi];
     const SubSched &sb = s->sched->s->sub[bi];
@@ -94,7 +99,7 @@ static TileArgs batch_member_args(dgt_batch *b, int bi, int mi) {
     A.src_vec = s->src_vec.p;
     A.dt = s->p.dt;
     A.src_amp = 0.0;
-    A.persist = 1;
+    A.persist = persist;
     A.ntiles = P.ntiles;
     A.tile_base = 0;
     A.need = sb.dep_need.p;
@@ -113,6 +118,8 @@ static BatchArgs batch_args(dgt_batch *b, int bi, uint32_t epoch) {
     dgt_batch::Sub &S = b->sub[bi];
     BatchArgs B{};
     B.args = S.args.p;
+    B.persist = 1;
+    B.seg_first = 0;
     B.epoch = epoch;
     B.amp_tab = b->amp.p;
     B.amp_stride = (int32_t)b->amp_cap;
@@ -158,10 +165,52 @@ static void batch_reset_counters(dgt_batch *b, hipStream_t st) {
     }
 }
 
+// colour c of sub-chain bi: one workgroup per item of every member
+static BatchArgs batch_colour_args(dgt_batch *b, int bi, int c) {
+    dgt_batch::Sub &S = b->sub[bi];
+    BatchArgs B{};
+    B.args = S.args_c.p;
+    B.persist = 0;
+    B.seg_first = S.cseg[c];
+    B.nseg = S.cseg[c + 1] - S.cseg[c];
+    B.ticket_base = S.cstart[c];
+    B.seg_start = S.seg_start.p;
+    B.seg_mesh = S.seg_mesh.p;
+    B.seg_local = S.seg_local.p;
+    B.total = S.cstart[c + 1] - S.cstart[c];
+    B.amp_tab = b->amp.p;
+    B.amp_stride = (int32_t)b->amp_cap;
+    return B;
+}
+
 template <int K, typename T>
 static void batch_launch(dgt_batch *b, int bi, const BatchArgs &B, hipStream_t st) {
     const dgt_batch::Sub &S = b->sub[bi];
-    tile_launch_batch<K, T>(b->upw, b->order, S.o0, S.nops, S.nt, S.slots, S.lds, st, B, TA_LAUNCH);
+    tile_launch_batch<K, T>(b->upw, b->order, S.o0, S.nops, S.nt, B.persist ? S.slots : (int)B.total, S.lds, st, B,
+                            TA_LAUNCH);
+}
+
+// the launches of step q of sub-chain bi (amp_base: the replay's offset, or NULL)
+template <int K, typename T>
+static void batch_launch_step(dgt_batch *b, int bi, uint32_t epoch, const int32_t *amp_base, int32_t amp_idx,
+                              hipStream_t st) {
+    dgt_batch::Sub &S = b->sub[bi];
+    if (b->sched == 1) {
+        BatchArgs B = batch_args(b, bi, epoch);
+        B.amp_base = amp_base;
+        B.amp_idx = amp_idx;
+        batch_launch<K, T>(b, bi, B, st);
+        ++b->launches;
+        return;
+    }
+    for (size_t c = 0; c + 1 < S.cstart.size(); ++c) {
+        if (S.cstart[c + 1] == S.cstart[c]) continue;
+        BatchArgs B = batch_colour_args(b, bi, (int)c);
+        B.amp_base = amp_base;
+        B.amp_idx = amp_idx;
+        batch_launch<K, T>(b, bi, B, st);
+        ++b->launches;
+    }
 }
 
 // steps [first, first + n) of the call, launched one by one (amplitudes at those indices)
@@ -170,11 +219,8 @@ static void batch_eager(dgt_batch *b, int64_t first, int64_t n) {
     for (int64_t q = first; q < first + n; ++q)
         for (int bi = 0; bi < b->nsub; ++bi) {
             dgt_batch::Sub &S = b->sub[bi];
-            BatchArgs B = batch_args(b, bi, ++S.epoch);
-            B.amp_base = nullptr;
-            B.amp_idx = (int32_t)q;
-            batch_launch<K, T>(b, bi, B, b->user);
-            ++b->launches;
+            const uint32_t ep = b->sched == 1 ? ++S.epoch : 0u;
+            batch_launch_step<K, T>(b, bi, ep, nullptr, (int32_t)q, b->user);
         }
 }
 
@@ -184,13 +230,11 @@ static void batch_capture(dgt_batch *b) {
     const int G = b->gsteps;
     DGT_HIP(hipStreamBeginCapture(b->gst, hipStreamCaptureModeThreadLocal));
     try {
+        const int64_t before = b->launches;
         for (int k = 0; k < G; ++k)
-            for (int bi = 0; bi < b->nsub; ++bi) {
-                BatchArgs B = batch_args(b, bi, (uint32_t)(k + 1));
-                B.amp_base = b->amp_base.p;
-                B.amp_idx = k;
-                batch_launch<K, T>(b, bi, B, b->gst);
-            }
+            for (int bi = 0; bi < b->nsub; ++bi) batch_launch_step<K, T>(b, bi, (uint32_t)(k + 1), b->amp_base.p, k, b->gst);
+        b->graph_nodes = b->launches - before;
+        b->launches = before;
     } catch (...) {
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(b->gst, &g);
@@ -249,15 +293,16 @@ static void batch_step(dgt_batch *b, int64_t nsteps, const double *t0) {
     DGT_HIP(hipEventRecord(b->join, b->user));
     DGT_HIP(hipStreamWaitEvent(b->gst, b->join, 0));
     for (int64_t r = 0; r < nrep; ++r) {
-        batch_reset_counters(b, b->gst);  // outside the graph
+        if (b->sched == 1) batch_reset_counters(b, b->gst);  // outside the graph
         b->base_host[r] = (int32_t)(r * G);
         DGT_HIP(hipMemcpyAsync(b->amp_base.p, b->base_host + r, sizeof(int32_t), hipMemcpyHostToDevice, b->gst));
         DGT_HIP(hipGraphLaunch(b->exec, b->gst));
         ++b->graph_launches;
-        b->launches += (int64_t)G * b->nsub;
+        b->launches += b->graph_nodes;
     }
     // the counters now hold G epochs of every sub-chain: the remaining steps continue them
-    for (auto &S : b->sub) S.epoch = (uint32_t)G;
+    if (b->sched == 1)
+        for (auto &S : b->sub) S.epoch = (uint32_t)G;
     DGT_HIP(hipEventRecord(b->join, b->gst));
     DGT_HIP(hipStreamWaitEvent(b->user, b->join, 0));
     if (rem) batch_eager<K, T>(b, nrep * G, rem);
@@ -326,7 +371,9 @@ dgt_status dgt_batch_create(dgt_solver *const *solvers, int32_t n, void *stream,
             }
             S.nt = std::max(S.nt, 256);
             uint64_t t = 0;
-            for (int c = 0; c < maxc; ++c)
+            for (int c = 0; c < maxc; ++c) {
+                S.cseg.push_back((int32_t)me.size());
+                S.cstart.push_back((uint32_t)t);
                 for (size_t i = 0; i < b->m.size(); ++i) {
                     const SubPlan &P = b->m[i]->plan[bi];
                     if (c >= P.ncolors) continue;
@@ -337,6 +384,9 @@ dgt_status dgt_batch_create(dgt_solver *const *solvers, int32_t n, void *stream,
                     lo.push_back((int32_t)((int64_t)P.color_off[c] * b->m[i]->nshots));
                     t += (uint64_t)cnt;
                 }
+            }
+            S.cseg.push_back((int32_t)me.size());
+            S.cstart.push_back((uint32_t)t);
             DGT_REQUIRE(t < (1ull << 31), DGT_EUNSUPPORTED, "more than 2^31 work items in one batched launch");
             st.push_back((int32_t)t);
             S.nseg = (int)me.size();
@@ -352,9 +402,13 @@ dgt_status dgt_batch_create(dgt_solver *const *solvers, int32_t n, void *stream,
             }
             S.head.alloc(1);
             DGT_HIP(hipMemsetAsync(S.head.p, 0, sizeof(uint32_t), b->user));
-            std::vector<TileArgs> margs;
-            for (size_t i = 0; i < b->m.size(); ++i) margs.push_back(batch_member_args(b.get(), bi, (int)i));
+            std::vector<TileArgs> margs, cargs;
+            for (size_t i = 0; i < b->m.size(); ++i) {
+                margs.push_back(batch_member_args(b.get(), bi, (int)i, 1));
+                cargs.push_back(batch_member_args(b.get(), bi, (int)i, 0));
+            }
             S.args.upload(margs, b->user);
+            S.args_c.upload(cargs, b->user);
             DGT_HIP(hipStreamSynchronize(b->user));
             int occ = 0;
             dgt_batch *bp = b.get();
@@ -377,6 +431,14 @@ dgt_status dgt_batch_set_graph(dgt_batch *b, int32_t steps_per_graph) {
         DGT_REQUIRE(b && steps_per_graph >= 0 && steps_per_graph <= 4096, DGT_EINVAL, "bad arguments");
         if (steps_per_graph != b->gsteps) b->drop_graph();
         b->gsteps = steps_per_graph;
+    });
+}
+
+dgt_status dgt_batch_set_schedule(dgt_batch *b, int32_t mode) {
+    return guard([&] {
+        DGT_REQUIRE(b && (mode == 0 || mode == 1), DGT_EINVAL, "bad arguments");
+        if (mode != b->sched) b->drop_graph();
+        b->sched = mode;
     });
 }
 

@@ -65,7 +65,10 @@ struct TileArgs {
 // ordered by colour, then mesh.
 struct BatchArgs {
     const TileArgs *args;      // [nmesh] per-mesh launch arguments (device)
-    int32_t nseg;
+    int32_t persist;           // 1: dependence-driven (tickets); 0: one colour, one item per workgroup
+    int32_t seg_first;         // colour launches: the colour's first segment, its first ticket
+    uint32_t ticket_base;
+    int32_t nseg;              // segments searched (from seg_first)
     const int32_t *seg_start;  // [nseg + 1] first ticket of each segment
     const int32_t *seg_mesh;   // [nseg] mesh of the segment
     const int32_t *seg_local;  // [nseg] the segment's first item in its mesh's own order

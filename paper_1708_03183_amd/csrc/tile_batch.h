@@ -1,13 +1,13 @@
 #pragma once
-// Several solvers (meshes, each with its shots) advanced by one launch per
-// sub-chain: the register-resident chain kernel under the dependence-driven
-// schedule, with one work queue over the (mesh, tile, shot) items of all of them.
-//
-// The queue is ordered by colour, then mesh: segment g of the queue holds the
-// items of one mesh's tiles of one colour, in that mesh's own execution order.
-// A tile's predecessors are tiles of the same mesh with lower colours, so they
-// sit in earlier segments and were taken by workgroups already running: the wait
-// argument of the single-mesh schedule holds unchanged.  Each mesh keeps its own
+// Several solvers (meshes, each with its shots) advanced together on the
+// register-resident chain kernel: one queue over the (mesh, tile, shot) items of
+// all of them, ordered by colour, then mesh (segment g holds the items of one
+// mesh's tiles of one colour, in that mesh's own execution order).  Colour
+// launches: one launch per colour of a sub-chain for all meshes, one item per
+// workgroup.  Dependence-driven: one launch per sub-chain, workgroups take
+// tickets; a tile's predecessors are tiles of the same mesh with lower colours,
+// so they sit in earlier segments and were taken by workgroups already running,
+// and the wait argument of the single-mesh schedule holds unchanged.  Each mesh keeps its own
 // fields, schedule, dependence counters and source; an item runs exactly the
 // arithmetic of the single-mesh kernel on its mesh's data.
 #include <hip/hip_runtime.h>
@@ -18,24 +18,25 @@ namespace dgt {
 
 
 template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int NT>
-__device__ __forceinline__ void batch_body(const RefC<K, T> &Rf, const BatchArgs &b, unsigned char *smem) {
+__device__ __forceinline__ void batch_body(const RefC<K, T> &Rf, const BatchArgs &b,
+                                           const TileArgs *__restrict__ args, unsigned char *smem) {
     __shared__ int s_tile, s_shot, s_mesh;
     __shared__ double s_amp;
     T *lds = reinterpret_cast<T *>(smem);
     for (;;) {
         if (threadIdx.x == 0) {
-            const uint32_t t = atomicAdd(b.head, 1u) - b.head_base;
-            if (t >= b.total) {
+            const uint32_t t = b.persist ? atomicAdd(b.head, 1u) - b.head_base : b.ticket_base + blockIdx.x;
+            if (b.persist && t >= b.total) {
                 s_tile = -1;
             } else {
-                int lo = 0, hi = b.nseg - 1;  // last segment starting at or before t
+                int lo = b.seg_first, hi = b.seg_first + b.nseg - 1;  // last segment starting at or before t
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
                     if ((uint32_t)b.seg_start[mid] <= t) lo = mid;
                     else hi = mid - 1;
                 }
                 const int m = b.seg_mesh[lo];
-                const TileArgs &a = b.args[m];
+                const TileArgs &a = args[m];
                 const uint32_t local = (uint32_t)b.seg_local[lo] + (t - (uint32_t)b.seg_start[lo]);
                 s_mesh = m;
                 s_shot = (int)(local % (uint32_t)a.nshots);
@@ -49,8 +50,9 @@ __device__ __forceinline__ void batch_body(const RefC<K, T> &Rf, const BatchArgs
         if (tile < 0) return;
         const int mesh = __builtin_amdgcn_readfirstlane(s_mesh);
         const int shot = __builtin_amdgcn_readfirstlane(s_shot);
-        const TileArgs &a = b.args[mesh];
+        const TileArgs &a = args[mesh];
         chain_tile<K, T, UPW, ORDER, O0, NOPS>(Rf, a, lds, tile, shot, (T)s_amp, b.epoch);
+        if (!b.persist) return;
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (threadIdx.x == 0)
@@ -61,7 +63,9 @@ __device__ __forceinline__ void batch_body(const RefC<K, T> &Rf, const BatchArgs
 }
 
 template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int NT>
-__global__ __launch_bounds__(NT) void k_tile_chain_batch(const BatchArgs b) {
+// args: the members' launch arguments (b.args), a separate read-only, non-aliased
+// kernel argument so that the compiler loads their fields into scalar registers
+__global__ __launch_bounds__(NT) void k_tile_chain_batch(const BatchArgs b, const TileArgs *__restrict__ args) {
     extern __shared__ __align__(16) unsigned char smem[];
     if constexpr (K <= 2 && UPW) {  // reference matrices in LDS, as in the single-mesh kernel
         __shared__ __align__(16) RefC<K, T> sref;
@@ -69,9 +73,9 @@ __global__ __launch_bounds__(NT) void k_tile_chain_batch(const BatchArgs b) {
         uint32_t *dst = reinterpret_cast<uint32_t *>(&sref);
         for (int i = threadIdx.x; i < (int)(sizeof(RefC<K, T>) / 4); i += NT) dst[i] = src[i];
         __syncthreads();
-        batch_body<K, T, UPW, ORDER, O0, NOPS, NT>(sref, b, smem);
+        batch_body<K, T, UPW, ORDER, O0, NOPS, NT>(sref, b, args, smem);
     } else {
-        batch_body<K, T, UPW, ORDER, O0, NOPS, NT>(R<K, T>(), b, smem);
+        batch_body<K, T, UPW, ORDER, O0, NOPS, NT>(R<K, T>(), b, args, smem);
     }
 }
 

@@ -78,17 +78,27 @@ __host__ __device__ constexpr int field_last_write(int order, int o0, int n, int
     return last;
 }
 
+// Device-memory pointers held in launch arguments that live in memory (the batched
+// kernels) reach the kernel as generic pointers; these say they point to global
+// memory, so accesses stay global_load / global_store instead of flat ones.
+template <typename T>
+using gptr_t = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr_t<T> gp(T *p) {
+    return (gptr_t<T>)p;
+}
+
 // Field accesses that can meet another tile's data within one launch of the
 // dependence-driven schedule (every write-back, and the gathers of fields the
 // sub-chain writes) are coherent at device scope: they neither hit a stale line of
 // another XCD's L2 nor stay dirty in one, so no cache write-back or invalidation is
 // needed between dependent tiles.
-template <typename T>
-__device__ __forceinline__ T load_field(const T *p, bool coherent) {
+template <typename P>
+__device__ __forceinline__ auto load_field(P p, bool coherent) {
     return coherent ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
 }
-template <typename T>
-__device__ __forceinline__ void store_field(T *p, T v, bool coherent) {
+template <typename P, typename T>
+__device__ __forceinline__ void store_field(P p, T v, bool coherent) {
     if (coherent) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else *p = v;
 }
@@ -125,7 +135,7 @@ __device__ __forceinline__ void chain_op(const RefC<K, T> &Rf, CellRegs<K, T> &r
             // (the dependence-driven schedule gathers the first operator's read-only fields
             // before its dependence wait)
             if (O == O0 && a.persist && field_last_write(ORDER, O0, NOPS, f) < 0) continue;
-            const T *F = reinterpret_cast<const T *>(a.F[f]) + shot * a.fshot[f];
+            const auto F = gp(reinterpret_cast<const T *>(a.F[f])) + shot * a.fshot[f];
             // only fields the sub-chain writes can change during the launch; the others
             // were written by earlier launches and need no device-scope coherence
             const bool coh = a.persist && field_last_write(ORDER, O0, NOPS, f) >= 0;
@@ -322,7 +332,7 @@ __device__ __forceinline__ void chain_op(const RefC<K, T> &Rf, CellRegs<K, T> &r
             T(&q)[3][NP] = r.f[D.vel ? F_V : F_S];
             const T dt = (T)a.dt;
             const bool src = !D.vel && x == a.src_cells[shot];
-            const T *sv = reinterpret_cast<const T *>(a.src_vec) + shot * NP;
+            const auto sv = gp(reinterpret_cast<const T *>(a.src_vec)) + shot * NP;
 #pragma unroll
             for (int c = 0; c < NO; ++c)
 #pragma unroll
@@ -338,7 +348,7 @@ __device__ __forceinline__ void chain_op(const RefC<K, T> &Rf, CellRegs<K, T> &r
 #pragma unroll
     for (int f = 0; f < F_COUNT; ++f) {
         if (field_last_write(ORDER, O0, NOPS, f) != O || !((fl >> (8 + f)) & 1)) continue;
-        T *F = reinterpret_cast<T *>(a.F[f]) + shot * a.fshot[f];
+        const auto F = gp(reinterpret_cast<T *>(a.F[f])) + shot * a.fshot[f];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             if (c >= field_ncomp(f)) break;
@@ -404,8 +414,8 @@ __device__ __forceinline__ void chain_tile(const RefC<K, T> &Rf, const TileArgs 
 #pragma unroll
             for (int i = 0; i < NP; ++i) r.f[f][c][i] = 0;
     if (act) {
-        acc = a.facc[f0 + s];
-        x = a.foot[f0 + s];
+        acc = gp(a.facc)[f0 + s];
+        x = gp(a.foot)[f0 + s];
         const bool single = acc >> 31;
 #pragma unroll
         for (int f = 0; f < F_COUNT; ++f) {
@@ -417,8 +427,8 @@ __device__ __forceinline__ void chain_tile(const RefC<K, T> &Rf, const TileArgs 
 #pragma unroll
         for (int q = 0; q < NOPS; ++q)
 #pragma unroll
-            for (int p = 0; p < 3; ++p) nb[q][p] = a.tnb[b0 + (q * 3 + p) * nfoot + s];
-        const T *geo = reinterpret_cast<const T *>(a.geo);
+            for (int p = 0; p < 3; ++p) nb[q][p] = gp(a.tnb)[b0 + (q * 3 + p) * nfoot + s];
+        const auto geo = gp(reinterpret_cast<const T *>(a.geo));
 #pragma unroll
         for (int q = 0; q < G_NROWS; ++q) r.g[q] = geo[(int64_t)q * a.nc + x];
         // the facet normals serve every operator of the sub-chain
@@ -437,7 +447,7 @@ __device__ __forceinline__ void chain_tile(const RefC<K, T> &Rf, const TileArgs 
                 if (field_first_op(ORDER, O0, NOPS, f) != O0 || field_last_write(ORDER, O0, NOPS, f) >= 0 ||
                     !((fl >> f) & 1))
                     continue;
-                const T *F = reinterpret_cast<const T *>(a.F[f]) + shot * a.fshot[f];
+                const auto F = gp(reinterpret_cast<const T *>(a.F[f])) + shot * a.fshot[f];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     if (c >= field_ncomp(f)) break;

@@ -60,7 +60,7 @@ static void batch_go(Kern kern, int nt, int grid, size_t lds, hipStream_t st, co
         DGT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, kern, nt, lds));
         return;
     }
-    kern<<<grid, nt, lds, st>>>(B);
+    kern<<<grid, nt, lds, st>>>(B, B.args);
 }
 
 template <int K, typename T, int NT>

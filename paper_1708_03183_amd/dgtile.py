@@ -105,6 +105,7 @@ _SIGS = {
     "dgt_solver_kernels": [_p, _i32, _p],
     "dgt_batch_create": [_p, C.c_int32, _p, C.POINTER(_p)],
     "dgt_batch_set_graph": [_p, C.c_int32],
+    "dgt_batch_set_schedule": [_p, C.c_int32],
     "dgt_batch_step": [_p, C.c_int64, _p],
     "dgt_batch_timing": [_p, C.POINTER(C.c_double), _i64, _i64],
     "dgt_batch_destroy": [_p],
@@ -488,6 +489,10 @@ class Batch:
 
     def set_graph(self, steps_per_graph: int):
         _check(lib().dgt_batch_set_graph(self.h, int(steps_per_graph)))
+
+    def set_schedule(self, mode: int):
+        """0: one launch per colour of a sub-chain; 1: dependence-driven, one per sub-chain."""
+        _check(lib().dgt_batch_set_schedule(self.h, int(mode)))
 
     def step(self, nsteps: int, t0):
         t = np.ascontiguousarray(np.broadcast_to(np.asarray(t0, np.float64), (len(self.solvers),)))

@@ -78,10 +78,11 @@ def _alone(mem, steps, t0):
     return res
 
 
-def _batched(D, mem, steps, t0, graph=0, calls=1):
+def _batched(D, mem, steps, t0, graph=0, calls=1, schedule=0):
     for x in mem:
         x["g"].upload(x["v0"].clone(), x["s0"].clone())
     b = D.Batch([x["g"] for x in mem])
+    b.set_schedule(schedule)
     b.set_graph(graph)
     outs = []
     for c in range(calls):
@@ -97,13 +98,15 @@ def _batched(D, mem, steps, t0, graph=0, calls=1):
     return outs
 
 
+@pytest.mark.parametrize("schedule", [0, 1])
 @pytest.mark.parametrize("k,prec,order,splits", [(2, 0, 4, (13,)), (2, 1, 4, (13,)), (1, 0, 2, ())])
-def test_batch_equals_members_alone(D, k, prec, order, splits):
+def test_batch_equals_members_alone(D, k, prec, order, splits, schedule):
     mem = _members(D, k, prec, order, splits)
     ref = _alone(mem, 5, 0.1)
-    (res, t), = _batched(D, mem, 5, 0.1)
+    (res, t), = _batched(D, mem, 5, 0.1, schedule=schedule)
     nsub = len(splits) + 1
-    assert t["launches"] == 5 * nsub and t["graph_launches"] == 0
+    ncol = [max(x["g"].schedule().sub_info(b)["ncolors"] for x in mem) for b in range(nsub)]
+    assert t["launches"] == 5 * (nsub if schedule else sum(ncol)) and t["graph_launches"] == 0
     worst = 0.0
     for q, ((v, s), (rv, rs)) in enumerate(zip(res, ref)):
         ok, d = _same((v, s), (rv, rs), prec)
@@ -118,25 +121,27 @@ def test_batch_equals_members_alone(D, k, prec, order, splits):
     gv, gs = res[0][0].double().cpu().numpy(), res[0][1].double().cpu().numpy()
     err = np.sqrt(((gv - v) ** 2).sum() + ((gs - s) ** 2).sum()) / np.sqrt((v ** 2).sum() + (s ** 2).sum())
     mx = max(np.abs(gv - v).max(), np.abs(gs - s).max()) / max(np.abs(v).max(), np.abs(s).max())
-    print(f"batch k={k} prec={prec} order={order}: {len(mem)} members, max-abs difference from their own runs "
+    print(f"batch k={k} prec={prec} order={order} schedule={schedule}: {len(mem)} members, max-abs difference "
+          f"from their own runs "
           f"{worst:.3e}; "
           f"member 0 vs oracle rel L2 {err:.3e}, rel max-abs {mx:.3e}")
     tol = 1e-5 if prec else 1e-12
     assert err <= tol and mx <= tol
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_batch_graph_replays_equal_direct_launches(D, prec):
+@pytest.mark.parametrize("prec,schedule", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_batch_graph_replays_equal_direct_launches(D, prec, schedule):
     """Three calls of 7 steps with 3-step graphs (two replays and one direct step
     per call), each compared with three calls of direct launches."""
     mem = _members(D, 2, prec)
-    direct = _batched(D, mem, 7, 0.1, graph=0, calls=3)
-    graphed = _batched(D, mem, 7, 0.1, graph=3, calls=3)
+    direct = _batched(D, mem, 7, 0.1, graph=0, calls=3, schedule=schedule)
+    graphed = _batched(D, mem, 7, 0.1, graph=3, calls=3, schedule=schedule)
     for c, ((rd, td), (rg, tg)) in enumerate(zip(direct, graphed)):
-        assert tg["graph_launches"] == 2 and tg["launches"] == td["launches"] == 14
+        assert tg["graph_launches"] == 2 and tg["launches"] == td["launches"]
         for q, ((v, s), (rv, rs)) in enumerate(zip(rg, rd)):
             assert torch.equal(v, rv) and torch.equal(s, rs), f"call {c}, member {q}: graph differs"
-        print(f"graph call {c}: {tg['ms']:.3f} ms vs direct {td['ms']:.3f} ms, bit-equal")
+        print(f"schedule {schedule} graph call {c}: {tg['ms']:.3f} ms vs direct {td['ms']:.3f} ms "
+              f"({td['launches']} launches), bit-equal")
     ref = _alone(mem, 21, 0.1)  # the three calls together equal 21 steps of each member alone
     for q, ((v, s), (rv, rs)) in enumerate(zip(graphed[-1][0], ref)):
         ok, d = _same((v, s), (rv, rs), prec)
