@@ -25,7 +25,8 @@ __device__ __forceinline__ void batch_body(const RefC<K, T> &Rf, const BatchArgs
     T *lds = reinterpret_cast<T *>(smem);
     for (;;) {
         if (threadIdx.x == 0) {
-            const uint32_t t = b.persist ? atomicAdd(b.head, 1u) - b.head_base : b.ticket_base + blockIdx.x;
+            const uint32_t t = b.persist ? atomicAdd(b.head, 1u) - b.head_base
+                                         : b.ticket_base + (uint32_t)xcd_item((int)blockIdx.x, (int)gridDim.x);
             if (b.persist && t >= b.total) {
                 s_tile = -1;
             } else {

@@ -78,6 +78,16 @@ __host__ __device__ constexpr int field_last_write(int order, int o0, int n, int
     return last;
 }
 
+// Workgroups of a launch go to the GPU's eight XCDs in turn (workgroup b to XCD b mod 8),
+// each XCD with its own L2.  A colour launch's workgroup b takes item xcd_item(b, n) of
+// its n items, so that every XCD runs one contiguous run of the items -- neighbouring
+// tiles in the seed order, which share halo cells, and the shots of a tile -- instead
+// of every eighth item.  (A bijection of [0, n); only locality depends on the dispatch.)
+__device__ __forceinline__ int xcd_item(int b, int n) {
+    const int x = b & 7, k = b >> 3, q = n >> 3, r = n & 7;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 // Device-memory pointers held in launch arguments that live in memory (the batched
 // kernels) reach the kernel as generic pointers; these say they point to global
 // memory, so accesses stay global_load / global_store instead of flat ones.
@@ -471,8 +481,9 @@ __device__ __forceinline__ void chain_kernel_body(const RefC<K, T> &Rf, const Ti
     __shared__ int s_next, s_shot;
     T *lds = reinterpret_cast<T *>(smem);
     if (!a.persist) {  // one launch per colour
-        chain_tile<K, T, UPW, ORDER, O0, NOPS>(Rf, a, lds, a.tiles[a.tile_base + (int)blockIdx.x / a.nshots],
-                                               (int)blockIdx.x % a.nshots, (T)a.src_amp, a.epoch);
+        const int item = xcd_item((int)blockIdx.x, (int)gridDim.x);
+        chain_tile<K, T, UPW, ORDER, O0, NOPS>(Rf, a, lds, a.tiles[a.tile_base + item / a.nshots], item % a.nshots,
+                                               (T)a.src_amp, a.epoch);
         return;
     }
     for (;;) {

@@ -16,6 +16,7 @@
 #include "dg_kernels.h"
 #include "refconst.h"
 #include "tile_args.h"
+#include "tile_chain.h"
 
 namespace dgt {
 
@@ -45,8 +46,9 @@ __global__ __launch_bounds__(NT) void k_tile(const TileArgs a) {
     constexpr int NG = K <= 2 ? 1 : (K == 3 ? 2 : 3);  // node groups per cell
     constexpr int NPG = (NP + NG - 1) / NG;             // nodes per group
     extern __shared__ __align__(16) unsigned char smem[];
-    const int tile = a.tiles[a.tile_base + (int)blockIdx.x / a.nshots];
-    const int shot = (int)blockIdx.x % a.nshots;
+    const int item = xcd_item((int)blockIdx.x, (int)gridDim.x);  // contiguous items per XCD
+    const int tile = a.tiles[a.tile_base + item / a.nshots];
+    const int shot = item % a.nshots;
     const int f0 = a.foot_off[tile];
     const int nfoot = a.foot_off[tile + 1] - f0;
     const int S = a.stride, NR = a.nrow;

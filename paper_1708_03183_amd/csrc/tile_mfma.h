@@ -475,8 +475,9 @@ __global__ __launch_bounds__(NT) void k_tile_mfma(const TileArgs a) {
     MfmaRef<K, T> Ar;
     Ar.load(R<K, T>(), threadIdx.x & 63);
     if (!a.persist) {  // one launch per colour
-        mfma_tile<K, T, UPW, ORDER, O0, NOPS, NT>(Ar, a, smem, a.tiles[a.tile_base + (int)blockIdx.x / a.nshots],
-                                                   (int)blockIdx.x % a.nshots);
+        const int item = xcd_item((int)blockIdx.x, (int)gridDim.x);
+        mfma_tile<K, T, UPW, ORDER, O0, NOPS, NT>(Ar, a, smem, a.tiles[a.tile_base + item / a.nshots],
+                                                   item % a.nshots);
         return;
     }
     for (;;) {  // dependence-driven schedule, as in the register-resident chain kernel
