@@ -84,7 +84,14 @@ def _declare(L):
     L.or_chain_map.argtypes = [_p, C.c_int, C.c_int, C.c_int, _i32p]
     L.or_chain_loop.argtypes = [_p, C.c_int, C.c_int, _i32p, _i32p, _i32p]
     L.or_chain_nloops.argtypes = [_p]
+    L.or_chain_set_size.argtypes = [_p, C.c_int]
+    L.or_chain_set_size.restype = C.c_int64
+    L.or_chain_get_loop.argtypes = [_p, C.c_int, _i32p, _i32p, _i32p, _i32p]
+    L.or_chain_get_map.argtypes = [_p, C.c_int, _i32p, _i32p, _i32p, _p]
     L.or_inspect.argtypes = [_p, C.c_int64, C.c_int, _p, C.c_int, C.c_int, _p, C.c_int, _p, C.POINTER(_p)]
+    L.or_inspect_regions.argtypes = [_p, C.c_int64, C.c_int, _p, C.c_int, C.c_int, _p, C.c_int, _p, _p, C.c_int,
+                                     C.POINTER(_p)]
+    L.or_sched_regions.argtypes = [_p, C.c_int, _p, _p]
     L.or_sched_free.argtypes = [_p]
     L.or_sched_nsub.argtypes = [_p]
     L.or_sched_sub_info.argtypes = [_p, C.c_int] + [C.POINTER(C.c_int32)] * 5
@@ -268,9 +275,32 @@ class OChain:
     def nloops(self):
         return lib().or_chain_nloops(self.h)
 
+    def set_size(self, set_id):
+        return int(lib().or_chain_set_size(self.h, set_id))
+
+    def loop_info(self, j):
+        """(set, [(map, mode), ...]) of loop j"""
+        st, nd = np.zeros(1, np.int32), np.zeros(1, np.int32)
+        mp, mo = np.zeros(8, np.int32), np.zeros(8, np.int32)
+        if lib().or_chain_get_loop(self.h, j, st, nd, mp, mo) < 0:
+            raise IndexError(j)
+        return int(st[0]), [(int(mp[i]), int(mo[i])) for i in range(int(nd[0]))]
+
+    def map_info(self, m):
+        """(from, to, values [size(from), arity]) of map m"""
+        fr, to, ar = np.zeros(1, np.int32), np.zeros(1, np.int32), np.zeros(1, np.int32)
+        if lib().or_chain_get_map(self.h, m, fr, to, ar, None) < 0:
+            raise IndexError(m)
+        vals = np.zeros(max(self.set_size(int(fr[0])) * int(ar[0]), 1), np.int32)
+        lib().or_chain_get_map(self.h, m, fr, to, ar, _ptr(vals))
+        n = self.set_size(int(fr[0]))
+        return int(fr[0]), int(to[0]), vals[: n * int(ar[0])].reshape(n, int(ar[0]))
+
     def inspect(self, ts, partition=0, seed_xy=None, max_rounds=64, splits=(), max_colour_tiles=0,
-                sub_tile_sizes=None):
-        """sub_tile_sizes: one seed tile size per sub-chain (len(splits) + 1), else ts for all."""
+                sub_tile_sizes=None, seed_region=None, carry=1):
+        """sub_tile_sizes: one seed tile size per sub-chain (len(splits) + 1), else ts for all.
+        seed_region: per seed iteration 0 core, 1 boundary, 2 non-exec (or None); carry: one
+        halo exchange for the whole chain (1) or one per sub-chain (0)."""
         xy = None if seed_xy is None else np.ascontiguousarray(seed_xy, np.float64)
         sp = np.ascontiguousarray(np.array(splits, np.int32))
         st = None
@@ -278,8 +308,14 @@ class OChain:
             st = np.ascontiguousarray(np.array(sub_tile_sizes, np.int32))
             assert st.size == len(sp) + 1
         h = C.c_void_p()
-        rc = lib().or_inspect(self.h, ts, partition, _ptr(xy), max_rounds, max_colour_tiles,
-                              _ptr(sp) if len(sp) else None, len(sp), _ptr(st), C.byref(h))
+        if seed_region is None:
+            rc = lib().or_inspect(self.h, ts, partition, _ptr(xy), max_rounds, max_colour_tiles,
+                                  _ptr(sp) if len(sp) else None, len(sp), _ptr(st), C.byref(h))
+        else:
+            reg = np.ascontiguousarray(seed_region, np.uint8)
+            rc = lib().or_inspect_regions(self.h, ts, partition, _ptr(xy), max_rounds, max_colour_tiles,
+                                          _ptr(sp) if len(sp) else None, len(sp), _ptr(st), _ptr(reg),
+                                          int(carry), C.byref(h))
         if rc:
             raise RuntimeError(f"or_inspect -> {rc}")
         return OSched(h, self)
@@ -358,6 +394,15 @@ class OSched:
         tl = np.zeros(info["ntiles"], np.int32)
         lib().or_sched_tiles_by_color(self.h, sub, coff, tl)
         return coff, tl
+
+    def regions(self, sub, seed_size):
+        """(core tiles, boundary tiles, T_ne id, T_ne colour), seed regions of the sub-chain;
+        None without regions."""
+        info = np.zeros(4, np.int32)
+        reg = np.zeros(max(seed_size, 1), np.uint8)
+        if lib().or_sched_regions(self.h, sub, _ptr(info), _ptr(reg)) < 0:
+            return None
+        return tuple(int(x) for x in info), reg[:seed_size]
 
     def set_color(self, sub, tile, color):
         lib().or_sched_set_color(self.h, sub, tile, color)

@@ -36,6 +36,22 @@
  *   R8 (seed order)        partition 1 sorts seed iterations by the Hilbert
  *       index of their quantised coordinates (2^16 per axis), ties by id.
  *   R9 (lists)             iteration lists and footprints are sorted by id.
+ *   R10 (regions, Sec. 3.3 and 5.1.2)  with seed regions (core 0, boundary 1,
+ *       non-exec 2) the seeds of each region are taken in seed order and cut into
+ *       blocks of ts: core tiles first, then boundary tiles, then one tile T_ne
+ *       holding every non-exec seed.  A GPU runs the tiles of one colour in
+ *       parallel, so each region is coloured by Jones-Plassmann (R5) on the tile
+ *       graph restricted to its own tiles; boundary colours follow all core
+ *       colours and T_ne takes the highest colour alone.  T_ne is never
+ *       executed; anything touching its data joins it through the MAX of
+ *       Alg. 3/4.  The colour-class cap (R5b) is not combined with regions.
+ *   R11 (one exchange per chain)  with carry set, the halo is exchanged once
+ *       before the first sub-chain only: every later sub-chain treats as
+ *       non-exec, besides the given non-exec seeds, every seed element that a
+ *       T_ne iteration of an earlier sub-chain wrote (its value is stale).  This
+ *       needs every write of the chain to land in the seed set.  Without carry,
+ *       every sub-chain starts from the given regions (the paper's case: each
+ *       loop chain exchanges its own halo).
  */
 #include "oracle.h"
 #include <math.h>
@@ -75,6 +91,11 @@ typedef struct {
     int64_t foot_len[MAXSETS];
     int32_t *foot_off[MAXSETS], *foot[MAXSETS];
     uint32_t *acc[MAXSETS];
+    /* regions (Sec. 3.3): core tiles [0, ncore), boundary tiles [ncore,
+     * ncore + nbnd), the non-exec tile tne = ncore + nbnd; region[] holds the
+     * seed regions this sub-chain was inspected with (NULL: no regions) */
+    int32_t ncore, nbnd, tne;
+    uint8_t *region;
 } sub_t;
 
 struct or_sched {
@@ -134,6 +155,28 @@ int or_chain_loop(or_chain *c, int set, int ndesc, const int32_t *maps, const in
 }
 
 int or_chain_nloops(const or_chain *c) { return c->nloops; }
+
+int64_t or_chain_set_size(const or_chain *c, int set) { return set < 0 || set >= c->nsets ? -1 : c->size[set]; }
+
+int or_chain_get_loop(const or_chain *c, int j, int32_t *set, int32_t *ndesc, int32_t *maps, int32_t *modes) {
+    if (j < 0 || j >= c->nloops) return -1;
+    *set = c->loops[j].set;
+    *ndesc = c->loops[j].ndesc;
+    for (int i = 0; i < c->loops[j].ndesc; i++) {
+        maps[i] = c->loops[j].d[i].map;
+        modes[i] = c->loops[j].d[i].mode;
+    }
+    return 0;
+}
+
+int or_chain_get_map(const or_chain *c, int m, int32_t *from, int32_t *to, int32_t *arity, int32_t *values) {
+    if (m < 0 || m >= c->nmaps) return -1;
+    *from = c->maps[m].from;
+    *to = c->maps[m].to;
+    *arity = c->maps[m].arity;
+    if (values) memcpy(values, c->maps[m].values, sizeof(int32_t) * c->size[c->maps[m].from] * c->maps[m].arity);
+    return 0;
+}
 
 /* target set of a descriptor */
 static int dset(const or_chain *c, const loop_t *L, const desc_t *D) {
@@ -546,9 +589,35 @@ int or_projection_after(const or_chain *c, const int32_t *tile0, int ntiles, con
     return 0;
 }
 
+/* Region-aware colouring (R10): Jones-Plassmann on the edges joining tiles of
+ * one region, then boundary colours shifted past the core ones and T_ne alone
+ * in the highest colour.  Returns the number of colours or -1. */
+static int colour_regions(int ntiles, const edges_t *E, const uint8_t *treg, int32_t *color) {
+    edges_t F;
+    F.e = malloc(sizeof(uint64_t) * (E->n + 1));
+    F.n = 0;
+    for (int64_t i = 0; i < E->n; i++) {
+        int32_t a = (int32_t)(E->e[i] >> 32), b = (int32_t)(E->e[i] & 0xffffffffu);
+        if (treg[a] == treg[b]) F.e[F.n++] = E->e[i];
+    }
+    int ncol = colour_tiles(ntiles, &F, color, 0);
+    free(F.e);
+    if (ncol < 0) return -1;
+    int ccore = 0, cbnd = 0; /* colours used by core and by boundary tiles */
+    for (int t = 0; t < ntiles; t++) {
+        if (treg[t] == 0 && color[t] + 1 > ccore) ccore = color[t] + 1;
+        if (treg[t] == 1 && color[t] + 1 > cbnd) cbnd = color[t] + 1;
+    }
+    for (int t = 0; t < ntiles; t++) {
+        if (treg[t] == 1) color[t] += ccore;
+        if (treg[t] == 2) color[t] = ccore + cbnd;
+    }
+    return ccore + cbnd + 1 > 64 ? -1 : ccore + cbnd + 1;
+}
+
 static int inspect_sub(const or_chain *c, or_sched *s, sub_t *sb, int64_t ts, int partition, const double *seed_xy,
                        int max_rounds,
-                       int cap) {
+                       int cap, const uint8_t *region) {
     int first = sb->first, nl = sb->n;
     int seedset = c->loops[first].set;
     int64_t n0 = c->size[seedset];
@@ -557,15 +626,41 @@ static int inspect_sub(const or_chain *c, or_sched *s, sub_t *sb, int64_t ts, in
     int32_t *rank = malloc(sizeof(int32_t) * (n0 ? n0 : 1));
     if (seed_ranks(n0, partition, seed_xy, rank)) { free(rank); return -1; }
     int32_t *tile0 = malloc(sizeof(int32_t) * (n0 ? n0 : 1));
-    for (int64_t i = 0; i < n0; i++) tile0[i] = (int32_t)(rank[i] / ts);
+    uint8_t *treg = NULL;
+    if (!region) {
+        for (int64_t i = 0; i < n0; i++) tile0[i] = (int32_t)(rank[i] / ts);
+    } else {
+        /* R10: blocks of ts seeds per region in seed order, then T_ne */
+        int64_t cnt[3] = {0, 0, 0};
+        for (int64_t i = 0; i < n0; i++) cnt[region[i]]++;
+        int32_t ncore = (int32_t)((cnt[0] + ts - 1) / ts), nbnd = (int32_t)((cnt[1] + ts - 1) / ts);
+        ntiles = ncore + nbnd + 1;
+        int32_t *order = malloc(sizeof(int32_t) * (n0 ? n0 : 1));
+        for (int64_t i = 0; i < n0; i++) order[rank[i]] = (int32_t)i;
+        int64_t q[2] = {0, 0};
+        for (int64_t p = 0; p < n0; p++) {
+            int32_t i = order[p];
+            int r = region[i];
+            if (r == 2) tile0[i] = ncore + nbnd;
+            else tile0[i] = (r == 0 ? 0 : ncore) + (int32_t)(q[r]++ / ts);
+        }
+        free(order);
+        treg = malloc((size_t)ntiles);
+        for (int t = 0; t < ntiles; t++) treg[t] = t < ncore ? 0 : (t < ncore + nbnd ? 1 : 2);
+        sb->ncore = ncore;
+        sb->nbnd = nbnd;
+        sb->tne = ncore + nbnd;
+        sb->region = malloc((size_t)(n0 ? n0 : 1));
+        memcpy(sb->region, region, (size_t)n0);
+    }
     free(rank);
     edges_t adj;
     seed_adjacency(c, first, nl, tile0, &adj);
     int32_t *color = malloc(sizeof(int32_t) * ntiles);
     int round, ncol = 0;
     for (round = 0; round < max_rounds; round++) {
-        ncol = colour_tiles(ntiles, &adj, color, cap);
-        if (ncol < 0) { free(tile0); free(color); free(adj.e); return -3; }
+        ncol = treg ? colour_regions(ntiles, &adj, treg, color) : colour_tiles(ntiles, &adj, color, cap);
+        if (ncol < 0) { free(tile0); free(color); free(adj.e); free(treg); return -3; }
         uint64_t *Phi[MAXSETS] = {0};
         memcpy(s->sigma[first], tile0, sizeof(int32_t) * n0);
         for (int j = first + 1; j < first + nl; j++) {
@@ -585,6 +680,7 @@ static int inspect_sub(const or_chain *c, or_sched *s, sub_t *sb, int64_t ts, in
     }
     free(tile0);
     free(adj.e);
+    free(treg);
     if (round == max_rounds) { free(color); return -4; }
     sb->ntiles = ntiles;
     sb->ncolors = ncol;
@@ -622,13 +718,54 @@ static int inspect_sub(const or_chain *c, or_sched *s, sub_t *sb, int64_t ts, in
     return 0;
 }
 
+/* R11: seeds written by a T_ne iteration of sub-chain sb become non-exec */
+static void carry_stale(const or_chain *c, const or_sched *s, const sub_t *sb, uint8_t *region) {
+    for (int j = sb->first; j < sb->first + sb->n; j++) {
+        const loop_t *L = &c->loops[j];
+        for (int64_t it = 0; it < c->size[L->set]; it++) {
+            if (s->sigma[j][it] != sb->tne) continue;
+            for (int i = 0; i < L->ndesc; i++) {
+                const desc_t *D = &L->d[i];
+                if (D->mode == OR_R) continue;
+                if (D->map < 0) region[it] = 2;
+                else
+                    for (int k = 0; k < c->maps[D->map].arity; k++)
+                        region[c->maps[D->map].values[it * c->maps[D->map].arity + k]] = 2;
+            }
+        }
+    }
+}
+
 int or_inspect(const or_chain *c, int64_t ts, int partition, const double *seed_xy, int max_rounds,
                int max_colour_tiles, const int32_t *splits, int nsplits, const int32_t *sub_ts, or_sched **out) {
+    return or_inspect_regions(c, ts, partition, seed_xy, max_rounds, max_colour_tiles, splits, nsplits, sub_ts, NULL,
+                              0, out);
+}
+
+int or_inspect_regions(const or_chain *c, int64_t ts, int partition, const double *seed_xy, int max_rounds,
+                       int max_colour_tiles, const int32_t *splits, int nsplits, const int32_t *sub_ts,
+                       const uint8_t *seed_region, int carry, or_sched **out) {
     *out = NULL;
     if (ts < 1 || c->nloops == 0 || max_rounds < 1 || max_colour_tiles < 0) return -1;
     if (sub_ts)
         for (int i = 0; i <= nsplits; i++)
             if (sub_ts[i] < 1) return -1;
+    uint8_t *region = NULL;
+    if (seed_region) {
+        /* every sub-chain seeds on the region set; no cap; carry needs all writes there */
+        int rset = c->loops[0].set;
+        if (max_colour_tiles != 0) return -1;
+        for (int i = 0; i < nsplits; i++)
+            if (splits[i] < 0 || splits[i] >= c->nloops || c->loops[splits[i]].set != rset) return -1;
+        for (int64_t e = 0; e < c->size[rset]; e++)
+            if (seed_region[e] > 2) return -1;
+        if (carry)
+            for (int j = 0; j < c->nloops; j++)
+                for (int i = 0; i < c->loops[j].ndesc; i++)
+                    if (c->loops[j].d[i].mode != OR_R && dset(c, &c->loops[j], &c->loops[j].d[i]) != rset) return -1;
+        region = malloc((size_t)(c->size[rset] ? c->size[rset] : 1));
+        memcpy(region, seed_region, (size_t)c->size[rset]);
+    }
     or_sched *s = calloc(1, sizeof(*s));
     s->nloops = c->nloops;
     for (int j = 0; j < c->nloops; j++) {
@@ -638,17 +775,33 @@ int or_inspect(const or_chain *c, int64_t ts, int partition, const double *seed_
     int start = 0;
     for (int i = 0; i <= nsplits; i++) {
         int end = (i < nsplits) ? splits[i] : c->nloops;
-        if (end <= start || end > c->nloops || end - start > 31) { or_sched_free(s); return -1; }
+        if (end <= start || end > c->nloops || end - start > 31) { or_sched_free(s); free(region); return -1; }
         sub_t *sb = &s->sub[s->nsub++];
         sb->first = start;
         sb->n = end - start;
         for (int j = start; j < end; j++) s->sub_of[j] = s->nsub - 1;
         /* a fusion scheme gives each sub-chain its own seed tile size (Sec. 7.2) */
-        int rc = inspect_sub(c, s, sb, sub_ts ? sub_ts[i] : ts, partition, seed_xy, max_rounds, max_colour_tiles);
-        if (rc) { or_sched_free(s); return rc; }
+        int rc = inspect_sub(c, s, sb, sub_ts ? sub_ts[i] : ts, partition, seed_xy, max_rounds, max_colour_tiles,
+                             region);
+        if (rc) { or_sched_free(s); free(region); return rc; }
+        if (region && carry) carry_stale(c, s, sb, region);
         start = end;
     }
+    free(region);
     *out = s;
+    return 0;
+}
+
+int or_sched_regions(const or_sched *s, int sub, int32_t *info, uint8_t *region) {
+    if (sub < 0 || sub >= s->nsub || !s->sub[sub].region) return -1;
+    const sub_t *b = &s->sub[sub];
+    if (info) {
+        info[0] = b->ncore;
+        info[1] = b->nbnd;
+        info[2] = b->tne;
+        info[3] = b->color[b->tne];
+    }
+    if (region) memcpy(region, b->region, (size_t)s->loop_size[b->first]);
     return 0;
 }
 
@@ -657,6 +810,7 @@ void or_sched_free(or_sched *s) {
     for (int j = 0; j < s->nloops; j++) free(s->sigma[j]);
     for (int i = 0; i < s->nsub; i++) {
         free(s->sub[i].color);
+        free(s->sub[i].region);
         for (int S = 0; S < MAXSETS; S++) {
             free(s->sub[i].foot_off[S]);
             free(s->sub[i].foot[S]);
@@ -892,6 +1046,7 @@ int or_instrumented_run(const or_chain *c, const or_sched *s, int nrep, uint64_t
                 or_sched_tiles_by_color(s, si, coff, tl);
                 for (int p = 0; p < b->ntiles; p++) {
                     int t = tl[p];
+                    if (b->region && t == b->tne) continue; /* T_ne is never executed */
                     for (int j = b->first; j < b->first + b->n; j++)
                         for (int64_t it = 0; it < c->size[c->loops[j].set]; it++)
                             if (s->sigma[j][it] == t) instr_iteration(c, j, it, data, NULL);
@@ -943,6 +1098,7 @@ int or_dg_step_tiled(or_dg *d, const or_sched *sch, double *v, double *s, int64_
             or_sched_tiles_by_color(sch, si, coff, tl);
             for (int p = 0; p < b->ntiles; p++) {
                 int t = tl[p];
+                if (b->region && t == b->tne) continue; /* T_ne is never executed (Alg. 2) */
                 for (int j = b->first; j < b->first + b->n; j++)
                     for (int32_t q = toff[j][t]; q < toff[j][t + 1]; q++) or_dg_iteration(d, j, its[j][q]);
             }

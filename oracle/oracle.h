@@ -81,12 +81,29 @@ int or_chain_map(or_chain *c, int from, int to, int arity, const int32_t *values
 int or_chain_loop(or_chain *c, int set, int ndesc, const int32_t *maps, const int32_t *modes,
                   const int32_t *data);
 int or_chain_nloops(const or_chain *c);
+/* read-back of the chain (tests): set sizes, loops (maps[ndesc], modes[ndesc], at
+ * most 8), maps (values[size(from)*arity] or NULL) */
+int64_t or_chain_set_size(const or_chain *c, int set);
+int or_chain_get_loop(const or_chain *c, int j, int32_t *set, int32_t *ndesc, int32_t *maps, int32_t *modes);
+int or_chain_get_map(const or_chain *c, int m, int32_t *from, int32_t *to, int32_t *arity, int32_t *values);
 
 /* Alg. 1 with readings C10-C17; splits = loop indices starting new sub-chains;
  * max_colour_tiles > 0 caps every colour class after each colouring (R5b in chain.c). */
 int or_inspect(const or_chain *c, int64_t ts, int partition, const double *seed_xy,
                int max_rounds, int max_colour_tiles, const int32_t *splits, int nsplits,
                const int32_t *sub_ts, or_sched **out);
+/* Alg. 1 with regions (Sec. 3.3, 5.1.2; readings R10, R11 in chain.c):
+ * seed_region[size(seed set)] in {0 core, 1 boundary, 2 non-exec}; every
+ * sub-chain must start on the seed set of loop 0; max_colour_tiles must be 0.
+ * carry = 1: one halo exchange for the whole chain (later sub-chains treat seeds
+ * written by an earlier T_ne as non-exec; every write must land in the seed
+ * set); carry = 0: each sub-chain starts from seed_region. */
+int or_inspect_regions(const or_chain *c, int64_t ts, int partition, const double *seed_xy,
+                       int max_rounds, int max_colour_tiles, const int32_t *splits, int nsplits,
+                       const int32_t *sub_ts, const uint8_t *seed_region, int carry, or_sched **out);
+/* info[4] = {core tiles, boundary tiles, T_ne id, T_ne colour}; region[size(seed
+ * set)] = the seed regions the sub-chain was inspected with.  -1 without regions. */
+int or_sched_regions(const or_sched *s, int sub, int32_t *info, uint8_t *region);
 void or_sched_free(or_sched *s);
 int or_sched_nsub(const or_sched *s);
 /* per sub-chain: loop range, ntiles, ncolors, rounds used */

@@ -174,6 +174,90 @@ def random_state(shape, seed: int) -> np.ndarray:
     return (2.0 * uniform01(seed, n) - 1.0).reshape(shape)
 
 
+# -- one GPU's share of a distributed mesh ----------------------------------
+# A mesh distributor (DMPlex in the paper's Firedrake setting, Sec. 5.2) hands each
+# process a contiguous block of cells plus layers of halo cells, with every cell
+# labelled by region (Sec. 3.3).  These helpers build that input for one part.
+
+CORE, BOUNDARY, NON_EXEC = 0, 1, 2
+
+
+@dataclass
+class MeshPart:
+    """Cells of one part: owned cells, `depth` layers of exec halo, one non-exec layer."""
+    cells: np.ndarray       # [nl] global cell ids of the local cells, ascending
+    layer: np.ndarray       # [nl] 0 owned, 1..depth exec halo, depth+1 non-exec
+    region: np.ndarray      # [nl] uint8: CORE, BOUNDARY (owned next to the halo, or exec), NON_EXEC
+    mesh: Mesh              # the local mesh (vertices of the local cells, ascending global id)
+    vertices: np.ndarray    # [nv_local] global vertex ids
+
+    @property
+    def owned(self) -> np.ndarray:
+        return self.layer == 0
+
+
+def cell_neighbours(mesh: Mesh) -> np.ndarray:
+    """[nc, 3] the cell across each edge (vertices l, l+1 mod 3), -1 on the boundary."""
+    if mesh.periodic:
+        raise ValueError("cell_neighbours takes non-periodic meshes")
+    nc = mesh.nc
+    a = mesh.c2v
+    ev = np.stack([a, np.roll(a, -1, axis=1)], axis=2).reshape(-1, 2).astype(np.int64)
+    key = np.minimum(ev[:, 0], ev[:, 1]) * (mesh.nv + 1) + np.maximum(ev[:, 0], ev[:, 1])
+    order = np.argsort(key, kind="stable")
+    ks = key[order]
+    nb = np.full(3 * nc, -1, np.int64)
+    same = np.nonzero(ks[1:] == ks[:-1])[0]
+    h0, h1 = order[same], order[same + 1]
+    nb[h0] = h1 // 3
+    nb[h1] = h0 // 3
+    return nb.reshape(nc, 3).astype(np.int32)
+
+
+def block_parts(mesh: Mesh, bx: int, by: int) -> np.ndarray:
+    """Part of each cell for bx x by rectangular blocks of the bounding box (by centroid)."""
+    c = mesh.centroids()
+    lo, hi = mesh.xy.min(axis=0), mesh.xy.max(axis=0)
+    ix = np.clip(np.floor((c[:, 0] - lo[0]) / (hi[0] - lo[0]) * bx), 0, bx - 1).astype(np.int32)
+    iy = np.clip(np.floor((c[:, 1] - lo[1]) / (hi[1] - lo[1]) * by), 0, by - 1).astype(np.int32)
+    return iy * bx + ix
+
+
+def mesh_part(mesh: Mesh, parts: np.ndarray, part: int, depth: int) -> MeshPart:
+    """Owned cells of `part`, `depth` exec layers around them (cells sharing an edge with
+    the previous layer), one non-exec layer beyond; regions: owned cells with a neighbour
+    outside the part are BOUNDARY (owned sub-region), the other owned cells CORE, exec
+    cells BOUNDARY, the last layer NON_EXEC."""
+    if depth < 0:
+        raise ValueError("depth must be >= 0")
+    nb = cell_neighbours(mesh)
+    layer = np.full(mesh.nc, -1, np.int32)
+    owned = np.asarray(parts) == part
+    layer[owned] = 0
+    front = np.nonzero(owned)[0]
+    for d in range(1, depth + 2):
+        cand = nb[front].ravel()
+        cand = np.unique(cand[cand >= 0])
+        cand = cand[layer[cand] < 0]
+        layer[cand] = d
+        front = cand
+    cells = np.nonzero(layer >= 0)[0].astype(np.int32)
+    lay = layer[cells]
+    region = np.where(lay == 0, CORE, np.where(lay <= depth, BOUNDARY, NON_EXEC)).astype(np.uint8)
+    nbo = nb[cells[lay == 0]]
+    touches = ((nbo >= 0) & (~owned[np.maximum(nbo, 0)])).any(axis=1)
+    r0 = region[lay == 0]
+    r0[touches] = BOUNDARY
+    region[lay == 0] = r0
+    verts = np.unique(mesh.c2v[cells].ravel())
+    remap = np.full(mesh.nv, -1, np.int64)
+    remap[verts] = np.arange(verts.size)
+    local = Mesh(n=mesh.n, xy=np.ascontiguousarray(mesh.xy[verts]),
+                 c2v=np.ascontiguousarray(remap[mesh.c2v[cells]].astype(np.int32)),
+                 meta=dict(part=part, depth=depth))
+    return MeshPart(cells=cells, layer=lay, region=region, mesh=local, vertices=verts.astype(np.int32))
+
+
 # -- named workloads ---------------------------------------------------------
 
 def workload(name: str):
