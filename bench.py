@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--no-config3", action="store_true",
                     help="skip the 1024x1024 P3/P4 FP32 extras of the default run")
     ap.add_argument("--config3-steps", type=int, default=100)
+    ap.add_argument("--no-part", action="store_true",
+                    help="skip one GPU's region-aware share of the 1024x1024 P3 workload")
     ap.add_argument("--config3-horizon", type=int, default=500)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain elementwise pass over 256 MiB (torch.neg: 256 MiB read, 256 MiB "
@@ -298,6 +300,122 @@ def config3(a):
         out[f"p{k}"] = r
         print(f"bench: config 3 P{k}: mfma {r['mfma']['ms_per_step']:.3f} ms, valu {r['valu']['ms_per_step']:.3f} "
               f"ms, untiled {r['untiled']['ms_per_step']:.3f} ms", file=sys.stderr, flush=True)
+    return out
+
+
+def part_block(a):
+    """One GPU's share of the 1024x1024 P3 FP32 workload: the mesh split into rectangular
+    blocks, one block with 6 exec halo layers (the facet loops of a step) and one
+    non-exec layer, inspected with regions (core tiles, boundary tiles, T_ne).  Before
+    every step the halo cells take a whole-mesh solver's state by a device-to-device
+    pack / unpack, the stand-in for the exchange between GPUs; the part's step never
+    launches T_ne.  Block 5 of 2 x 4 (262,144 owned cells) is checked against the
+    whole-mesh solver after two steps and timed with and without the halo fill; parts
+    of 1 x 1 (the whole mesh with regions), 1 x 2, 2 x 2, 2 x 4 and 4 x 4 blocks give
+    the owned cells' rate against the whole-mesh rate on the same GPU.  Both run the
+    register-resident kernel in its P3 configuration (the faster P3 kernel)."""
+    import numpy as np
+    import torch
+    from paper_1708_03183_amd import dgtile as D
+    from paper_1708_03183_amd import inputs as I
+    k, depth = 3, 6
+    npk = (k + 1) * (k + 2) // 2
+    m = I.square_mesh(1024, jitter=0.2, jitter_seed=1, renumber_seed=2)
+    lam, mu, rho = I.lognormal_material(m)
+    dt = cfl_dt(m, lam, mu, rho, k)
+    ts, splits, sch = VALU_DEFAULTS[k]
+    os.environ["DGT_TILE_OP"] = "1"
+    try:
+        g = D.Solver(D.Mesh.from_mesh(m), lam, mu, rho, degree=k, flux=1, time_order=4, precision=1, free_sides=0x8,
+                     dt=dt)
+        g.inspect(ts, partition=1, splits=splits)
+    finally:
+        del os.environ["DGT_TILE_OP"]
+    g.set_schedule(sch)
+    gv = torch.from_numpy(I.random_state((2, npk, m.nc), 61)).float().cuda().contiguous()
+    gs = torch.from_numpy(I.random_state((3, npk, m.nc), 62)).float().cuda().contiguous()
+    g.upload(gv, gs)
+
+    def timed(fn, n):
+        fn(3)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn(n)
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t) / n
+
+    n = a.config3_steps
+    ms_whole = timed(lambda q: g.step(q, mode=1, t0=0.0), n)
+    whole_rate = 5 * npk * m.nc / ms_whole * 1e3
+
+    def part(blocks, pid, check):
+        t0 = time.time()
+        P = I.mesh_part(m, I.block_parts(m, *blocks), pid, depth)
+        t_part = time.time() - t0
+        c = P.cells
+        os.environ["DGT_TILE_OP"] = "1"
+        try:
+            lp = D.Solver(D.Mesh.from_mesh(P.mesh), lam[c], mu[c], rho[c], degree=k, flux=1, time_order=4,
+                          precision=1, free_sides=0x8, dt=dt)
+            t0 = time.time()
+            lp.inspect(ts, partition=1, splits=splits, seed_region=P.region, region_carry=1)
+            t_insp = time.time() - t0
+        finally:
+            del os.environ["DGT_TILE_OP"]
+        lp.set_schedule(sch)
+        halo = np.nonzero(~P.owned)[0]
+        send, recv = g.cell_list(c[halo]), lp.cell_list(halo)
+        bv = torch.empty(2, npk, halo.size, dtype=torch.float32, device="cuda")
+        bs = torch.empty(3, npk, halo.size, dtype=torch.float32, device="cuda")
+        ci = torch.from_numpy(c.astype(np.int64)).cuda()
+        g.download(gv, gs)
+        lp.upload(gv[:, :, ci].contiguous(), gs[:, :, ci].contiguous())
+
+        def run(q, fill, step, both=False):
+            for i in range(q):
+                if fill:
+                    g.pack(send, bv, bs)
+                    lp.unpack(recv, bv, bs)
+                if both:
+                    g.step(1, mode=1, t0=i * dt)
+                if step:
+                    lp.step(1, mode=1, t0=i * dt)
+
+        owned = int(P.owned.sum())
+        r = {"blocks": f"{blocks[0]}x{blocks[1]}", "part": pid, "owned_cells": owned,
+             "core_cells": int(np.sum(P.region == 0)),
+             "exec_cells": int(np.sum((P.layer >= 1) & (P.layer <= depth))),
+             "nonexec_cells": int(np.sum(P.layer > depth)), "local_cells": int(c.size)}
+        if check:  # two steps of both with the halo fill between them
+            run(2, True, True, both=True)
+            lv, ls = lp.zeros()
+            lp.download(lv, ls)
+            g.download(gv, gs)
+            torch.cuda.synchronize()
+            oi = torch.from_numpy(np.nonzero(P.owned)[0].astype(np.int64)).cuda()
+            r["owned_vs_whole_mesh_max_rel_after_2_steps"] = max(
+                (lv[:, :, oi] - gv[:, :, ci[oi]]).abs().max().item(),
+                (ls[:, :, oi] - gs[:, :, ci[oi]]).abs().max().item()) / max(gv.abs().max().item(),
+                                                                             gs.abs().max().item())
+            sched = lp.schedule()
+            r["tiles_core_boundary_per_subchain"] = [sched.regions(b, c.size)[0][:2] for b in range(sched.nsub)]
+            r["ms_step_only"] = timed(lambda q: run(q, False, True), n)
+            r["ms_halo_fill"] = timed(lambda q: run(q, True, False), n)
+            r["halo_bytes_per_step"] = int(halo.size * 5 * npk * 4)
+            r["part_build_s"], r["inspect_wall_s"] = t_part, t_insp
+        r["ms_per_step"] = timed(lambda q: run(q, True, True), n)
+        r["owned_dof_updates_per_s"] = 5 * npk * owned / r["ms_per_step"] * 1e3
+        r["rate_vs_whole_mesh"] = r["owned_dof_updates_per_s"] / whole_rate
+        return r
+
+    out = {"workload": "jitter1024 P3 FP32 (lognormal, upwind, order 4) split into rectangular blocks; one "
+                       "block with 6 exec layers and 1 non-exec layer, halo filled by device-to-device "
+                       "pack/unpack from a whole-mesh solver",
+           "kernel": "register-resident", "tile_size": ts, "splits": list(splits), "schedule": sch,
+           "whole_mesh_ms_per_step": ms_whole, "whole_mesh_dof_updates_per_s": whole_rate}
+    out["block_5_of_2x4"] = part((2, 4), 5, True)
+    out["by_part_size"] = [part(b, p, False) for b, p in (((1, 1), 0), ((1, 2), 1), ((2, 2), 3), ((2, 4), 5),
+                                                          ((4, 4), 9))]
     return out
 
 
@@ -897,6 +1015,9 @@ def main():
     if not a.no_config3 and a.n == 512 and k == 2:
         progress("config 3 extras (1024x1024 P3/P4 FP32)")
         out["config3"] = config3(a)
+    if not a.no_part and a.n == 512 and k == 2:
+        progress("one GPU's share of the 1024x1024 P3 workload (regions, halo pack/unpack)")
+        out["part_block"] = part_block(a)
     if "untiled" in res:
         gain = (res["untiled"]["ms_per_step"] - out["ms_per_step"]) / 1e3
         out["inspector"]["steps_to_amortise"] = (t_insp_wall / gain) if gain > 0 else None

@@ -115,6 +115,30 @@ typedef struct {
                                      sub-chain (a fusion scheme fixes one per
                                      sub-chain, Sec. 7.2), each >= 1; NULL:
                                      tile_size for all */
+    const uint8_t *seed_region;   /* host [size(seed set)] or NULL.  The region of
+                                     each seed iteration on one process's part of a
+                                     distributed mesh (Sec. 3.3): 0 core, 1 boundary
+                                     (owned iterations next to the halo, and exec
+                                     halo), 2 non-exec halo.  Seeds of each region
+                                     are cut into blocks of tile_size in seed order:
+                                     core tiles 0.., then boundary tiles, then one
+                                     tile T_ne with every non-exec seed (Sec.
+                                     5.1.2).  Each region's tiles are coloured apart
+                                     (Jones-Plassmann on the edges inside the
+                                     region); boundary colours follow the core ones
+                                     and T_ne alone takes the highest colour; it is
+                                     never executed (Alg. 2).  Every sub-chain must
+                                     start on the seed set of loop 0, and
+                                     max_colour_tiles must be 0 (else DGT_EINVAL). */
+    int32_t region_carry;         /* with seed_region: 0, every sub-chain starts from
+                                     seed_region (one halo exchange before each
+                                     sub-chain, as in the paper); 1, one exchange
+                                     before the first sub-chain only: a later
+                                     sub-chain also treats as non-exec every seed
+                                     element that T_ne of an earlier sub-chain
+                                     writes (its value is stale), which needs every
+                                     write of the chain to land in the seed set
+                                     (else DGT_EINVAL). */
 } dgt_inspect_params;
 
 /* Run the inspector on the GPU (Alg. 1 with Alg. 3 projections and Alg. 4
@@ -144,6 +168,11 @@ dgt_status dgt_schedule_footprint(const dgt_schedule *s, int32_t sub, int32_t se
                                   int32_t *elem, uint32_t *acc);
 /* tiles in execution order (colour ascending, then id): host color_off[ncolors+1], tiles[ntiles] */
 dgt_status dgt_schedule_tiles_by_color(const dgt_schedule *s, int32_t sub, int32_t *color_off, int32_t *tiles);
+/* Regions of sub-chain `sub` of a region-aware schedule: info[4] = {core tiles,
+ * boundary tiles, id of T_ne, colour of T_ne}; region (host [size(seed set)] or
+ * NULL) = the seed regions the sub-chain was inspected with (after carrying
+ * stale seeds).  DGT_EINVAL for a schedule without regions. */
+dgt_status dgt_schedule_regions(const dgt_schedule *s, int32_t sub, int32_t *info, uint8_t *region);
 /* JSON inspection summary (tiles, colours, rounds, footprint sizes, GPU time
  * of the inspector in ms); writes at most len bytes including the NUL. */
 dgt_status dgt_schedule_summary_json(const dgt_schedule *s, char *buf, size_t len);
@@ -207,7 +236,9 @@ dgt_status dgt_solver_inspect(dgt_solver *s, const dgt_inspect_params *p);
  * runs one step and then trial_steps timed steps (HIP events) with each
  * schedule its kernels support, from a zero state with the solver's sources
  * and shots.  The caller's state is kept (restored afterwards); without an
- * uploaded state the fields are zero afterwards.  Synchronises the stream.
+ * uploaded state the fields are zero afterwards.  A solver last inspected with
+ * seed regions keeps them (one halo exchange per step) for every candidate.
+ * Synchronises the stream.
  * EINVAL for bad parameters, EUNSUPPORTED when no candidate fits. */
 typedef struct {
     const int32_t *tile_sizes;  /* host [ntile_sizes] candidate seed tile sizes, >= 1 */
@@ -250,6 +281,23 @@ dgt_status dgt_solver_set_shots(dgt_solver *s, int32_t nshots, const double *xy,
  * the stream). */
 dgt_status dgt_state_upload(dgt_solver *s, const void *v, const void *sig);
 dgt_status dgt_state_download(dgt_solver *s, void *v, void *sig);
+/* Halo exchange of a distributed step (Sec. 4, Alg. 2): before a step, each GPU's
+ * part receives the state of its exec and non-exec halo cells from the GPUs that
+ * own them.  A cell list names cells of one solver's mesh (host ids in the mesh's
+ * numbering, each in [0, nc), copied to the device; DGT_EINVAL otherwise);
+ * dgt_state_pack copies their state into packed device buffers
+ * v[nshots][2][Np][n], sig[nshots][3][Np][n] (solver precision), and
+ * dgt_state_unpack copies such buffers into them.  Between GPUs the packed buffers
+ * travel by RCCL point-to-point; on one GPU, packing from a solver of the whole
+ * mesh and unpacking into the part's halo is the device-to-device fill.  The list
+ * must belong to a solver of the same mesh size and device; both calls need an
+ * uploaded state and are enqueued on the solver's stream.  An empty list copies
+ * nothing (its buffers may be NULL). */
+typedef struct dgt_cell_list dgt_cell_list;
+dgt_status dgt_cell_list_create(const dgt_solver *s, int64_t n, const int32_t *cells, dgt_cell_list **out);
+void dgt_cell_list_destroy(dgt_cell_list *l);
+dgt_status dgt_state_pack(dgt_solver *s, const dgt_cell_list *l, void *v, void *sig);
+dgt_status dgt_state_unpack(dgt_solver *s, const dgt_cell_list *l, const void *v, const void *sig);
 /* Advance nsteps time steps starting at time t0 (sigma at t0, v at t0 - dt/2).
  * mode 0: untiled chain (one kernel per loop); mode 1: sparse-tiled fused
  * executor (requires dgt_solver_inspect).  Enqueued on the stream. */
@@ -309,9 +357,11 @@ dgt_status dgt_fwi_gradient(dgt_solver *s, const dgt_fwi_params *p, const double
  * device-coherent accesses, and each workgroup waits for its stores to
  * complete before it counts its successors), so no colour waits for a whole
  * earlier colour.
- * Every wait is bounded: if one gives up, the next dgt_step or
- * dgt_state_download returns DGT_ESTATE and the counters are reset.  In mode 1,
- * dgt_step synchronises the stream on entry.  mode: 0 or 1, else DGT_EINVAL. */
+ * Every wait is bounded: if one gives up, the next dgt_state_download (which
+ * waits for the stream) returns DGT_ESTATE and the counters are reset; a later
+ * dgt_step or dgt_state_pack reports it as well once the flags of the failed call
+ * have reached the host (they are copied behind each call; neither waits for
+ * them).  mode: 0 or 1, else DGT_EINVAL. */
 dgt_status dgt_solver_set_schedule(dgt_solver *s, int32_t mode);
 /* Polls of a dependence wait (schedule 1) before it gives up, 1..2^32-1; default
  * 2^20 (about a second).  A tiny value makes waits time out on purpose, which

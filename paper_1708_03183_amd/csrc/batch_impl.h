@@ -101,6 +101,7 @@ static TileArgs batch_member_args(dgt_batch *b, int bi, int mi, int persist) {
     A.src_amp = 0.0;
     A.persist = persist;
     A.ntiles = P.ntiles;
+    A.nexec = P.nexec;
     A.tile_base = 0;
     A.need = sb.dep_need.p;
     A.succ_off = sb.dep_off.p;
@@ -339,6 +340,7 @@ dgt_status dgt_batch_create(dgt_solver *const *solvers, int32_t n, void *stream,
                 DGT_REQUIRE(P.kind == TK_CHAIN && P.o0 == P0.o0 && P.nops == P0.nops && P.first == P0.first &&
                                 P.n == P0.n,
                             DGT_EINVAL, "members must run the same chain-kernel sub-chains");
+                DGT_REQUIRE(P.tne < 0, DGT_EINVAL, "a member inspected with regions runs on its own");
             }
             b->m.push_back(s);
             b->gen.push_back(s->gen);

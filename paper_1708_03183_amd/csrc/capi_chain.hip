@@ -22,7 +22,7 @@ extern "C" {
 
 const char *dgt_last_error(void) { return g_last_error.c_str(); }
 
-int dgt_version(void) { return 106; }
+int dgt_version(void) { return 107; }
 
 dgt_status dgt_chain_create(dgt_chain **out) {
     return guard([&] {
@@ -100,7 +100,7 @@ dgt_status dgt_inspect(const dgt_chain *c, const dgt_inspect_params *p, void *st
         std::vector<int32_t> sub_ts;
         if (p->sub_tile_sizes) sub_ts.assign(p->sub_tile_sizes, p->sub_tile_sizes + p->nsplits + 1);
         sch->s = insp.run(p->tile_size, p->partition, p->seed_xy, nullptr, p->max_conflict_rounds,
-                          p->max_colour_tiles, splits, sub_ts);
+                          p->max_colour_tiles, splits, sub_ts, p->seed_region, p->region_carry);
         *out = sch.release();
     });
 }
@@ -187,6 +187,20 @@ dgt_status dgt_schedule_tiles_by_color(const dgt_schedule *s, int32_t sub, int32
         std::memcpy(color_off, co.data(), sizeof(int32_t) * (b.ncolors + 1));
         auto tl = b.tiles_by_color.download(s->s->stream, b.ntiles);
         std::memcpy(tiles, tl.data(), sizeof(int32_t) * b.ntiles);
+    });
+}
+
+dgt_status dgt_schedule_regions(const dgt_schedule *s, int32_t sub, int32_t *info, uint8_t *region) {
+    return guard([&] {
+        const SubSched &b = sub_of(s, sub);
+        DGT_REQUIRE(b.tne >= 0, DGT_EINVAL, "the schedule has no regions");
+        if (info) {
+            info[0] = b.ncore;
+            info[1] = b.nbnd;
+            info[2] = b.tne;
+            info[3] = b.color.download(s->s->stream, b.ntiles)[b.tne];
+        }
+        if (region && !b.region.empty()) std::memcpy(region, b.region.data(), b.region.size());
     });
 }
 

@@ -282,8 +282,9 @@ __device__ __forceinline__ int slot_of(const int32_t *__restrict__ foot, int b, 
 }
 
 // kind: 0 cell loop, 1 interior facet loop, 2 exterior facet loop
+// (iterations of tile skip, the never-executed tile of a region-aware schedule, get 0)
 __global__ void k_lmap(int kind, const int32_t *__restrict__ it_off, const int32_t *__restrict__ iters, int32_t ntiles,
-                       int64_t n, const int32_t *__restrict__ foot_off, const int32_t *__restrict__ efoot,
+                       int32_t skip, int64_t n, const int32_t *__restrict__ foot_off, const int32_t *__restrict__ efoot,
                        const int32_t *__restrict__ rank, const int32_t *__restrict__ f2c,
                        const int8_t *__restrict__ f2l, const int32_t *__restrict__ b2c,
                        const int8_t *__restrict__ b2l, const uint8_t *__restrict__ bfree,
@@ -295,6 +296,10 @@ __global__ void k_lmap(int kind, const int32_t *__restrict__ it_off, const int32
         const int mid = (lo + hi) >> 1;
         if (it_off[mid] <= q) lo = mid;
         else hi = mid;
+    }
+    if (lo == skip) {
+        lmap[q] = 0u;
+        return;
     }
     const int b = foot_off[lo], e = foot_off[lo + 1];
     const int32_t it = iters[q];
@@ -329,6 +334,20 @@ __global__ void k_permute_rows(const T *__restrict__ src, T *__restrict__ dst, c
     const int64_t r = t / nc, c = t - r * nc;
     if (to_exec) dst[r * nc + map[c]] = src[t];
     else dst[t] = src[r * nc + map[c]];
+}
+
+// Halo buffers: buf[q][r][i] = field[q][r][rank[cells[i]]] (pack) or the reverse
+// (unpack), for nshots copies of `rows` rows; cells were checked against nc.
+template <typename T>
+__global__ void k_halo_copy(T *__restrict__ fld, T *__restrict__ buf, const int32_t *__restrict__ rank,
+                            const int32_t *__restrict__ cells, int64_t n, int64_t rows, int64_t nc, int64_t total,
+                            int unpack) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int64_t qr = t / n, i = t - qr * n;  // qr = shot * rows + row
+    const int64_t f = qr * nc + rank[cells[i]];
+    if (unpack) fld[f] = buf[t];
+    else buf[t] = fld[f];
 }
 
 template <int K, typename T>

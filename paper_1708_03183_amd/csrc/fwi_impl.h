@@ -245,6 +245,8 @@ static void fwi_check(dgt_solver *s, const dgt_fwi_params *p) {
     DGT_REQUIRE(p->mode == 0 || p->mode == 1, DGT_EINVAL, "mode must be 0 or 1");
     DGT_REQUIRE(p->mode == 0 || (s->plan_status == DGT_OK && s->inspected), DGT_ESTATE,
                 "tiled mode needs a successful dgt_solver_inspect");
+    DGT_REQUIRE(p->mode == 0 || s->last_region.empty(), DGT_EUNSUPPORTED,
+                "full-waveform inversion runs on a whole mesh, not on a region-aware part");
 }
 
 template <int K, typename T>

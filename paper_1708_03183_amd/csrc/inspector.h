@@ -40,6 +40,10 @@ struct SubSched {
     // footprints of tiles a and b share an element of any set and a has the lower colour
     int64_t dep_edges = 0;
     DBuf<int32_t> dep_need, dep_off, dep_succ;  // [ntiles], [ntiles+1], [dep_edges]
+    // regions (Sec. 3.3): core tiles [0, ncore), boundary tiles [ncore, tne), the
+    // never-executed tile tne (highest colour); tne < 0 without regions
+    int32_t ncore = 0, nbnd = 0, tne = -1;
+    std::vector<uint8_t> region;  // seed regions this sub-chain was inspected with
 };
 
 // Output of the inspector, resident in device memory.
@@ -64,7 +68,8 @@ class Inspector {
     Inspector(const ChainDesc &c, hipStream_t st);
     std::unique_ptr<Schedule> run(int64_t ts, int partition, const double *xy_host, const double *xy_dev,
                                   int max_rounds, int cap, const std::vector<int32_t> &splits,
-                                  const std::vector<int32_t> &sub_ts = {});
+                                  const std::vector<int32_t> &sub_ts = {}, const uint8_t *region = nullptr,
+                                  int carry = 0);
     const ChainDesc &chain;
     hipStream_t stream;
     DBuf<int32_t> dmap[kMaxMaps], inv_off[kMaxMaps], inv_val[kMaxMaps];
@@ -79,10 +84,13 @@ class Inspector {
     void build_inverse(const ChainDesc &c, int mi, hipStream_t st);
     void seed_partition(int seedset, int64_t ts, int partition, const double *xy_host, const double *xy_dev,
                         DBuf<int32_t> &tile0, DBuf<int32_t> &rank);
+    void region_partition(int64_t n0, int64_t ts, const DBuf<int32_t> &rank, SubSched &sb, DBuf<int32_t> &tile0);
     int64_t seed_edges(int first, int nl, const DBuf<int32_t> &tile0, DBuf<uint64_t> &edges);
-    int colour(int32_t ntiles, const DBuf<uint64_t> &edges, int64_t ne, DBuf<int32_t> &color, int cap);
+    int colour(int32_t ntiles, const DBuf<uint64_t> &edges, int64_t ne, DBuf<int32_t> &color, int cap,
+               const SubSched *regions = nullptr);
     void run_sub(Schedule &S, SubSched &sb, int64_t ts, int partition, const double *xy_host,
                  const double *xy_dev, int max_rounds, int cap);
+    void carry_stale(const Schedule &S, const SubSched &sb, std::vector<uint8_t> &region);
     int64_t touches(int first, int nl, int s, DBuf<uint64_t> &keys, DBuf<uint32_t> &bits, const Schedule &S);
     int64_t conflicts(int first, int nl, const DBuf<int32_t> &color, DBuf<uint64_t> &edges, int64_t &ne);
     void footprints(int first, int nl, SubSched &sb);

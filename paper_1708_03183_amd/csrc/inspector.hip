@@ -151,6 +151,40 @@ __global__ void k_tile0_identity(int64_t n, int64_t ts, int32_t *__restrict__ ti
     if (rank) rank[i] = (int32_t)i;
 }
 
+// regions (Sec. 3.3, 5.1.2): keys (region << 32 | seed rank), sorted to give the
+// seeds of each region in seed order
+__global__ void k_region_keys(const uint8_t *__restrict__ region, const int32_t *__restrict__ rank, int64_t n,
+                              uint64_t *__restrict__ keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) keys[i] = ((uint64_t)region[i] << 32) | (uint32_t)rank[i];
+}
+
+__global__ void k_rank_order(const int32_t *__restrict__ rank, int64_t n, int32_t *__restrict__ order) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) order[rank[i]] = (int32_t)i;
+}
+
+// blocks of ts seeds per region: core tiles from 0, boundary tiles from ncore, and
+// every non-exec seed in tile tne
+__global__ void k_tile0_regions(const uint64_t *__restrict__ sorted, int64_t n, const int32_t *__restrict__ order,
+                                int64_t start1, int32_t ncore, int32_t tne, int64_t ts, int32_t *__restrict__ tile0) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t r = (uint32_t)(sorted[p] >> 32);
+    const int32_t i = order[sorted[p] & 0xffffffffull];
+    tile0[i] = r == 2 ? tne : (r == 1 ? ncore + (int32_t)((p - start1) / ts) : (int32_t)(p / ts));
+}
+
+// one halo exchange per chain: seeds written by an iteration of T_ne become stale
+__global__ void k_stale(const int32_t *__restrict__ sigma, int64_t n, int32_t tne, const int32_t *__restrict__ map,
+                        int arity, uint8_t *__restrict__ region) {
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= n || sigma[it] != tne) return;
+    if (!map) region[it] = 2;
+    else
+        for (int k = 0; k < arity; ++k) region[map[it * arity + k]] = 2;
+}
+
 // inverse map (Fig. 8): keys (target<<32 | source)
 __global__ void k_inv_keys(const int32_t *__restrict__ vals, int64_t nsrc, int arity, uint64_t *__restrict__ keys,
                            int32_t *__restrict__ count) {
@@ -233,8 +267,10 @@ __global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
 }
 
 // Jones-Plassmann round, part 1: uncoloured local maxima of the priority
+// (with tile regions treg, only neighbours in the tile's own region count)
 __global__ void k_jp_mark(const int32_t *__restrict__ off, const int32_t *__restrict__ adj,
-                          const int32_t *__restrict__ color, int32_t n, int8_t *__restrict__ mark) {
+                          const int32_t *__restrict__ color, int32_t n, int8_t *__restrict__ mark,
+                          const uint8_t *__restrict__ treg) {
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     int8_t m = 0;
@@ -243,7 +279,7 @@ __global__ void k_jp_mark(const int32_t *__restrict__ off, const int32_t *__rest
         m = 1;
         for (int32_t k = off[t]; k < off[t + 1]; ++k) {
             const int32_t u = adj[k];
-            if (color[u] >= 0) continue;
+            if (color[u] >= 0 || (treg && treg[u] != treg[t])) continue;
             const uint64_t pu = ((uint64_t)fmix32((uint32_t)u) << 32) | (uint32_t)u;
             if (pu > pt) { m = 0; break; }
         }
@@ -254,11 +290,13 @@ __global__ void k_jp_mark(const int32_t *__restrict__ off, const int32_t *__rest
 // part 2: each marked tile takes the smallest colour unused by coloured neighbours
 __global__ void k_jp_assign(const int32_t *__restrict__ off, const int32_t *__restrict__ adj,
                             int32_t *__restrict__ color, int32_t n, const int8_t *__restrict__ mark,
-                            int32_t *__restrict__ stats /* [0] coloured this round, [1] max colour, [2] overflow */) {
+                            int32_t *__restrict__ stats /* [0] coloured this round, [1] max colour, [2] overflow */,
+                            const uint8_t *__restrict__ treg) {
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n || !mark[t]) return;
     uint64_t used = 0;
     for (int32_t k = off[t]; k < off[t + 1]; ++k) {
+        if (treg && treg[adj[k]] != treg[t]) continue;
         const int32_t c = color[adj[k]];
         if (c >= 64) atomicExch(&stats[2], 1);
         else if (c >= 0) used |= 1ull << c;
@@ -558,6 +596,28 @@ void Inspector::seed_partition(int seedset, int64_t ts, int partition, const dou
     k_tile0_from_sorted<<<blocks_for(n0, 256), 256, 0, st>>>(keys.p, n0, ts, tile0.p, rank.p);
 }
 
+// Seed partition with regions (Sec. 5.1.2): the seeds of each region in seed
+// order, cut into blocks of ts; core tiles first, then boundary tiles, then T_ne.
+void Inspector::region_partition(int64_t n0, int64_t ts, const DBuf<int32_t> &rank, SubSched &sb,
+                                 DBuf<int32_t> &tile0) {
+    hipStream_t st = stream;
+    int64_t cnt[3] = {0, 0, 0};
+    for (int64_t i = 0; i < n0; ++i) cnt[sb.region[i]]++;
+    sb.ncore = (int32_t)((cnt[0] + ts - 1) / ts);
+    sb.nbnd = (int32_t)((cnt[1] + ts - 1) / ts);
+    sb.tne = sb.ncore + sb.nbnd;
+    if (n0 == 0) return;
+    DBuf<uint8_t> reg;
+    reg.upload(sb.region, st);
+    DBuf<uint64_t> keys(n0);
+    DBuf<int32_t> order(n0);
+    k_region_keys<<<blocks_for(n0, 256), 256, 0, st>>>(reg.p, rank.p, n0, keys.p);
+    k_rank_order<<<blocks_for(n0, 256), 256, 0, st>>>(rank.p, n0, order.p);
+    sort_keys(keys, n0, st);
+    k_tile0_regions<<<blocks_for(n0, 256), 256, 0, st>>>(keys.p, n0, order.p, cnt[0], sb.ncore, sb.tne, ts,
+                                                          tile0.p);
+}
+
 int64_t Inspector::seed_edges(int first, int nl, const DBuf<int32_t> &tile0, DBuf<uint64_t> &edges) {
     hipStream_t st = stream;
     const int seed = chain.loops[first].set;
@@ -636,8 +696,17 @@ static int cap_colour_classes(int32_t ntiles, const std::vector<int32_t> &off, c
 
 // Jones-Plassmann colouring of the tile graph given by unique edges (a<b),
 // then the colour-class cap when cap > 0
-int Inspector::colour(int32_t ntiles, const DBuf<uint64_t> &edges, int64_t ne, DBuf<int32_t> &color, int cap) {
+int Inspector::colour(int32_t ntiles, const DBuf<uint64_t> &edges, int64_t ne, DBuf<int32_t> &color, int cap,
+                      const SubSched *regions) {
     hipStream_t st = stream;
+    // regions: each region's tiles are coloured on the edges inside it
+    DBuf<uint8_t> treg;
+    std::vector<uint8_t> treg_h;  // kept until the colouring has synchronised
+    if (regions) {
+        treg_h.resize(ntiles);
+        for (int32_t t = 0; t < ntiles; ++t) treg_h[t] = t < regions->ncore ? 0 : (t < regions->tne ? 1 : 2);
+        treg.upload(treg_h, st);
+    }
     DBuf<uint64_t> sym(2 * ne > 0 ? 2 * ne : 1);
     if (ne) k_sym_edges<<<blocks_for(ne, 256), 256, 0, st>>>(edges.p, ne, sym.p);
     sort_keys(sym, 2 * ne, st);
@@ -654,8 +723,9 @@ int Inspector::colour(int32_t ntiles, const DBuf<uint64_t> &edges, int64_t ne, D
     while (done < ntiles) {
         // several rounds between host checks
         for (int r = 0; r < 8; ++r) {
-            k_jp_mark<<<blocks_for(ntiles, 256), 256, 0, st>>>(off.p, adj.p, color.p, ntiles, mark.p);
-            k_jp_assign<<<blocks_for(ntiles, 256), 256, 0, st>>>(off.p, adj.p, color.p, ntiles, mark.p, stats.p);
+            k_jp_mark<<<blocks_for(ntiles, 256), 256, 0, st>>>(off.p, adj.p, color.p, ntiles, mark.p, treg.p);
+            k_jp_assign<<<blocks_for(ntiles, 256), 256, 0, st>>>(off.p, adj.p, color.p, ntiles, mark.p, stats.p,
+                                                                 treg.p);
         }
         auto h = stats.download(st);
         DGT_REQUIRE(h[2] == 0, DGT_EUNSUPPORTED, "tile colouring needs more than 64 colours");
@@ -663,6 +733,19 @@ int Inspector::colour(int32_t ntiles, const DBuf<uint64_t> &edges, int64_t ne, D
         DGT_REQUIRE(++guard_rounds < 1000000, DGT_ESTATE, "colouring did not terminate");
         if (done >= ntiles) {
             int ncol = h[1] + 1;
+            if (regions) {  // boundary colours after the core ones, T_ne alone on top
+                auto hc = color.download(st, ntiles);
+                int ccore = 0, cbnd = 0;
+                for (int32_t t = 0; t < ntiles; ++t) {
+                    if (t < regions->ncore) ccore = std::max(ccore, hc[t] + 1);
+                    else if (t < regions->tne) cbnd = std::max(cbnd, hc[t] + 1);
+                }
+                for (int32_t t = regions->ncore; t < ntiles; ++t) hc[t] = t < regions->tne ? hc[t] + ccore : ccore + cbnd;
+                ncol = ccore + cbnd + 1;
+                DGT_REQUIRE(ncol <= 64, DGT_EUNSUPPORTED, "tile colouring needs more than 64 colours");
+                color.upload(hc, st);
+                return ncol;
+            }
             if (cap > 0) {
                 auto hc = color.download(st, ntiles);
                 auto ho = off.download(st, ntiles + 1);
@@ -686,6 +769,11 @@ void Inspector::run_sub(Schedule &S, SubSched &sb, int64_t ts, int partition, co
     if (ntiles == 0) ntiles = 1;
     DBuf<int32_t> tile0, rank;
     seed_partition(seedset, ts, partition, xy_host, xy_dev, tile0, rank);
+    const bool regions = sb.tne >= 0;
+    if (regions) {
+        region_partition(n0, ts, rank, sb, tile0);
+        ntiles = sb.tne + 1;
+    }
     if (first == 0 || !S.seed_rank.p) {
         S.seed_rank = std::move(rank);
         S.seed_set = seedset;
@@ -698,7 +786,7 @@ void Inspector::run_sub(Schedule &S, SubSched &sb, int64_t ts, int partition, co
     for (int s = 0; s < chain.nsets; ++s) phi[s].alloc(chain.size[s] > 0 ? chain.size[s] : 1);
     int round = 0, ncol = 0;
     for (; round < max_rounds; ++round) {
-        ncol = colour(ntiles, edges, ne, sb.color, cap);
+        ncol = colour(ntiles, edges, ne, sb.color, cap, regions ? &sb : nullptr);
         // default tile: first tile of colour 0
         int32_t big = INT32_MAX;
         DGT_HIP(hipMemcpyAsync(deft.p, &big, 4, hipMemcpyHostToDevice, st));
@@ -952,9 +1040,31 @@ void Inspector::dependences(SubSched &sb, const DBuf<uint64_t> *keys, const int6
     if (ne) k_low32<<<blocks_for(ne, 256), 256, 0, st>>>(edges.p, ne, sb.dep_succ.p);
 }
 
+// One halo exchange per chain: seeds written by T_ne of sub-chain sb turn non-exec.
+void Inspector::carry_stale(const Schedule &S, const SubSched &sb, std::vector<uint8_t> &region) {
+    hipStream_t st = stream;
+    const int64_t n0 = (int64_t)region.size();
+    if (n0 == 0) return;
+    DBuf<uint8_t> reg;
+    reg.upload(region, st);
+    for (int j = sb.first; j < sb.first + sb.n; ++j) {
+        const ChainLoop &L = chain.loops[j];
+        const int64_t n = chain.size[L.set];
+        if (n == 0) continue;
+        for (int i = 0; i < L.ndesc; ++i) {
+            if (L.d[i].mode == DGT_R) continue;
+            const int mp = L.d[i].map;
+            k_stale<<<blocks_for(n, 256), 256, 0, st>>>(S.sigma[j].p, n, sb.tne, mp < 0 ? nullptr : dmap[mp].p,
+                                                        mp < 0 ? 1 : chain.maps[mp].arity, reg.p);
+        }
+    }
+    region = reg.download(st, n0);
+}
+
 std::unique_ptr<Schedule> Inspector::run(int64_t ts, int partition, const double *xy_host, const double *xy_dev,
                                          int max_rounds, int cap, const std::vector<int32_t> &splits,
-                                         const std::vector<int32_t> &sub_ts) {
+                                         const std::vector<int32_t> &sub_ts, const uint8_t *region_host,
+                                         int carry) {
     hipStream_t st = stream;
     DGT_REQUIRE(ts >= 1, DGT_EINVAL, "tile_size must be >= 1");
     DGT_REQUIRE(sub_ts.empty() || sub_ts.size() == splits.size() + 1, DGT_EINVAL,
@@ -963,6 +1073,25 @@ std::unique_ptr<Schedule> Inspector::run(int64_t ts, int partition, const double
     DGT_REQUIRE(cap >= 0, DGT_EINVAL, "max_colour_tiles must be >= 0");
     DGT_REQUIRE(max_rounds >= 1, DGT_EINVAL, "max_conflict_rounds must be >= 1");
     DGT_REQUIRE(chain.nloops >= 1, DGT_EINVAL, "empty loop chain");
+    std::vector<uint8_t> region;
+    if (region_host) {
+        const int rset = chain.loops[0].set;
+        DGT_REQUIRE(cap == 0, DGT_EINVAL, "seed regions do not combine with max_colour_tiles");
+        DGT_REQUIRE(carry == 0 || carry == 1, DGT_EINVAL, "region_carry must be 0 or 1");
+        for (int32_t sp : splits)
+            DGT_REQUIRE(sp >= 0 && sp < chain.nloops && chain.loops[sp].set == rset, DGT_EINVAL,
+                        "with seed regions every sub-chain starts on the seed set of loop 0");
+        region.assign(region_host, region_host + chain.size[rset]);
+        for (uint8_t r : region) DGT_REQUIRE(r <= 2, DGT_EINVAL, "seed regions are 0, 1 or 2");
+        if (carry)
+            for (int j = 0; j < chain.nloops; ++j)
+                for (int i = 0; i < chain.loops[j].ndesc; ++i) {
+                    const dgt_desc &d = chain.loops[j].d[i];
+                    const int tset = d.map < 0 ? chain.loops[j].set : chain.maps[d.map].to;
+                    DGT_REQUIRE(d.mode == DGT_R || tset == rset, DGT_EINVAL,
+                                "region_carry needs every write of the chain to land in the seed set");
+                }
+    }
     auto S = std::make_unique<Schedule>();
     cur = S.get();
     S->nloops = chain.nloops;
@@ -988,8 +1117,13 @@ std::unique_ptr<Schedule> Inspector::run(int64_t ts, int partition, const double
         sb.first = start;
         sb.n = end - start;
         for (int j = start; j < end; ++j) S->sub_of[j] = (int)S->sub.size() - 1;
+        if (region_host) {
+            sb.region = region;
+            sb.tne = 0;  // regions requested; run_sub sets the tile ranges
+        }
         // a fusion scheme gives each sub-chain its own seed tile size (Sec. 7.2)
         run_sub(*S, sb, sub_ts.empty() ? ts : sub_ts[i], partition, xy_host, xy_dev, max_rounds, cap);
+        if (region_host && carry) carry_stale(*S, sb, region);
         start = end;
     }
     DGT_HIP(hipEventRecord(e1, st));

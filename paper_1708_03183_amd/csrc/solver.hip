@@ -23,6 +23,9 @@ struct GLoop {
 
 struct SubPlan {
     int first = 0, n = 0, ntiles = 0, ncolors = 0;
+    // a region-aware schedule never runs its last tile T_ne (the only tile of the
+    // last colour): colours [0, nexec_colors) hold the nexec tiles that run
+    int tne = -1, nexec = 0, nexec_colors = 0;
     DBuf<int32_t> efoot;
     DBuf<uint32_t> eacc;
     DBuf<uint32_t> lmap[31];
@@ -90,8 +93,14 @@ struct dgt_solver {
     uint64_t gen = 0;  // counts inspections and field reallocations (batches built on this solver check it)
     dgt_inspect_params last_ip{};
     std::vector<int32_t> last_splits, last_sub_ts;
+    std::vector<uint8_t> last_region;  // seed regions of the last inspection (empty: none)
     int last_cap = 0;
     std::string plan_error = "tiled mode needs dgt_solver_inspect";
+    // error flags of the dependence-driven launches, copied to pinned memory after each
+    // tiled call and read once the copy has landed (no wait on the next call)
+    int32_t *err_host = nullptr;  // [kMaxLoops]
+    hipEvent_t err_ev = nullptr;
+    bool err_pending = false;
     // timing of the last step
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_ms = 0;
@@ -114,6 +123,8 @@ struct dgt_solver {
         delete sched;
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
+        if (err_ev) (void)hipEventDestroy(err_ev);
+        if (err_host) (void)hipHostFree(err_host);
     }
 };
 
@@ -371,6 +382,9 @@ static void build_plan(dgt_solver *s) {
         P.ntiles = sb.ntiles;
         P.ncolors = sb.ncolors;
         P.color_off = sb.color_off.download(st, sb.ncolors + 1);
+        P.tne = sb.tne;
+        P.nexec_colors = sb.tne >= 0 ? sb.ncolors - 1 : sb.ncolors;
+        P.nexec = P.color_off[P.nexec_colors];
         // footprints renumbered into exec order, sorted per tile
         const int64_t len = sb.foot_len[0];
         DGT_REQUIRE(len > 0 || s->nc == 0, DGT_ESTATE, "empty cell footprint");
@@ -388,7 +402,8 @@ static void build_plan(dgt_solver *s) {
             P.eacc = std::move(vals);
         }
         auto foff = sb.foot_off[0].download(st, sb.ntiles + 1);
-        for (int t = 0; t < sb.ntiles; ++t) P.max_foot = std::max(P.max_foot, foff[t + 1] - foff[t]);
+        for (int t = 0; t < sb.ntiles; ++t)
+            if (t != sb.tne) P.max_foot = std::max(P.max_foot, foff[t + 1] - foff[t]);
         DGT_REQUIRE(P.max_foot <= 0x3fff, DGT_EUNSUPPORTED, "tile footprint exceeds 16383 cells");
         // local maps of the facet loops (cell loops take their iterations from the footprint's loop bits)
         DBuf<int32_t> err(1);
@@ -400,7 +415,7 @@ static void build_plan(dgt_solver *s) {
             auto &lm = P.lmap[j - sb.first];
             lm.alloc(std::max<int64_t>(n, 1));
             if (n)
-                k_lmap<<<blocks_for(n, 256), 256, 0, st>>>(kind, S.it_off[j].p, S.iters[j].p, sb.ntiles, n,
+                k_lmap<<<blocks_for(n, 256), 256, 0, st>>>(kind, S.it_off[j].p, S.iters[j].p, sb.ntiles, sb.tne, n,
                                                            sb.foot_off[0].p, P.efoot.p, s->rank.p, s->f2c.p,
                                                            s->f2l.p, s->b2c.p, s->b2l.p, s->bfree.p, lm.p, err.p);
         }
@@ -508,13 +523,14 @@ static void build_plan(dgt_solver *s) {
                 }
             std::vector<int32_t> toff(sb.ntiles + 1, 0);
             for (int t = 0; t < sb.ntiles; ++t) {
-                const int64_t len = (int64_t)A.nfl * 3 * (foff[t + 1] - foff[t]);
+                const int64_t len = t == sb.tne ? 0 : (int64_t)A.nfl * 3 * (foff[t + 1] - foff[t]);
                 DGT_REQUIRE(toff[t] + len < INT32_MAX, DGT_EUNSUPPORTED, "neighbour tables exceed 2^31 entries");
                 toff[t + 1] = (int32_t)(toff[t] + len);
             }
             std::vector<uint32_t> tab(std::max<int32_t>(toff[sb.ntiles], 1), 0u);
             bool dup = false;
             for (int t = 0; t < sb.ntiles; ++t) {
+                if (t == sb.tne) continue;  // never executed: no neighbour tables
                 const int nfoot = foff[t + 1] - foff[t];
                 for (int gi = 0; gi < A.nfl; ++gi) {
                     uint32_t *T3 = tab.data() + toff[t] + (size_t)gi * 3 * nfoot;
@@ -785,20 +801,66 @@ static void build_graph(dgt_solver *s, int b, SubPlan &P) {
     P.graph = true;
 }
 
+static void reset_graph(dgt_solver *s, SubPlan &P) {
+    DGT_HIP(hipMemsetAsync(P.cnt.p, 0, sizeof(uint32_t) * P.ntiles * s->nshots, s->st));
+    DGT_HIP(hipMemsetAsync(P.head.p, 0, sizeof(uint32_t), s->st));
+    DGT_HIP(hipMemsetAsync(P.err.p, 0, sizeof(int32_t), s->st));
+    P.epoch = 0;
+}
+
 // Raises DGT_ESTATE (and resets the counters) when a dependence wait timed out.
-static void check_graphs(dgt_solver *s) {
+// blocking: read the flags now (synchronises the stream).  Otherwise read the copy
+// that the last tiled call enqueued, if it has landed; a flag raised later is seen
+// by a later call (every wait is bounded, so launches in between end too, with
+// invalid results that the error then covers).
+static void check_graphs(dgt_solver *s, bool blocking = true) {
     bool bad = false;
-    for (auto &P : s->plan) {
-        if (!P.graph) continue;
-        if (P.err.download(s->st)[0] != 0) {
-            bad = true;
-            DGT_HIP(hipMemsetAsync(P.cnt.p, 0, sizeof(uint32_t) * P.ntiles * s->nshots, s->st));
-            DGT_HIP(hipMemsetAsync(P.head.p, 0, sizeof(uint32_t), s->st));
-            DGT_HIP(hipMemsetAsync(P.err.p, 0, sizeof(int32_t), s->st));
-            P.epoch = 0;
+    if (blocking) {
+        for (auto &P : s->plan) {
+            if (!P.graph) continue;
+            if (P.err.download(s->st)[0] != 0) {
+                bad = true;
+                reset_graph(s, P);
+            }
         }
+        s->err_pending = false;
+    } else {
+        if (!s->err_pending) return;
+        const hipError_t q = hipEventQuery(s->err_ev);
+        if (q == hipErrorNotReady) {
+            (void)hipGetLastError();  // not an error: the copy is still in flight
+            return;
+        }
+        DGT_HIP(q);
+        s->err_pending = false;
+        for (size_t b = 0; b < s->plan.size() && b < (size_t)kMaxLoops; ++b)
+            if (s->plan[b].graph && s->err_host[b] != 0) {
+                bad = true;
+                reset_graph(s, s->plan[b]);
+            }
     }
+    if (bad && s->err_host)
+        for (int b = 0; b < kMaxLoops; ++b) s->err_host[b] = 0;
     DGT_REQUIRE(!bad, DGT_ESTATE, "a dependence wait of the tiled executor timed out; its results are invalid");
+}
+
+// after a dependence-driven call: copy the error flags to pinned memory behind it
+static void post_graph_flags(dgt_solver *s) {
+    if (s->sched_mode != 1) return;
+    if (!s->err_host) {
+        DGT_HIP(hipHostMalloc((void **)&s->err_host, sizeof(int32_t) * kMaxLoops, hipHostMallocDefault));
+        for (int b = 0; b < kMaxLoops; ++b) s->err_host[b] = 0;
+        DGT_HIP(hipEventCreateWithFlags(&s->err_ev, hipEventDisableTiming));
+    }
+    bool any = false;
+    for (size_t b = 0; b < s->plan.size() && b < (size_t)kMaxLoops; ++b) {
+        if (!s->plan[b].graph) continue;
+        DGT_HIP(hipMemcpyAsync(s->err_host + b, s->plan[b].err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
+        any = true;
+    }
+    if (!any) return;
+    DGT_HIP(hipEventRecord(s->err_ev, s->st));
+    s->err_pending = true;
 }
 
 // extra_persist: fields written back for every cell that writes them (the FWI
@@ -830,6 +892,7 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
             if (s->sched_mode == 1 && P.kind != TK_GENERIC) {  // one launch for all colours
                 A.persist = 1;
                 A.ntiles = P.ntiles;
+                A.nexec = P.nexec;
                 A.tile_base = 0;
                 const SubSched &sb = s->sched->s->sub[b];
                 A.need = sb.dep_need.p;
@@ -838,7 +901,7 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
                 A.cnt = P.cnt.p;
                 A.head = P.head.p;
                 A.err = P.err.p;
-                A.head_base = P.epoch * (uint32_t)(P.ntiles * s->nshots + P.slots);
+                A.head_base = P.epoch * (uint32_t)(P.nexec * s->nshots + P.slots);
                 A.epoch = ++P.epoch;
                 A.spin_limit = s->wait_limit;
                 s->mark();
@@ -849,7 +912,7 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
                 if (after) (*after)(b);
                 continue;
             }
-            for (int c = 0; c < P.ncolors; ++c) {
+            for (int c = 0; c < P.nexec_colors; ++c) {
                 const int ntiles = P.color_off[c + 1] - P.color_off[c];
                 if (ntiles == 0) continue;
                 A.tile_base = P.color_off[c];
@@ -1098,7 +1161,7 @@ static int plan_slots(dgt_solver *s, const SubPlan &P) {
 // Counters and workgroup counts of the dependence-driven schedule (schedule 1).
 static void prepare_tiled(dgt_solver *s) {
     if (s->sched_mode != 1) return;
-    check_graphs(s);  // synchronises: reports a wait that timed out earlier
+    check_graphs(s, false);  // reports a wait that timed out in an earlier call, without waiting
     for (size_t b = 0; b < s->plan.size(); ++b) {
         SubPlan &P = s->plan[b];
         if (P.kind == TK_GENERIC) continue;
@@ -1118,6 +1181,9 @@ static void solver_inspect_once(dgt_solver *s, const dgt_inspect_params *p, int 
     if (p->sub_tile_sizes) s->last_sub_ts.assign(p->sub_tile_sizes, p->sub_tile_sizes + p->nsplits + 1);
     else s->last_sub_ts.clear();
     s->last_ip.sub_tile_sizes = nullptr;
+    if (p->seed_region) s->last_region.assign(p->seed_region, p->seed_region + s->nc);
+    else s->last_region.clear();
+    s->last_ip.seed_region = nullptr;
     s->last_cap = cap;
     delete s->sched;
     s->sched = nullptr;
@@ -1132,7 +1198,7 @@ static void solver_inspect_once(dgt_solver *s, const dgt_inspect_params *p, int 
     Inspector insp(sch->chain_copy, st);
     std::vector<int32_t> splits(p->splits, p->splits + p->nsplits);
     sch->s = insp.run(p->tile_size, p->partition, nullptr, cxy.p, p->max_conflict_rounds, cap, splits,
-                      s->last_sub_ts);
+                      s->last_sub_ts, s->last_region.empty() ? nullptr : s->last_region.data(), p->region_carry);
     s->sched = sch.release();
     // executor layout follows the seed order of the schedule
     auto rank = s->sched->s->seed_rank.download(st, s->nc);
@@ -1157,8 +1223,14 @@ dgt_status dgt_solver_inspect(dgt_solver *s, const dgt_inspect_params *p) {
         DGT_REQUIRE(p->partition == 0 || p->partition == 1, DGT_EINVAL, "partition must be 0 or 1");
         DGT_REQUIRE(p->nsplits >= 0 && (p->nsplits == 0 || p->splits), DGT_EINVAL, "bad splits");
         DGT_REQUIRE(p->max_colour_tiles >= -1, DGT_EINVAL, "max_colour_tiles must be >= -1");
+        if (p->seed_region) {
+            // a step runs all its sub-chains after one halo exchange
+            DGT_REQUIRE(p->nsplits == 0 || p->region_carry == 1, DGT_EINVAL,
+                        "seed regions with several sub-chains need region_carry = 1 (one exchange per step)");
+            DGT_REQUIRE(p->max_colour_tiles <= 0, DGT_EINVAL, "seed regions do not combine with max_colour_tiles");
+        }
         solver_inspect_once(s, p, p->max_colour_tiles > 0 ? p->max_colour_tiles : 0);
-        if (p->max_colour_tiles == -1 && s->plan_status == DGT_OK) {
+        if (p->max_colour_tiles == -1 && !p->seed_region && s->plan_status == DGT_OK) {
             // cap the colour classes at the number of tile workgroups resident at once when
             // some class would need more than one round of them
             int slots = INT32_MAX;
@@ -1199,6 +1271,11 @@ dgt_status dgt_solver_autotune(dgt_solver *s, const dgt_autotune_params *p, dgt_
         ip.max_conflict_rounds = 64;
         ip.splits = p->splits;
         ip.nsplits = p->nsplits;
+        const std::vector<uint8_t> regions = s->last_region;  // a part keeps its regions
+        if (!regions.empty()) {
+            ip.seed_region = regions.data();
+            ip.region_carry = 1;
+        }
         struct Cand { int ts; double foot; };
         std::vector<Cand> cands;
         int skipped = 0, timed = 0;
@@ -1334,6 +1411,57 @@ dgt_status dgt_state_download(dgt_solver *s, void *v, void *sig) {
     });
 }
 
+struct dgt_cell_list {
+    int64_t nc = 0, n = 0;
+    int dev = 0;
+    DBuf<int32_t> cells;  // mesh cell ids
+};
+
+dgt_status dgt_cell_list_create(const dgt_solver *s, int64_t n, const int32_t *cells, dgt_cell_list **out) {
+    return guard([&] {
+        DGT_REQUIRE(s && out && n >= 0 && (n == 0 || cells), DGT_EINVAL, "bad arguments");
+        *out = nullptr;
+        for (int64_t i = 0; i < n; ++i)
+            DGT_REQUIRE(cells[i] >= 0 && cells[i] < s->nc, DGT_EINVAL, "cell id out of range");
+        auto l = std::make_unique<dgt_cell_list>();
+        l->nc = s->nc;
+        l->n = n;
+        l->dev = s->dev;
+        l->cells.alloc(std::max<int64_t>(n, 1));
+        if (n) l->cells.upload(cells, (size_t)n, s->st);
+        DGT_HIP(hipStreamSynchronize(s->st));
+        *out = l.release();
+    });
+}
+
+void dgt_cell_list_destroy(dgt_cell_list *l) { delete l; }
+
+static void halo_copy(dgt_solver *s, const dgt_cell_list *l, const void *v, const void *sig, bool unpack) {
+    DGT_REQUIRE(s && l, DGT_EINVAL, "NULL argument");
+    DGT_REQUIRE(l->nc == s->nc && l->dev == s->dev, DGT_EINVAL, "the cell list belongs to another mesh or device");
+    DGT_REQUIRE(s->state_valid, DGT_ESTATE, "no state uploaded");
+    if (!unpack) check_graphs(s, false);
+    if (l->n == 0) return;  // empty buffers may be NULL
+    DGT_REQUIRE(v && sig, DGT_EINVAL, "NULL buffer");
+    dispatch(s, [&]<int K, typename T>() {
+        for (int f : {F_V, F_S}) {
+            const int64_t rows = field_ncomp(f) * s->E.np, total = rows * s->nshots * l->n;
+            T *buf = (T *)(f == F_V ? v : sig);
+            k_halo_copy<T><<<blocks_for(total, 256), 256, 0, s->st>>>((T *)s->fld[f].p, buf, s->rank.p, l->cells.p,
+                                                                      l->n, rows, s->nc, total, unpack ? 1 : 0);
+        }
+    });
+    DGT_HIP(hipGetLastError());
+}
+
+dgt_status dgt_state_pack(dgt_solver *s, const dgt_cell_list *l, void *v, void *sig) {
+    return guard([&] { halo_copy(s, l, v, sig, false); });
+}
+
+dgt_status dgt_state_unpack(dgt_solver *s, const dgt_cell_list *l, const void *v, const void *sig) {
+    return guard([&] { halo_copy(s, l, v, sig, true); });
+}
+
 dgt_status dgt_step(dgt_solver *s, int64_t nsteps, int32_t mode, double t0) {
     return guard([&] {
         DGT_REQUIRE(s && nsteps >= 0, DGT_EINVAL, "bad arguments");
@@ -1350,6 +1478,7 @@ dgt_status dgt_step(dgt_solver *s, int64_t nsteps, int32_t mode, double t0) {
         });
         DGT_HIP(hipGetLastError());
         DGT_HIP(hipEventRecord(s->ev1, s->st));
+        if (mode == 1) post_graph_flags(s);
         s->last_launches = launches;
         s->last_ms = -1.0;
     });

@@ -49,6 +49,7 @@ struct TileArgs {
     // lower-colour tile whose footprint meets its own has finished
     int32_t persist;            // 0: one launch per colour (tiles[tile_base + blockIdx.x])
     int32_t ntiles;             // tiles of the sub-chain
+    int32_t nexec;              // tiles that run (all but a region-aware schedule's T_ne)
     const int32_t *need;        // [ntiles] predecessors per tile
     const int32_t *succ_off;    // [ntiles+1] successors (CSR)
     const int32_t *succ;

@@ -376,7 +376,7 @@ __device__ __forceinline__ void chain_op(const RefC<K, T> &Rf, CellRegs<K, T> &r
 // too (the error flag tells the host, and the tile's results are invalid).
 __device__ __forceinline__ int take_ticket(const TileArgs &a, int &shot) {
     const uint32_t ticket = atomicAdd(a.head, 1u) - a.head_base;
-    if (ticket >= (uint32_t)a.ntiles * (uint32_t)a.nshots) return -1;
+    if (ticket >= (uint32_t)a.nexec * (uint32_t)a.nshots) return -1;
     shot = (int)(ticket % (uint32_t)a.nshots);
     return a.tiles[ticket / (uint32_t)a.nshots];
 }

@@ -48,7 +48,8 @@ class _Desc(C.Structure):
 class _InspectParams(C.Structure):
     _fields_ = [("tile_size", C.c_int64), ("partition", C.c_int32), ("seed_xy", C.c_void_p),
                 ("max_conflict_rounds", C.c_int32), ("splits", C.c_void_p), ("nsplits", C.c_int32),
-                ("max_colour_tiles", C.c_int32), ("sub_tile_sizes", C.c_void_p)]
+                ("max_colour_tiles", C.c_int32), ("sub_tile_sizes", C.c_void_p), ("seed_region", C.c_void_p),
+                ("region_carry", C.c_int32)]
 
 
 class _SolverParams(C.Structure):
@@ -76,6 +77,7 @@ _SIGS = {
     "dgt_schedule_iters": [_p, C.c_int32, _p, _p],
     "dgt_schedule_footprint": [_p, C.c_int32, C.c_int32, _i64, _p, _p, _p],
     "dgt_schedule_tiles_by_color": [_p, C.c_int32, _p, _p],
+    "dgt_schedule_regions": [_p, C.c_int32, _p, _p],
     "dgt_schedule_summary_json": [_p, C.c_char_p, C.c_size_t],
     "dgt_schedule_destroy": [_p],
     "dgt_mesh_create": [C.c_int64, _p, C.c_int64, _p, C.c_int32, C.POINTER(_p)],
@@ -92,6 +94,10 @@ _SIGS = {
     "dgt_fwi_gradient": [_p, _p, _p, _p, _p, _p, _p],
     "dgt_state_upload": [_p, _p, _p],
     "dgt_state_download": [_p, _p, _p],
+    "dgt_cell_list_create": [_p, C.c_int64, _p, C.POINTER(_p)],
+    "dgt_cell_list_destroy": [_p],
+    "dgt_state_pack": [_p, _p, _p, _p],
+    "dgt_state_unpack": [_p, _p, _p, _p],
     "dgt_step": [_p, C.c_int64, C.c_int32, C.c_double],
     "dgt_energy": [_p, _p, _p, _p, C.POINTER(C.c_double)],
     "dgt_energy_noalloc": [_p, _p, _p, _p, C.POINTER(C.c_double)],
@@ -112,7 +118,8 @@ _SIGS = {
     "dgt_last_error": [],
     "dgt_version": [],
 }
-_VOID = {"dgt_chain_destroy", "dgt_schedule_destroy", "dgt_mesh_destroy", "dgt_solver_destroy", "dgt_batch_destroy"}
+_VOID = {"dgt_chain_destroy", "dgt_schedule_destroy", "dgt_mesh_destroy", "dgt_solver_destroy", "dgt_batch_destroy",
+         "dgt_cell_list_destroy"}
 
 
 def exported_symbols() -> list[str]:
@@ -154,8 +161,10 @@ def _stream_handle(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
-def _inspect_params(tile_size, partition, seed_xy, max_rounds, splits, max_colour_tiles=0, sub_tile_sizes=None):
+def _inspect_params(tile_size, partition, seed_xy, max_rounds, splits, max_colour_tiles=0, sub_tile_sizes=None,
+                    seed_region=None, region_carry=1):
     sp = np.ascontiguousarray(np.array(list(splits), np.int32))
+    reg = None if seed_region is None else np.ascontiguousarray(seed_region, np.uint8)
     xy = None if seed_xy is None else np.ascontiguousarray(seed_xy, np.float64)
     st = None
     if sub_tile_sizes is not None:
@@ -163,8 +172,9 @@ def _inspect_params(tile_size, partition, seed_xy, max_rounds, splits, max_colou
         if st.size != len(sp) + 1:
             raise ValueError("sub_tile_sizes needs one tile size per sub-chain (len(splits) + 1)")
     p = _InspectParams(int(tile_size), int(partition), _np_ptr(xy), int(max_rounds),
-                       _np_ptr(sp) if len(sp) else None, len(sp), int(max_colour_tiles), _np_ptr(st))
-    return p, (sp, xy, st)
+                       _np_ptr(sp) if len(sp) else None, len(sp), int(max_colour_tiles), _np_ptr(st), _np_ptr(reg),
+                       int(region_carry))
+    return p, (sp, xy, st, reg)
 
 
 # --------------------------------------------------------------- tier 1
@@ -207,8 +217,9 @@ class Chain:
         return out.value
 
     def inspect(self, tile_size, partition=0, seed_xy=None, max_rounds=64, splits=(), stream=None,
-                max_colour_tiles=0, sub_tile_sizes=None) -> "Schedule":
-        p, keep = _inspect_params(tile_size, partition, seed_xy, max_rounds, splits, max_colour_tiles, sub_tile_sizes)
+                max_colour_tiles=0, sub_tile_sizes=None, seed_region=None, region_carry=1) -> "Schedule":
+        p, keep = _inspect_params(tile_size, partition, seed_xy, max_rounds, splits, max_colour_tiles, sub_tile_sizes,
+                                  seed_region, region_carry)
         h = C.c_void_p()
         _check(lib().dgt_inspect(self.h, C.byref(p), _stream_handle(stream), C.byref(h)))
         return Schedule(h, owner=True, loop_sizes=[self.sizes[s] for s in self.loop_sets])
@@ -267,6 +278,14 @@ class Schedule:
         tl = np.zeros(info["ntiles"], np.int32)
         _check(lib().dgt_schedule_tiles_by_color(self.h, sub, _np_ptr(coff), _np_ptr(tl)))
         return coff, tl
+
+    def regions(self, sub: int, seed_size: int):
+        """((core tiles, boundary tiles, T_ne id, T_ne colour), seed regions) of a region-aware
+        schedule."""
+        info = np.zeros(4, np.int32)
+        reg = np.zeros(max(seed_size, 1), np.uint8)
+        _check(lib().dgt_schedule_regions(self.h, sub, _np_ptr(info), _np_ptr(reg)))
+        return tuple(int(x) for x in info), reg[:seed_size]
 
     def summary(self) -> str:
         buf = C.create_string_buffer(1 << 16)
@@ -344,10 +363,13 @@ class Solver:
         return (torch.zeros(self._shape(2), dtype=self.dtype, device=device),
                 torch.zeros(self._shape(3), dtype=self.dtype, device=device))
 
-    def inspect(self, tile_size, partition=1, max_rounds=64, splits=(), max_colour_tiles=0, sub_tile_sizes=None):
+    def inspect(self, tile_size, partition=1, max_rounds=64, splits=(), max_colour_tiles=0, sub_tile_sizes=None,
+                seed_region=None, region_carry=1):
         """max_colour_tiles: 0 none, > 0 cap per colour class, -1 the GPU's resident tile count;
-        sub_tile_sizes: one seed tile size per sub-chain (else tile_size for all)."""
-        p, keep = _inspect_params(tile_size, partition, None, max_rounds, splits, max_colour_tiles, sub_tile_sizes)
+        sub_tile_sizes: one seed tile size per sub-chain (else tile_size for all); seed_region:
+        per cell 0 core, 1 boundary, 2 non-exec for one part of a distributed mesh."""
+        p, keep = _inspect_params(tile_size, partition, None, max_rounds, splits, max_colour_tiles, sub_tile_sizes,
+                                  seed_region, region_carry)
         _check(lib().dgt_solver_inspect(self.h, C.byref(p)))
 
     def autotune(self, tile_sizes=(64, 96, 128, 192, 256, 384, 512), splits=(), partition=1, trial_steps=5,
@@ -429,6 +451,24 @@ class Solver:
     def step(self, nsteps: int, mode: int = 1, t0: float = 0.0):
         _check(lib().dgt_step(self.h, int(nsteps), int(mode), float(t0)))
 
+    def cell_list(self, cells) -> "CellList":
+        return CellList(self, cells)
+
+    def _halo_shape(self, comps, n):
+        return (comps, self.np, n) if self.nshots == 1 else (self.nshots, comps, self.np, n)
+
+    def pack(self, cl: "CellList", v, s):
+        """State of the listed cells into packed buffers v[.., 2, Np, n], s[.., 3, Np, n]."""
+        assert v.dtype == self.dtype and s.dtype == self.dtype and v.is_contiguous() and s.is_contiguous()
+        assert tuple(v.shape) == self._halo_shape(2, cl.n) and tuple(s.shape) == self._halo_shape(3, cl.n)
+        _check(lib().dgt_state_pack(self.h, cl.h, C.c_void_p(v.data_ptr()), C.c_void_p(s.data_ptr())))
+
+    def unpack(self, cl: "CellList", v, s):
+        """Packed buffers into the state of the listed cells (a halo receive)."""
+        assert v.dtype == self.dtype and s.dtype == self.dtype and v.is_contiguous() and s.is_contiguous()
+        assert tuple(v.shape) == self._halo_shape(2, cl.n) and tuple(s.shape) == self._halo_shape(3, cl.n)
+        _check(lib().dgt_state_unpack(self.h, cl.h, C.c_void_p(v.data_ptr()), C.c_void_p(s.data_ptr())))
+
     def energy(self, v, s_new, s_old, noalloc: bool = False) -> float:
         """Energy of one shot's state (tensors of one shot, contiguous);
         noalloc selects dgt_energy_noalloc."""
@@ -474,6 +514,22 @@ class Solver:
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.dgt_solver_destroy(self.h)
+            self.h = None
+
+
+class CellList:
+    """Cells of a solver's mesh for halo packing and unpacking (ids in the mesh's numbering)."""
+
+    def __init__(self, solver: "Solver", cells):
+        c = np.ascontiguousarray(cells, np.int32)
+        self.n = int(c.size)
+        h = C.c_void_p()
+        _check(lib().dgt_cell_list_create(solver.h, self.n, _np_ptr(c), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.dgt_cell_list_destroy(self.h)
             self.h = None
 
 

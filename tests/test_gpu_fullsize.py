@@ -201,3 +201,74 @@ def test_full_size_energy_conserved_over_1000_tiled_steps(D):
           f"the stress moved by {moved:.3f} of its norm")
     assert drift <= 1e-12
     assert moved > 0.1  # the state did evolve
+
+
+def test_full_size_part_block_matches_oracle(D):
+    """One GPU's share of the 1024x1024 P3 FP32 workload: block 5 of 2 x 4 rectangular
+    blocks (262,144 owned cells), 6 exec halo layers and one non-exec layer, inspected
+    with regions in the bench's launch configuration; before each of 2 steps the halo
+    takes a whole-mesh GPU solver's state by pack / unpack.  Every owned cell follows
+    the whole-mesh solver, and sampled owned cells (random ones and ones next to the
+    halo) match the FP64 oracle run on their patches of the whole mesh."""
+    k, steps, t0 = 3, 2, 0.1
+    m = I.square_mesh(1024, jitter=0.2, jitter_seed=1, renumber_seed=2)
+    lam, mu, rho = I.lognormal_material(m)
+    dt = _cfl_dt(m, lam, mu, rho, k)
+    npk = (k + 1) * (k + 2) // 2
+    P = I.mesh_part(m, I.block_parts(m, 2, 4), 5, 6)
+    c = P.cells
+    print(f"part: {int(P.owned.sum())} owned, {int(np.sum(P.region == 0))} core, {c.size} local cells", flush=True)
+    v = I.random_state((2, npk, m.nc), 51).astype(np.float32).astype(np.float64)
+    s = I.random_state((3, npk, m.nc), 52).astype(np.float32).astype(np.float64)
+    src = (0.75, 0.6)
+    g = D.Solver(D.Mesh.from_mesh(m), lam, mu, rho, degree=k, flux=1, time_order=4, precision=1, free_sides=0x8,
+                 dt=dt)
+    g.set_source(*src)
+    g.inspect(256, partition=1, splits=OPS)
+    lp = D.Solver(D.Mesh.from_mesh(P.mesh), lam[c], mu[c], rho[c], degree=k, flux=1, time_order=4, precision=1,
+                  free_sides=0x8, dt=dt)
+    lp.set_source(*src)
+    lp.inspect(256, partition=1, splits=OPS, seed_region=P.region, region_carry=1)
+    assert set(lp.kernels()) == {2}
+    gv = torch.from_numpy(v).float().cuda().contiguous()
+    gs = torch.from_numpy(s).float().cuda().contiguous()
+    g.upload(gv, gs)
+    ci = torch.from_numpy(c.astype(np.int64)).cuda()
+    lp.upload(gv[:, :, ci].contiguous(), gs[:, :, ci].contiguous())
+    halo = np.nonzero(~P.owned)[0]
+    send, recv = g.cell_list(c[halo]), lp.cell_list(halo)
+    bv = torch.empty(2, npk, halo.size, dtype=torch.float32, device="cuda")
+    bs = torch.empty(3, npk, halo.size, dtype=torch.float32, device="cuda")
+    for i in range(steps):
+        g.pack(send, bv, bs)
+        lp.unpack(recv, bv, bs)
+        g.step(1, mode=1, t0=t0 + i * dt)
+        lp.step(1, mode=1, t0=t0 + i * dt)
+    lv, ls = lp.zeros()
+    lp.download(lv, ls)
+    g.download(gv, gs)
+    torch.cuda.synchronize()
+    own = np.nonzero(P.owned)[0]
+    oi = torch.from_numpy(own.astype(np.int64)).cuda()
+    ref = max(gv.abs().max().item(), gs.abs().max().item())
+    diff = max((lv[:, :, oi] - gv[:, :, ci[oi]]).abs().max().item(),
+               (ls[:, :, oi] - gs[:, :, ci[oi]]).abs().max().item()) / ref
+    print(f"owned cells vs whole-mesh GPU solver after {steps} steps: max-abs / max = {diff:.3e}")
+    assert diff <= 1e-5
+    rv, rs = lv.double().cpu().numpy(), ls.double().cpu().numpy()
+    rng = np.random.default_rng(9)
+    edge = own[np.nonzero(P.region[own] == 1)[0]]
+    picks = sorted(set(int(x) for x in np.concatenate([rng.choice(own, 6, replace=False),
+                                                       rng.choice(edge, 6, replace=False)])))
+    off, nb = _adjacency(m)
+    worst = 0.0
+    for j in picks:
+        cg = int(c[j])
+        patch = _patch(off, nb, cg, 6 * steps + 1)
+        pv, ps = _oracle_on_patch(m, patch, lam, mu, rho, k, 4, dt, v, s, steps, src, t0)
+        q = int(np.searchsorted(patch, cg))
+        e = np.sqrt(((rv[:, :, j] - pv[:, :, q]) ** 2).sum() + ((rs[:, :, j] - ps[:, :, q]) ** 2).sum())
+        r = np.sqrt((pv[:, :, q] ** 2).sum() + (ps[:, :, q] ** 2).sum())
+        worst = max(worst, e / r)
+    print(f"sampled owned cells (6 random, 6 next to the halo) vs FP64 oracle: worst cell rel L2 {worst:.3e}")
+    assert worst <= 1e-4

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(L, name), name
     assert set(declared) == set(D.exported_symbols())
-    assert L.dgt_version() == 106
+    assert L.dgt_version() == 107
 
 
 @pytest.mark.parametrize("n,jit,ren,per", [(1, 0, None, 0), (5, 0.2, 3, 0), (16, 0.2, 7, 0), (6, 0.0, None, 3),
