@@ -224,6 +224,18 @@ dgt_status dgt_solver_create(const dgt_mesh *m, const double *lam, const double 
  * returned, and dgt_step in tiled mode then fails with DGT_EUNSUPPORTED
  * (smaller tile_size or more splits needed).  Synchronises the stream. */
 dgt_status dgt_solver_inspect(dgt_solver *s, const dgt_inspect_params *p);
+/* Multi-step fusion (an extension of the paper's fusion schemes, which stay within
+ * one time step): the loop chain handed to the inspector spans `steps`
+ * consecutive time steps (26 loops per step at order 4, 8 at order 2; at most 64
+ * loops, each sub-chain at most 31), so a sub-chain may run the loops of two or
+ * more steps in one tile pass; splits index the fused chain.  Drops the current
+ * inspection (call dgt_solver_inspect again).  Tiled dgt_step then needs nsteps to
+ * be a multiple of `steps` (DGT_EINVAL otherwise); the untiled chain is unchanged.
+ * The chain kernel runs two whole second-order steps and the stress half of a
+ * fourth-order step fused with the next velocity half; other fused sub-chains run
+ * on the generic or matrix-core kernels.  Batches and the tiled FWI refuse fused
+ * solvers.  DGT_EINVAL for steps < 1 or more than 64 loops. */
+dgt_status dgt_solver_fuse_steps(dgt_solver *s, int32_t steps);
 /* Autotuner: picks the seed tile size (from tile_sizes) and the executor
  * schedule (0 or 1, see dgt_solver_set_schedule) by timing trial steps, and
  * leaves the solver inspected and scheduled with the fastest pair.  Each

@@ -78,6 +78,7 @@ def _declare(L):
     L.or_ricker.restype = C.c_double
     L.or_dg_rate.argtypes = [_p, _f64p, _f64p, _f64p, _f64p]
     L.or_dg_chain.argtypes = [_p, C.POINTER(_p)]
+    L.or_dg_chain_steps.argtypes = [_p, C.c_int, C.POINTER(_p)]
     L.or_chain_create.argtypes = [C.POINTER(_p)]
     L.or_chain_free.argtypes = [_p]
     L.or_chain_set.argtypes = [_p, C.c_int64]
@@ -229,9 +230,11 @@ class ODG:
         lib().or_dg_rate(self.h, np.ascontiguousarray(v), np.ascontiguousarray(s), dv, ds)
         return dv, ds
 
-    def chain(self) -> "OChain":
+    def chain(self, steps: int = 1) -> "OChain":
+        """The loop chain of `steps` consecutive time steps."""
         h = C.c_void_p()
-        lib().or_dg_chain(self.h, C.byref(h))
+        if lib().or_dg_chain_steps(self.h, int(steps), C.byref(h)):
+            raise ValueError("bad number of steps")
         return OChain(handle=h)
 
     def __del__(self):

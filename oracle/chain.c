@@ -1074,10 +1074,16 @@ void or_dg_store(const or_dg *d, double *v, double *s);
 double or_dg_dt(const or_dg *d);
 
 /* Alg. 2 on one shared-memory node: colour by colour, tile by tile, and
- * inside a tile every loop's iterations in chain order. */
+ * inside a tile every loop's iterations in chain order.  A schedule of a chain
+ * fused over F steps (F times the step's loops) runs F steps per pass; loop j
+ * belongs to step j / (loops per step) of the pass and takes that step's time. */
 int or_dg_step_tiled(or_dg *d, const or_sched *sch, double *v, double *s, int64_t nsteps, double t0) {
+    int lps = or_dg_nloops(d);
+    if (sch->nloops % lps) return -1;
+    int fuse = sch->nloops / lps;
+    if (nsteps % fuse) return -1;
     or_chain *c;
-    or_dg_chain(d, &c);
+    if (or_dg_chain_steps(d, fuse, &c)) return -1;
     if (sch->nloops != c->nloops) { or_chain_free(c); return -1; }
     /* per loop, per tile iteration lists */
     int32_t *toff[MAXLOOPS], *its[MAXLOOPS];
@@ -1089,8 +1095,7 @@ int or_dg_step_tiled(or_dg *d, const or_sched *sch, double *v, double *s, int64_
     }
     or_dg_load(d, v, s);
     double dt = or_dg_dt(d);
-    for (int64_t n = 0; n < nsteps; n++) {
-        or_dg_begin_step(d, t0 + ((double)n + 0.5) * dt);
+    for (int64_t n = 0; n < nsteps; n += fuse) {
         for (int si = 0; si < sch->nsub; si++) {
             const sub_t *b = &sch->sub[si];
             int32_t *coff = malloc(sizeof(int32_t) * (b->ncolors + 1));
@@ -1099,8 +1104,10 @@ int or_dg_step_tiled(or_dg *d, const or_sched *sch, double *v, double *s, int64_
             for (int p = 0; p < b->ntiles; p++) {
                 int t = tl[p];
                 if (b->region && t == b->tne) continue; /* T_ne is never executed (Alg. 2) */
-                for (int j = b->first; j < b->first + b->n; j++)
-                    for (int32_t q = toff[j][t]; q < toff[j][t + 1]; q++) or_dg_iteration(d, j, its[j][q]);
+                for (int j = b->first; j < b->first + b->n; j++) {
+                    or_dg_begin_step(d, t0 + ((double)(n + j / lps) + 0.5) * dt);
+                    for (int32_t q = toff[j][t]; q < toff[j][t + 1]; q++) or_dg_iteration(d, j % lps, its[j][q]);
+                }
             }
             free(coff);
             free(tl);

@@ -708,7 +708,12 @@ int or_dg_rate(or_dg *d, const double *v, const double *s, double *dv, double *d
 
 /* The chain as a generic loop chain: sets C=0, F=1, B=2; maps f2c=0, b2c=1.
  * Data-space ids are the D_* indices above. */
-int or_dg_chain(const or_dg *d, or_chain **out) {
+int or_dg_chain(const or_dg *d, or_chain **out) { return or_dg_chain_steps(d, 1, out); }
+
+/* The chain of `steps` consecutive time steps: the step's loops repeated (a chain
+ * fused over several steps, an extension of the paper's per-step loop chain). */
+int or_dg_chain_steps(const or_dg *d, int steps, or_chain **out) {
+    if (steps < 1 || steps * d->nloops > 64) return -1;
     or_chain *ch;
     or_chain_create(&ch);
     or_chain_set(ch, d->nc);
@@ -716,8 +721,8 @@ int or_dg_chain(const or_dg *d, or_chain **out) {
     or_chain_set(ch, d->nb);
     or_chain_map(ch, 1, 0, 2, d->f2c);
     or_chain_map(ch, 2, 0, 1, d->b2c);
-    for (int j = 0; j < d->nloops; j++) {
-        const dg_loop *L = &d->loops[j];
+    for (int jj = 0; jj < steps * d->nloops; jj++) {
+        const dg_loop *L = &d->loops[jj % d->nloops];
         int32_t maps[8], modes[8], data[8];
         int nd = 0;
 #define ADD(m_, mo_, da_) do { maps[nd] = (m_); modes[nd] = (mo_); data[nd] = (da_); nd++; } while (0)

@@ -68,6 +68,8 @@ int or_dg_rate(or_dg *d, const double *v, const double *s, double *dv, double *d
 /* The chain as a generic loop chain (sets C, F, B; maps f2c, b2c). */
 struct or_chain;
 int or_dg_chain(const or_dg *d, struct or_chain **out);
+/* The chain of `steps` consecutive steps (the step's loops repeated; at most 64). */
+int or_dg_chain_steps(const or_dg *d, int steps, struct or_chain **out);
 
 /* ---------------- loop chain + inspector ---------------- */
 typedef struct or_chain or_chain;
@@ -144,7 +146,9 @@ int or_projection_after(const or_chain *c, const int32_t *tile0, int ntiles, con
 void or_set_literal_projection(int on);
 
 /* Tiled DG step: the same per-iteration kernels as or_dg_step run in
- * schedule order (Alg. 2: colour by colour, tile by tile, loop by loop). */
+ * schedule order (Alg. 2: colour by colour, tile by tile, loop by loop).  A
+ * schedule of the chain of F steps (or_dg_chain_steps) runs F steps per pass;
+ * nsteps must be a multiple of F. */
 int or_dg_step_tiled(or_dg *d, const or_sched *sch, double *v, double *s, int64_t nsteps, double t0);
 
 #ifdef __cplusplus

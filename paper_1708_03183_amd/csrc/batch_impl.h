@@ -341,6 +341,7 @@ dgt_status dgt_batch_create(dgt_solver *const *solvers, int32_t n, void *stream,
                                 P.n == P0.n,
                             DGT_EINVAL, "members must run the same chain-kernel sub-chains");
                 DGT_REQUIRE(P.tne < 0, DGT_EINVAL, "a member inspected with regions runs on its own");
+                DGT_REQUIRE(s->fuse == 1, DGT_EINVAL, "a member fused over several steps runs on its own");
             }
             b->m.push_back(s);
             b->gen.push_back(s->gen);

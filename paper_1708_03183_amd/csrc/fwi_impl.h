@@ -247,6 +247,8 @@ static void fwi_check(dgt_solver *s, const dgt_fwi_params *p) {
                 "tiled mode needs a successful dgt_solver_inspect");
     DGT_REQUIRE(p->mode == 0 || s->last_region.empty(), DGT_EUNSUPPORTED,
                 "full-waveform inversion runs on a whole mesh, not on a region-aware part");
+    DGT_REQUIRE(p->mode == 0 || s->fuse == 1, DGT_EUNSUPPORTED,
+                "full-waveform inversion samples receivers after every step: no chain fused over steps");
 }
 
 template <int K, typename T>

@@ -18,7 +18,8 @@ namespace dgt {
 struct GLoop {
     int8_t kind, in, out, pen;
     double scale, pscale;
-    int set;  // 0 cells, 1 interior facets, 2 exterior facets
+    int set;   // 0 cells, 1 interior facets, 2 exterior facets
+    int step;  // time step of the loop in a chain fused over several steps
 };
 
 struct SubPlan {
@@ -26,6 +27,7 @@ struct SubPlan {
     // a region-aware schedule never runs its last tile T_ne (the only tile of the
     // last colour): colours [0, nexec_colors) hold the nexec tiles that run
     int tne = -1, nexec = 0, nexec_colors = 0;
+    int step0 = 0;  // step of the first loop within a chain fused over steps
     DBuf<int32_t> efoot;
     DBuf<uint32_t> eacc;
     DBuf<uint32_t> lmap[31];
@@ -84,6 +86,7 @@ struct dgt_solver {
     int64_t fshot(int f) const { return (int64_t)dgt::field_ncomp(f) * E.np * nc; }
     // chain, schedule, plan
     std::vector<dgt::GLoop> loops;
+    int fuse = 1;  // time steps in the chain handed to the inspector
     dgt_chain chain;
     dgt_schedule *sched = nullptr;
     std::vector<dgt::SubPlan> plan;
@@ -188,6 +191,14 @@ static void build_loops(dgt_solver *s) {
         app(false, F_V, F_Z, dt, pens, dt);
         L.push_back({KV_UPD2_S, -1, F_S, -1, dt, 0.0, 0});
     }
+    // a chain fused over several time steps repeats the step's loops
+    const size_t per = L.size();
+    for (int r = 1; r < s->fuse; ++r)
+        for (size_t j = 0; j < per; ++j) {
+            GLoop g = L[j];
+            g.step = r;
+            L.push_back(g);
+        }
     // the loop chain seen by the inspector: sets C, F, B; maps f2c, b2c
     dgt::ChainDesc &c = s->chain.c;
     c = dgt::ChainDesc();
@@ -462,6 +473,7 @@ static void build_plan(dgt_solver *s) {
             t.kind = g.kind;
             t.in = g.in;
             t.out = g.out;
+            t.step = (int8_t)(g.step - s->loops[sb.first].step);
             t.pen = g.pen;
             t.partner = -1;
             t.grp = -1;
@@ -567,10 +579,12 @@ static void build_plan(dgt_solver *s) {
         // a sub-chain of whole consecutive operator applications (each with its update, the
         // last one's optional) runs on the chain kernel
         {
-            const int order = s->p.time_order, nop = order == 4 ? 6 : 2;
+            // operators are numbered on across the steps of a fused chain
+            const int order = s->p.time_order, nop = ops_per_step(order) * s->fuse;
             int o = 0;
             while (o < nop && op_first_loop(order, o) != sb.first) ++o;
             const int first_op = o;
+            P.step0 = s->loops[sb.first].step;  // also for sub-chains that start inside an operator
             int j = sb.first;
             const int end = sb.first + sb.n;
             bool ok = o < nop;
@@ -595,7 +609,8 @@ static void build_plan(dgt_solver *s) {
             }
             const int nops = o - first_op;
             bool known = false;
-            for (const auto &c : TILE_CHAINS) known |= c[0] == order && c[1] == first_op && c[2] == nops;
+            for (const auto &c : TILE_CHAINS)
+                known |= c[0] == order && c[1] == first_op % ops_per_step(order) && c[2] == nops;
             const bool whole = ok && j == end && known && A.nfl == nops;
             const int cap = s->K == 4 && s->esz == 8 ? TILE_NT[1] : TILE_NT[2];
             // DGT_TILE_OP: 0 forces the generic kernel, 1 the register-resident chain kernel
@@ -659,7 +674,7 @@ static void build_plan(dgt_solver *s) {
                     A.stride = S16;
                     A.nrow = rows * S16;  // geometry rows start here
                     P.kind = TK_MFMA;
-                    P.o0 = first_op;
+                    P.o0 = first_op % ops_per_step(order);
                     P.nops = nops;
                     P.lds_bytes = bytes;
                 }
@@ -675,7 +690,7 @@ static void build_plan(dgt_solver *s) {
                 if ((size_t)nrow * A.stride * s->esz + refb <= budget) {
                     A.nrow = nrow;
                     P.kind = TK_CHAIN;
-                    P.o0 = first_op;
+                    P.o0 = first_op % ops_per_step(order);
                     P.nops = nops;
                     P.lds_bytes = (size_t)A.nrow * A.stride * s->esz;
                 }
@@ -874,8 +889,8 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
     for (auto &P : s->plan)
         tile_launch<K, T>(P.kind, P.threads, s->upw, s->haspen, s->p.time_order, P.o0, P.nops, 0, P.lds_bytes,
                           st, P.args, TA_ATTR);
-    for (int64_t n = 0; n < nsteps; ++n) {
-        const double th = t0 + ((double)n + 0.5) * dt;
+    // a chain fused over F steps runs F steps per pass (callers pass multiples of F)
+    for (int64_t n = 0; n + s->fuse <= nsteps; n += s->fuse) {
         for (size_t b = 0; b < s->plan.size(); ++b) {
             SubPlan &P = s->plan[b];
             TileArgs A = P.args;
@@ -888,7 +903,12 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
             A.src_vec = s->src_vec.p;
             A.persistent_mask |= extra_persist;
             A.dt = dt;
-            A.src_amp = s->has_src ? dt * ricker(th, s->sf0, s->st0, s->samp) : 0.0;
+            // source amplitudes of the sub-chain's steps (a sub-chain spans at most four)
+            for (int q = 0; q < 4; ++q) {
+                const double th = t0 + ((double)(n + P.step0 + q) + 0.5) * dt;
+                A.src_amps[q] = s->has_src ? dt * ricker(th, s->sf0, s->st0, s->samp) : 0.0;
+            }
+            A.src_amp = A.src_amps[0];
             if (s->sched_mode == 1 && P.kind != TK_GENERIC) {  // one launch for all colours
                 A.persist = 1;
                 A.ntiles = P.ntiles;
@@ -1315,9 +1335,9 @@ dgt_status dgt_solver_autotune(dgt_solver *s, const dgt_autotune_params *p, dgt_
                 prepare_tiled(s);
                 int64_t launches = 0;
                 dispatch(s, [&]<int K, typename T>() {
-                    step_tiled<K, T>(s, 1, 0.0, launches);  // first launches: code and caches warm
+                    step_tiled<K, T>(s, s->fuse, 0.0, launches);  // first launches: code and caches warm
                     DGT_HIP(hipEventRecord(s->ev0, st));
-                    step_tiled<K, T>(s, p->trial_steps, s->p.dt, launches);
+                    step_tiled<K, T>(s, (int64_t)p->trial_steps * s->fuse, s->p.dt * s->fuse, launches);
                     DGT_HIP(hipEventRecord(s->ev1, st));
                 });
                 DGT_HIP(hipGetLastError());
@@ -1326,7 +1346,7 @@ dgt_status dgt_solver_autotune(dgt_solver *s, const dgt_autotune_params *p, dgt_
                 DGT_HIP(hipEventElapsedTime(&ms, s->ev0, s->ev1));
                 check_graphs(s);
                 ++timed;
-                const double per = ms / p->trial_steps;
+                const double per = ms / ((double)p->trial_steps * s->fuse);
                 if (per < best_ms) {
                     best_ms = per;
                     best_ts = c.ts;
@@ -1468,6 +1488,8 @@ dgt_status dgt_step(dgt_solver *s, int64_t nsteps, int32_t mode, double t0) {
         DGT_REQUIRE(s->state_valid, DGT_ESTATE, "state not uploaded");
         DGT_REQUIRE(mode == 0 || mode == 1, DGT_EINVAL, "mode must be 0 or 1");
         DGT_REQUIRE(mode == 0 || s->plan_status == DGT_OK, s->plan_status, s->plan_error);
+        DGT_REQUIRE(mode == 0 || nsteps % s->fuse == 0, DGT_EINVAL,
+                    "a chain fused over several steps runs a multiple of that many steps");
         if (mode == 1) prepare_tiled(s);
         int64_t launches = 0;
         s->npev = 0;
@@ -1574,6 +1596,24 @@ dgt_status dgt_solver_info(const dgt_solver *s, int64_t *np, int64_t *bytes_per_
         size_t mx = 0;
         for (auto &P : s->plan) mx = std::max(mx, P.lds_bytes);
         if (lds_bytes) *lds_bytes = (int64_t)mx;
+    });
+}
+
+dgt_status dgt_solver_fuse_steps(dgt_solver *s, int32_t steps) {
+    return guard([&] {
+        DGT_REQUIRE(s, DGT_EINVAL, "NULL solver");
+        DGT_REQUIRE(steps >= 1 && steps * loops_per_step(s->p.time_order) <= kMaxLoops, DGT_EINVAL,
+                    "steps must be >= 1 with at most 64 loops in the chain");
+        s->fuse = steps;
+        build_loops(s);
+        // the old schedule and plan describe another chain
+        s->inspected = false;
+        ++s->gen;
+        delete s->sched;
+        s->sched = nullptr;
+        s->plan.clear();
+        s->plan_status = DGT_ESTATE;
+        s->plan_error = "tiled mode needs dgt_solver_inspect after dgt_solver_fuse_steps";
     });
 }
 

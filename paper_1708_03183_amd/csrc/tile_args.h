@@ -10,6 +10,7 @@ struct TLoop {
     int8_t kind, in, out, pen;
     int8_t partner;  // exterior loop fused into this interior loop, or -1
     int8_t grp;      // neighbour table of a facet loop, or -1
+    int8_t step;     // time step of the loop counted from the sub-chain's first (fused chains)
     float scale_f, pscale_f;
     double scale_d, pscale_d;
 };
@@ -43,6 +44,7 @@ struct TileArgs {
     int64_t fshot[F_COUNT];     // elements between two shots' copies of a field
     const int32_t *src_cells;   // [nshots] exec id of each shot's source cell, or -1
     double dt, src_amp;         // src_amp = dt * r(t^{n+1/2}), the same wavelet for every shot
+    double src_amps[4];         // the same for the sub-chain's steps n, n+1, ... (chains fused over steps)
     const void *src_vec;        // [nshots][Np] inverse mass times the basis at each source
     // dependence-driven schedule (chain kernel): one launch per sub-chain; workgroups take
     // tiles in colour order from a ticket counter, and a tile starts once every

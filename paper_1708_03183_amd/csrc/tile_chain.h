@@ -27,7 +27,14 @@ struct OpDesc {
     int part;     // field added with weight dt by the fourth-order update, or -1
 };
 
+// operators and loops of one step; a chain fused over several steps numbers its
+// operators on across the steps (operator o is operator o mod ops_per_step of step
+// o / ops_per_step)
+__host__ __device__ constexpr int ops_per_step(int order) { return order == 4 ? 6 : 2; }
+__host__ __device__ constexpr int loops_per_step(int order) { return order == 4 ? 26 : 8; }
+
 __host__ __device__ constexpr OpDesc op_desc(int order, int o) {
+    o %= ops_per_step(order);
     if (order == 2)
         return o == 0 ? OpDesc{true, F_S, F_Z, F_V, 2, -1} : OpDesc{false, F_V, F_Z, F_S, 2, -1};
     switch (o) {
@@ -44,7 +51,8 @@ __host__ __device__ constexpr OpDesc op_desc(int order, int o) {
 // interior facets, exterior facets, then a solve at order 4; updates after
 // operators 2 and 5 at order 4, after both at order 2)
 __host__ __device__ constexpr int op_first_loop(int order, int o) {
-    return order == 2 ? 4 * o : 4 * o + (o >= 3 ? 1 : 0);
+    const int st = o / ops_per_step(order), q = o % ops_per_step(order);
+    return st * loops_per_step(order) + (order == 2 ? 4 * q : 4 * q + (q >= 3 ? 1 : 0));
 }
 
 __host__ __device__ constexpr int op_upd_loop(int order, int o) { return op_first_loop(order, o) + (order == 2 ? 3 : 4); }
@@ -349,7 +357,13 @@ __device__ __forceinline__ void chain_op(const RefC<K, T> &Rf, CellRegs<K, T> &r
                 for (int i = 0; i < NP; ++i) {
                     T add = o[c][i];
                     if constexpr (D.upd == 1) add = dt * r.f[D.part < 0 ? 0 : D.part][c][i] + add;
-                    if (src && c < 2) add += amp * sv[i];
+                    // amp is the source amplitude of the sub-chain's first step; an operator of
+                    // a later step of a fused chain takes its own step's
+                    if constexpr (O / ops_per_step(ORDER) == 0) {
+                        if (src && c < 2) add += amp * sv[i];
+                    } else {
+                        if (src && c < 2) add += (T)a.src_amps[O / ops_per_step(ORDER)] * sv[i];
+                    }
                     q[c][i] += add;
                 }
         }

@@ -10,9 +10,12 @@ namespace dgt {
 
 enum TileKernel { TK_GENERIC = 0, TK_CHAIN = 1, TK_MFMA = 2 };
 
-// operator sequences the chain kernel is built for: (time order, first operator, operators)
-constexpr int TILE_CHAINS[12][3] = {{4, 0, 3}, {4, 3, 3}, {4, 0, 6}, {2, 0, 2}, {4, 0, 1}, {4, 1, 1},
-                                    {4, 2, 1}, {4, 3, 1}, {4, 4, 1}, {4, 5, 1}, {2, 0, 1}, {2, 1, 1}};
+// operator sequences the chain kernel is built for: (time order, first operator, operators);
+// operators past the step's last belong to the next step of a chain fused over steps: two
+// whole second-order steps, and the stress half of a fourth-order step with the velocity
+// half of the next
+constexpr int TILE_CHAINS[14][3] = {{4, 0, 3}, {4, 3, 3}, {4, 0, 6}, {2, 0, 2}, {4, 0, 1}, {4, 1, 1}, {4, 2, 1},
+                                    {4, 3, 1}, {4, 4, 1}, {4, 5, 1}, {2, 0, 1}, {2, 1, 1}, {2, 0, 4}, {4, 3, 6}};
 
 // Multi-operator chains hold every field of a cell in registers; from P3 on they
 // no longer fit (spills, one wave per SIMD), so only single operators are built.

@@ -288,7 +288,7 @@ __global__ __launch_bounds__(NT) void k_tile(const TileArgs a) {
                 for (int ii = 0; ii < NPG; ++ii) {
                     const int i = g * NPG + ii;
                     if (NG > 1 && i >= NP) break;
-                    const T sa = src ? (T)a.src_amp * sv[i] : T(0);
+                    const T sa = src ? (T)a.src_amps[L.step] * sv[i] : T(0);
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
                         Sg[c * NP + i] += (o4 ? dt * X[c * NP + i] : T(0)) + Z[c * NP + i] + (c < 2 ? sa : T(0));

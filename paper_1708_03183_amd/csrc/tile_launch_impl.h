@@ -37,6 +37,8 @@ static void tile_launch_chain(bool upw, int order, int o0, int nops, int grid, s
         if (order == 4 && o0 == 3 && nops == 3) return pick.template operator()<4, 3, 3>();
         if (order == 4 && o0 == 0 && nops == 6) return pick.template operator()<4, 0, 6>();
         if (order == 2 && o0 == 0 && nops == 2) return pick.template operator()<2, 0, 2>();
+        if (order == 2 && o0 == 0 && nops == 4) return pick.template operator()<2, 0, 4>();
+        if (order == 4 && o0 == 3 && nops == 6) return pick.template operator()<4, 3, 6>();
     }
     if (order == 4 && nops == 1 && o0 == 0) pick.template operator()<4, 0, 1>();
     else if (order == 4 && nops == 1 && o0 == 1) pick.template operator()<4, 1, 1>();

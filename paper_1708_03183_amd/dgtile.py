@@ -86,6 +86,7 @@ _SIGS = {
     "dgt_mesh_destroy": [_p],
     "dgt_solver_create": [_p, _p, _p, _p, C.POINTER(_SolverParams), _p, C.POINTER(_p)],
     "dgt_solver_inspect": [_p, C.POINTER(_InspectParams)],
+    "dgt_solver_fuse_steps": [_p, C.c_int32],
     "dgt_solver_schedule": [_p, C.POINTER(_p)],
     "dgt_set_source": [_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double],
     "dgt_solver_set_shots": [_p, C.c_int32, _p, C.c_double, C.c_double, C.c_double],
@@ -418,7 +419,7 @@ class Solver:
         m = self.mesh
         sizes = {0: m.nc, 1: m.nf, 2: m.nb}
         nl = 26 if self._order() == 4 else 8
-        pat = ([0, 1, 2, 0] * 3 + [0]) * 2 if nl == 26 else [0, 1, 2, 0] * 2
+        pat = (([0, 1, 2, 0] * 3 + [0]) * 2 if nl == 26 else [0, 1, 2, 0] * 2) * getattr(self, "_fuse", 1)
         return Schedule(h, owner=False, loop_sizes=[sizes[s] for s in pat])
 
     def _order(self):
@@ -450,6 +451,11 @@ class Solver:
 
     def step(self, nsteps: int, mode: int = 1, t0: float = 0.0):
         _check(lib().dgt_step(self.h, int(nsteps), int(mode), float(t0)))
+
+    def fuse_steps(self, steps: int):
+        """Hand the inspector a chain of `steps` consecutive time steps (inspect again after)."""
+        _check(lib().dgt_solver_fuse_steps(self.h, int(steps)))
+        self._fuse = int(steps)
 
     def cell_list(self, cells) -> "CellList":
         return CellList(self, cells)

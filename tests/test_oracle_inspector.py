@@ -330,3 +330,31 @@ def test_hilbert_curve_is_continuous_at_order4():
     assert walk[0] == (0, 0) and walk[-1] == (15, 0)
     steps = [abs(a[0] - b[0]) + abs(a[1] - b[1]) for a, b in zip(walk, walk[1:])]
     assert steps == [1] * 255
+
+
+@pytest.mark.parametrize("order,steps,splits,k", [(2, 2, (), 1), (2, 3, (), 2), (2, 2, (4, 12), 1),
+                                                  (4, 2, (13, 39), 1), (4, 2, (13, 26, 39), 2)])
+def test_chain_fused_over_steps(order, steps, splits, k):
+    """A chain of several time steps (the step's loops repeated) tiled in one pass per
+    sub-chain: the schedule is legal, the integer-instrumented chain is bit-identical
+    tiled and untiled, and the tiled DG run (F steps per pass, each loop at its own
+    step's time) equals the untiled one to rounding."""
+    m, om, d = _dg(11, k=k, order=order, flux=1, free=0x8, ren=5)
+    d.set_source(0.43, 0.52)
+    ch = d.chain(steps)
+    assert ch.nloops == steps * d.chain().nloops
+    s = ch.inspect(9, partition=1, seed_xy=m.centroids(), splits=splits)
+    assert s.check() == 0
+    assert ch.instrumented(None) == ch.instrumented(s)
+    v, sg = d.zeros()
+    v[:] = I.random_state(v.shape, 3)
+    sg[:] = I.random_state(sg.shape, 4)
+    v2, s2 = v.copy(), sg.copy()
+    n = 2 * steps
+    d.step(v, sg, n, t0=0.1)
+    d.step_tiled(s, v2, s2, n, t0=0.1)
+    err = max(np.abs(v - v2).max(), np.abs(sg - s2).max()) / max(np.abs(v).max(), np.abs(sg).max())
+    print(f"order {order}, {steps} steps per chain, splits {splits}: tiled vs untiled {err:.2e}")
+    assert err <= 1e-14
+    with pytest.raises(ValueError):  # not a multiple of the fused steps
+        d.step_tiled(s, v2, s2, steps + 1, t0=0.0)
