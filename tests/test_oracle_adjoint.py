@@ -128,3 +128,83 @@ def test_misfit_vanishes_on_its_own_traces():
     assert O.fwi_misfit(mk(lam, mu, rho), RECS, SHOTS, 12, own, f0=8.0, t0=0.05) == 0.0
     e = np.random.default_rng(1).standard_normal(own.shape)
     assert abs(O.fwi_misfit(mk(lam, mu, rho), RECS, SHOTS, 12, own + e, f0=8.0, t0=0.05) - 0.5 * (e ** 2).sum()) <= 1e-12
+
+
+def _rate_blocks(d, npk, nc):
+    """Dense blocks of the semi-discrete operator u' = L u: dv = A s + Dv v, ds = B v + Ds s."""
+    nv, ns = 2 * npk * nc, 3 * npk * nc
+    L = np.zeros((nv + ns, nv + ns))
+    for j in range(nv + ns):
+        x = np.zeros(nv + ns)
+        x[j] = 1.0
+        dv, ds = d.rate(x[:nv].reshape(2, npk, nc), x[nv:].reshape(3, npk, nc))
+        L[:, j] = np.concatenate([dv.ravel(), ds.ravel()])
+    return L[:nv, nv:], L[nv:, :nv], L[:nv, :nv], L[nv:, nv:]
+
+
+@pytest.mark.parametrize("k,order,free", [(1, 4, 0x8), (2, 4, 0x0), (1, 2, 0xF), (2, 2, 0x5)])
+def test_upwind_adjoint_structure(k, order, free):
+    """Upwind flux (exact Riemann states at impedance jumps), free and absorbing sides.
+    In the energy inner product W = blockdiag(rho M_J, M_J C^-1) the operator parts are
+    skew (W_v A = -(W_s B)^T) and the penalties self-adjoint and dissipative (W_v Dv,
+    W_s Ds symmetric, negative semidefinite).  The oracle's step is
+    S2 S1 with S1 = [[I + dt Dv, dt A + c A B A], [0, I]] and
+    S2 = [[I, 0], [dt B + c B A B, I + dt Ds]] (c = dt^3/24 at order 4, else 0), so in the
+    variables alpha = W^-1 lambda its transpose is
+    [[I + dt Dv, 0], [-(dt B + c B A B), I]] [[I, -(dt A + c A B A)], [0, I + dt Ds]]:
+    the operators with -dt, the penalties with +dt, each penalty acting in the other
+    half step than in the forward step."""
+    m = I.square_mesh(3, jitter=0.2, renumber_seed=3)
+    lam, mu, rho = _material(m, seed=4)
+    lam, mu, rho = lam * np.where(np.arange(m.nc) % 3 == 0, 4.0, 1.0), mu, rho * np.where(np.arange(m.nc) % 2, 3.0, 1.0)
+    om = O.OMesh.from_mesh(m)
+    dt = O.cfl_dt(om, k, lam, mu, rho)
+    npk, nc = O.np_of(k), om.nc
+    d = O.ODG(om, k, lam, mu, rho, flux=1, order=order, dt=dt, free_sides=free)
+    A, B, Dv, Ds = _rate_blocks(d, npk, nc)
+    T = _T(om, k, lam, mu, rho)
+    W = np.linalg.inv(T)
+    nv = 2 * npk * nc
+    Wv, Ws = W[:nv, :nv], W[nv:, nv:]
+    scale = max(np.abs(Wv @ A).max(), 1e-300)
+    skew = np.abs(Wv @ A + (Ws @ B).T).max() / scale
+    sv = Wv @ Dv
+    ss = Ws @ Ds
+    symv = np.abs(sv - sv.T).max() / max(np.abs(sv).max(), 1e-300)
+    syms = np.abs(ss - ss.T).max() / max(np.abs(ss).max(), 1e-300)
+    ev = np.linalg.eigvalsh(0.5 * (sv + sv.T)).max() / np.abs(sv).max()
+    es = np.linalg.eigvalsh(0.5 * (ss + ss.T)).max() / np.abs(ss).max()
+    print(f"k={k} order={order} free={free:#x}: skew {skew:.1e}, sym {symv:.1e} / {syms:.1e}, "
+          f"largest eigenvalue / scale {ev:.1e} / {es:.1e}")
+    assert skew <= 1e-13 and symv <= 1e-13 and syms <= 1e-13
+    assert ev <= 1e-13 and es <= 1e-13
+    assert np.abs(sv).max() > 0 and np.abs(ss).max() > 0  # the penalties are on
+    # the step from the blocks, and its transpose in closed form
+    c = dt ** 3 / 24.0 if order == 4 else 0.0
+    ns = 3 * npk * nc
+    Iv, Is = np.eye(nv), np.eye(ns)
+    Z = np.zeros((nv, ns))
+    S1 = np.block([[Iv + dt * Dv, dt * A + c * A @ B @ A], [Z.T, Is]])
+    S2 = np.block([[Iv, Z], [dt * B + c * B @ A @ B, Is + dt * Ds]])
+    F = _step_matrix_flux(om, k, lam, mu, rho, order, dt, free, 1)
+    err_step = np.abs(F - S2 @ S1).max() / np.abs(F).max()
+    Sa = np.block([[Iv, -(dt * A + c * A @ B @ A)], [Z.T, Is + dt * Ds]])
+    Sb = np.block([[Iv + dt * Dv, Z], [-(dt * B + c * B @ A @ B), Is]])
+    err_adj = np.abs(T @ F.T @ W - Sb @ Sa).max() / np.abs(F).max()
+    print(f"  step vs blocks {err_step:.1e}, transpose vs closed form {err_adj:.1e}")
+    assert err_step <= 1e-13 and err_adj <= 1e-12
+
+
+def _step_matrix_flux(om, k, lam, mu, rho, order, dt, free, flux):
+    d = O.ODG(om, k, lam, mu, rho, flux=flux, order=order, dt=dt, free_sides=free)
+    npk, nc = O.np_of(k), om.nc
+    N = 5 * npk * nc
+    F = np.zeros((N, N))
+    for j in range(N):
+        x = np.zeros(N)
+        x[j] = 1.0
+        v = x[:2 * npk * nc].reshape(2, npk, nc).copy()
+        s = x[2 * npk * nc:].reshape(3, npk, nc).copy()
+        d.step(v, s, 1, t0=0.0)
+        F[:, j] = np.concatenate([v.ravel(), s.ravel()])
+    return F
