@@ -61,6 +61,9 @@ def parse():
                          "mesh (P2, FP32 state, FP64 gradient)")
     ap.add_argument("--fwi-steps", type=int, default=2000)
     ap.add_argument("--fwi-snapshots", type=int, default=32)
+    ap.add_argument("--fwi-boundaries", choices=["absorbing", "free"], default="absorbing",
+                    help="fwi: upwind flux with a free top and absorbing other sides (closed-form transposed "
+                         "step), or central flux with free surfaces everywhere (the reversed chain)")
     ap.add_argument("--shots", type=int, default=64)
     ap.add_argument("--graph-steps", type=int, default=10,
                     help="batched workload: steps per HIP graph of the one-launch batch")
@@ -676,10 +679,11 @@ def fwi(a):
     """Full-waveform-inversion gradient: 256x256 jittered renumbered mesh (131,072
     cells), DG P2, 16 Ricker shots at seeded positions just below the top edge, 128
     velocity receivers along the top edge, observed data from the 3-layer true model, gradient at a
-    homogeneous starting model (the true model's means), central flux and free
-    surfaces (the discretisation whose adjoint is the reversed chain), order-4
-    leapfrog, FP32 state, FP64 gradient, 32 checkpoints, tiled executor (tile size and
-    schedule by the autotuner).  Reports the wall time of one gradient, of one
+    homogeneous starting model (the true model's means), upwind flux with a free top and
+    absorbing other sides (the closed-form transposed step; --fwi-boundaries free: the
+    central flux with free surfaces everywhere, whose transposed step is the reversed
+    chain), order-4 leapfrog, FP32 state, FP64 gradient, 32 checkpoints, tiled forward
+    executor (tile size and schedule by the autotuner).  Reports the wall time of one gradient, of one
     forward run of the same shots, and the FP32 gradient's difference from an FP64
     gradient of the first shot alone."""
     import numpy as np
@@ -703,8 +707,11 @@ def fwi(a):
     gm = D.Mesh.from_mesh(m)
     npk = (k + 1) * (k + 2) // 2
 
+    absorbing = a.fwi_boundaries == "absorbing"
+    flux, free = (1, 0x8) if absorbing else (0, 0xF)
+
     def make(lam, mu, rho, prec, ns=nshots, tune=True):
-        s = D.Solver(gm, lam, mu, rho, degree=k, flux=0, time_order=4, precision=prec, free_sides=0xF, dt=dt)
+        s = D.Solver(gm, lam, mu, rho, degree=k, flux=flux, time_order=4, precision=prec, free_sides=free, dt=dt)
         s.set_shots(ns, shots[:ns], f0, t0, 1.0)
         if tune:
             r = s.autotune((64, 128, 256, 512), splits=(13,), partition=1, trial_steps=3)
@@ -761,7 +768,9 @@ def fwi(a):
         "config": {"workload": f"fwi256_p2: {n}x{n} jittered renumbered triangulation, {m.nc} cells, DG P2, "
                                f"{nshots} shots at y in [0.96, 0.99] (Ricker f0 = {f0}, t0 = {t0}), {nrec} receivers at y = 1, "
                                f"3-layer true model, homogeneous start, "
-                               f"central flux, free surfaces, order-4 leapfrog",
+                               + ("upwind flux, free top, absorbing other sides" if absorbing
+                                  else "central flux, free surfaces")
+                               + ", order-4 leapfrog",
                    "cells": m.nc, "shots": nshots, "receivers": nrec, "snapshots": nsnap,
                    "dofs_per_step_all_shots": 5 * npk * m.nc * nshots, "tuned": tuned},
         "forward_s": t_fwd,

@@ -352,12 +352,16 @@ dgt_status dgt_fwi_forward(dgt_solver *s, const dgt_fwi_params *p, double *trace
  * (device, layout of dgt_fwi_forward) and its gradient with respect to each
  * cell's lambda, mu, rho: g_lam, g_mu, g_rho device [nc] FP64 in the mesh's cell
  * numbering, caller-owned, summed over the shots.  Discrete adjoint of the
- * time-stepped chain: the reversed chain runs the same loops with -dt on a
- * second solver (same inspection and schedule); forward states are recomputed
- * from nsnap checkpoints by a binomial reversal schedule; the per-cell terms are
- * accumulated in FP64.  EUNSUPPORTED unless the flux is central and every
- * exterior facet is a free surface (or the mesh is periodic): the adjoint is the
- * reversed step only for that energy-conserving discretisation.  *misfit host. */
+ * time-stepped chain; forward states are recomputed from nsnap checkpoints by a
+ * binomial reversal schedule; the per-cell terms are accumulated in FP64.  With
+ * the central flux and free or periodic boundaries the
+ * transposed step is the reversed chain (-dt) on a second solver (same inspection
+ * and schedule); with the upwind
+ * flux or absorbing sides it is the closed form of the transposed step in the energy
+ * inner product (operator parts skew, penalties self-adjoint: the operators run with
+ * -dt and the penalties with +dt, each penalty in the other half step), built from
+ * untiled operator applications, and the gradient adds the derivatives of the flux
+ * weights with respect to the impedances of both cells of every facet.  *misfit host. */
 dgt_status dgt_fwi_gradient(dgt_solver *s, const dgt_fwi_params *p, const double *observed, double *misfit,
                             double *g_lam, double *g_mu, double *g_rho);
 /* Schedule of the tiled executor (default 0).  0: one kernel launch per colour

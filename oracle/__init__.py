@@ -466,6 +466,29 @@ def fwi_misfit(od: ODG, rec_xy, shots_xy, nsteps, observed, f0=5.0, t0=0.2, amp=
 
 
 
+def fwi_gradient_fd(make, lam, mu, rho, rec_xy, shots_xy, nsteps, observed, f0=5.0, t0=0.2, amp=1.0, h=1e-3):
+    """The misfit's gradient with respect to each cell's lam, mu, rho by its definition:
+    central differences of J in one parameter at a time (relative steps h and h/2),
+    Richardson-extrapolated (truncation error O(h^4)).  make(lam, mu, rho) -> ODG with a
+    fixed time step.  Any flux and boundaries; slow (4 misfits per parameter)."""
+    base = [np.array(lam, np.float64), np.array(mu, np.float64), np.array(rho, np.float64)]
+    nc = base[0].size
+    g = np.zeros((3, nc))
+
+    def J(p, c, eps):
+        m = [x.copy() for x in base]
+        m[p][c] *= 1.0 + eps
+        return fwi_misfit(make(*m), rec_xy, shots_xy, nsteps, observed, f0, t0, amp)
+
+    for p in range(3):
+        for c in range(nc):
+            step = h * base[p][c]
+            d1 = (J(p, c, h) - J(p, c, -h)) / (2.0 * step)
+            d2 = (J(p, c, 0.5 * h) - J(p, c, -0.5 * h)) / step
+            g[p, c] = (4.0 * d2 - d1) / 3.0
+    return g
+
+
 def fwi_gradient_adjoint(od: ODG, od_rev: ODG, order, rec_xy, shots_xy, nsteps, observed, f0=5.0, t0=0.2, amp=1.0):
     """Misfit and its gradient (g_lam, g_mu, g_rho per cell) by the discrete adjoint,
     storing every forward state.  Valid for the central flux with free-surface or

@@ -28,6 +28,8 @@
 // Forward states are recomputed from checkpoints by a binomial (revolve-style)
 // reversal schedule.
 
+#include "fwi_upwind.h"
+
 namespace dgt {
 
 // receiver r at step n of shot q: out[((q * nsteps + n) * nrec + r) * 2 + c]
@@ -285,6 +287,124 @@ struct FwiRun {
     std::vector<DBuf<char>> snap;
     DBuf<T> U, Xp, Zs, V1, X1, Y, V2s, W, Wp, tV, tS, As;
     DBuf<double> res, g, part;
+    // upwind flux or absorbing sides: the closed-form transposed step (fwi_upwind.h)
+    bool upw = false;
+    FacetMass m1{};
+    DBuf<T> fU1, fX1, fZ1, fPV, fV1, fX2, fU2, fZ2, fPS;  // forward intermediates of a step
+    DBuf<T> aA, aBA, aABA, aPS, aMu, aB, aAB, aBAB, aPV;  // adjoint-side vectors
+    DBuf<double> fb, eb;                                  // facet parts per facet, side and shot
+
+    void alloc_upwind() {
+        const size_t nv = (size_t)vsh * S, ns = (size_t)ssh * S;
+        for (auto *b : {&fU1, &fZ1, &fPV, &fV1, &fU2, &aA, &aABA, &aMu, &aAB, &aPV}) b->alloc(nv);
+        for (auto *b : {&fX1, &fX2, &fZ2, &fPS, &aBA, &aPS, &aB, &aBAB}) b->alloc(ns);
+        fb.alloc((size_t)S * std::max<int64_t>(f->nf, 1) * 6);
+        eb.alloc((size_t)S * std::max<int64_t>(f->nb, 1) * 3);
+        DGT_HIP(hipMemsetAsync(fb.p, 0, fb.n * sizeof(double), f->st));
+        DGT_HIP(hipMemsetAsync(eb.p, 0, eb.n * sizeof(double), f->st));
+        const int nfp = K + 1;
+        for (int i = 0; i < nfp * nfp; ++i) m1.m[i] = f->E.M1[i];
+    }
+    // one term coef * a^T W dOp b (ob = Op b): cell part, and the facet part when the
+    // flux weights of Op depend on the impedances
+    template <int KIND>
+    void pair(const T *a_, const T *b_, const T *ob, double coef) {
+        hipStream_t st = f->st;
+        const int64_t nc = f->nc, nf = f->nf, nb = f->nb;
+        constexpr bool VEL = KIND == FK_A || KIND == FK_DV;  // kind of a and ob
+        const int64_t sh = VEL ? vsh : ssh;
+        const T *geo = (const T *)f->geo.p;
+        k_fwi_cell_pair<K, T, KIND><<<dim3(blocks_for(nc, 256), S), 256, 0, st>>>(a_, ob, sh, geo, nc, coef, part.p);
+        // interior facets weigh by the impedances with the upwind flux only; exterior ones
+        // only in the penalties (absorbing facets always, free surfaces with the upwind flux)
+        if (f->upw && nf) {
+            const int64_t bsh = (KIND == FK_A || KIND == FK_DS) ? ssh : vsh;
+            k_fwi_facet_pair<K, T, KIND><<<dim3(blocks_for(nf, 256), S), 256, 0, st>>>(
+                a_, b_, sh, bsh, f->ef2c.p, f->ef2l.p, geo, nc, nf, m1, coef, fb.p);
+        }
+        if ((KIND == FK_DV || KIND == FK_DS) && f->haspen && nb)
+            k_fwi_ext_pair<K, T, KIND><<<dim3(blocks_for(nb, 256), S), 256, 0, st>>>(
+                a_, b_, sh, f->eb2c.p, f->eb2l.p, geo, nc, nb, m1, coef, f->upw ? 1 : 0, eb.p);
+    }
+    // The reversal of step n with the upwind flux or absorbing sides: the forward state u_n
+    // is in f, alpha_{n+1} in a.  Forward: U1 = A s, X1 = B U1, Z1 = A X1, PV = Dv v,
+    // v' = v + dt U1 + c Z1 + dt PV, X2 = B v', U2 = A X2, Z2 = B U2, PS = Ds s.  Adjoint:
+    // mu = alpha_v - dt A alpha_s - c A B A alpha_s (the velocity part after the first
+    // transposed half).  Terms of the gradient, each coef * a^T W dOp b:
+    //   (alpha_s, v') B dt, (alpha_s, U2) B c, (A alpha_s, X2) A -c, (B A alpha_s, v') B c,
+    //   (alpha_s, s) Ds dt, (mu, s) A dt, (mu, X1) A c, (B mu, U1) B -c, (A B mu, s) A c,
+    //   (mu, v) Dv dt
+    // (from d(S2 S1) = dS2 S1 + S2 dS1 and W_v A = -(W_s B)^T).
+    void step_back_upw(int64_t n) {
+        hipStream_t st = f->st;
+        const bool o4 = f->p.time_order == 4;
+        const double dt = f->p.dt, c3 = o4 ? dt * dt * dt / 24.0 : 0.0;
+        int64_t launches = 0;
+        const int64_t nvS = vsh * S, nsS = ssh * S;
+        const T *v0 = (const T *)f->fld[F_V].p, *s0 = (const T *)f->fld[F_S].p;
+        T *av = (T *)a->fld[F_V].p, *as = (T *)a->fld[F_S].p;
+        auto vop = [&](const T *in, T *out) { apply_op<K, T>(f, true, in, out, 1.0, nullptr, 0.0, launches, S, ssh, vsh); };
+        auto sop = [&](const T *in, T *out) { apply_op<K, T>(f, false, in, out, 1.0, nullptr, 0.0, launches, S, vsh, ssh); };
+        // penalties alone: the operator part scaled by zero (its input only needs finite values)
+        auto vpen = [&](const T *pv, T *out) { apply_op<K, T>(f, true, s0, out, 0.0, pv, 1.0, launches, S, ssh, vsh, vsh); };
+        auto spen = [&](const T *ps, T *out) { apply_op<K, T>(f, false, v0, out, 0.0, ps, 1.0, launches, S, vsh, ssh, ssh); };
+        auto lin = [&](T *out, int64_t cnt, const T *x0, double c0, const T *x1, double c1, const T *x2, double c2,
+                       const T *x3, double c3_) {
+            k_fwi_lin<T><<<blocks_for(cnt, 256), 256, 0, st>>>(out, x0, c0, x1, c1, x2, c2, x3, c3_, cnt);
+        };
+        sample(n);
+        const bool pen = f->haspen;
+        // forward intermediates
+        vop(s0, fU1.p);
+        if (o4) {
+            sop(fU1.p, fX1.p);
+            vop(fX1.p, fZ1.p);
+        }
+        if (pen) vpen(v0, fPV.p);
+        lin(fV1.p, nvS, v0, 1.0, fU1.p, dt, o4 ? fZ1.p : nullptr, c3, pen ? fPV.p : nullptr, dt);
+        sop(fV1.p, fX2.p);
+        if (o4) {
+            vop(fX2.p, fU2.p);
+            sop(fU2.p, fZ2.p);
+        }
+        if (pen) spen(s0, fPS.p);
+        // adjoint-side vectors
+        vop(as, aA.p);
+        if (o4) {
+            sop(aA.p, aBA.p);
+            vop(aBA.p, aABA.p);
+        }
+        if (pen) spen(as, aPS.p);
+        lin(aMu.p, nvS, av, 1.0, aA.p, -dt, o4 ? aABA.p : nullptr, -c3, nullptr, 0.0);
+        sop(aMu.p, aB.p);
+        if (o4) {
+            vop(aB.p, aAB.p);
+            sop(aAB.p, aBAB.p);
+        }
+        if (pen) vpen(aMu.p, aPV.p);
+        // gradient terms of this step
+        DGT_HIP(hipMemsetAsync(part.p, 0, part.n * sizeof(double), st));
+        pair<FK_B>(as, fV1.p, fX2.p, dt);
+        pair<FK_A>(aMu.p, s0, fU1.p, dt);
+        if (o4) {
+            pair<FK_B>(as, fU2.p, fZ2.p, c3);
+            pair<FK_A>(aA.p, fX2.p, fU2.p, -c3);
+            pair<FK_B>(aBA.p, fV1.p, fX2.p, c3);
+            pair<FK_A>(aMu.p, fX1.p, fZ1.p, c3);
+            pair<FK_B>(aB.p, fU1.p, fX1.p, -c3);
+            pair<FK_A>(aAB.p, s0, fU1.p, c3);
+        }
+        if (pen) {
+            pair<FK_DS>(as, s0, fPS.p, dt);
+            pair<FK_DV>(aMu.p, v0, fPV.p, dt);
+        }
+        k_fwi_grad_sum<<<blocks_for(3 * f->nc, 256), 256, 0, st>>>(f->nc, S, part.p, g.p);
+        // the transposed step: alpha_s += dt Ds alpha_s - dt B mu - c B A B mu; alpha_v = mu + dt Dv mu
+        lin(as, nsS, as, 1.0, pen ? aPS.p : nullptr, dt, aB.p, -dt, o4 ? aBAB.p : nullptr, -c3);
+        lin(av, nvS, aMu.p, 1.0, pen ? aPV.p : nullptr, dt, nullptr, 0.0, nullptr, 0.0);
+        ++reversed;
+        add_residual(n);
+    }
 
     void store(int slot) {
         const size_t bv = (size_t)vsh * S * sizeof(T), bs = (size_t)ssh * S * sizeof(T);
@@ -356,6 +476,7 @@ struct FwiRun {
     }
     // the forward state u_n is in f, alpha_{n+1} in a
     void step_back(int64_t n) {
+        if (upw) return step_back_upw(n);
         hipStream_t st = f->st;
         const int64_t nc = f->nc;
         const bool o4 = f->p.time_order == 4;
@@ -513,8 +634,14 @@ dgt_status dgt_fwi_gradient(dgt_solver *s, const dgt_fwi_params *p, const double
         DGT_REQUIRE(s && p && observed && misfit && g_lam && g_mu && g_rho, DGT_EINVAL, "NULL argument");
         fwi_check(s, p);
         DGT_REQUIRE(p->nsnap >= 1, DGT_EINVAL, "nsnap must be >= 1");
-        DGT_REQUIRE(!s->upw && !s->haspen, DGT_EUNSUPPORTED,
-                    "the adjoint needs the central flux and free-surface or periodic boundaries");
+        // the reversed chain is the transposed step for the central flux with free or
+        // periodic boundaries; otherwise the closed-form transposed step of fwi_upwind.h
+        bool any_absorbing = false;
+        {
+            const auto bf = s->bfree.download(s->st, std::max<int64_t>(s->nb, 1));
+            for (int64_t b = 0; b < s->nb; ++b) any_absorbing |= bf[b] == 0;
+        }
+        const bool upw_path = s->upw || s->haspen || any_absorbing || std::getenv("DGT_FWI_CLOSED_FORM");
         FwiReceivers R;
         fwi_receivers(s, p->nrec, p->rec_xy, R);
         auto adj = fwi_adjoint_solver(s, s->mesh_handle);
@@ -546,7 +673,9 @@ dgt_status dgt_fwi_gradient(dgt_solver *s, const dgt_fwi_params *p, const double
             run.part.alloc((size_t)3 * nc * S);
             DGT_HIP(hipMemsetAsync(run.g.p, 0, 8 * 3 * nc, st));
             run.snap.resize(p->nsnap);
-            run.rec = run.recordable() && !std::getenv("DGT_FWI_UNTILED_INTERMEDIATES");
+            run.upw = upw_path;
+            if (run.upw) run.alloc_upwind();
+            run.rec = !run.upw && run.recordable() && !std::getenv("DGT_FWI_UNTILED_INTERMEDIATES");
             // forward sweep from rest: misfit; the start state is the first checkpoint
             for (int f = 0; f < F_COUNT; ++f) DGT_HIP(hipMemsetAsync(s->fld[f].p, 0, s->fld[f].n, st));
             run.store(0);
@@ -556,6 +685,9 @@ dgt_status dgt_fwi_gradient(dgt_solver *s, const dgt_fwi_params *p, const double
             for (int f = 0; f < F_COUNT; ++f) DGT_HIP(hipMemsetAsync(adj->fld[f].p, 0, adj->fld[f].n, st));
             run.inject(p->nsteps);
             run.reverse(0, p->nsteps, 0, p->nsnap - 1);
+            if (run.upw)
+                k_fwi_facet_gather<<<blocks_for(nc, 256), 256, 0, st>>>(s->c2f.p, run.fb.p, run.eb.p, nc, s->nf, s->nb,
+                                                                       S, run.g.p);
             // gradient into the mesh numbering
             for (int m = 0; m < 3; ++m)
                 k_permute_rows<double><<<blocks_for(nc, 256), 256, 0, st>>>(
