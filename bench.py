@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--no-config3", action="store_true",
                     help="skip the 1024x1024 P3/P4 FP32 extras of the default run")
     ap.add_argument("--config3-steps", type=int, default=100)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the tile-size sweep (256-4096 seeds)")
+    ap.add_argument("--sweep-steps", type=int, default=20)
     ap.add_argument("--no-part", action="store_true",
                     help="skip one GPU's region-aware share of the 1024x1024 P3 workload")
     ap.add_argument("--config3-horizon", type=int, default=500)
@@ -1024,6 +1026,19 @@ def main():
     if not a.no_config3 and a.n == 512 and k == 2:
         progress("config 3 extras (1024x1024 P3/P4 FP32)")
         out["config3"] = config3(a)
+    if not a.no_sweep and a.n == 512 and k == 2:
+        progress("tile sizes 256-4096 (working sets beyond the LDS in global memory)")
+        sweep = []
+        for ts_ in (256, 512, 1024, 2048, 4096):
+            s_ = make(prec)
+            s_.inspect(ts_, partition=1, splits=splits)
+            kinds = s_.kernels()
+            s_.set_schedule(1 if all(x in (1, 2) for x in kinds) else 0)
+            w_, tot_, _, _, _, _ = run(s_, 1, a.sweep_steps, 2)
+            sweep.append({"tile_size": ts_, "kernels": kinds, "ms_per_step": 1e3 * w_ / a.sweep_steps,
+                          "value": dofs / (w_ / a.sweep_steps)})
+            del s_
+        out["tile_size_sweep"] = sweep
     if not a.no_part and a.n == 512 and k == 2:
         progress("one GPU's share of the 1024x1024 P3 workload (regions, halo pack/unpack)")
         out["part_block"] = part_block(a)

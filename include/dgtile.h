@@ -46,7 +46,7 @@ typedef enum {
     DGT_ESTATE = 4,        /* call not valid in the object's state, or the
                               inspector exceeded max_conflict_rounds */
     DGT_EUNSUPPORTED = 5   /* valid request this build cannot run (e.g. a tile
-                              footprint larger than the LDS budget) */
+                              footprint beyond 16,383 cells) */
 } dgt_status;
 
 /* Message for the calling thread's last failing call (never NULL). */
@@ -219,9 +219,12 @@ dgt_status dgt_solver_create(const dgt_mesh *m, const double *lam, const double 
                              const dgt_solver_params *p, void *stream, dgt_solver **out);
 /* Inspect the solver's chain on the GPU (dgt_inspect; seed_xy is ignored and
  * the cell centroids are used) and build the executor plan: cells renumbered
- * into seed order, per-tile footprints in LDS slots and local maps.  When a
- * tile's footprint exceeds the LDS budget the schedule is still built and
- * returned, and dgt_step in tiled mode then fails with DGT_EUNSUPPORTED
+ * into seed order, per-tile footprints in LDS slots and local maps.  A tile whose
+ * working set exceeds the LDS runs on the generic tile kernel with that working set
+ * in a global scratch region per workgroup (it stays in L2 and the MALL while the
+ * tile runs; sized for the largest colour launch, allocated at the first tiled
+ * step).  A footprint beyond 16,383 cells cannot be addressed: the schedule is still
+ * built and returned, and dgt_step in tiled mode then fails with DGT_EUNSUPPORTED
  * (smaller tile_size or more splits needed).  Synchronises the stream. */
 dgt_status dgt_solver_inspect(dgt_solver *s, const dgt_inspect_params *p);
 /* Multi-step fusion (an extension of the paper's fusion schemes, which stay within
@@ -239,7 +242,7 @@ dgt_status dgt_solver_fuse_steps(dgt_solver *s, int32_t steps);
 /* Autotuner: picks the seed tile size (from tile_sizes) and the executor
  * schedule (0 or 1, see dgt_solver_set_schedule) by timing trial steps, and
  * leaves the solver inspected and scheduled with the fastest pair.  Each
- * candidate is inspected; those whose tiles exceed the LDS budget are skipped.
+ * candidate is inspected; those the tiled executor cannot run are skipped.
  * A footprint model orders the rest: the cells every tile gathers, summed over
  * tiles and sub-chains and divided by the mesh's cells (the data a step moves
  * per cell, larger for smaller tiles, in the spirit of the paper's estimates of
@@ -266,7 +269,7 @@ typedef struct {
     int32_t schedule;   /* chosen schedule */
     double ms_per_step; /* its trial time */
     int32_t timed;      /* (tile size, schedule) pairs timed */
-    int32_t skipped;    /* tile sizes not timed (LDS budget or model) */
+    int32_t skipped;    /* tile sizes not timed (not runnable, or the model) */
 } dgt_autotune_result;
 dgt_status dgt_solver_autotune(dgt_solver *s, const dgt_autotune_params *p, dgt_autotune_result *out);
 /* The schedule of the last dgt_solver_inspect (borrowed; NULL before). */
@@ -449,8 +452,9 @@ void dgt_batch_destroy(dgt_batch *b);
  * dgt_solver_inspect; *nsub = 0 before): 0 the generic in-LDS executor, 1 the
  * register-resident chain kernel (whole operator applications, one thread per
  * footprint cell), 2 the matrix-core kernel (whole operator applications at
- * degrees 3 and 4, per-cell contractions as 16x16x4 MFMA products).  kinds: host
- * [*nsub] or NULL.  The environment variable DGT_TILE_OP read at inspection
+ * degrees 3 and 4, per-cell contractions as 16x16x4 MFMA products), 3 the generic
+ * executor with its working set in global memory (tiles beyond the LDS).  kinds:
+ * host [*nsub] or NULL.  The environment variable DGT_TILE_OP read at inspection
  * selects 0 (generic everywhere) or 1 (the chain kernel where it is built) instead
  * of the default. */
 dgt_status dgt_solver_kernels(const dgt_solver *s, int32_t *nsub, int32_t *kinds);

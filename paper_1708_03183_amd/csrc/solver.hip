@@ -28,6 +28,8 @@ struct SubPlan {
     // last colour): colours [0, nexec_colors) hold the nexec tiles that run
     int tne = -1, nexec = 0, nexec_colors = 0;
     int step0 = 0;  // step of the first loop within a chain fused over steps
+    int64_t gmem_bytes = 0;  // working set per workgroup in global scratch (0: in LDS)
+    DBuf<char> gmem;         // the scratch of the largest colour launch
     DBuf<int32_t> efoot;
     DBuf<uint32_t> eacc;
     DBuf<uint32_t> lmap[31];
@@ -649,7 +651,10 @@ static void build_plan(dgt_solver *s) {
                 }
                 std::vector<std::array<int, 3>> regions;  // row offset, rows, free after op
                 int rows = 0;
-                for (int f = 0; f < F_COUNT; ++f) A.lds_row[f] = -1;
+                // laid out apart from the generic layout, which stays in force when this one
+                // does not fit
+                int mrow[F_COUNT];
+                for (int f = 0; f < F_COUNT; ++f) mrow[f] = -1;
                 for (int q = first_op; q < first_op + nops; ++q)
                     for (int f = 0; f < F_COUNT; ++f) {
                         if (!res[f] || first[f] != q) continue;
@@ -663,7 +668,7 @@ static void build_plan(dgt_solver *s) {
                             pick = (int)regions.size() - 1;
                         }
                         regions[pick][2] = last[f];
-                        A.lds_row[f] = regions[pick][0] * S16;
+                        mrow[f] = regions[pick][0] * S16;
                     }
                 // fields, geometry and facet normals, loop bits, cell ids, flags, neighbour tables
                 const size_t bytes = (size_t)(rows + G_NROWS + 9) * S16 * s->esz + (size_t)S16 * (4 + 4 + 2) +
@@ -671,6 +676,7 @@ static void build_plan(dgt_solver *s) {
                 // the kernel addresses a field's component-node rows with 32-bit offsets
                 const bool fits32 = (uint64_t)s->nc * 3 * np < (uint64_t)UINT32_MAX;
                 if (bytes <= budget && fits32) {
+                    for (int f = 0; f < F_COUNT; ++f) A.lds_row[f] = mrow[f];
                     A.stride = S16;
                     A.nrow = rows * S16;  // geometry rows start here
                     P.kind = TK_MFMA;
@@ -696,14 +702,20 @@ static void build_plan(dgt_solver *s) {
                 }
             }
         }
-        DGT_REQUIRE(P.lds_bytes <= budget, DGT_EUNSUPPORTED,
-                    "tile footprint of " + std::to_string(P.max_foot) + " cells needs " +
-                        std::to_string(P.lds_bytes) + " B of LDS (budget " + std::to_string(budget) +
-                        "): use a smaller tile_size or split the chain");
+        // a tile whose working set exceeds the LDS runs on the generic kernel with the same
+        // working set in a global scratch region per workgroup (L2 / MALL resident)
+        P.gmem_bytes = 0;
+        if (P.lds_bytes > budget) {
+            DGT_REQUIRE(P.kind == TK_GENERIC, DGT_ESTATE, "a specialised tile kernel exceeds the LDS budget");
+            P.gmem_bytes = (int64_t)((P.lds_bytes + 255) / 256 * 256);
+            P.lds_bytes = 0;
+            A.scratch_bytes = P.gmem_bytes;
+        }
         // one work item per footprint slot (and node group of the generic kernel)
         const int ng = P.kind == TK_CHAIN || s->K <= 2 ? 1 : (s->K == 3 ? 2 : 3);
         const int items = A.stride * ng;
         P.threads = items <= TILE_NT[0] ? TILE_NT[0] : (items <= TILE_NT[1] ? TILE_NT[1] : TILE_NT[2]);
+        if (P.gmem_bytes) P.threads = TILE_NT[2];
         if (P.kind == TK_MFMA) P.threads = MFMA_NT;
         if (const char *e = std::getenv("DGT_TILE_THREADS"); e && P.kind == TK_GENERIC) P.threads = std::atoi(e);
     }
@@ -931,6 +943,13 @@ static void step_tiled(dgt_solver *s, int64_t nsteps, double t0, int64_t &launch
                 ++launches;
                 if (after) (*after)(b);
                 continue;
+            }
+            if (P.gmem_bytes) {  // one working set per workgroup of the largest colour launch
+                int most = 0;
+                for (int c = 0; c < P.nexec_colors; ++c) most = std::max(most, P.color_off[c + 1] - P.color_off[c]);
+                const size_t need = (size_t)most * s->nshots * (size_t)P.gmem_bytes;
+                if (P.gmem.n < need) P.gmem.alloc(need);
+                A.scratch = P.gmem.p;
             }
             for (int c = 0; c < P.nexec_colors; ++c) {
                 const int ntiles = P.color_off[c + 1] - P.color_off[c];
@@ -1223,8 +1242,8 @@ static void solver_inspect_once(dgt_solver *s, const dgt_inspect_params *p, int 
     // executor layout follows the seed order of the schedule
     auto rank = s->sched->s->seed_rank.download(st, s->nc);
     set_exec_order(s, rank);
-    // the schedule stays valid when its tiles do not fit the LDS budget;
-    // only the tiled executor is then unavailable
+    // the schedule stays valid when the tiled executor cannot run its tiles
+    // (footprints beyond 16,383 cells); only the tiled executor is then unavailable
     try {
         build_plan(s);
         s->plan_status = DGT_OK;
@@ -1315,7 +1334,7 @@ dgt_status dgt_solver_autotune(dgt_solver *s, const dgt_autotune_params *p, dgt_
             for (const auto &sb : s->sched->s->sub) f += (double)sb.foot_len[0];
             cands.push_back({p->tile_sizes[i], f / (double)s->nc});
         }
-        DGT_REQUIRE(!cands.empty(), DGT_EUNSUPPORTED, "no candidate tile size fits the LDS budget");
+        DGT_REQUIRE(!cands.empty(), DGT_EUNSUPPORTED, "no candidate tile size has tiles the executor can run");
         std::stable_sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.foot < b.foot; });
         double best_ms = 1e300;
         int best_ts = cands[0].ts, best_sched = 0;
@@ -1624,7 +1643,7 @@ dgt_status dgt_solver_kernels(const dgt_solver *s, int32_t *nsub, int32_t *kinds
         DGT_REQUIRE(s && nsub, DGT_EINVAL, "NULL argument");
         *nsub = (int32_t)s->plan.size();
         if (kinds)
-            for (size_t b = 0; b < s->plan.size(); ++b) kinds[b] = (int32_t)s->plan[b].kind;
+            for (size_t b = 0; b < s->plan.size(); ++b) kinds[b] = s->plan[b].gmem_bytes ? 3 : (int32_t)s->plan[b].kind;
     });
 }
 

@@ -37,6 +37,8 @@ struct TileArgs {
     int32_t nrow;              // LDS elements per slot (odd), geometry in the last G_NROWS
     int32_t stride;            // slot capacity (largest footprint of the sub-chain)
     int32_t nfl;               // facet loops with a neighbour table
+    void *scratch;             // generic kernel with tiles beyond the LDS: per-workgroup working sets
+    int64_t scratch_bytes;     // bytes of one working set (a multiple of 256)
     // shots: independent states on the same mesh; a work item is a (tile, shot) pair,
     // item i taking tile i / nshots and shot i % nshots, so consecutive workgroups share
     // a tile's metadata and geometry

@@ -40,12 +40,18 @@ __device__ __forceinline__ void stage_field(T *__restrict__ row, const TileArgs 
     }
 }
 
-template <int K, typename T, bool UPW, bool PEN, int NT>
+// GMEM: the tile's working set (the same layout) lives in a global scratch region of
+// the workgroup instead of LDS, for tiles whose footprint exceeds the LDS (it stays in
+// L2 and the MALL while the tile runs); the barriers order it as they order LDS, since a
+// workgroup's waves share one compute unit and its vector L1.
+template <int K, typename T, bool UPW, bool PEN, int NT, bool GMEM = false>
 __global__ __launch_bounds__(NT) void k_tile(const TileArgs a) {
     constexpr int NP = np_of(K), NFP = K + 1;
     constexpr int NG = K <= 2 ? 1 : (K == 3 ? 2 : 3);  // node groups per cell
     constexpr int NPG = (NP + NG - 1) / NG;             // nodes per group
-    extern __shared__ __align__(16) unsigned char smem[];
+    extern __shared__ __align__(16) unsigned char smem_lds[];
+    unsigned char *smem = GMEM ? reinterpret_cast<unsigned char *>(a.scratch) + (size_t)blockIdx.x * a.scratch_bytes
+                               : smem_lds;
     const int item = xcd_item((int)blockIdx.x, (int)gridDim.x);  // contiguous items per XCD
     const int tile = a.tiles[a.tile_base + item / a.nshots];
     const int shot = item % a.nshots;

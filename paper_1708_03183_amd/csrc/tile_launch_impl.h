@@ -117,6 +117,15 @@ static void tile_launch_mfma(bool upw, int order, int o0, int nops, int grid, si
 template <int K, typename T, int NT>
 static void tile_launch_nt(bool upw, bool pen, int grid, size_t lds, hipStream_t st, const TileArgs &A, TileAction act,
                            int *occ) {
+    if constexpr (NT == 512) {
+        if (A.scratch) {  // working sets in global scratch (no dynamic LDS)
+            auto kern = upw ? (pen ? k_tile<K, T, true, true, NT, true> : k_tile<K, T, true, false, NT, true>)
+                            : (pen ? k_tile<K, T, false, true, NT, true> : k_tile<K, T, false, false, NT, true>);
+            tile_go(kern, NT, grid, 0, st, A, act, occ);
+            return;
+        }
+    }
+    DGT_REQUIRE(!A.scratch, DGT_EINVAL, "global working sets run with workgroups of 512");
     auto kern = upw ? (pen ? k_tile<K, T, true, true, NT> : k_tile<K, T, true, false, NT>)
                     : (pen ? k_tile<K, T, false, true, NT> : k_tile<K, T, false, false, NT>);
     tile_go(kern, NT, grid, lds, st, A, act, occ);

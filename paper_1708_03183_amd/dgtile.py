@@ -488,7 +488,8 @@ class Solver:
         return out.value
 
     def kernels(self) -> list:
-        """Tile kernel per sub-chain: 0 generic, 1 register-resident chain, 2 matrix-core."""
+        """Tile kernel per sub-chain: 0 generic, 1 register-resident chain, 2 matrix-core,
+        3 generic with the working set in global memory."""
         n = C.c_int32()
         _check(lib().dgt_solver_kernels(self.h, C.byref(n), None))
         k = np.zeros(n.value, np.int32)
