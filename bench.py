@@ -13,7 +13,11 @@ fields x Np nodes x cells per step, per second) with the state resident in HBM.
 Reported beside it: the untiled chain on the same (Hilbert) cell order and on
 the mesh's own order, the inspector time and the steps that amortise it, the
 measured error against the FP64 oracle, the tile kernel's roofline from HIP
-events, and the oracle timed on the host.
+events, and the oracle timed on the host; then, as extra keys, the 1024x1024
+P3/P4 FP32 workload, a tile-size sweep, one GPU's part of the 1024x1024 mesh,
+the batched shots on six meshes (`config4`, shortened to --config4-steps) and
+the FWI gradient (`config5`).  --workload batched / fwi print those two
+records alone, at full length.
 """
 from __future__ import annotations
 
@@ -77,6 +81,11 @@ def parse():
                     help="skip the 1024x1024 P3/P4 FP32 extras of the default run")
     ap.add_argument("--config3-steps", type=int, default=100)
     ap.add_argument("--no-sweep", action="store_true", help="skip the tile-size sweep (256-4096 seeds)")
+    ap.add_argument("--no-config4", action="store_true",
+                    help="skip the batched-shots record (six meshes, 64 shots) in the default line")
+    ap.add_argument("--config4-steps", type=int, default=50)
+    ap.add_argument("--no-config5", action="store_true",
+                    help="skip the FWI-gradient record in the default line")
     ap.add_argument("--sweep-steps", type=int, default=20)
     ap.add_argument("--no-part", action="store_true",
                     help="skip one GPU's region-aware share of the 1024x1024 P3 workload")
@@ -674,7 +683,7 @@ def batched(a):
         "inspect_and_tune_wall_s": t_insp,
         "mesh_gen_s": t_gen,
     }
-    print(json.dumps(out))
+    return out
 
 
 def fwi(a):
@@ -783,7 +792,7 @@ def fwi(a):
         "err_window": f"{ws} steps, shot 0 alone",
         "tune_s": t_tune,
     }
-    print(json.dumps(out))
+    return out
 
 
 def main():
@@ -793,10 +802,10 @@ def main():
                           "n_gpus": a.gpus}))
         sys.exit(2)
     if a.workload == "batched":
-        batched(a)
+        print(json.dumps(batched(a)))
         return
     if a.workload == "fwi":
-        fwi(a)
+        print(json.dumps(fwi(a)))
         return
     import numpy as np
     import torch
@@ -1045,6 +1054,22 @@ def main():
     if "untiled" in res:
         gain = (res["untiled"]["ms_per_step"] - out["ms_per_step"]) / 1e3
         out["inspector"]["steps_to_amortise"] = (t_insp_wall / gain) if gain > 0 else None
+    if not a.no_config4 and a.n == 512 and k == 2:
+        # the batched workload's record, shortened to config4_steps timed steps
+        progress(f"config 4 extras (batched shots on six meshes, {a.config4_steps} steps)")
+        a4 = argparse.Namespace(**vars(a))
+        a4.steps, a4.warmup = a.config4_steps, 5
+        r4 = batched(a4)
+        out["config4"] = {key: r4[key] for key in ("metric", "value", "unit", "ms_per_step", "steps", "dtype",
+                                                    "config", "one_launch", "plain", "speedup_batched_vs_plain",
+                                                    "batched_equals_plain_bitwise", "max_rel_l2_diff_batched_vs_plain",
+                                                    "err_fp32_run_vs_fp64_oracle_rel_l2")}
+    if not a.no_config5 and a.n == 512 and k == 2:
+        progress(f"config 5 extras (FWI gradient, {a.fwi_steps} steps)")
+        r5 = fwi(a)
+        out["config5"] = {key: r5[key] for key in ("metric", "value", "unit", "steps", "ms_per_step", "dtype",
+                                                    "config", "forward_s", "gradient_over_forward", "misfit",
+                                                    "gradient_norm", "err_fp32_vs_fp64_gradient_rel_l2", "err_window")}
     print(json.dumps(out))
 
 
