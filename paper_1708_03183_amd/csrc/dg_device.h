@@ -226,6 +226,137 @@ __global__ __launch_bounds__(256) void k_lift(T *__restrict__ out, const int32_t
     for (int q = 0; q < NCO; ++q) out[((int64_t)q * NP + i) * nc + c] += acc[q];
 }
 
+// One whole operator application per cell (volume term, the cell's side of its three
+// facets, lift) in one pass: out = scale * op(in) (+ pscale * the upwind penalty of pin).
+// The same arithmetic as k_vol, k_flux_int / k_flux_ext and k_lift: each facet's flux
+// is evaluated from the cell's own side (its outward normal, the neighbour's trace at the
+// matching node as the other side), which is the other side's value of the facet-loop
+// form with the two cells and the sign of the normal exchanged.  One thread per cell;
+// the facet terms never leave registers.  blockIdx.y selects a shot.
+template <int K, typename T, bool VEL, bool UPW, bool PEN>
+__global__ __launch_bounds__(256) void k_op_cell(const T *__restrict__ in, const T *__restrict__ pin,
+                                                 T *__restrict__ out, const int32_t *__restrict__ c2f,
+                                                 const int32_t *__restrict__ f2c, const uint8_t *__restrict__ f2l,
+                                                 const uint8_t *__restrict__ b2l, const T *__restrict__ geo,
+                                                 int64_t nc, T scale, T pscale, int64_t ish, int64_t osh,
+                                                 int64_t psh) {
+    constexpr int NP = np_of(K), NFP = K + 1, NCI = VEL ? 3 : 2, NCO = VEL ? 2 : 3;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    in += blockIdx.y * ish;
+    out += blockIdx.y * osh;
+    if (PEN) pin += blockIdx.y * psh;
+    const auto &Rf = R<K, T>();
+    const T rx = geo[G_RX * nc + c], ry = geo[G_RY * nc + c], sx = geo[G_SX * nc + c], sy = geo[G_SY * nc + c];
+    const T zp0 = geo[G_ZP * nc + c], zs0 = geo[G_ZS * nc + c];
+    T u[NCI][NP], o[NCO][NP];
+#pragma unroll
+    for (int q = 0; q < NCI; ++q)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) u[q][j] = in[((int64_t)q * NP + j) * nc + c];
+    // volume term
+    const T irho = VEL ? geo[G_IRHO * nc + c] : T(0);
+    const T lam = VEL ? T(0) : geo[G_LAM * nc + c], mu = VEL ? T(0) : geo[G_MU * nc + c];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        T ar[NCI], as[NCI];
+#pragma unroll
+        for (int q = 0; q < NCI; ++q) ar[q] = as[q] = 0;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            const T dr = Rf.Dr[i * NP + j], ds = Rf.Ds[i * NP + j];
+#pragma unroll
+            for (int q = 0; q < NCI; ++q) {
+                ar[q] += dr * u[q][j];
+                as[q] += ds * u[q][j];
+            }
+        }
+        if constexpr (VEL) {
+            const T dxx = rx * ar[0] + sx * as[0], dyy = ry * ar[1] + sy * as[1];
+            const T dxy_x = rx * ar[2] + sx * as[2], dxy_y = ry * ar[2] + sy * as[2];
+            o[0][i] = scale * irho * (dxx + dxy_y);
+            o[1][i] = scale * irho * (dxy_x + dyy);
+        } else {
+            const T exx = rx * ar[0] + sx * as[0], eyy = ry * ar[1] + sy * as[1];
+            const T exy = T(0.5) * ((ry * ar[0] + sy * as[0]) + (rx * ar[1] + sx * as[1]));
+            o[0][i] = scale * ((lam + 2 * mu) * exx + lam * eyy);
+            o[1][i] = scale * (lam * exx + (lam + 2 * mu) * eyy);
+            o[2][i] = scale * (2 * mu * exy);
+        }
+    }
+    // facet terms, lifted at once
+    T lacc[NCO][NP];
+#pragma unroll
+    for (int q = 0; q < NCO; ++q)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) lacc[q][i] = 0;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        T nx, ny, fs;
+        facet_normal<T>(p, rx, ry, sx, sy, nx, ny, fs);
+        const int32_t code = c2f[(int64_t)p * nc + c];
+        T g[NFP][3];
+        if (code >= 0) {
+            const int64_t f = code >> 1;
+            const int side = code & 1;
+            const int64_t c1 = f2c[2 * f + (1 - side)];
+            const int l1 = side == 0 ? (f2l[f] >> 2) & 3 : f2l[f] & 3;
+            const T zp1 = geo[G_ZP * nc + c1], zs1 = geo[G_ZS * nc + c1];
+#pragma unroll
+            for (int m = 0; m < NFP; ++m) {
+                const int n0 = fnode(K, p, m), n1 = Rf.fn[l1 * NFP + (K - m)];
+                T a0[3], a1[3], p0[3] = {0, 0, 0}, p1[3] = {0, 0, 0}, g1[3];
+#pragma unroll
+                for (int q = 0; q < NCI; ++q) {
+                    a0[q] = u[q][n0];
+                    a1[q] = in[((int64_t)q * NP + n1) * nc + c1];
+                }
+                if (PEN) {
+#pragma unroll
+                    for (int q = 0; q < NCO; ++q) {
+                        p0[q] = pin[((int64_t)q * NP + n0) * nc + c];
+                        p1[q] = pin[((int64_t)q * NP + n1) * nc + c1];
+                    }
+                }
+                if constexpr (VEL)
+                    flux_v_int<T, UPW, PEN>(a0, a1, p0, p1, nx, ny, zp0, zs0, zp1, zs1, fs * irho, T(0), scale,
+                                            pscale, g[m], g1);
+                else
+                    flux_s_int<T, UPW, PEN>(a0, a1, p0, p1, nx, ny, zp0, zs0, zp1, zs1, lam, mu, lam, mu, fs, T(0),
+                                            scale, pscale, g[m], g1);
+            }
+        } else {
+            const int64_t b = -(int64_t)code - 1;
+            const bool fr = (b2l[b] >> 2) & 1;
+#pragma unroll
+            for (int m = 0; m < NFP; ++m) {
+                const int n0 = fnode(K, p, m);
+                T a0[3], p0[3] = {0, 0, 0};
+#pragma unroll
+                for (int q = 0; q < NCI; ++q) a0[q] = u[q][n0];
+                if (PEN) {
+#pragma unroll
+                    for (int q = 0; q < NCO; ++q) p0[q] = pin[((int64_t)q * NP + n0) * nc + c];
+                }
+                if constexpr (VEL)
+                    flux_v_ext<T, UPW, PEN>(a0, p0, fr, nx, ny, zp0, zs0, fs * irho, scale, pscale, g[m]);
+                else
+                    flux_s_ext<T, UPW, PEN>(a0, p0, fr, nx, ny, zp0, zs0, lam, mu, fs, scale, pscale, g[m]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+#pragma unroll
+            for (int q = 0; q < NCO; ++q)
+#pragma unroll
+                for (int m = 0; m < NFP; ++m) lacc[q][i] += Rf.lift[(p * NP + i) * NFP + m] * g[m][q];
+    }
+#pragma unroll
+    for (int q = 0; q < NCO; ++q)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) out[((int64_t)q * NP + i) * nc + c] = o[q][i] + lacc[q][i];
+}
+
 // v += dt*U + Z (order 4) ; v += Z (order 2, dt folded into Z)
 template <typename T>
 __global__ __launch_bounds__(256) void k_upd_v(T *__restrict__ V, const T *__restrict__ U, const T *__restrict__ Z,

@@ -343,11 +343,11 @@ struct FwiRun {
         const int64_t nvS = vsh * S, nsS = ssh * S;
         const T *v0 = (const T *)f->fld[F_V].p, *s0 = (const T *)f->fld[F_S].p;
         T *av = (T *)a->fld[F_V].p, *as = (T *)a->fld[F_S].p;
-        auto vop = [&](const T *in, T *out) { apply_op<K, T>(f, true, in, out, 1.0, nullptr, 0.0, launches, S, ssh, vsh); };
-        auto sop = [&](const T *in, T *out) { apply_op<K, T>(f, false, in, out, 1.0, nullptr, 0.0, launches, S, vsh, ssh); };
+        auto vop = [&](const T *in, T *out) { apply_op_cell<K, T>(f, true, in, out, 1.0, nullptr, 0.0, launches, S, ssh, vsh); };
+        auto sop = [&](const T *in, T *out) { apply_op_cell<K, T>(f, false, in, out, 1.0, nullptr, 0.0, launches, S, vsh, ssh); };
         // penalties alone: the operator part scaled by zero (its input only needs finite values)
-        auto vpen = [&](const T *pv, T *out) { apply_op<K, T>(f, true, s0, out, 0.0, pv, 1.0, launches, S, ssh, vsh, vsh); };
-        auto spen = [&](const T *ps, T *out) { apply_op<K, T>(f, false, v0, out, 0.0, ps, 1.0, launches, S, vsh, ssh, ssh); };
+        auto vpen = [&](const T *pv, T *out) { apply_op_cell<K, T>(f, true, s0, out, 0.0, pv, 1.0, launches, S, ssh, vsh, vsh); };
+        auto spen = [&](const T *ps, T *out) { apply_op_cell<K, T>(f, false, v0, out, 0.0, ps, 1.0, launches, S, vsh, ssh, ssh); };
         auto lin = [&](T *out, int64_t cnt, const T *x0, double c0, const T *x1, double c1, const T *x2, double c2,
                        const T *x3, double c3_) {
             k_fwi_lin<T><<<blocks_for(cnt, 256), 256, 0, st>>>(out, x0, c0, x1, c1, x2, c2, x3, c3_, cnt);
@@ -501,8 +501,8 @@ struct FwiRun {
         }
         const T *v0 = (const T *)f->fld[F_V].p, *s0 = (const T *)f->fld[F_S].p;
         // every operator application covers all shots in one launch per kernel
-        auto vop = [&](const T *in, T *out, double sc) { apply_op<K, T>(f, true, in, out, sc, nullptr, 0.0, launches, S, ssh, vsh); };
-        auto sop = [&](const T *in, T *out, double sc) { apply_op<K, T>(f, false, in, out, sc, nullptr, 0.0, launches, S, vsh, ssh); };
+        auto vop = [&](const T *in, T *out, double sc) { apply_op_cell<K, T>(f, true, in, out, sc, nullptr, 0.0, launches, S, ssh, vsh); };
+        auto sop = [&](const T *in, T *out, double sc) { apply_op_cell<K, T>(f, false, in, out, sc, nullptr, 0.0, launches, S, vsh, ssh); };
         vop(s0, U.p, 1.0);
         if (o4) {
             sop(U.p, Xp.p, 1.0);

@@ -770,6 +770,36 @@ static void apply_op(dgt_solver *s, bool vel, const T *fin, T *fout, double scal
     ++launches;
 }
 
+// The same operator application in one cell-centric launch (k_op_cell): no facet
+// buffers, each cell's facet terms lifted in registers.  The untiled chain keeps the
+// per-loop kernels above; this form serves callers that apply single operators to
+// arbitrary fields (the FWI reversal).
+template <int K, typename T>
+static void apply_op_cell(dgt_solver *s, bool vel, const T *fin, T *fout, double scale, const T *fpen,
+                          double pscale, int64_t &launches, int shots = 1, int64_t ish = 0, int64_t osh = 0,
+                          int64_t psh = 0) {
+    const int64_t nc = s->nc;
+    if (nc == 0) return;
+    const T sc = (T)scale, ps = (T)pscale;
+    const dim3 g(blocks_for(nc, 256), shots);
+    // exterior-facet kinds come from eb2l, interior neighbours from ef2c / ef2l; a mesh
+    // without facets of one kind never reads its (placeholder) table
+    auto go = [&]<bool VEL, bool UPW, bool PEN>() {
+        k_op_cell<K, T, VEL, UPW, PEN><<<g, 256, 0, s->st>>>(fin, fpen, fout, s->c2f.p, s->ef2c.p, s->ef2l.p,
+                                                            s->eb2l.p, (const T *)s->geo.p, nc, sc, ps, ish, osh,
+                                                            psh);
+    };
+    const bool pn = fpen != nullptr;
+    if (vel) {
+        if (s->upw) { if (pn) go.template operator()<true, true, true>(); else go.template operator()<true, true, false>(); }
+        else { if (pn) go.template operator()<true, false, true>(); else go.template operator()<true, false, false>(); }
+    } else {
+        if (s->upw) { if (pn) go.template operator()<false, true, true>(); else go.template operator()<false, true, false>(); }
+        else { if (pn) go.template operator()<false, false, true>(); else go.template operator()<false, false, false>(); }
+    }
+    ++launches;
+}
+
 template <int K, typename T>
 static void apply_untiled(dgt_solver *s, int shot, bool vel, int in, int out, double scale, int pen, double pscale,
                           int64_t &launches) {
