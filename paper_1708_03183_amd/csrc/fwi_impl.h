@@ -305,6 +305,18 @@ struct FwiRun {
         const int nfp = K + 1;
         for (int i = 0; i < nfp * nfp; ++i) m1.m[i] = f->E.M1[i];
     }
+    // cell and interior-facet parts of the queued pairs, one launch each
+    FwiCellPairs<T> cq{};
+    FwiPairs<T> fq{};
+    void flush_pairs() {
+        if (cq.n)
+            k_fwi_cell_pairs<K, T><<<dim3(blocks_for(f->nc, 256), S), 256, 0, f->st>>>(cq, (const T *)f->geo.p,
+                                                                                      f->nc, part.p);
+        if (fq.n)
+            k_fwi_facet_pairs<K, T><<<dim3(blocks_for(f->nf, 256), S), 256, 0, f->st>>>(
+                fq, f->ef2c.p, f->ef2l.p, (const T *)f->geo.p, f->nc, f->nf, m1, fb.p);
+        cq.n = fq.n = 0;
+    }
     // one term coef * a^T W dOp b (ob = Op b): cell part, and the facet part when the
     // flux weights of Op depend on the impedances
     template <int KIND>
@@ -314,13 +326,25 @@ struct FwiRun {
         constexpr bool VEL = KIND == FK_A || KIND == FK_DV;  // kind of a and ob
         const int64_t sh = VEL ? vsh : ssh;
         const T *geo = (const T *)f->geo.p;
-        k_fwi_cell_pair<K, T, KIND><<<dim3(blocks_for(nc, 256), S), 256, 0, st>>>(a_, ob, sh, geo, nc, coef, part.p);
+        // the cell and interior-facet parts are queued and summed in one pass each by
+        // flush_pairs
+        if (fq.n == FWI_MAX_PAIRS || cq.n == FWI_MAX_PAIRS) flush_pairs();
+        const int k = cq.n++;
+        cq.kind[k] = KIND;
+        cq.a[k] = a_;
+        cq.ob[k] = ob;
+        cq.sh[k] = sh;
+        cq.coef[k] = coef;
         // interior facets weigh by the impedances with the upwind flux only; exterior ones
         // only in the penalties (absorbing facets always, free surfaces with the upwind flux)
         if (f->upw && nf) {
-            const int64_t bsh = (KIND == FK_A || KIND == FK_DS) ? ssh : vsh;
-            k_fwi_facet_pair<K, T, KIND><<<dim3(blocks_for(nf, 256), S), 256, 0, st>>>(
-                a_, b_, sh, bsh, f->ef2c.p, f->ef2l.p, geo, nc, nf, m1, coef, fb.p);
+            const int i = fq.n++;
+            fq.kind[i] = KIND;
+            fq.a[i] = a_;
+            fq.b[i] = b_;
+            fq.ash[i] = sh;
+            fq.bsh[i] = (KIND == FK_A || KIND == FK_DS) ? ssh : vsh;
+            fq.coef[i] = coef;
         }
         if ((KIND == FK_DV || KIND == FK_DS) && f->haspen && nb)
             k_fwi_ext_pair<K, T, KIND><<<dim3(blocks_for(nb, 256), S), 256, 0, st>>>(
@@ -398,6 +422,7 @@ struct FwiRun {
             pair<FK_DS>(as, s0, fPS.p, dt);
             pair<FK_DV>(aMu.p, v0, fPV.p, dt);
         }
+        flush_pairs();
         k_fwi_grad_sum<<<blocks_for(3 * f->nc, 256), 256, 0, st>>>(f->nc, S, part.p, g.p);
         // the transposed step: alpha_s += dt Ds alpha_s - dt B mu - c B A B mu; alpha_v = mu + dt Dv mu
         lin(as, nsS, as, 1.0, pen ? aPS.p : nullptr, dt, aB.p, -dt, o4 ? aBAB.p : nullptr, -c3);

@@ -33,6 +33,9 @@ namespace dgt {
 
 enum FwiKind { FK_A = 0, FK_B = 1, FK_DV = 2, FK_DS = 3 };
 
+// pairs (a, b) whose gradient terms one launch sums
+constexpr int FWI_MAX_PAIRS = 12;
+
 struct FacetMass {
     double m[25];  // [nfp][nfp] reference facet mass on [0, 1]
 };
@@ -50,59 +53,76 @@ __global__ __launch_bounds__(256) void k_fwi_lin(T *out, const T *x0, double c0,
     out[t] = (T)v;
 }
 
-// Cell part of coef * a^T W dOp b for one shot (blockIdx.y), given ob = Op b:
-// velocity kinds (A, Dv) add -coef |J| a . M ob to d/drho, stress kinds (B, Ds) add
-// coef |J| sum_j (C^-1 (M a)_j) . C_m (C^-1 ob_j) to d/dlam and d/dmu.
-template <int K, typename T, int KIND>
-__global__ __launch_bounds__(256) void k_fwi_cell_pair(const T *__restrict__ a, const T *__restrict__ ob, int64_t sh,
-                                                       const T *__restrict__ geo, int64_t nc, double coef,
-                                                       double *__restrict__ part) {
+// Cell parts of coef * a^T W dOp b for several pairs (a, ob = Op b) in one pass, one
+// thread per cell and shot (blockIdx.y): velocity kinds (A, Dv) add -coef |J| a . M ob
+// to d/drho, stress kinds (B, Ds) add coef |J| sum_j (C^-1 (M a)_j) . C_m (C^-1 ob_j)
+// to d/dlam and d/dmu; the sums of all pairs are added to part once.
+template <typename T>
+struct FwiCellPairs {
+    int n;
+    int kind[FWI_MAX_PAIRS];
+    const T *a[FWI_MAX_PAIRS];
+    const T *ob[FWI_MAX_PAIRS];
+    int64_t sh[FWI_MAX_PAIRS];
+    double coef[FWI_MAX_PAIRS];
+};
+
+template <int K, typename T>
+__global__ __launch_bounds__(256) void k_fwi_cell_pairs(const FwiCellPairs<T> P, const T *__restrict__ geo,
+                                                        int64_t nc, double *__restrict__ part) {
     constexpr int NP = np_of(K);
-    constexpr bool VEL = KIND == FK_A || KIND == FK_DV;
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= nc) return;
     const int q = blockIdx.y;
     const auto &Rf = R<K, T>();
-    a += q * sh;
-    ob += q * sh;
     const double det = geo[G_DET * nc + x];
-    double *o = part + (int64_t)q * 3 * nc;
-    if constexpr (VEL) {
-        double acc = 0.0;
+    const double lam = geo[G_LAM * nc + x], mu = geo[G_MU * nc + x];
+    const double cA = (lam + 2 * mu) / (4 * mu * (lam + mu)), cB = -lam / (4 * mu * (lam + mu)), cC = 1.0 / mu;
+    double gr = 0.0, gl = 0.0, gm = 0.0;
+    for (int p = 0; p < P.n; ++p) {
+        const T *a = P.a[p] + q * P.sh[p], *ob = P.ob[p] + q * P.sh[p];
+        const double coef = P.coef[p];
+        if (P.kind[p] == FK_A || P.kind[p] == FK_DV) {
+            double acc = 0.0;
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int j = 0; j < NP; ++j) {
+                    double ma = 0.0;
+#pragma unroll
+                    for (int i = 0; i < NP; ++i)
+                        ma += (double)a[(int64_t)(c * NP + i) * nc + x] * (double)Rf.M[i * NP + j];
+                    acc += ma * (double)ob[(int64_t)(c * NP + j) * nc + x];
+                }
+            gr -= coef * det * acc;
+        } else {
+            double sl = 0.0, sm = 0.0;
 #pragma unroll
             for (int j = 0; j < NP; ++j) {
-                double ma = 0.0;
+                double ma[3];
 #pragma unroll
-                for (int i = 0; i < NP; ++i) ma += (double)a[(int64_t)(c * NP + i) * nc + x] * (double)Rf.M[i * NP + j];
-                acc += ma * (double)ob[(int64_t)(c * NP + j) * nc + x];
+                for (int c = 0; c < 3; ++c) {
+                    ma[c] = 0.0;
+#pragma unroll
+                    for (int i = 0; i < NP; ++i)
+                        ma[c] += (double)a[(int64_t)(c * NP + i) * nc + x] * (double)Rf.M[i * NP + j];
+                }
+                const double b0 = (double)ob[(int64_t)(0 * NP + j) * nc + x],
+                             b1 = (double)ob[(int64_t)(1 * NP + j) * nc + x],
+                             b2 = (double)ob[(int64_t)(2 * NP + j) * nc + x];
+                const double ax = cA * ma[0] + cB * ma[1], ay = cB * ma[0] + cA * ma[1], axy = cC * ma[2];
+                const double ex = cA * b0 + cB * b1, ey = cB * b0 + cA * b1, exy = cC * b2;
+                sl += (ax + ay) * (ex + ey);
+                sm += 2 * (ax * ex + ay * ey) + axy * exy;
             }
-        o[2 * nc + x] -= coef * det * acc;
-    } else {
-        const double lam = geo[G_LAM * nc + x], mu = geo[G_MU * nc + x];
-        const double cA = (lam + 2 * mu) / (4 * mu * (lam + mu)), cB = -lam / (4 * mu * (lam + mu)), cC = 1.0 / mu;
-        double gl = 0.0, gm = 0.0;
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-            double ma[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                ma[c] = 0.0;
-#pragma unroll
-                for (int i = 0; i < NP; ++i)
-                    ma[c] += (double)a[(int64_t)(c * NP + i) * nc + x] * (double)Rf.M[i * NP + j];
-            }
-            const double b0 = (double)ob[(int64_t)(0 * NP + j) * nc + x], b1 = (double)ob[(int64_t)(1 * NP + j) * nc + x],
-                         b2 = (double)ob[(int64_t)(2 * NP + j) * nc + x];
-            const double ax = cA * ma[0] + cB * ma[1], ay = cB * ma[0] + cA * ma[1], axy = cC * ma[2];
-            const double ex = cA * b0 + cB * b1, ey = cB * b0 + cA * b1, exy = cC * b2;
-            gl += (ax + ay) * (ex + ey);
-            gm += 2 * (ax * ex + ay * ey) + axy * exy;
+            gl += coef * det * sl;
+            gm += coef * det * sm;
         }
-        o[x] += coef * det * gl;
-        o[nc + x] += coef * det * gm;
     }
+    double *o = part + (int64_t)q * 3 * nc;
+    o[x] += gl;
+    o[nc + x] += gm;
+    o[2 * nc + x] += gr;
 }
 
 // impedance derivatives of one side -> (d/dlam, d/dmu, d/drho)
@@ -124,21 +144,31 @@ __device__ __forceinline__ double fwi_fdot(const FacetMass &m1, const double (&x
     return s;
 }
 
-// Facet part of coef * a^T dOp~ b at interior facets (one thread per facet and shot),
-// added to fb[shot][facet][side][lam, mu, rho].  Velocity-like fields have 2
-// components, stress-like ones 3 (a: the output kind of Op, b: its input kind).
-template <int K, typename T, int KIND>
-__global__ __launch_bounds__(256) void k_fwi_facet_pair(const T *__restrict__ a, const T *__restrict__ b, int64_t ash,
-                                                        int64_t bsh, const int32_t *__restrict__ ef2c,
-                                                        const uint8_t *__restrict__ ef2l, const T *__restrict__ geo,
-                                                        int64_t nc, int64_t nf, FacetMass m1, double coef,
-                                                        double *__restrict__ fb) {
+// Facet parts of coef * a^T dOp~ b at interior facets for several pairs (a, b) in one
+// pass (one thread per facet and shot): the impedance derivatives of every pair are
+// summed per facet side, then turned into (lam, mu, rho) derivatives and added to
+// fb[shot][facet][side][lam, mu, rho] once (the conversion is linear), so fb is read and
+// written once per reversed step.  Velocity-like fields have 2 components, stress-like
+// ones 3 (a: the output kind of Op, b: its input kind).
+template <typename T>
+struct FwiPairs {
+    int n;
+    int kind[FWI_MAX_PAIRS];
+    const T *a[FWI_MAX_PAIRS];
+    const T *b[FWI_MAX_PAIRS];
+    int64_t ash[FWI_MAX_PAIRS], bsh[FWI_MAX_PAIRS];
+    double coef[FWI_MAX_PAIRS];
+};
+
+template <int K, typename T>
+__global__ __launch_bounds__(256) void k_fwi_facet_pairs(const FwiPairs<T> P, const int32_t *__restrict__ ef2c,
+                                                         const uint8_t *__restrict__ ef2l, const T *__restrict__ geo,
+                                                         int64_t nc, int64_t nf, FacetMass m1,
+                                                         double *__restrict__ fb) {
     constexpr int NP = np_of(K), NFP = K + 1;
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= nf) return;
     const int q = blockIdx.y;
-    a += q * ash;
-    b += q * bsh;
     const auto &Rf = R<K, T>();
     const int64_t c[2] = {ef2c[2 * f], ef2c[2 * f + 1]};
     const int l0 = ef2l[f] & 3, l1 = (ef2l[f] >> 2) & 3;
@@ -147,41 +177,6 @@ __global__ __launch_bounds__(256) void k_fwi_facet_pair(const T *__restrict__ a,
                     nyT, fsT);
     const double nx = nxT, ny = nyT, tx = -ny, ty = nx;
     const double len = (double)fsT * (double)geo[G_DET * nc + c[0]];
-    // velocity-like field at node m of side s: components along n and t;
-    // stress-like: its traction with the normal of side 0, along n and t
-    auto nt = [&](const T *F, bool stress, int s, int m, double &vn, double &vt) {
-        const int node = s == 0 ? Rf.fn[l0 * NFP + m] : Rf.fn[l1 * NFP + (K - m)];
-        const int64_t x = c[s];
-        double wx, wy;
-        if (stress) {
-            const double sxx = F[(int64_t)(0 * NP + node) * nc + x], syy = F[(int64_t)(1 * NP + node) * nc + x],
-                         sxy = F[(int64_t)(2 * NP + node) * nc + x];
-            wx = sxx * nx + sxy * ny;
-            wy = sxy * nx + syy * ny;
-        } else {
-            wx = F[(int64_t)(0 * NP + node) * nc + x];
-            wy = F[(int64_t)(1 * NP + node) * nc + x];
-        }
-        vn = wx * nx + wy * ny;
-        vt = wx * tx + wy * ty;
-    };
-    constexpr bool AS = KIND == FK_B || KIND == FK_DS;  // a stress-like
-    constexpr bool BS = KIND == FK_A || KIND == FK_DS;  // b stress-like
-    double xn[NFP], xt[NFP], yn[NFP], yt[NFP];
-#pragma unroll
-    for (int m = 0; m < NFP; ++m) {
-        double a0n, a0t, a1n, a1t, b0n, b0t, b1n, b1t;
-        nt(a, AS, 0, m, a0n, a0t);
-        nt(a, AS, 1, m, a1n, a1t);
-        nt(b, BS, 0, m, b0n, b0t);
-        nt(b, BS, 1, m, b1n, b1t);
-        xn[m] = a0n - a1n;
-        xt[m] = a0t - a1t;
-        // A: T(b)1 - T(b)0; B, Dv, Ds: b0 - b1 (tractions for Ds)
-        yn[m] = KIND == FK_A ? b1n - b0n : b0n - b1n;
-        yt[m] = KIND == FK_A ? b1t - b0t : b0t - b1t;
-    }
-    const double Pn = coef * len * fwi_fdot<NFP>(m1, xn, yn), Pt = coef * len * fwi_fdot<NFP>(m1, xt, yt);
     double zp[2], zs[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -189,20 +184,65 @@ __global__ __launch_bounds__(256) void k_fwi_facet_pair(const T *__restrict__ a,
         zs[s] = geo[G_ZS * nc + c[s]];
     }
     const double Sp = zp[0] + zp[1], Ss = zs[0] + zs[1];
-    double dzp[2], dzs[2];
-    if (KIND == FK_A || KIND == FK_B) {  // Z1 P / S^2 and -Z0 P / S^2
-        dzp[0] = zp[1] * Pn / (Sp * Sp);
-        dzp[1] = -zp[0] * Pn / (Sp * Sp);
-        dzs[0] = Ss > 0 ? zs[1] * Pt / (Ss * Ss) : 0.0;
-        dzs[1] = Ss > 0 ? -zs[0] * Pt / (Ss * Ss) : 0.0;
-    } else if (KIND == FK_DV) {  // d(Z0 Z1 / S)/dZ0 = Z1^2 / S^2
-        dzp[0] = -zp[1] * zp[1] * Pn / (Sp * Sp);
-        dzp[1] = -zp[0] * zp[0] * Pn / (Sp * Sp);
-        dzs[0] = Ss > 0 ? -zs[1] * zs[1] * Pt / (Ss * Ss) : 0.0;
-        dzs[1] = Ss > 0 ? -zs[0] * zs[0] * Pt / (Ss * Ss) : 0.0;
-    } else {  // d(1/S)/dZ = -1/S^2 with the form's minus sign
-        dzp[0] = dzp[1] = Pn / (Sp * Sp);
-        dzs[0] = dzs[1] = Ss > 0 ? Pt / (Ss * Ss) : 0.0;
+    int node[2][NFP];
+#pragma unroll
+    for (int m = 0; m < NFP; ++m) {
+        node[0][m] = Rf.fn[l0 * NFP + m];
+        node[1][m] = Rf.fn[l1 * NFP + (K - m)];
+    }
+    // velocity-like field at node m of side s: components along n and t; stress-like:
+    // its traction with the normal of side 0, along n and t
+    auto nt = [&](const T *F, bool stress, int s, int m, double &vn, double &vt) {
+        const int64_t x = c[s];
+        const int nd = node[s][m];
+        double wx, wy;
+        if (stress) {
+            const double sxx = F[(int64_t)(0 * NP + nd) * nc + x], syy = F[(int64_t)(1 * NP + nd) * nc + x],
+                         sxy = F[(int64_t)(2 * NP + nd) * nc + x];
+            wx = sxx * nx + sxy * ny;
+            wy = sxy * nx + syy * ny;
+        } else {
+            wx = F[(int64_t)(0 * NP + nd) * nc + x];
+            wy = F[(int64_t)(1 * NP + nd) * nc + x];
+        }
+        vn = wx * nx + wy * ny;
+        vt = wx * tx + wy * ty;
+    };
+    double dzp[2] = {0.0, 0.0}, dzs[2] = {0.0, 0.0};
+    for (int i = 0; i < P.n; ++i) {
+        const int kind = P.kind[i];
+        const T *a = P.a[i] + q * P.ash[i], *b = P.b[i] + q * P.bsh[i];
+        const bool as_ = kind == FK_B || kind == FK_DS, bs_ = kind == FK_A || kind == FK_DS;
+        double xn[NFP], xt[NFP], yn[NFP], yt[NFP];
+#pragma unroll
+        for (int m = 0; m < NFP; ++m) {
+            double a0n, a0t, a1n, a1t, b0n, b0t, b1n, b1t;
+            nt(a, as_, 0, m, a0n, a0t);
+            nt(a, as_, 1, m, a1n, a1t);
+            nt(b, bs_, 0, m, b0n, b0t);
+            nt(b, bs_, 1, m, b1n, b1t);
+            xn[m] = a0n - a1n;
+            xt[m] = a0t - a1t;
+            yn[m] = kind == FK_A ? b1n - b0n : b0n - b1n;
+            yt[m] = kind == FK_A ? b1t - b0t : b0t - b1t;
+        }
+        const double Pn = P.coef[i] * len * fwi_fdot<NFP>(m1, xn, yn), Pt = P.coef[i] * len * fwi_fdot<NFP>(m1, xt, yt);
+        if (kind == FK_A || kind == FK_B) {
+            dzp[0] += zp[1] * Pn / (Sp * Sp);
+            dzp[1] += -zp[0] * Pn / (Sp * Sp);
+            dzs[0] += Ss > 0 ? zs[1] * Pt / (Ss * Ss) : 0.0;
+            dzs[1] += Ss > 0 ? -zs[0] * Pt / (Ss * Ss) : 0.0;
+        } else if (kind == FK_DV) {
+            dzp[0] += -zp[1] * zp[1] * Pn / (Sp * Sp);
+            dzp[1] += -zp[0] * zp[0] * Pn / (Sp * Sp);
+            dzs[0] += Ss > 0 ? -zs[1] * zs[1] * Pt / (Ss * Ss) : 0.0;
+            dzs[1] += Ss > 0 ? -zs[0] * zs[0] * Pt / (Ss * Ss) : 0.0;
+        } else {
+            dzp[0] += Pn / (Sp * Sp);
+            dzp[1] += Pn / (Sp * Sp);
+            dzs[0] += Ss > 0 ? Pt / (Ss * Ss) : 0.0;
+            dzs[1] += Ss > 0 ? Pt / (Ss * Ss) : 0.0;
+        }
     }
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
