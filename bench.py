@@ -113,6 +113,19 @@ DEFAULTS = {
 VALU_DEFAULTS = {3: (192, OPS, 1), 4: (192, OPS, 0)}
 
 
+def host_cpu_model():
+    """The host processor's model name (Linux), else the platform's description."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
 def material(m, k, which):
     from paper_1708_03183_amd import inputs as I
     if which == "auto":
@@ -857,7 +870,10 @@ def main():
     sol.set_schedule(schedule)
     torch.cuda.synchronize()
     t_insp_wall = time.time() - ti0
-    sched = json.loads(sol.schedule().summary())
+    sch_obj = sol.schedule()
+    sched = json.loads(sch_obj.summary())
+    insp_bytes = 4 * sum(sch_obj.loop_sizes) + 4 * (2 * mesh.nf + mesh.nb)
+    del sch_obj
     info = sol.info()
 
     def run(solver, mode, steps, warm):
@@ -930,6 +946,7 @@ def main():
 
     # ---- oracle on the host: a bounded sample of the same workload
     cpu = None
+    insp_cpu = None
     err_oracle = None
     err_fp32 = None
     if not a.no_cpu_baseline:
@@ -957,9 +974,26 @@ def main():
         od.step(v, s, a.cpu_steps, t0=tstart)
         tcpu = time.perf_counter() - tc
         cpu = {"value": 5 * npk * len(cells) * a.cpu_steps / tcpu, "unit": "dof-updates/s", "cores": 1,
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": host_cpu_model(),
                "sample": f"{a.cpu_steps} step(s) of {where}, from the GPU's final state "
                          f"({tcpu:.1f} s, FP64, single thread)"}
+        # the oracle's inspection of the same chain (tile size, partition, splits) on the
+        # mesh of half the side from the same generator: a sample of ~10 s on one core
+        hn = max(a.n // 2, 8)
+        progress(f"oracle inspector on the {hn}x{hn} mesh")
+        mi = I.square_mesh(hn, jitter=0.2, jitter_seed=1, renumber_seed=2 if a.mesh_order == "renumbered" else None)
+        (li, ui, ri), _ = material(mi, k, a.material)
+        odi = O.ODG(O.OMesh.from_mesh(mi), k, li, ui, ri, flux=1, order=4, dt=dt, free_sides=0x8)
+        chi = odi.chain(1)
+        tc = time.perf_counter()
+        chi.inspect(ts, partition=a.partition, seed_xy=mi.centroids() if a.partition else None, splits=splits,
+                    max_colour_tiles=a.colour_cap, sub_tile_sizes=sub_ts)
+        ti_cpu = time.perf_counter() - tc
+        insp_cpu = {"s": ti_cpu, "cells": int(mi.c2v.shape[0]), "cells_per_s": mi.c2v.shape[0] / ti_cpu,
+                    "cores": 1, "kind": "oracle",
+                    "sample": f"the same chain, tile size and splits on the {hn}x{hn} mesh of the same "
+                              f"generator ({mi.c2v.shape[0]} cells), single thread"}
+        del chi, odi
         if a.cpu_cores != 1:
             ncores = a.cpu_cores or min(16, os.cpu_count() or 1)
             progress(f"cpu baseline on {ncores} cores")
@@ -1024,6 +1058,12 @@ def main():
         "err_fp32_run_vs_fp64_oracle_rel_l2": err_fp32,
         "repeats_ms_per_step": {"steps": rsteps, "median": reps[2], "min": reps[0], "max": reps[-1]},
         "inspector": {"gpu_ms": sched.get("inspector_gpu_ms"), "wall_s": t_insp_wall,
+                      "cells_per_s_wall": mesh.nc / t_insp_wall,
+                      # the maps read once and every loop's tile assignment written once
+                      "bytes_maps_and_sigma": insp_bytes,
+                      "effective_gbs": (insp_bytes / (sched["inspector_gpu_ms"] * 1e-3) / 1e9
+                                        if sched.get("inspector_gpu_ms") else None),
+                      "oracle_on_host": insp_cpu,
                       "subchains": sched.get("subchains"), "lds_bytes": info["lds_bytes"]},
         "launches_per_step": launches_t / a.steps,
         "mesh_gen_s": t_gen,
