@@ -324,6 +324,25 @@ def config3(a):
             torch.cuda.synchronize()
             del ref
             r["horizon"] = horizon(D, make, a.config3_horizon, k, (v, st), 1, dt)
+        if not a.no_cpu_baseline:
+            # the oracle on the host: 2 steps on a patch around the centre sized to ~10 s of
+            # one core, reported per dof-update
+            import numpy as np
+            import oracle as O
+            csteps = 2
+            cells, _, sub, where = oracle_patch(m, npk, csteps, 1e7, (0.5, 0.5))
+            od = O.ODG(O.OMesh(sub.xy, sub.c2v, sub.periodic), k, lam[cells], mu[cells], rho[cells], flux=1,
+                       order=4, dt=dt, free_sides=0x8)
+            ov, os_ = od.zeros()
+            ov[:] = I.random_state(ov.shape, 41)
+            os_[:] = I.random_state(os_.shape, 42)
+            tc = time.perf_counter()
+            od.step(ov, os_, csteps, t0=0.0)
+            tcpu = time.perf_counter() - tc
+            r["oracle_on_host"] = {"value": 5 * npk * len(cells) * csteps / tcpu, "unit": "dof-updates/s",
+                                   "cores": 1, "kind": "oracle", "cpu_model": host_cpu_model(),
+                                   "sample": f"{csteps} steps of {where.rsplit(',', 1)[0]} ({tcpu:.1f} s, FP64, single thread)"}
+            del od
         out[f"p{k}"] = r
         print(f"bench: config 3 P{k}: mfma {r['mfma']['ms_per_step']:.3f} ms, valu {r['valu']['ms_per_step']:.3f} "
               f"ms, untiled {r['untiled']['ms_per_step']:.3f} ms", file=sys.stderr, flush=True)
