@@ -47,7 +47,7 @@ struct SubPlan {
     DBuf<int32_t> err;
     DBuf<uint32_t> cnt, head;
     uint32_t epoch = 0;
-    int slots = 0;  // workgroup size of the tile kernel
+    int slots = 0;  // workgroups of the tile kernel the whole GPU holds at once
 };
 
 }  // namespace dgt
