@@ -363,8 +363,13 @@ dgt_status dgt_fwi_forward(dgt_solver *s, const dgt_fwi_params *p, double *trace
  * flux or absorbing sides it is the closed form of the transposed step in the energy
  * inner product (operator parts skew, penalties self-adjoint: the operators run with
  * -dt and the penalties with +dt, each penalty in the other half step), built from
- * untiled operator applications, and the gradient adds the derivatives of the flux
- * weights with respect to the impedances of both cells of every facet.  *misfit host. */
+ * untiled operator applications (one cell-centric launch each over all shots), and
+ * the gradient adds the derivatives of the flux weights with respect to the
+ * impedances of both cells of every facet.  *misfit host.  Environment, read per
+ * call: DGT_FWI_CLOSED_FORM takes the closed form also where the reversed chain
+ * applies (the two agree); DGT_FWI_UNTILED_INTERMEDIATES computes the reversed
+ * chain's intermediates by untiled operator applications instead of recording them
+ * from tiled steps. */
 dgt_status dgt_fwi_gradient(dgt_solver *s, const dgt_fwi_params *p, const double *observed, double *misfit,
                             double *g_lam, double *g_mu, double *g_rho);
 /* Schedule of the tiled executor (default 0).  0: one kernel launch per colour
