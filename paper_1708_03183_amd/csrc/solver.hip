@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 #include <numeric>
+#include <string>
 
 #include "dg_device.h"
 #include "tile_chain.h"
@@ -1240,6 +1241,39 @@ static void prepare_tiled(dgt_solver *s) {
     }
 }
 
+// Cell order of the executor within each seed tile (tile t holds the seeds of ranks
+// [t ts, (t+1) ts)): the cells only its own footprint holds first, then the cells that
+// other tiles' footprints also gather, grouped by the lowest such tile, each group in
+// seed order.  The fields are stored [component][node][cell], so a cell gathered as
+// part of another tile's halo pulls a memory sector per component and node; with a
+// neighbour's halo cells in one run those sectors are shared.  The order is only a
+// permutation of the executor's layout: schedules, results and the caller's
+// numbering are unchanged.
+static void group_halo_cells(dgt_solver *s, std::vector<int32_t> &rank, int64_t ts) {
+    hipStream_t st = s->st;
+    const SubSched &sb = s->sched->s->sub[0];
+    const int64_t nc = s->nc;
+    if (nc == 0 || sb.ntiles == 0 || ts <= 0) return;
+    const std::vector<int32_t> foff = sb.foot_off[0].download(st, sb.ntiles + 1);
+    const std::vector<int32_t> foot = sb.foot[0].download(st, std::max<int64_t>(foff[sb.ntiles], 1));
+    std::vector<int32_t> nbt(nc, INT32_MAX);
+    for (int t = 0; t < sb.ntiles; ++t)
+        for (int q = foff[t]; q < foff[t + 1]; ++q) {
+            const int32_t x = foot[q];
+            if (rank[x] / ts != t) nbt[x] = std::min(nbt[x], t);
+        }
+    std::vector<int32_t> order(nc);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const int64_t ta = rank[a] / ts, tb = rank[b] / ts;
+        if (ta != tb) return ta < tb;
+        const int32_t ga = nbt[a] == INT32_MAX ? -1 : nbt[a], gb = nbt[b] == INT32_MAX ? -1 : nbt[b];
+        if (ga != gb) return ga < gb;
+        return rank[a] < rank[b];
+    });
+    for (int64_t i = 0; i < nc; ++i) rank[order[i]] = (int32_t)i;
+}
+
 static void solver_inspect_once(dgt_solver *s, const dgt_inspect_params *p, int cap) {
     hipStream_t st = s->st;
     s->inspected = false;
@@ -1271,6 +1305,9 @@ static void solver_inspect_once(dgt_solver *s, const dgt_inspect_params *p, int 
     s->sched = sch.release();
     // executor layout follows the seed order of the schedule
     auto rank = s->sched->s->seed_rank.download(st, s->nc);
+    const char *eo = std::getenv("DGT_EXEC_ORDER");
+    if (s->last_region.empty() && !(eo && std::string(eo) == "seed"))
+        group_halo_cells(s, rank, s->last_sub_ts.empty() ? p->tile_size : s->last_sub_ts[0]);
     set_exec_order(s, rank);
     // the schedule stays valid when the tiled executor cannot run its tiles
     // (footprints beyond 16,383 cells); only the tiled executor is then unavailable
