@@ -465,7 +465,8 @@ def part_block(a):
     return out
 
 
-TILE_SOURCES = ("tile_chain.h", "dg_kernels.h", "tile_args.h")
+# the tile kernel and the host code that lays out its data (cell order, footprints)
+TILE_SOURCES = ("tile_chain.h", "dg_kernels.h", "tile_args.h", "solver.hip")
 
 
 def measured_traffic(workload, dtype, ts, splits, schedule):

@@ -1241,37 +1241,41 @@ static void prepare_tiled(dgt_solver *s) {
     }
 }
 
-// Cell order of the executor within each seed tile (tile t holds the seeds of ranks
-// [t ts, (t+1) ts)): the cells only its own footprint holds first, then the cells that
-// other tiles' footprints also gather, grouped by the lowest such tile, each group in
-// seed order.  The fields are stored [component][node][cell], so a cell gathered as
-// part of another tile's halo pulls a memory sector per component and node; with a
-// neighbour's halo cells in one run those sectors are shared.  The order is only a
-// permutation of the executor's layout: schedules, results and the caller's
-// numbering are unchanged.
-static void group_halo_cells(dgt_solver *s, std::vector<int32_t> &rank, int64_t ts) {
+// Cell order of the executor within each seed tile (the tile that runs a cell's
+// iteration of the first loop, whose assignment is the seed partition): the cells
+// only its own footprint holds first, then the cells that other tiles' footprints
+// also gather, grouped by the lowest such tile, each group in seed order.  The fields
+// are stored [component][node][cell], so a cell gathered as part of another tile's
+// halo pulls a memory sector per component and node; with a neighbour's halo cells in
+// one run those sectors are shared.  The order is only a permutation of the
+// executor's layout: schedules, results and the caller's numbering are unchanged.
+static void group_halo_cells(dgt_solver *s, std::vector<int32_t> &rank) {
     hipStream_t st = s->st;
-    const SubSched &sb = s->sched->s->sub[0];
+    const Schedule &S = *s->sched->s;
+    const SubSched &sb = S.sub[0];
     const int64_t nc = s->nc;
-    if (nc == 0 || sb.ntiles == 0 || ts <= 0) return;
+    if (nc == 0 || sb.ntiles == 0 || S.seed_set != 0 || S.loop_size[0] != nc) return;
+    const std::vector<int32_t> owner = S.sigma[0].download(st, nc);
     const std::vector<int32_t> foff = sb.foot_off[0].download(st, sb.ntiles + 1);
     const std::vector<int32_t> foot = sb.foot[0].download(st, std::max<int64_t>(foff[sb.ntiles], 1));
     std::vector<int32_t> nbt(nc, INT32_MAX);
     for (int t = 0; t < sb.ntiles; ++t)
         for (int q = foff[t]; q < foff[t + 1]; ++q) {
             const int32_t x = foot[q];
-            if (rank[x] / ts != t) nbt[x] = std::min(nbt[x], t);
+            if (owner[x] != t) nbt[x] = std::min(nbt[x], t);
         }
-    std::vector<int32_t> order(nc);
-    std::iota(order.begin(), order.end(), 0);
-    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        const int64_t ta = rank[a] / ts, tb = rank[b] / ts;
-        if (ta != tb) return ta < tb;
-        const int32_t ga = nbt[a] == INT32_MAX ? -1 : nbt[a], gb = nbt[b] == INT32_MAX ? -1 : nbt[b];
-        if (ga != gb) return ga < gb;
-        return rank[a] < rank[b];
-    });
-    for (int64_t i = 0; i < nc; ++i) rank[order[i]] = (int32_t)i;
+    // key (seed tile, group: 0 interior, 1 + the neighbouring tile), then the seed rank
+    struct Key {
+        uint64_t hi;
+        int32_t rank, cell;
+    };
+    std::vector<Key> keys(nc);
+    for (int64_t x = 0; x < nc; ++x)
+        keys[x] = {((uint64_t)(uint32_t)owner[x] << 32) | (uint64_t)(nbt[x] == INT32_MAX ? 0 : (uint32_t)nbt[x] + 1u),
+                   rank[x], (int32_t)x};
+    std::sort(keys.begin(), keys.end(),
+              [](const Key &a, const Key &b) { return a.hi != b.hi ? a.hi < b.hi : a.rank < b.rank; });
+    for (int64_t i = 0; i < nc; ++i) rank[keys[i].cell] = (int32_t)i;
 }
 
 static void solver_inspect_once(dgt_solver *s, const dgt_inspect_params *p, int cap) {
@@ -1306,8 +1310,7 @@ static void solver_inspect_once(dgt_solver *s, const dgt_inspect_params *p, int 
     // executor layout follows the seed order of the schedule
     auto rank = s->sched->s->seed_rank.download(st, s->nc);
     const char *eo = std::getenv("DGT_EXEC_ORDER");
-    if (s->last_region.empty() && !(eo && std::string(eo) == "seed"))
-        group_halo_cells(s, rank, s->last_sub_ts.empty() ? p->tile_size : s->last_sub_ts[0]);
+    if (!(eo && std::string(eo) == "seed")) group_halo_cells(s, rank);
     set_exec_order(s, rank);
     // the schedule stays valid when the tiled executor cannot run its tiles
     // (footprints beyond 16,383 cells); only the tiled executor is then unavailable
