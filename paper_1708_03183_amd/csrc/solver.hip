@@ -1241,10 +1241,11 @@ static void prepare_tiled(dgt_solver *s) {
     }
 }
 
-// Cell order of the executor within each seed tile (the tile that runs a cell's
-// iteration of the first loop, whose assignment is the seed partition): the cells
-// only its own footprint holds first, then the cells that other tiles' footprints
-// also gather, grouped by the lowest such tile, each group in seed order.  The fields
+// Cell order of the executor within each seed tile of the sub-chain with the finest
+// seed partition (the tile that runs a cell's iteration of the sub-chain's first
+// loop, whose assignment is the seed partition): the cells only its own footprint
+// holds first, then the cells that other tiles' footprints also gather, grouped by
+// the lowest such tile, each group in seed order.  The fields
 // are stored [component][node][cell], so a cell gathered as part of another tile's
 // halo pulls a memory sector per component and node; with a neighbour's halo cells in
 // one run those sectors are shared.  The order is only a permutation of the
@@ -1252,10 +1253,15 @@ static void prepare_tiled(dgt_solver *s) {
 static void group_halo_cells(dgt_solver *s, std::vector<int32_t> &rank) {
     hipStream_t st = s->st;
     const Schedule &S = *s->sched->s;
-    const SubSched &sb = S.sub[0];
+    // the sub-chain with the finest seed partition (the most tiles)
+    size_t bf = 0;
+    for (size_t b = 1; b < S.sub.size(); ++b)
+        if (S.sub[b].ntiles > S.sub[bf].ntiles) bf = b;
+    const SubSched &sb = S.sub[bf];
     const int64_t nc = s->nc;
-    if (nc == 0 || sb.ntiles == 0 || S.seed_set != 0 || S.loop_size[0] != nc) return;
-    const std::vector<int32_t> owner = S.sigma[0].download(st, nc);
+    if (nc == 0 || sb.ntiles == 0 || S.seed_set != 0 || s->loops[sb.first].set != 0 || S.loop_size[sb.first] != nc)
+        return;
+    const std::vector<int32_t> owner = S.sigma[sb.first].download(st, nc);
     const std::vector<int32_t> foff = sb.foot_off[0].download(st, sb.ntiles + 1);
     const std::vector<int32_t> foot = sb.foot[0].download(st, std::max<int64_t>(foff[sb.ntiles], 1));
     std::vector<int32_t> nbt(nc, INT32_MAX);
