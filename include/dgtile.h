@@ -219,7 +219,10 @@ dgt_status dgt_solver_create(const dgt_mesh *m, const double *lam, const double 
                              const dgt_solver_params *p, void *stream, dgt_solver **out);
 /* Inspect the solver's chain on the GPU (dgt_inspect; seed_xy is ignored and
  * the cell centroids are used) and build the executor plan: cells renumbered
- * into seed order, per-tile footprints in LDS slots and local maps.  A tile whose
+ * by seed tile, within a tile the cells that other tiles' footprints gather last,
+ * grouped by the neighbouring tile (the environment variable DGT_EXEC_ORDER=seed,
+ * read here, keeps the plain seed order; results are identical), per-tile
+ * footprints in LDS slots and local maps.  A tile whose
  * working set exceeds the LDS runs on the generic tile kernel with that working set
  * in a global scratch region per workgroup (it stays in L2 and the MALL while the
  * tile runs; sized for the largest colour launch, allocated at the first tiled
