@@ -36,6 +36,7 @@ struct SubPlan {
     DBuf<uint32_t> lmap[31];
     DBuf<uint32_t> tnb;
     DBuf<int32_t> tnb_off;
+    DBuf<int32_t> tmeta;  // [ntiles][4] in colour order: tile, first slot, footprint length, table offset
     std::vector<int32_t> color_off;
     TileArgs args{};
     size_t lds_bytes = 0;
@@ -573,6 +574,19 @@ static void build_plan(dgt_solver *s) {
             DGT_REQUIRE(!dup, DGT_ESTATE, "a cell facet appears twice in one facet loop of a tile");
             P.tnb.upload(tab, st);
             P.tnb_off.upload(toff, st);
+            {
+                const std::vector<int32_t> byc = sb.tiles_by_color.download(st, sb.ntiles);
+                std::vector<int32_t> meta(4 * std::max<int32_t>(sb.ntiles, 1), 0);
+                for (int i = 0; i < sb.ntiles; ++i) {
+                    const int t = byc[i];
+                    meta[4 * i] = t;
+                    meta[4 * i + 1] = foff[t];
+                    meta[4 * i + 2] = foff[t + 1] - foff[t];
+                    meta[4 * i + 3] = toff[t];
+                }
+                P.tmeta.upload(meta, st);
+                A.tmeta = P.tmeta.p;
+            }
             A.tnb = P.tnb.p;
             A.tnb_off = P.tnb_off.p;
             for (int i = 0; i < sb.n; ++i) P.lmap[i].release();

@@ -27,6 +27,9 @@ struct TileArgs {
     const uint32_t *tnb;      // per tile: [nfl][3][nfoot] neighbour codes
     const int32_t *tnb_off;   // [ntiles+1]
     const int32_t *tiles;     // tiles of this sub-chain in execution order
+    // per position of `tiles`: the tile, its first footprint slot, its footprint length
+    // and its neighbour-table offset, read by the chain kernel in one load
+    const int32_t *tmeta;     // [ntiles][4]
     int32_t tile_base;        // first tile of the colour in `tiles`
     void *F[F_COUNT];
     const void *geo;

@@ -20,7 +20,7 @@ namespace dgt {
 template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int NT>
 __device__ __forceinline__ void batch_body(const RefC<K, T> &Rf, const BatchArgs &b,
                                            const TileArgs *__restrict__ args, unsigned char *smem) {
-    __shared__ int s_tile, s_shot, s_mesh;
+    __shared__ int s_tile, s_shot, s_mesh, s_f0, s_nfoot, s_b0;
     __shared__ double s_amp;
     T *lds = reinterpret_cast<T *>(smem);
     for (;;) {
@@ -41,7 +41,11 @@ __device__ __forceinline__ void batch_body(const RefC<K, T> &Rf, const BatchArgs
                 const uint32_t local = (uint32_t)b.seg_local[lo] + (t - (uint32_t)b.seg_start[lo]);
                 s_mesh = m;
                 s_shot = (int)(local % (uint32_t)a.nshots);
-                s_tile = a.tiles[local / (uint32_t)a.nshots];
+                const TileMeta mt = tile_meta(a, (int)(local / (uint32_t)a.nshots));
+                s_tile = mt.x;
+                s_f0 = mt.y;
+                s_nfoot = mt.z;
+                s_b0 = mt.w;
                 s_amp = b.amp_tab[(int64_t)m * b.amp_stride + (b.amp_base ? *b.amp_base : 0) + b.amp_idx];
             }
         }
@@ -52,7 +56,7 @@ __device__ __forceinline__ void batch_body(const RefC<K, T> &Rf, const BatchArgs
         const int mesh = __builtin_amdgcn_readfirstlane(s_mesh);
         const int shot = __builtin_amdgcn_readfirstlane(s_shot);
         const TileArgs &a = args[mesh];
-        chain_tile<K, T, UPW, ORDER, O0, NOPS>(Rf, a, lds, tile, shot, (T)s_amp, b.epoch);
+        chain_tile<K, T, UPW, ORDER, O0, NOPS>(Rf, a, lds, tile, s_f0, s_nfoot, s_b0, shot, (T)s_amp, b.epoch);
         if (!b.persist) return;
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();

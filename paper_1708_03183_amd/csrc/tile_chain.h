@@ -416,12 +416,22 @@ __device__ __forceinline__ int next_tile(const TileArgs &a, int &shot) {
     return tile;
 }
 
+// Tile metadata at position pos of the sub-chain's colour order: the tile, its first
+// footprint slot, its footprint length and its neighbour-table offset.
+struct TileMeta {
+    int x, y, z, w;  // tile, first footprint slot, footprint length, neighbour-table offset
+};
+__device__ __forceinline__ TileMeta tile_meta(const TileArgs &a, int pos) {
+    const auto p = gp(a.tmeta) + 4 * (int64_t)pos;
+    return TileMeta{p[0], p[1], p[2], p[3]};
+}
+
+// f0, nfoot, b0: the tile's first footprint slot, footprint length and neighbour-table
+// offset (from tile_meta)
 template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS>
 __device__ __forceinline__ void chain_tile(const RefC<K, T> &Rf, const TileArgs &a, T *__restrict__ lds, int tile,
-                                           int shot, T amp, uint32_t epoch) {
+                                           int f0, int nfoot, int b0, int shot, T amp, uint32_t epoch) {
     constexpr int NP = np_of(K);
-    const int f0 = a.foot_off[tile];
-    const int nfoot = a.foot_off[tile + 1] - f0;
     const int s = threadIdx.x;
     const bool act = s < nfoot;
 
@@ -447,7 +457,6 @@ __device__ __forceinline__ void chain_tile(const RefC<K, T> &Rf, const TileArgs 
             if (m && ((m & (~m + 1u)) & a.rfirst_mask[f])) fl |= 1u << f;
             if ((acc & a.writes_mask[f]) && (((a.persistent_mask >> f) & 1) || !single)) fl |= 1u << (8 + f);
         }
-        const int b0 = a.tnb_off[tile];
 #pragma unroll
         for (int q = 0; q < NOPS; ++q)
 #pragma unroll
@@ -492,20 +501,33 @@ __device__ __forceinline__ void chain_tile(const RefC<K, T> &Rf, const TileArgs 
 
 template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int NT>
 __device__ __forceinline__ void chain_kernel_body(const RefC<K, T> &Rf, const TileArgs &a, unsigned char *smem) {
-    __shared__ int s_next, s_shot;
+    __shared__ int s_next, s_shot, s_f0, s_nfoot, s_b0;
     T *lds = reinterpret_cast<T *>(smem);
     if (!a.persist) {  // one launch per colour
         const int item = xcd_item((int)blockIdx.x, (int)gridDim.x);
-        chain_tile<K, T, UPW, ORDER, O0, NOPS>(Rf, a, lds, a.tiles[a.tile_base + item / a.nshots], item % a.nshots,
-                                               (T)a.src_amp, a.epoch);
+        const TileMeta m = tile_meta(a, a.tile_base + item / a.nshots);
+        chain_tile<K, T, UPW, ORDER, O0, NOPS>(Rf, a, lds, m.x, m.y, m.z, m.w, item % a.nshots, (T)a.src_amp,
+                                               a.epoch);
         return;
     }
     for (;;) {
-        if (threadIdx.x == 0) s_next = take_ticket(a, s_shot);  // chain_tile waits for the predecessors
+        if (threadIdx.x == 0) {  // the next (tile, shot) ticket; chain_tile waits for the predecessors
+            const uint32_t ticket = atomicAdd(a.head, 1u) - a.head_base;
+            if (ticket >= (uint32_t)a.nexec * (uint32_t)a.nshots) {
+                s_next = -1;
+            } else {
+                const TileMeta m = tile_meta(a, (int)(ticket / (uint32_t)a.nshots));
+                s_shot = (int)(ticket % (uint32_t)a.nshots);
+                s_next = m.x;
+                s_f0 = m.y;
+                s_nfoot = m.z;
+                s_b0 = m.w;
+            }
+        }
         __syncthreads();
         const int tile = s_next, shot = s_shot;
         if (tile < 0) return;
-        chain_tile<K, T, UPW, ORDER, O0, NOPS>(Rf, a, lds, tile, shot, (T)a.src_amp, a.epoch);
+        chain_tile<K, T, UPW, ORDER, O0, NOPS>(Rf, a, lds, tile, s_f0, s_nfoot, s_b0, shot, (T)a.src_amp, a.epoch);
         // every wave waits for its coherent field stores to complete, so once the barrier
         // is passed the whole tile is visible at device scope and its successors may start
         __builtin_amdgcn_s_waitcnt(0);
