@@ -382,19 +382,13 @@ __device__ __forceinline__ void chain_op(const RefC<K, T> &Rf, CellRegs<K, T> &r
     }
 }
 
-// Dependence-driven schedule, thread 0 of a workgroup.  take_ticket: the next (tile,
-// shot) item, tiles in colour order; -1 when none is left.  wait_preds: wait until
-// every predecessor of the tile has finished for the same shot.  Predecessors have
-// lower colours, hence lower tickets, so they were taken by workgroups already
-// running: the wait ends unless a counter is wrong, and the poll limit ends it then
-// too (the error flag tells the host, and the tile's results are invalid).
-__device__ __forceinline__ int take_ticket(const TileArgs &a, int &shot) {
-    const uint32_t ticket = atomicAdd(a.head, 1u) - a.head_base;
-    if (ticket >= (uint32_t)a.nexec * (uint32_t)a.nshots) return -1;
-    shot = (int)(ticket % (uint32_t)a.nshots);
-    return a.tiles[ticket / (uint32_t)a.nshots];
-}
-
+// Dependence-driven schedule, thread 0 of a workgroup: the next (tile, shot) item is
+// ticket t of the launch (tiles in colour order, tile_meta of position t / nshots);
+// wait_preds waits until every predecessor of the tile has finished for the same
+// shot.  Predecessors have lower colours, hence lower tickets, so they were taken by
+// workgroups already running: the wait ends unless a counter is wrong, and the poll
+// limit ends it then too (the error flag tells the host, and the tile's results are
+// invalid).
 __device__ __forceinline__ bool wait_preds(const TileArgs &a, int tile, int shot, uint32_t epoch) {
     const uint32_t need = (uint32_t)a.need[tile], base = (epoch - 1u) * need;
     const uint32_t *cnt = a.cnt + (int64_t)shot * a.ntiles + tile;
@@ -407,13 +401,6 @@ __device__ __forceinline__ bool wait_preds(const TileArgs &a, int tile, int shot
         __builtin_amdgcn_s_sleep(2);
     }
     return true;
-}
-
-// both: -1 also when the wait gave up
-__device__ __forceinline__ int next_tile(const TileArgs &a, int &shot) {
-    const int tile = take_ticket(a, shot);
-    if (tile < 0 || !wait_preds(a, tile, shot, a.epoch)) return -1;
-    return tile;
 }
 
 // Tile metadata at position pos of the sub-chain's colour order: the tile, its first

@@ -401,7 +401,7 @@ __device__ __forceinline__ void mfma_op(const MfmaRef<K, T> &Ar, const TileArgs 
 
 template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int NT>
 __device__ __forceinline__ void mfma_tile(const MfmaRef<K, T> &Ar, const TileArgs &a, unsigned char *smem, int tile,
-                                          int shot) {
+                                          int f0, int nfoot, int b0, int shot) {
     MfmaTile<T> tl;
     tl.S = a.stride;
     tl.f = reinterpret_cast<T *>(smem);
@@ -411,8 +411,8 @@ __device__ __forceinline__ void mfma_tile(const MfmaRef<K, T> &Ar, const TileArg
     tl.nb = reinterpret_cast<uint32_t *>(tl.fl + tl.S + (tl.S & 1));
     tl.tile = tile;
     tl.shot = shot;
-    tl.f0 = a.foot_off[tile];
-    tl.nfoot = a.foot_off[tile + 1] - tl.f0;
+    tl.f0 = f0;
+    tl.nfoot = nfoot;
     const int tid = threadIdx.x;
     // the tile's cells, loop bits, gather / write-back flags and geometry
     {
@@ -457,7 +457,6 @@ __device__ __forceinline__ void mfma_tile(const MfmaRef<K, T> &Ar, const TileArg
             for (int q = 0; q < 3 * NOPS; ++q) tl.nb[q * tl.S + s] = 0u;
         }
         // the neighbour tables of the tile's facet loops ([operator][facet][slot])
-        const int b0 = a.tnb_off[tile];
         for (int i = tid; i < 3 * NOPS * tl.nfoot; i += NT) {
             const int q = i / tl.nfoot, s = i - q * tl.nfoot;
             tl.nb[q * tl.S + s] = a.tnb[b0 + i];
@@ -471,21 +470,33 @@ __device__ __forceinline__ void mfma_tile(const MfmaRef<K, T> &Ar, const TileArg
 template <int K, typename T, bool UPW, int ORDER, int O0, int NOPS, int NT>
 __global__ __launch_bounds__(NT) void k_tile_mfma(const TileArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_next, s_shot;
+    __shared__ int s_next, s_shot, s_f0, s_nfoot, s_b0;
     MfmaRef<K, T> Ar;
     Ar.load(R<K, T>(), threadIdx.x & 63);
     if (!a.persist) {  // one launch per colour
         const int item = xcd_item((int)blockIdx.x, (int)gridDim.x);
-        mfma_tile<K, T, UPW, ORDER, O0, NOPS, NT>(Ar, a, smem, a.tiles[a.tile_base + item / a.nshots],
-                                                   item % a.nshots);
+        const TileMeta m = tile_meta(a, a.tile_base + item / a.nshots);
+        mfma_tile<K, T, UPW, ORDER, O0, NOPS, NT>(Ar, a, smem, m.x, m.y, m.z, m.w, item % a.nshots);
         return;
     }
     for (;;) {  // dependence-driven schedule, as in the register-resident chain kernel
-        if (threadIdx.x == 0) s_next = next_tile(a, s_shot);
+        if (threadIdx.x == 0) {
+            const uint32_t ticket = atomicAdd(a.head, 1u) - a.head_base;
+            s_next = -1;
+            if (ticket < (uint32_t)a.nexec * (uint32_t)a.nshots) {
+                const TileMeta m = tile_meta(a, (int)(ticket / (uint32_t)a.nshots));
+                const int shot = (int)(ticket % (uint32_t)a.nshots);
+                s_shot = shot;
+                s_f0 = m.y;
+                s_nfoot = m.z;
+                s_b0 = m.w;
+                if (wait_preds(a, m.x, shot, a.epoch)) s_next = m.x;  // -1 also when the wait gave up
+            }
+        }
         __syncthreads();
         const int tile = s_next, shot = s_shot;
         if (tile < 0) return;
-        mfma_tile<K, T, UPW, ORDER, O0, NOPS, NT>(Ar, a, smem, tile, shot);
+        mfma_tile<K, T, UPW, ORDER, O0, NOPS, NT>(Ar, a, smem, tile, s_f0, s_nfoot, s_b0, shot);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (threadIdx.x == 0)
