@@ -245,8 +245,9 @@ dgt_status dgt_solver_fuse_steps(dgt_solver *s, int32_t steps);
 /* Autotuner: picks the seed tile size (from tile_sizes) and the executor
  * schedule (0 or 1, see dgt_solver_set_schedule) by timing trial steps, and
  * leaves the solver inspected and scheduled with the fastest pair.  Each
- * candidate is inspected; those the tiled executor cannot run are skipped.
- * A footprint model orders the rest: the cells every tile gathers, summed over
+ * candidate is inspected; those the tiled executor cannot run are skipped, and
+ * so are those with tiles beyond the LDS (run from global scratch) when any
+ * candidate fits the LDS.  A footprint model orders the rest: the cells every tile gathers, summed over
  * tiles and sub-chains and divided by the mesh's cells (the data a step moves
  * per cell, larger for smaller tiles, in the spirit of the paper's estimates of
  * tile footprints and reuse); with prune > 0 a candidate whose model cost
@@ -272,7 +273,7 @@ typedef struct {
     int32_t schedule;   /* chosen schedule */
     double ms_per_step; /* its trial time */
     int32_t timed;      /* (tile size, schedule) pairs timed */
-    int32_t skipped;    /* tile sizes not timed (not runnable, or the model) */
+    int32_t skipped;    /* tile sizes not timed (not runnable, beyond the LDS, or the model) */
 } dgt_autotune_result;
 dgt_status dgt_solver_autotune(dgt_solver *s, const dgt_autotune_params *p, dgt_autotune_result *out);
 /* The schedule of the last dgt_solver_inspect (borrowed; NULL before). */

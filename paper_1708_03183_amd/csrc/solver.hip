@@ -1405,7 +1405,7 @@ dgt_status dgt_solver_autotune(dgt_solver *s, const dgt_autotune_params *p, dgt_
             ip.seed_region = regions.data();
             ip.region_carry = 1;
         }
-        struct Cand { int ts; double foot; };
+        struct Cand { int ts; double foot; bool gmem; };
         std::vector<Cand> cands;
         int skipped = 0, timed = 0;
         // footprint model: the cells a tile gathers over all its sub-chains, summed over
@@ -1422,9 +1422,18 @@ dgt_status dgt_solver_autotune(dgt_solver *s, const dgt_autotune_params *p, dgt_
             }
             double f = 0;
             for (const auto &sb : s->sched->s->sub) f += (double)sb.foot_len[0];
-            cands.push_back({p->tile_sizes[i], f / (double)s->nc});
+            bool gmem = false;
+            for (const auto &P : s->plan) gmem |= P.gmem_bytes > 0;
+            cands.push_back({p->tile_sizes[i], f / (double)s->nc, gmem});
         }
         DGT_REQUIRE(!cands.empty(), DGT_EUNSUPPORTED, "no candidate tile size has tiles the executor can run");
+        // tiles whose working set leaves the LDS run from global scratch at a fraction of
+        // the speed: they are timed only when no candidate fits the LDS
+        if (std::any_of(cands.begin(), cands.end(), [](const Cand &c) { return !c.gmem; })) {
+            const size_t before = cands.size();
+            cands.erase(std::remove_if(cands.begin(), cands.end(), [](const Cand &c) { return c.gmem; }), cands.end());
+            skipped += (int)(before - cands.size());
+        }
         std::stable_sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.foot < b.foot; });
         double best_ms = 1e300;
         int best_ts = cands[0].ts, best_sched = 0;
